@@ -1,0 +1,254 @@
+"""Python binding of the float64 CPU oracle (oracle/rt_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the benchmark's
+CPU-baseline leg are the only users.  The product library never imports this
+module.  The C source is compiled on first use (gcc, -O2, contraction off).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "rt_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+MAX_BINS = 16
+FATE_TRUNC, FATE_ESCAPE = 1, 2
+TRACE_HDR = 8
+
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle shared library next to its source."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class Grid(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("cell_cm", C.c_double), ("y_he", C.c_double),
+                ("n_bins", C.c_int32), ("e_ev", C.c_double * MAX_BINS),
+                ("sigma", (C.c_double * MAX_BINS) * 3), ("redshift", C.c_double),
+                ("tau_kill", C.c_double), ("n_chem", C.c_int32), ("flags", C.c_uint32)]
+
+
+class Rates(C.Structure):
+    _fields_ = [("a_hii", C.c_double), ("a_heii", C.c_double), ("a_heiii", C.c_double),
+                ("b_hi", C.c_double), ("b_hei", C.c_double), ("b_heii", C.c_double)]
+
+
+_P = C.POINTER
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            L = C.CDLL(LIB)
+            dp, ip, i64p, u64p = _P(C.c_double), _P(C.c_int32), _P(C.c_int64), _P(C.c_uint64)
+            gp = _P(Grid)
+            L.orc_philox4x64_10.argtypes = [u64p, u64p, u64p]
+            L.orc_direction.argtypes = [C.c_uint64] * 4 + [C.c_int, ip]
+            L.orc_direction.restype = C.c_int
+            L.orc_trace_ray.argtypes = [ip, ip, ip, C.c_int64, i64p, dp, ip]
+            L.orc_trace_ray.restype = C.c_int64
+            L.orc_march.argtypes = [gp, dp, C.c_int32, ip, dp, dp, C.c_uint32, C.c_double,
+                                    C.c_int64, C.c_uint64, C.c_uint64, C.c_uint64,
+                                    C.c_int64, C.c_int64, dp, dp, C.c_int32, C.c_int32, ip]
+            L.orc_rates_at.argtypes = [C.c_double, _P(Rates)]
+            L.orc_cooling.argtypes = [C.c_double] * 7
+            L.orc_cooling.restype = C.c_double
+            L.orc_compton_coeff.argtypes = [C.c_double]
+            L.orc_compton_coeff.restype = C.c_double
+            L.orc_update_cell_ex.argtypes = [gp, C.c_double, C.c_double, dp, dp, dp,
+                                             _P(Rates), C.c_int]
+            L.orc_update_cells.argtypes = [gp, C.c_double, dp, dp, dp, dp, C.c_int64, i64p]
+            L.orc_absorbers.argtypes = [gp, dp, dp, dp]
+            L.orc_step.argtypes = [gp, dp, dp, dp, C.c_int32, ip, dp, dp, C.c_uint32,
+                                   C.c_double, C.c_int64, C.c_int32, C.c_uint64, C.c_uint64,
+                                   u64p, dp, dp, dp, C.c_int32, C.c_int32, ip]
+            L.orc_step.restype = C.c_int
+            _lib = L
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray], ct):
+    if a is None:
+        return None
+    return a.ctypes.data_as(_P(ct))
+
+
+def _c64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ----------------------------------------------------------------------------
+def philox(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, np.uint64)
+    lib().orc_philox4x64_10(_ptr(c, C.c_uint64), _ptr(k, C.c_uint64), _ptr(out, C.c_uint64))
+    return out
+
+
+def direction(seed: int, solve_id: int, g: int, step_index: int, octant: bool = False):
+    c = np.zeros(3, np.int32)
+    att = lib().orc_direction(seed, solve_id, g, step_index, int(octant), _ptr(c, C.c_int32))
+    return c, att
+
+
+def trace_ray(n, o, c, max_len: int = 4096):
+    n = np.ascontiguousarray(n, np.int32)
+    o = np.ascontiguousarray(o, np.int32)
+    c = np.ascontiguousarray(c, np.int32)
+    cells = np.zeros(max_len, np.int64)
+    s = np.zeros(max_len, np.float64)
+    face = np.zeros(1, np.int32)
+    cnt = lib().orc_trace_ray(_ptr(n, C.c_int32), _ptr(o, C.c_int32), _ptr(c, C.c_int32),
+                              max_len, _ptr(cells, C.c_int64), _ptr(s, C.c_double),
+                              _ptr(face, C.c_int32))
+    m = min(cnt, max_len)
+    return cells[:m].copy(), s[:m].copy(), int(face[0]), int(cnt)
+
+
+def make_grid(work, flags: Optional[int] = None, n_chem: Optional[int] = None) -> Grid:
+    g = Grid()
+    for a in range(3):
+        g.n[a] = int(work.n[a])
+    g.cell_cm = float(work.cell_cm)
+    g.y_he = float(work.y_he)
+    nb = work.bins.n_bins
+    g.n_bins = nb
+    for j in range(nb):
+        g.e_ev[j] = float(work.bins.e_ev[j])
+        for s in range(3):
+            g.sigma[s][j] = float(work.bins.sigma[s, j])
+    g.redshift = float(work.redshift)
+    g.tau_kill = float(work.tau_kill)
+    g.n_chem = int(work.n_chem if n_chem is None else n_chem)
+    g.flags = int(work.flags if flags is None else flags) & 1
+    return g
+
+
+def rates_at(T: float) -> Rates:
+    r = Rates()
+    lib().orc_rates_at(float(T), C.byref(r))
+    return r
+
+
+def cooling(T, ne, n_hi, n_hii, n_hei, n_heii, n_heiii) -> float:
+    return lib().orc_cooling(*(float(v) for v in (T, ne, n_hi, n_hii, n_hei, n_heii, n_heiii)))
+
+
+def compton_coeff(z: float) -> float:
+    return lib().orc_compton_coeff(float(z))
+
+
+def update_cell(grid: Grid, dt: float, nh: float, x, T: float, acc,
+                fixed: Optional[Rates] = None, no_cool: bool = False):
+    """Advance one cell; returns (x[5], T)."""
+    xv = _c64(np.array(x, dtype=np.float64).copy())
+    tv = np.array([T], np.float64)
+    av = _c64(acc)
+    lib().orc_update_cell_ex(C.byref(grid), float(dt), float(nh), _ptr(xv, C.c_double),
+                             _ptr(tv, C.c_double), _ptr(av, C.c_double),
+                             C.byref(fixed) if fixed is not None else None, int(no_cool))
+    return xv, float(tv[0])
+
+
+LEDGER_KEYS = ("emitted", "absorbed", "escaped", "truncated")
+
+
+def ledger_dict(led: np.ndarray) -> dict:
+    d = {k: float(led[2 * i] + led[2 * i + 1]) for i, k in enumerate(LEDGER_KEYS)}
+    d.update(crossings=int(led[8]), n_escaped=int(led[9]), n_truncated=int(led[10]),
+             packets=int(led[11]))
+    return d
+
+
+class OracleSolve:
+    """Float64 state of one solve in natural cell order, advanced by the oracle."""
+
+    def __init__(self, work, seed: Optional[int] = None):
+        self.work = work
+        self.grid = make_grid(work)
+        nc = work.ncell
+        self.nh = _c64(work.n_h).copy()
+        self.x = _c64(work.x).reshape(5, nc).copy()
+        self.T = _c64(work.temp).copy()
+        self.src_ijk = np.ascontiguousarray(work.src_ijk, np.int32).reshape(-1, 3)
+        self.src_ndot = _c64(work.src_ndot)
+        self.src_sed = _c64(work.src_sed).reshape(len(self.src_ndot), -1)
+        self.src_flags = int(work.src_flags)
+        self.acc = np.zeros((4, nc))
+        self.kappa = np.zeros((3, nc))
+        self.step_index = np.zeros(1, np.uint64)
+        self.seed = work.seed if seed is None else seed
+        self.trace = None
+
+    def step(self, dt: Optional[float] = None, packets: Optional[int] = None,
+             seed: Optional[int] = None, trace_n: int = 0, trace_len: int = 0) -> dict:
+        w = self.work
+        dt = w.dt_s if dt is None else dt
+        packets = w.packets if packets is None else packets
+        seed = self.seed if seed is None else seed
+        led = np.zeros(16)
+        tr = np.zeros((max(trace_n, 0), TRACE_HDR + trace_len), np.int32) if trace_n else None
+        rc = lib().orc_step(C.byref(self.grid), _ptr(self.nh, C.c_double), _ptr(self.x, C.c_double),
+                            _ptr(self.T, C.c_double), len(self.src_ndot),
+                            _ptr(self.src_ijk, C.c_int32), _ptr(self.src_ndot, C.c_double),
+                            _ptr(self.src_sed, C.c_double), self.src_flags, float(dt),
+                            int(packets), int(w.n_sub), int(seed), int(w.solve_id),
+                            _ptr(self.step_index, C.c_uint64), _ptr(self.acc, C.c_double),
+                            _ptr(self.kappa, C.c_double), _ptr(led, C.c_double),
+                            int(trace_n), int(trace_len), _ptr(tr, C.c_int32))
+        if rc != 0:
+            raise ValueError("oracle step rejected: fewer packets than sources in a sub-step")
+        self.trace = tr
+        return ledger_dict(led)
+
+    def absorbers(self) -> np.ndarray:
+        lib().orc_absorbers(C.byref(self.grid), _ptr(self.nh, C.c_double),
+                            _ptr(self.x, C.c_double), _ptr(self.kappa, C.c_double))
+        return self.kappa
+
+    def march(self, g_begin: int, g_end: int, *, dt: float, packets: int, seed: int,
+              step_index: int, trace_n: int = 0, trace_len: int = 0, acc=None):
+        """March packet ids [g_begin, g_end) of one sub-step over the current
+        frozen state (absorbers recomputed); returns (acc, ledger, trace)."""
+        self.absorbers()
+        acc = np.zeros((4, self.work.ncell)) if acc is None else acc
+        led = np.zeros(16)
+        tr = np.zeros((max(trace_n, 0), TRACE_HDR + trace_len), np.int32) if trace_n else None
+        lib().orc_march(C.byref(self.grid), _ptr(self.kappa, C.c_double), len(self.src_ndot),
+                        _ptr(self.src_ijk, C.c_int32), _ptr(self.src_ndot, C.c_double),
+                        _ptr(self.src_sed, C.c_double), self.src_flags, float(dt), int(packets),
+                        int(seed), int(self.work.solve_id), int(step_index), int(g_begin),
+                        int(g_end), _ptr(acc, C.c_double), _ptr(led, C.c_double),
+                        int(trace_n), int(trace_len), _ptr(tr, C.c_int32))
+        return acc, ledger_dict(led), tr
+
+    def update_cells(self, dt: float, acc: np.ndarray, idx: Optional[np.ndarray] = None):
+        """Apply the cell update to the cells in idx (all when None) in place."""
+        acc = _c64(acc)
+        if idx is None:
+            lib().orc_update_cells(C.byref(self.grid), float(dt), _ptr(self.nh, C.c_double),
+                                   _ptr(self.x, C.c_double), _ptr(self.T, C.c_double),
+                                   _ptr(acc, C.c_double), self.work.ncell, None)
+        else:
+            ix = np.ascontiguousarray(idx, np.int64)
+            lib().orc_update_cells(C.byref(self.grid), float(dt), _ptr(self.nh, C.c_double),
+                                   _ptr(self.x, C.c_double), _ptr(self.T, C.c_double),
+                                   _ptr(acc, C.c_double), len(ix), _ptr(ix, C.c_int64))

@@ -66,7 +66,7 @@ def lib():
             L.orc_trace_ray.restype = C.c_int64
             L.orc_march.argtypes = [gp, dp, C.c_int32, ip, dp, dp, C.c_uint32, C.c_double,
                                     C.c_int64, C.c_uint64, C.c_uint64, C.c_uint64,
-                                    C.c_int64, C.c_int64, dp, dp, C.c_int32, C.c_int32, ip]
+                                    C.c_int64, C.c_int64, dp, dp, C.c_int32, C.c_int32, C.c_int32, ip]
             L.orc_rates_at.argtypes = [C.c_double, _P(Rates)]
             L.orc_cooling.argtypes = [C.c_double] * 7
             L.orc_cooling.restype = C.c_double
@@ -78,7 +78,7 @@ def lib():
             L.orc_absorbers.argtypes = [gp, dp, dp, dp]
             L.orc_step.argtypes = [gp, dp, dp, dp, C.c_int32, ip, dp, dp, C.c_uint32,
                                    C.c_double, C.c_int64, C.c_int32, C.c_uint64, C.c_uint64,
-                                   u64p, dp, dp, dp, C.c_int32, C.c_int32, ip]
+                                   u64p, dp, dp, dp, C.c_int32, C.c_int32, C.c_int32, ip]
             L.orc_step.restype = C.c_int
             _lib = L
     return _lib
@@ -190,7 +190,7 @@ class OracleSolve:
         self.T = _c64(work.temp).copy()
         self.src_ijk = np.ascontiguousarray(work.src_ijk, np.int32).reshape(-1, 3)
         self.src_ndot = _c64(work.src_ndot)
-        self.src_sed = _c64(work.src_sed).reshape(len(self.src_ndot), -1)
+        self.src_sed = _c64(work.src_sed).reshape(len(self.src_ndot), work.bins.n_bins)
         self.src_flags = int(work.src_flags)
         self.acc = np.zeros((4, nc))
         self.kappa = np.zeros((3, nc))
@@ -199,7 +199,8 @@ class OracleSolve:
         self.trace = None
 
     def step(self, dt: Optional[float] = None, packets: Optional[int] = None,
-             seed: Optional[int] = None, trace_n: int = 0, trace_len: int = 0) -> dict:
+             seed: Optional[int] = None, trace_n: int = 0, trace_len: int = 0,
+             trace_stride: int = 1) -> dict:
         w = self.work
         dt = w.dt_s if dt is None else dt
         packets = w.packets if packets is None else packets
@@ -213,7 +214,7 @@ class OracleSolve:
                             int(packets), int(w.n_sub), int(seed), int(w.solve_id),
                             _ptr(self.step_index, C.c_uint64), _ptr(self.acc, C.c_double),
                             _ptr(self.kappa, C.c_double), _ptr(led, C.c_double),
-                            int(trace_n), int(trace_len), _ptr(tr, C.c_int32))
+                            int(trace_n), int(trace_len), int(trace_stride), _ptr(tr, C.c_int32))
         if rc != 0:
             raise ValueError("oracle step rejected: fewer packets than sources in a sub-step")
         self.trace = tr
@@ -225,10 +226,13 @@ class OracleSolve:
         return self.kappa
 
     def march(self, g_begin: int, g_end: int, *, dt: float, packets: int, seed: int,
-              step_index: int, trace_n: int = 0, trace_len: int = 0, acc=None):
+              step_index: int, trace_n: int = 0, trace_len: int = 0, trace_stride: int = 1,
+              acc=None, absorbers: bool = True):
         """March packet ids [g_begin, g_end) of one sub-step over the current
-        frozen state (absorbers recomputed); returns (acc, ledger, trace)."""
-        self.absorbers()
+        frozen state (absorbers recomputed unless absorbers=False); returns
+        (acc, ledger, trace)."""
+        if absorbers:
+            self.absorbers()
         acc = np.zeros((4, self.work.ncell)) if acc is None else acc
         led = np.zeros(16)
         tr = np.zeros((max(trace_n, 0), TRACE_HDR + trace_len), np.int32) if trace_n else None
@@ -237,7 +241,7 @@ class OracleSolve:
                         _ptr(self.src_sed, C.c_double), self.src_flags, float(dt), int(packets),
                         int(seed), int(self.work.solve_id), int(step_index), int(g_begin),
                         int(g_end), _ptr(acc, C.c_double), _ptr(led, C.c_double),
-                        int(trace_n), int(trace_len), _ptr(tr, C.c_int32))
+                        int(trace_n), int(trace_len), int(trace_stride), _ptr(tr, C.c_int32))
         return acc, ledger_dict(led), tr
 
     def update_cells(self, dt: float, acc: np.ndarray, idx: Optional[np.ndarray] = None):

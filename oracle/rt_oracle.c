@@ -241,15 +241,16 @@ static int64_t source_of(int64_t g, int64_t P, int64_t S, int64_t *n_s)
  *   kappa : [3][ncell] absorber densities (HI, HeI, HeII), natural order
  *   acc   : [4][ncell] accumulators D_HI, D_HeI, D_HeII (photons), Q (erg)
  *   ledger: see enum above (accumulated, not cleared)
- *   trace : optional, trace_n records of (8 + trace_len) int32 for packet ids
- *           g < trace_n: count, fate, face, last cell, c[3], source, cells...
+ *   trace : optional, trace_n records of (8 + trace_len) int32; packet ids
+ *           g = r * trace_stride (r < trace_n) fill record r: count, fate, face,
+ *           last cell, c[3], source, then the crossed cells
  */
 void orc_march(const orc_grid *G, const double *kappa,
                int32_t n_src, const int32_t *src_ijk, const double *src_ndot,
                const double *src_sed, uint32_t src_flags,
                double dt, int64_t P, uint64_t seed, uint64_t solve_id, uint64_t step_index,
                int64_t g_begin, int64_t g_end, double *acc, double *ledger,
-               int32_t trace_n, int32_t trace_len, int32_t *trace)
+               int32_t trace_n, int32_t trace_len, int32_t trace_stride, int32_t *trace)
 {
     const int64_t ncell = (int64_t)G->n[0] * G->n[1] * G->n[2];
     const int nb = G->n_bins;
@@ -289,7 +290,9 @@ void orc_march(const orc_grid *G, const double *kappa,
         int64_t count = 0;
         int fate = 0, face = 0;
         int64_t last = -1;
-        int32_t *rec = (trace && g < trace_n) ? trace + (int64_t)g * (8 + trace_len) : NULL;
+        const int64_t stride = trace_stride > 0 ? trace_stride : 1;
+        int32_t *rec = (trace && g % stride == 0 && g / stride < trace_n)
+                     ? trace + (g / stride) * (8 + trace_len) : NULL;
 
         for (;;) {
             int64_t num, den;
@@ -602,7 +605,7 @@ int orc_step(const orc_grid *G, const double *nh, double *x, double *T,
              const double *src_sed, uint32_t src_flags,
              double dt, int64_t P, int32_t n_sub, uint64_t seed, uint64_t solve_id,
              uint64_t *step_index, double *acc, double *kappa, double *ledger,
-             int32_t trace_n, int32_t trace_len, int32_t *trace)
+             int32_t trace_n, int32_t trace_len, int32_t trace_stride, int32_t *trace)
 {
     const int64_t ncell = (int64_t)G->n[0] * G->n[1] * G->n[2];
     if (n_src > 0 && P / n_sub < n_src) return -1;
@@ -613,7 +616,8 @@ int orc_step(const orc_grid *G, const double *nh, double *x, double *T,
         memset(acc, 0, sizeof(double) * 4 * ncell);
         if (n_src > 0)
             orc_march(G, kappa, n_src, src_ijk, src_ndot, src_sed, src_flags, dts, Pi,
-                      seed, solve_id, *step_index, 0, Pi, acc, ledger, trace_n, trace_len, trace);
+                      seed, solve_id, *step_index, 0, Pi, acc, ledger, trace_n, trace_len,
+                      trace_stride, trace);
         orc_update_cells(G, dts, nh, x, T, acc, ncell, NULL);
         *step_index += 1;
     }

@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of the Monte-Carlo radiative-transfer hot path on one MI355X.
+
+A step is one full pass of the path over the step's packets: absorber table
+from the frozen state, the packet march (emission, traversal, Eq. (1)
+attenuation, deposition), the ledger and the per-cell ionisation/temperature
+update.  Workload: 256^3 lognormal H+He gas at z = 9, 1e4 black-body sources in
+the densest 1 % of cells, 8 frequency bins, 1e8 packets per step; inputs are
+seeded and synthetic and already resident in HBM when timing starts.
+
+Prints one JSON line: whole-step cell crossings/s of the float32-march /
+float64-accumulate form, the march kernel's roofline (algorithmic bytes per
+crossing over its HIP-event duration), the plain float64 form measured the
+same way, and the float64 CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell crossings/s + HBM GB/s at 256^3; batched-solve p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+# algorithmic HBM bytes per crossing: absorber gather + four float64
+# accumulator updates (H+He with heating)
+BYTES_F32 = 3 * 4 + 4 * 8
+BYTES_F64 = 3 * 8 + 4 * 8
+MARCH_SRC = os.path.join(ROOT, "paper_1101_4127_amd", "csrc", "rt_march.hip")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "march_traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def march_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("rt_march.hip", "rt_device.h", "rt_internal.h"):
+        with open(os.path.join(ROOT, "paper_1101_4127_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def workload(name: str, packets):
+    from paper_1101_4127_amd import workloads as W
+    if name == "lognormal_256":
+        return W.lognormal_256(packets=packets or 100_000_000)
+    if name == "lognormal_128":
+        return W.lognormal_128(packets=packets or 10_000_000)
+    if name == "lognormal_512":
+        return W.lognormal_512(packets=packets or 500_000_000)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def time_form(work, *, fp64: bool, steps: int, warmup: int, tiles: dict):
+    import torch
+    from paper_1101_4127_amd import rt
+    s = rt.Solve(work, fp64=fp64, time_march=True, **tiles)
+    for i in range(warmup):
+        s.step(seed=1000 + i)
+    torch.cuda.synchronize()
+    cross = 0
+    march_ms = 0.0
+    launches = 0
+    resid = 0.0
+    t0 = time.perf_counter()
+    for i in range(steps):
+        st = s.step(seed=1 + i)
+        cross += st["crossings"]
+        march_ms += st["march_ms"]
+        launches += st["substeps"]
+        resid = max(resid, abs(st["emitted"] - st["absorbed"] - st["escaped"] - st["truncated"]) / st["emitted"])
+        if st["nonfinite"]:
+            raise SystemExit("non-finite cell state")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    s.release()
+    return dict(crossings=cross, wall_s=wall, march_ms=march_ms, launches=launches, resid=resid)
+
+
+def cpu_baseline(work, target_s: float):
+    """The float64 oracle on a bounded sample of the same step: packet ranges
+    spread over all sources plus a random sample of cell updates, scaled to a
+    full step."""
+    import numpy as np
+    from oracle import oracle as O
+    o = O.OracleSolve(work)
+    o.absorbers()
+    P = work.packets
+    nrange = 64
+    per = 400
+    acc = np.zeros((4, work.ncell))
+    cross = 0
+    used = 0
+    t_march = 0.0
+    k = 0
+    while True:
+        g0 = (k * 7919 % nrange) * (P // nrange) + (k // nrange) * per
+        t0 = time.perf_counter()
+        _, led, _ = o.march(g0, g0 + per, dt=work.dt_s, packets=P, seed=1, step_index=0, acc=acc,
+                            absorbers=False)
+        t_march += time.perf_counter() - t0
+        cross += led["crossings"]
+        used += per
+        k += 1
+        if t_march > 0.8 * target_s or used >= P:
+            break
+    rng = np.random.default_rng(0)
+    nupd = min(work.ncell, 200_000)
+    idx = np.sort(rng.choice(work.ncell, nupd, replace=False))
+    t0 = time.perf_counter()
+    o.update_cells(work.dt_s, acc, idx)
+    t_upd = time.perf_counter() - t0
+    full_cross = cross * P / used
+    full_time = t_march * P / used + t_upd * work.ncell / nupd
+    return {
+        "value": full_cross / full_time, "unit": "crossings/s", "cores": 1, "kind": "oracle",
+        "sample": (f"{used} packets in {k} ranges spread over all sources ({cross} crossings, "
+                   f"{t_march:.1f} s) + {nupd} cell updates ({t_upd:.1f} s), scaled to one full step "
+                   f"of {P} packets and {work.ncell} cells; single-threaded float64 C oracle"),
+        "march_crossings_per_s": cross / t_march,
+        "update_cells_per_s": nupd / t_upd,
+    }
+
+
+def traffic_for(launch_crossings: float):
+    """HBM bytes per march launch from committed rocprofv3 counter runs, or
+    None when the counters were taken on a different march kernel."""
+    if not os.path.exists(TRAFFIC_JSON):
+        return None
+    with open(TRAFFIC_JSON) as f:
+        t = json.load(f)
+    if t.get("march_hash") != march_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="lognormal_256")
+    ap.add_argument("--packets", type=int, default=None)
+    ap.add_argument("--fp64-steps", type=int, default=2, help="timed steps of the plain float64 form")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--brick", type=int, default=-1)
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--refill", type=int, default=0)
+    ap.add_argument("--bpcu", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
+              "this build has no multi-GPU path", file=sys.stderr)
+        raise SystemExit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU")
+    from paper_1101_4127_amd import rt
+    rt.lib()
+
+    tiles = dict(brick_log2=args.brick, wave_chunk=args.chunk, refill_min=args.refill,
+                 blocks_per_cu=args.bpcu)
+    t0 = time.perf_counter()
+    work = workload(args.workload, args.packets)
+    log(f"workload {work.name}: {work.ncell} cells, {len(work.src_ndot)} sources, "
+        f"{work.packets} packets/step ({time.perf_counter() - t0:.1f} s to generate)")
+
+    f32 = time_form(work, fp64=False, steps=args.steps, warmup=args.warmup, tiles=tiles)
+    value = f32["crossings"] / f32["wall_s"]
+    per_launch = f32["crossings"] / max(f32["launches"], 1)
+    avg_ms = f32["march_ms"] / max(f32["launches"], 1)
+    achieved = BYTES_F32 * per_launch / (avg_ms * 1e-3) / 1e9
+    log(f"float32 march: {value:.4g} crossings/s, march {avg_ms:.2f} ms/launch, {achieved:.0f} GB/s "
+        f"algorithmic, conservation residual {f32['resid']:.2e}")
+    out = {
+        "metric": METRIC, "value": value, "unit": "crossings/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * f32["wall_s"] / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": work.name, "grid": list(work.n), "sources": len(work.src_ndot),
+                   "packets_per_step": work.packets, "bins": work.bins.n_bins,
+                   "form": "float32 march, float64 accumulators and cell update",
+                   "crossings_per_step": f32["crossings"] / args.steps},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(per_launch),
+                     "kernel": "k_march<float,3,true,8>", "bytes_per_crossing": BYTES_F32,
+                     "march_ms_per_launch": avg_ms},
+        "conservation_residual": f32["resid"],
+    }
+    if args.fp64_steps > 0:
+        f64 = time_form(work, fp64=True, steps=args.fp64_steps, warmup=1, tiles=tiles)
+        v64 = f64["crossings"] / f64["wall_s"]
+        ms64 = f64["march_ms"] / max(f64["launches"], 1)
+        a64 = BYTES_F64 * (f64["crossings"] / max(f64["launches"], 1)) / (ms64 * 1e-3) / 1e9
+        log(f"float64 plain: {v64:.4g} crossings/s, march {ms64:.2f} ms/launch, {a64:.0f} GB/s")
+        out["fp64_plain"] = {"value": v64, "unit": "crossings/s", "march_ms_per_launch": ms64,
+                             "achieved_gbs": a64, "bytes_per_crossing": BYTES_F64,
+                             "speedup_of_fp32_form": value / v64, "conservation_residual": f64["resid"]}
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(work, args.cpu_seconds)
+        log(f"cpu baseline: {out['cpu_baseline']['value']:.4g} crossings/s "
+            f"({time.perf_counter() - t0:.1f} s)")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,207 @@
+/*
+ * rt_mcrt.h -- C ABI of the MI355X Monte-Carlo radiative-transfer hot path.
+ *
+ * Method (Partl et al. 2011, "Enabling parallel computing in CRASH", Sec. 2):
+ * point sources emit coloured photon packets in random directions; each packet
+ * is followed cell by cell through a Cartesian grid, its optical depth in every
+ * crossed cell summed over HI, HeI and HeII, the absorbed photons per frequency
+ * bin given by Eq. (1) and shared among the absorbers in proportion to their
+ * optical depth; the ionisation fractions and temperature of the cells are then
+ * advanced from the absorbed photons.  Here the cell state is frozen while the
+ * packets of one sub-step fly and every cell is updated once per sub-step.
+ *
+ * Conventions shared by every call:
+ *  - Cells are addressed (i, j, k), 0 <= i < n[0] etc.; the natural linear
+ *    index is i + n[0] * (j + n[1] * k).  Every field passed in or out uses
+ *    natural order.  Inside the library the fields live in a brick layout.
+ *  - Units are cgs: cm, cm^-3, s, K, erg; photon energies in eV.
+ *  - Device pointers are plain HIP device addresses owned by the caller.  The
+ *    library never allocates device memory: all of its state lives in the
+ *    caller-provided workspace, which must outlive the handle.
+ *  - Host pointers are read (or written) during the call only.
+ *  - Every call returns RT_OK (0) or a negative status; nothing is thrown.  A
+ *    failed call that returns RT_EINVAL or RT_ENOMEM leaves the handle as it
+ *    was.  After RT_EDEVICE the handle only accepts rt_release.
+ *  - Calls on one handle must not overlap; different handles are independent.
+ */
+#ifndef RT_MCRT_H
+#define RT_MCRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RT_MAX_BINS 16
+#define RT_SUPPORTED_BINS 8
+#define RT_MAX_CELLS_PER_AXIS 1024
+
+/* status codes */
+#define RT_OK 0
+#define RT_EINVAL (-1)      /* invalid argument; nothing changed */
+#define RT_ENOMEM (-2)      /* workspace too small, or too many sources */
+#define RT_EDEVICE (-3)     /* HIP error; the handle is unusable */
+#define RT_ESTATE (-4)      /* call not valid in the handle's state */
+#define RT_EOVERFLOW (-5)   /* a size exceeds what the library supports */
+
+/* rt_grid_desc.flags */
+#define RT_ISOTHERMAL 0x1u  /* temperature held fixed */
+#define RT_FP64 0x2u        /* plain form: march, absorber table and stored state
+                               in float64 (default: float32 march and state,
+                               float64 accumulators and float64 cell update) */
+#define RT_TIME_MARCH 0x4u  /* time every march launch with HIP events on the
+                               handle's stream (rt_step_stats.march_ms) */
+
+/* rt_add_sources src_flags */
+#define RT_SRC_CORNER_OCTANT 0x1u /* source at the lowest corner of its cell,
+                                     directions folded into the + octant; the
+                                     box receives 1/8 of its luminosity */
+
+/* rt_fetch_fields masks (fields are written in this bit order) */
+#define RT_F_NH 0x001u     /* hydrogen number density */
+#define RT_F_XHI 0x002u    /* ionisation fractions */
+#define RT_F_XHII 0x004u
+#define RT_F_XHEI 0x008u
+#define RT_F_XHEII 0x010u
+#define RT_F_XHEIII 0x020u
+#define RT_F_T 0x040u      /* temperature */
+#define RT_F_DHI 0x080u    /* photons absorbed by HI in the last sub-step */
+#define RT_F_DHEI 0x100u   /* ... by HeI */
+#define RT_F_DHEII 0x200u  /* ... by HeII */
+#define RT_F_Q 0x400u      /* photo-heating energy [erg] of the last sub-step */
+#define RT_F_ALL 0x7ffu
+
+/* trace record: RT_TRACE_HDR int32 words then trace_len cell indices */
+#define RT_TRACE_HDR 8
+#define RT_FATE_TRUNC 1     /* extinguished: every populated bin reached tau_kill */
+#define RT_FATE_ESCAPE 2    /* left the grid (non-periodic boundaries) */
+
+typedef struct rt_solve *rt_solve_t;
+
+/* Problem statement of one solve (Sec. 2: a static H/He density on a Cartesian
+ * grid, photon packets with N_nu frequency bins, per-species cross-sections). */
+typedef struct {
+    int32_t n[3];                 /* cells per axis, 1..RT_MAX_CELLS_PER_AXIS */
+    double cell_cm;               /* proper cell size */
+    double y_he;                  /* n_He / n_H ; 0 = pure hydrogen */
+    int32_t n_bins;               /* frequency bins, 1..RT_SUPPORTED_BINS (arrays
+                                     hold RT_MAX_BINS; larger counts -> RT_EINVAL) */
+    double e_bin_ev[RT_MAX_BINS]; /* photon energy of each bin (heat per absorption
+                                     is E_j minus the species' threshold) */
+    double sigma_cm2[3][RT_MAX_BINS]; /* HI, HeI, HeII cross-sections per bin;
+                                     must be 0 where E_j is below the threshold */
+    double redshift;              /* Compton exchange with T_cmb = 2.725 (1+z);
+                                     < 0 disables it */
+    double tau_kill;              /* a packet ends once every bin it carries has
+                                     accumulated optical depth >= tau_kill */
+    int32_t n_sub;                /* frozen sub-steps per rt_step */
+    int32_t n_chem;               /* fixed chemistry sub-steps per frozen sub-step */
+    uint32_t flags;               /* RT_ISOTHERMAL | RT_FP64 */
+    uint64_t solve_id;            /* second word of the Philox key */
+    uint64_t step_index0;         /* Philox sub-step counter to start from (resume) */
+    int32_t brick_log2;           /* brick side 2^b, b in 0..3 (0 = natural order); -1 = default */
+    int32_t wave_chunk;           /* packets a wavefront claims at a time; 0 = default */
+    int32_t refill_min;           /* dead lanes a wavefront gathers before it
+                                     refills them; 0 = default */
+    int32_t blocks_per_cu;        /* persistent march blocks per compute unit; 0 = default */
+    int32_t trace_packets;        /* number of traced packets per sub-step (0 = off):
+                                     ids g = r * trace_stride, r < trace_packets,
+                                     go to trace record r */
+    int32_t trace_len;            /* cells recorded per traced packet */
+    int32_t trace_stride;         /* spacing of traced packet ids; 0 = 1 */
+} rt_grid_desc;
+
+/* Photon ledger and counters of the most recent rt_step (all its sub-steps). */
+typedef struct {
+    double emitted;     /* photons emitted into the box */
+    double absorbed;    /* photons absorbed in cells */
+    double escaped;     /* photons that left the grid */
+    double truncated;   /* photons still carried by extinguished packets */
+    int64_t crossings;  /* (packet, cell) pairs with positive path length */
+    int64_t packets;
+    int64_t n_escaped;
+    int64_t n_truncated;
+    int64_t substeps;
+    uint32_t nonfinite; /* nonzero if the cell update produced a non-finite value */
+    uint32_t pad;
+    double march_ms;    /* summed march kernel time (RT_TIME_MARCH), else 0 */
+} rt_step_stats;
+
+/* Fill *d with defaults: 1 bin, tau_kill 30, n_sub 1, n_chem 8, redshift -1,
+ * tiles chosen by the library, tracing off.  Returns RT_OK or RT_EINVAL. */
+int32_t rt_desc_defaults(rt_grid_desc *d);
+
+/* Workspace bytes a solve with this description and at most max_sources
+ * sources needs.  Returns RT_EINVAL for an invalid description. */
+int32_t rt_workspace_bytes(const rt_grid_desc *d, int64_t max_sources, size_t *bytes_out);
+
+/* Create a solve in the caller's device workspace and load its initial state.
+ *   d_ws, ws_bytes : device workspace (>= rt_workspace_bytes), 256-byte aligned
+ *   d_nh           : [ncell] hydrogen density, > 0
+ *   d_x            : [5][ncell] x_HI, x_HII, x_HeI, x_HeII, x_HeIII
+ *   d_temp         : [ncell] temperature
+ *   fields_fp64    : 1 if the three arrays are float64, 0 if float32
+ *   hip_stream     : hipStream_t every call of this handle is ordered on (NULL = default)
+ * Sources are added with rt_add_sources.  Stream-ordered; returns after the
+ * copies are enqueued. */
+int32_t rt_init_grid(const rt_grid_desc *d, void *d_ws, size_t ws_bytes, int64_t max_sources,
+                     const void *d_nh, const void *d_x, const void *d_temp, int32_t fields_fp64,
+                     void *hip_stream, rt_solve_t *out);
+
+/* Append n point sources (Sec. 2: position, luminosity L_s in photons/s, SED
+ * over the bins by photon number).  Host arrays:
+ *   h_ijk [3n] cell of each source, h_ndot [n] photons/s (>= 0, finite),
+ *   h_sed [n * n_bins] photon fraction per bin (>= 0, row sum > 0).
+ * Returns RT_ENOMEM beyond max_sources.  Synchronous. */
+int32_t rt_add_sources(rt_solve_t h, int32_t n, const int32_t *h_ijk, const double *h_ndot,
+                       const double *h_sed, uint32_t src_flags);
+
+/* Advance the solve by dt_s: n_sub frozen sub-steps of dt_s / n_sub, the
+ * n_packets shared evenly among the sub-steps and, within a sub-step, equally
+ * among the sources (the first P mod S sources get one more; Sec. 3.2: N_p/N_t
+ * packets per source per step).  Each sub-step: absorber densities from the
+ * frozen state, the packet march with deposition, then the cell update.
+ * Every sub-step must give each source at least one packet (else RT_EINVAL);
+ * a solve without sources runs the cell update only.  Stream-ordered and
+ * asynchronous; if stats is not NULL the call synchronises and fills it. */
+int32_t rt_step(rt_solve_t h, double dt_s, int64_t n_packets, uint64_t seed, rt_step_stats *stats);
+
+/* Synchronise the handle's stream and return the ledger of the last rt_step. */
+int32_t rt_read_stats(rt_solve_t h, rt_step_stats *stats);
+
+/* Copy the fields selected by mask, in bit order, each as ncell values in
+ * natural order, into dst (device or host memory; float64 if as_fp64 else
+ * float32).  Deposits are those of the last sub-step.  Synchronises. */
+int32_t rt_fetch_fields(rt_solve_t h, uint32_t mask, void *dst, int32_t dst_is_device,
+                        int32_t as_fp64);
+
+/* Copy count trace records (RT_TRACE_HDR + trace_len int32 each: crossings,
+ * fate, exit face, last cell, c[3], source, cells...) of the last sub-step to
+ * host memory; cell slots past a record's crossing count are unspecified.
+ * Synchronises. */
+int32_t rt_fetch_trace(rt_solve_t h, int32_t *h_dst, int64_t count);
+
+/* Cells crossed by m rays through the handle's grid, with the same traversal
+ * the march uses.  Device arrays: d_origin [3m] start points in half-cell units
+ * (inside or on the boundary), d_dir [3m] integer directions (|c_a| <= 2^20, not
+ * all zero), d_cells [m * max_len] natural indices, d_count [m] cells crossed
+ * (may exceed max_len), d_face [m] exit face (bit a: left through axis a,
+ * bit 3+a: through its + side).  Stream-ordered. */
+int32_t rt_trace_rays(rt_solve_t h, int32_t m, const int32_t *d_origin, const int32_t *d_dir,
+                      int32_t max_len, int32_t *d_cells, int32_t *d_count, int32_t *d_face);
+
+/* Current Philox sub-step counter (for checkpoint and resume). */
+int32_t rt_get_step_index(rt_solve_t h, uint64_t *out);
+
+/* Synchronise and destroy the handle (the workspace may then be freed). */
+int32_t rt_release(rt_solve_t h);
+
+/* Static description of a status code. */
+const char *rt_strerror(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RT_MCRT_H */

@@ -1,0 +1,503 @@
+// rt_abi.cpp -- host side of the C ABI declared in include/rt_mcrt.h: argument
+// validation, workspace layout, and the order of kernels in a step
+// (absorbers -> march -> ledger -> cell update, once per frozen sub-step).
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "rt_internal.h"
+#include "rt_mcrt.h"
+
+namespace {
+
+constexpr uint64_t kMagic = 0x52544d4352543031ull;   // handle tag
+constexpr int kMaxMarchBlocks = 8192;                // ledger slots reserved in the workspace
+constexpr size_t kAlign = 256;
+const double kThresholdEv[3] = {13.598434, 24.587387, 54.417760};
+
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+constexpr int kMaxSupportedBins = 8;   // widest compiled march instance
+
+int bin_capacity(int n_bins) { return n_bins <= 1 ? 1 : 8; }
+
+struct Plan {
+    int species, thermal, fp64, mb, acc_stride, bl;
+    rtk::GridGeom geo;
+    int64_t ncell;
+    size_t real;
+    size_t off_state, off_kappa, off_acc, off_src, off_ndot, off_sedsum, off_sed, off_tab, off_slots,
+        off_ledger, off_queue, off_trace, off_stage, total;
+};
+
+bool finite_nonneg(double v) { return isfinite(v) && v >= 0.0; }
+
+int32_t validate_desc(const rt_grid_desc *d) {
+    if (!d) return RT_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (d->n[a] < 1 || d->n[a] > RT_MAX_CELLS_PER_AXIS) return RT_EINVAL;
+    if (!(isfinite(d->cell_cm) && d->cell_cm > 0.0)) return RT_EINVAL;
+    if (!finite_nonneg(d->y_he)) return RT_EINVAL;
+    if (d->n_bins < 1 || d->n_bins > kMaxSupportedBins) return RT_EINVAL;
+    for (int j = 0; j < d->n_bins; ++j) {
+        if (!finite_nonneg(d->e_bin_ev[j])) return RT_EINVAL;
+        for (int s = 0; s < 3; ++s) {
+            if (!finite_nonneg(d->sigma_cm2[s][j])) return RT_EINVAL;
+            if (d->sigma_cm2[s][j] > 0.0 && d->e_bin_ev[j] < kThresholdEv[s]) return RT_EINVAL;
+        }
+    }
+    if (!isfinite(d->redshift)) return RT_EINVAL;
+    if (!(isfinite(d->tau_kill) && d->tau_kill > 0.0)) return RT_EINVAL;
+    if (d->n_sub < 1 || d->n_chem < 1) return RT_EINVAL;
+    if (d->flags & ~(RT_ISOTHERMAL | RT_FP64 | RT_TIME_MARCH)) return RT_EINVAL;
+    if (d->brick_log2 < -1 || d->brick_log2 > 3) return RT_EINVAL;
+    if (d->wave_chunk < 0 || d->wave_chunk % 64 != 0 || d->wave_chunk > (1 << 20)) return RT_EINVAL;
+    if (d->refill_min < 0 || d->refill_min > 64) return RT_EINVAL;
+    if (d->blocks_per_cu < 0 || d->blocks_per_cu > 32) return RT_EINVAL;
+    if (d->trace_packets < 0 || d->trace_len < 0) return RT_EINVAL;
+    if (d->trace_packets > 0 && d->trace_len < 1) return RT_EINVAL;
+    if (d->trace_stride < 0) return RT_EINVAL;
+    return RT_OK;
+}
+
+int32_t make_plan(const rt_grid_desc *d, int64_t max_sources, Plan *p) {
+    const int32_t v = validate_desc(d);
+    if (v != RT_OK) return v;
+    if (max_sources < 0 || max_sources > (int64_t)1 << 30) return RT_EINVAL;
+    p->species = d->y_he > 0.0 ? 3 : 1;
+    p->thermal = (d->flags & RT_ISOTHERMAL) ? 0 : 1;
+    p->fp64 = (d->flags & RT_FP64) ? 1 : 0;
+    p->mb = bin_capacity(d->n_bins);
+    p->acc_stride = p->species == 1 ? (p->thermal ? 2 : 1) : 4;
+    p->bl = d->brick_log2 < 0 ? 1 : d->brick_log2;
+    rtk::GridGeom &g = p->geo;
+    uint64_t np = 1;
+    for (int a = 0; a < 3; ++a) {
+        g.n[a] = d->n[a];
+        g.nb[a] = (d->n[a] + (1 << p->bl) - 1) >> p->bl;
+        np *= (uint64_t)g.nb[a] << p->bl;
+    }
+    g.bl = p->bl;
+    if (p->bl == 0) np = (uint64_t)d->n[0] * d->n[1] * d->n[2];
+    if (np >= (1ull << 32)) return RT_EOVERFLOW;
+    g.ncell_pad = (uint32_t)np;
+    p->ncell = (int64_t)d->n[0] * d->n[1] * d->n[2];
+    p->real = p->fp64 ? sizeof(double) : sizeof(float);
+    const size_t kap_vec = p->species == 1 ? 1 : 4;
+    size_t o = 0;
+    p->off_state = o; o = align_up(o + 7 * np * p->real);
+    p->off_kappa = o; o = align_up(o + kap_vec * np * p->real);
+    p->off_acc = o; o = align_up(o + (size_t)p->acc_stride * np * sizeof(double));
+    const size_t ms = (size_t)(max_sources > 0 ? max_sources : 1);
+    p->off_src = o; o = align_up(o + ms * sizeof(rtk::SourceRec));
+    p->off_ndot = o; o = align_up(o + ms * sizeof(double));
+    p->off_sedsum = o; o = align_up(o + ms * sizeof(double));
+    p->off_sed = o; o = align_up(o + ms * p->mb * p->real);
+    p->off_tab = o; o = align_up(o + 6 * (size_t)p->mb * p->real);
+    p->off_slots = o; o = align_up(o + kMaxMarchBlocks * sizeof(rtk::LedgerSlot));
+    p->off_ledger = o; o = align_up(o + sizeof(rtk::StepLedger));
+    p->off_queue = o; o = align_up(o + sizeof(unsigned long long));
+    p->off_trace = o;
+    o = align_up(o + (size_t)d->trace_packets * (RT_TRACE_HDR + (size_t)d->trace_len) * sizeof(int32_t));
+    p->off_stage = o; o = align_up(o + (size_t)p->ncell * sizeof(double));
+    p->total = o;
+    return RT_OK;
+}
+
+// Per-bin march table, [2][3][mb] in the march precision.  Row 0: the
+// cross-sections (float32 form: in units of 1e-18 cm^2, lengths then in 1e18
+// cm, so optical depths stay far from the float32 range limits).  Row 1: heat
+// factors in eV: pure hydrogen E_j - E_th,HI; H+He sigma_s,j (E_j - E_th,s).
+std::vector<double> march_table(const rt_grid_desc *d, const Plan &p) {
+    std::vector<double> t(6 * (size_t)p.mb, 0.0);
+    const double scale = p.fp64 ? 1.0 : 1.0e18;
+    for (int s = 0; s < 3; ++s)
+        for (int j = 0; j < d->n_bins; ++j) {
+            const double sig = d->sigma_cm2[s][j];
+            const double de = sig > 0.0 ? d->e_bin_ev[j] - kThresholdEv[s] : 0.0;
+            t[(size_t)s * p.mb + j] = sig * scale;
+            t[(size_t)(3 + s) * p.mb + j] = p.species == 1 ? de : sig * scale * de;
+        }
+    return t;
+}
+
+}  // namespace
+
+struct rt_solve {
+    uint64_t magic;
+    rt_grid_desc d;
+    Plan plan;
+    hipStream_t stream;
+    int device;
+    char *ws;
+    int64_t max_src, n_src;
+    uint64_t step_index;
+    int blocks, chunk, refill_min;
+    bool dead;
+    // march timing (RT_TIME_MARCH): one event pair per timed sub-step of the last rt_step
+    std::vector<hipEvent_t> ev;
+    int timed;
+};
+
+namespace {
+constexpr int kMaxTimedSubsteps = 1024;
+}
+
+namespace {
+
+bool valid(rt_solve_t h) { return h && h->magic == kMagic; }
+
+int32_t fail(rt_solve_t h) {
+    if (h) h->dead = true;
+    return RT_EDEVICE;
+}
+
+rtk::CellLaunch cell_launch(rt_solve_t h, double dt) {
+    const Plan &p = h->plan;
+    rtk::CellLaunch c;
+    c.geo = p.geo;
+    c.fp64 = p.fp64;
+    c.species = p.species;
+    c.thermal = p.thermal;
+    c.state = h->ws + p.off_state;
+    c.kappa = h->ws + p.off_kappa;
+    c.acc = reinterpret_cast<double *>(h->ws + p.off_acc);
+    c.acc_stride = p.acc_stride;
+    c.y_he = h->d.y_he;
+    c.cell_cm = h->d.cell_cm;
+    c.dt = dt;
+    c.redshift = h->d.redshift;
+    c.n_chem = h->d.n_chem;
+    c.queue = reinterpret_cast<unsigned long long *>(h->ws + p.off_queue);
+    c.ledger = reinterpret_cast<rtk::StepLedger *>(h->ws + p.off_ledger);
+    c.stream = h->stream;
+    return c;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t rt_desc_defaults(rt_grid_desc *d) {
+    if (!d) return RT_EINVAL;
+    memset(d, 0, sizeof(*d));
+    d->n[0] = d->n[1] = d->n[2] = 1;
+    d->cell_cm = 1.0;
+    d->n_bins = 1;
+    d->e_bin_ev[0] = 13.6;
+    d->redshift = -1.0;
+    d->tau_kill = 30.0;
+    d->n_sub = 1;
+    d->n_chem = 8;
+    d->brick_log2 = -1;
+    return RT_OK;
+}
+
+int32_t rt_workspace_bytes(const rt_grid_desc *d, int64_t max_sources, size_t *bytes_out) {
+    if (!bytes_out) return RT_EINVAL;
+    Plan p;
+    const int32_t r = make_plan(d, max_sources, &p);
+    if (r != RT_OK) return r;
+    *bytes_out = p.total;
+    return RT_OK;
+}
+
+int32_t rt_init_grid(const rt_grid_desc *d, void *d_ws, size_t ws_bytes, int64_t max_sources,
+                     const void *d_nh, const void *d_x, const void *d_temp, int32_t fields_fp64,
+                     void *hip_stream, rt_solve_t *out) {
+    if (!out) return RT_EINVAL;
+    *out = nullptr;
+    Plan p;
+    const int32_t r = make_plan(d, max_sources, &p);
+    if (r != RT_OK) return r;
+    if (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0) return RT_EINVAL;
+    if (!d_nh || !d_x || !d_temp || (fields_fp64 != 0 && fields_fp64 != 1)) return RT_EINVAL;
+    if (ws_bytes < p.total) return RT_ENOMEM;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return RT_EDEVICE;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return RT_EDEVICE;
+    int bpcu = d->blocks_per_cu;
+    if (bpcu == 0) {
+        if (rtk::march_occupancy(p.species, p.thermal, p.fp64, p.mb, &bpcu) != hipSuccess) return RT_EDEVICE;
+        if (bpcu < 1) bpcu = 1;
+    }
+    int blocks = cus * bpcu;
+    if (blocks > kMaxMarchBlocks) blocks = kMaxMarchBlocks;
+
+    rt_solve *h = new (std::nothrow) rt_solve;
+    if (!h) return RT_ENOMEM;
+    h->magic = kMagic;
+    h->d = *d;
+    h->plan = p;
+    h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    h->device = dev;
+    h->ws = reinterpret_cast<char *>(d_ws);
+    h->max_src = max_sources;
+    h->n_src = 0;
+    h->step_index = d->step_index0;
+    h->blocks = blocks;
+    h->chunk = d->wave_chunk > 0 ? d->wave_chunk : 256;
+    h->refill_min = d->refill_min > 0 ? d->refill_min : 8;
+    h->dead = false;
+    h->timed = 0;
+    if (d->flags & RT_TIME_MARCH) {
+        h->ev.resize(2 * kMaxTimedSubsteps);
+        for (size_t i = 0; i < h->ev.size(); ++i)
+            if (hipEventCreate(&h->ev[i]) != hipSuccess) {
+                for (size_t k = 0; k < i; ++k) (void)hipEventDestroy(h->ev[k]);
+                delete h;
+                return RT_EDEVICE;
+            }
+    }
+
+    rtk::CellLaunch c = cell_launch(h, 0.0);
+    const std::vector<double> tab = march_table(d, p);
+    std::vector<float> tab_f(tab.begin(), tab.end());
+    const void *tab_src = p.fp64 ? (const void *)tab.data() : (const void *)tab_f.data();
+    if (hipMemcpyAsync(h->ws + p.off_tab, tab_src, tab.size() * p.real, hipMemcpyHostToDevice, h->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess ||
+        rtk::launch_import(c, d_nh, d_x, d_temp, fields_fp64, p.ncell) != hipSuccess ||
+        rtk::launch_ledger_zero(c.ledger, h->stream) != hipSuccess) {
+        for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+        delete h;
+        return RT_EDEVICE;
+    }
+    *out = h;
+    return RT_OK;
+}
+
+int32_t rt_add_sources(rt_solve_t h, int32_t n, const int32_t *h_ijk, const double *h_ndot,
+                       const double *h_sed, uint32_t src_flags) {
+    if (!valid(h)) return RT_EINVAL;
+    if (h->dead) return RT_ESTATE;
+    if (n < 0 || (src_flags & ~RT_SRC_CORNER_OCTANT)) return RT_EINVAL;
+    if (n == 0) return RT_OK;
+    if (!h_ijk || !h_ndot || !h_sed) return RT_EINVAL;
+    if (h->n_src + n > h->max_src) return RT_ENOMEM;
+    const Plan &p = h->plan;
+    const int nb = h->d.n_bins, mb = p.mb;
+    const bool oct = (src_flags & RT_SRC_CORNER_OCTANT) != 0;
+    std::vector<rtk::SourceRec> rec(n);
+    std::vector<double> sedsum(n), sed_d((size_t)n * mb, 0.0);
+    std::vector<float> sed_f((size_t)n * mb, 0.0f);
+    for (int i = 0; i < n; ++i) {
+        for (int a = 0; a < 3; ++a) {
+            const int32_t v = h_ijk[3 * i + a];
+            if (v < 0 || v >= h->d.n[a]) return RT_EINVAL;
+            rec[i].o[a] = 2 * v + (oct ? 0 : 1);
+        }
+        rec[i].octant = oct ? 1 : 0;
+        if (!finite_nonneg(h_ndot[i])) return RT_EINVAL;
+        double s = 0.0;
+        for (int j = 0; j < nb; ++j) {
+            const double v = h_sed[(size_t)i * nb + j];
+            if (!finite_nonneg(v)) return RT_EINVAL;
+            s += v;
+            sed_d[(size_t)i * mb + j] = v;
+            sed_f[(size_t)i * mb + j] = (float)v;
+        }
+        if (!(s > 0.0)) return RT_EINVAL;
+        sedsum[i] = s;
+    }
+    const size_t k = (size_t)h->n_src;
+    hipStream_t st = h->stream;
+    if (hipMemcpyAsync(h->ws + p.off_src + k * sizeof(rtk::SourceRec), rec.data(), n * sizeof(rtk::SourceRec),
+                       hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(h->ws + p.off_ndot + k * sizeof(double), h_ndot, n * sizeof(double),
+                       hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(h->ws + p.off_sedsum + k * sizeof(double), sedsum.data(), n * sizeof(double),
+                       hipMemcpyHostToDevice, st) != hipSuccess)
+        return fail(h);
+    const void *sed = p.fp64 ? (const void *)sed_d.data() : (const void *)sed_f.data();
+    if (hipMemcpyAsync(h->ws + p.off_sed + k * mb * p.real, sed, (size_t)n * mb * p.real,
+                       hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return fail(h);
+    h->n_src += n;
+    return RT_OK;
+}
+
+int32_t rt_read_stats(rt_solve_t h, rt_step_stats *stats) {
+    if (!valid(h) || !stats) return RT_EINVAL;
+    if (h->dead) return RT_ESTATE;
+    rtk::StepLedger l;
+    if (hipMemcpyAsync(&l, h->ws + h->plan.off_ledger, sizeof(l), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+        return fail(h);
+    stats->emitted = l.s[0] + l.s[1];
+    stats->absorbed = l.s[2] + l.s[3];
+    stats->escaped = l.s[4] + l.s[5];
+    stats->truncated = l.s[6] + l.s[7];
+    stats->crossings = (int64_t)l.c[0];
+    stats->packets = (int64_t)l.c[1];
+    stats->n_escaped = (int64_t)l.c[2];
+    stats->n_truncated = (int64_t)l.c[3];
+    stats->substeps = (int64_t)l.substeps;
+    stats->nonfinite = l.nonfinite;
+    stats->pad = 0;
+    stats->march_ms = 0.0;
+    for (int i = 0; i < h->timed; ++i) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]) != hipSuccess) return fail(h);
+        stats->march_ms += ms;
+    }
+    return RT_OK;
+}
+
+int32_t rt_step(rt_solve_t h, double dt_s, int64_t n_packets, uint64_t seed, rt_step_stats *stats) {
+    if (!valid(h)) return RT_EINVAL;
+    if (h->dead) return RT_ESTATE;
+    if (!(isfinite(dt_s) && dt_s > 0.0) || n_packets < 0) return RT_EINVAL;
+    const int32_t nsub = h->d.n_sub;
+    const int64_t base = n_packets / nsub, extra = n_packets % nsub;
+    if (h->n_src > 0 && base < h->n_src) return RT_EINVAL;
+    if (base + 1 > ((int64_t)1 << 31)) return RT_EOVERFLOW;
+    const Plan &p = h->plan;
+    const double dts = dt_s / nsub;
+    rtk::CellLaunch c = cell_launch(h, dts);
+    if (rtk::launch_ledger_zero(c.ledger, h->stream) != hipSuccess) return fail(h);
+
+    rtk::MarchLaunch m;
+    memset(&m, 0, sizeof(m));
+    m.geo = p.geo;
+    m.half_dl = 0.5 * h->d.cell_cm;
+    m.species = p.species;
+    m.thermal = p.thermal;
+    m.fp64 = p.fp64;
+    m.n_bins = h->d.n_bins;
+    m.mb = p.mb;
+    m.src = reinterpret_cast<const rtk::SourceRec *>(h->ws + p.off_src);
+    m.src_ndot = reinterpret_cast<const double *>(h->ws + p.off_ndot);
+    m.src_sedsum = reinterpret_cast<const double *>(h->ws + p.off_sedsum);
+    m.sed = h->ws + p.off_sed;
+    m.n_src = (int32_t)h->n_src;
+    m.dt = dts;
+    m.seed = seed;
+    m.solve_id = h->d.solve_id;
+    m.tab = h->ws + p.off_tab;
+    m.tau_kill = h->d.tau_kill;
+    m.kappa = c.kappa;
+    m.acc = c.acc;
+    m.acc_stride = p.acc_stride;
+    m.queue = c.queue;
+    m.slots = reinterpret_cast<rtk::LedgerSlot *>(h->ws + p.off_slots);
+    m.trace = h->d.trace_packets > 0 ? reinterpret_cast<int32_t *>(h->ws + p.off_trace) : nullptr;
+    m.trace_n = h->d.trace_packets;
+    m.trace_len = h->d.trace_len;
+    m.trace_stride = h->d.trace_stride > 0 ? h->d.trace_stride : 1;
+    m.chunk = h->chunk;
+    m.refill_min = h->refill_min;
+    m.blocks = h->blocks;
+    m.stream = h->stream;
+
+    h->timed = 0;
+    for (int32_t i = 0; i < nsub; ++i) {
+        const int64_t Pi = base + (i < extra ? 1 : 0);
+        if (rtk::launch_prep(c) != hipSuccess) return fail(h);
+        const bool march = h->n_src > 0 && Pi > 0;
+        if (march) {
+            m.packets = (uint32_t)Pi;
+            m.step_index = h->step_index;
+            const bool timed = !h->ev.empty() && h->timed < kMaxTimedSubsteps;
+            if (timed && hipEventRecord(h->ev[2 * h->timed], h->stream) != hipSuccess) return fail(h);
+            if (rtk::launch_march(m) != hipSuccess) return fail(h);
+            if (timed) {
+                if (hipEventRecord(h->ev[2 * h->timed + 1], h->stream) != hipSuccess) return fail(h);
+                ++h->timed;
+            }
+        }
+        if (rtk::launch_ledger_reduce(m.slots, march ? h->blocks : 0, c.ledger, h->stream) != hipSuccess)
+            return fail(h);
+        if (rtk::launch_update(c) != hipSuccess) return fail(h);
+        h->step_index += 1;
+    }
+    if (stats) return rt_read_stats(h, stats);
+    return RT_OK;
+}
+
+int32_t rt_fetch_fields(rt_solve_t h, uint32_t mask, void *dst, int32_t dst_is_device, int32_t as_fp64) {
+    if (!valid(h)) return RT_EINVAL;
+    if (h->dead) return RT_ESTATE;
+    if (!dst || mask == 0 || (mask & ~RT_F_ALL) || (as_fp64 != 0 && as_fp64 != 1) ||
+        (dst_is_device != 0 && dst_is_device != 1))
+        return RT_EINVAL;
+    const Plan &p = h->plan;
+    rtk::CellLaunch c = cell_launch(h, 0.0);
+    const size_t esz = as_fp64 ? sizeof(double) : sizeof(float);
+    if (dst_is_device) {
+        if (rtk::launch_export(c, mask, dst, as_fp64, p.ncell) != hipSuccess) return fail(h);
+    } else {
+        void *stage = h->ws + p.off_stage;
+        char *out = reinterpret_cast<char *>(dst);
+        for (int f = 0; f < 11; ++f) {
+            if (!(mask & (1u << f))) continue;
+            if (rtk::launch_export(c, 1u << f, stage, as_fp64, p.ncell) != hipSuccess ||
+                hipMemcpyAsync(out, stage, (size_t)p.ncell * esz, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+                hipStreamSynchronize(h->stream) != hipSuccess)
+                return fail(h);
+            out += (size_t)p.ncell * esz;
+        }
+    }
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(h);
+    return RT_OK;
+}
+
+int32_t rt_fetch_trace(rt_solve_t h, int32_t *h_dst, int64_t count) {
+    if (!valid(h)) return RT_EINVAL;
+    if (h->dead) return RT_ESTATE;
+    if (count < 0 || count > h->d.trace_packets || (count > 0 && !h_dst)) return RT_EINVAL;
+    const size_t bytes = (size_t)count * (RT_TRACE_HDR + (size_t)h->d.trace_len) * sizeof(int32_t);
+    if (bytes == 0) return RT_OK;
+    if (hipMemcpyAsync(h_dst, h->ws + h->plan.off_trace, bytes, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+        return fail(h);
+    return RT_OK;
+}
+
+int32_t rt_trace_rays(rt_solve_t h, int32_t m, const int32_t *d_origin, const int32_t *d_dir, int32_t max_len,
+                      int32_t *d_cells, int32_t *d_count, int32_t *d_face) {
+    if (!valid(h)) return RT_EINVAL;
+    if (h->dead) return RT_ESTATE;
+    if (m < 0 || max_len < 0) return RT_EINVAL;
+    if (m == 0) return RT_OK;
+    if (!d_origin || !d_dir || !d_count || !d_face || (max_len > 0 && !d_cells)) return RT_EINVAL;
+    if (rtk::launch_trace_rays(h->plan.geo, m, d_origin, d_dir, max_len, d_cells, d_count, d_face, h->stream) !=
+        hipSuccess)
+        return fail(h);
+    return RT_OK;
+}
+
+int32_t rt_get_step_index(rt_solve_t h, uint64_t *out) {
+    if (!valid(h) || !out) return RT_EINVAL;
+    *out = h->step_index;
+    return RT_OK;
+}
+
+int32_t rt_release(rt_solve_t h) {
+    if (!valid(h)) return RT_EINVAL;
+    const bool ok = h->dead || hipStreamSynchronize(h->stream) == hipSuccess;
+    for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    h->magic = 0;
+    delete h;
+    return ok ? RT_OK : RT_EDEVICE;
+}
+
+const char *rt_strerror(int32_t status) {
+    switch (status) {
+    case RT_OK: return "ok";
+    case RT_EINVAL: return "invalid argument";
+    case RT_ENOMEM: return "workspace too small or too many sources";
+    case RT_EDEVICE: return "HIP device error; the handle is unusable";
+    case RT_ESTATE: return "call not valid in the handle's state";
+    case RT_EOVERFLOW: return "size beyond what the library supports";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,509 @@
+// rt_cells.hip -- per-cell kernels around the packet march: the frozen-state
+// absorber table, the float64 ionisation/temperature update (Partl et al.
+// 2011, Sec. 2: network for HI, HeI, HeII and the temperature with
+// photo-heating and the change in free particles), layout conversion between
+// natural order and bricks, the photon ledger and a geometric ray tracer.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <type_traits>
+
+#include "rt_device.h"
+#include "rt_internal.h"
+
+namespace rtk {
+
+constexpr int kCellBlock = 256;
+
+template <typename R> struct V4;
+template <> struct V4<float> { using T = float4; };
+template <> struct V4<double> { using T = double4; };
+
+static inline int cell_blocks(uint64_t n) {
+    const uint64_t b = (n + kCellBlock - 1) / kCellBlock;
+    return (int)(b < 65536 ? (b > 0 ? b : 1) : 65536);
+}
+
+// ---------------------------------------------------------------------------
+// Absorber densities of the frozen state, accumulators cleared, march queue
+// reset: kappa = (n_H x_HI, (y n_H) x_HeI, (y n_H) x_HeII).
+// ---------------------------------------------------------------------------
+template <typename R, int S>
+__global__ void __launch_bounds__(kCellBlock) k_prep(GridGeom G, const R *__restrict__ st,
+                                                     void *__restrict__ kappa, double *__restrict__ acc,
+                                                     int acc_stride, double y_he, unsigned long long *queue) {
+    const uint32_t np = G.ncell_pad;
+    const uint32_t step = gridDim.x * blockDim.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *queue = 0ull;
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < np; s += step) {
+        const double nh = (double)st[s];
+        const double xhi = (double)st[(size_t)np + s];
+        if (S == 1) {
+            reinterpret_cast<R *>(kappa)[s] = (R)(nh * xhi);
+        } else {
+            const double yn = y_he * nh;
+            typename V4<R>::T v;
+            v.x = (R)(nh * xhi);
+            v.y = (R)(yn * (double)st[3 * (size_t)np + s]);
+            v.z = (R)(yn * (double)st[4 * (size_t)np + s]);
+            v.w = R(0);
+            reinterpret_cast<typename V4<R>::T *>(kappa)[s] = v;
+        }
+        double *a = acc + (size_t)s * acc_stride;
+        for (int i = 0; i < acc_stride; ++i) a[i] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Rates (cgs).  Recombination: case B of Hui & Gnedin (1997) for HII and
+// HeIII (the hydrogenic form scaled by Z = 2), their HeII fit plus dielectronic
+// recombination; collisional ionisation and cooling after Cen (1992);
+// bremsstrahlung with a temperature-dependent Gaunt factor; Compton exchange
+// with the CMB.
+// ---------------------------------------------------------------------------
+struct Rates {
+    double rec_hii, rec_heii, rec_heiii;   // cm^3 / s
+    double col_hi, col_hei, col_heii;      // cm^3 / s
+};
+
+__device__ double hydrogenic_caseb(double T, double t_ion) {
+    const double lam = 2.0 * t_ion / T;
+    return 2.753e-14 * pow(lam, 1.5) / pow(1.0 + pow(lam / 2.740, 0.407), 2.242);
+}
+
+__device__ Rates rates_at(double T) {
+    Rates r;
+    const double damp = 1.0 / (1.0 + sqrt(T * 1.0e-5));
+    const double rt = sqrt(T);
+    r.rec_hii = hydrogenic_caseb(T, 157807.0);
+    r.rec_heiii = 2.0 * hydrogenic_caseb(T, 631515.0);
+    const double diel = 1.9e-3 * pow(T, -1.5) * exp(-470000.0 / T) * (1.0 + 0.3 * exp(-94000.0 / T));
+    r.rec_heii = 1.26e-14 * pow(570670.0 / T, 0.750) + diel;
+    r.col_hi = 5.85e-11 * rt * exp(-157809.1 / T) * damp;
+    r.col_hei = 2.38e-11 * rt * exp(-285335.4 / T) * damp;
+    r.col_heii = 5.68e-12 * rt * exp(-631515.0 / T) * damp;
+    return r;
+}
+
+// Cooling [erg cm^-3 s^-1] without the Compton term.
+__device__ double cooling_rate(double T, double ne, double n_hi, double n_hii, double n_hei,
+                               double n_heii, double n_heiii) {
+    const double damp = 1.0 / (1.0 + sqrt(T * 1.0e-5));
+    const double rt = sqrt(T);
+    const double e_hi = exp(-157809.1 / T), e_hei = exp(-285335.4 / T), e_heii = exp(-631515.0 / T);
+    const double t3 = pow(T * 1.0e-3, -0.2);
+    const double t6 = 1.0 / (1.0 + pow(T * 1.0e-6, 0.7));
+    const double lg = log10(T);
+    const double gaunt = 1.1 + 0.34 * exp(-(5.5 - lg) * (5.5 - lg) / 3.0);
+    double per_ne_hi = 7.50e-19 * exp(-118348.0 / T) * damp      // excitation
+                     + 1.27e-21 * rt * e_hi * damp;              // ionisation
+    double per_ne_heii = 5.54e-17 * pow(T, -0.397) * exp(-473638.0 / T) * damp
+                       + 4.95e-22 * rt * e_heii * damp
+                       + 1.55e-26 * pow(T, 0.3647)                 // recombination
+                       + 1.24e-13 * pow(T, -1.5) * exp(-470000.0 / T) * (1.0 + 0.3 * exp(-94000.0 / T));
+    double lam = ne * (per_ne_hi * n_hi + per_ne_heii * n_heii
+                       + 9.38e-22 * rt * e_hei * damp * n_hei
+                       + 8.70e-27 * rt * t3 * t6 * n_hii
+                       + 3.48e-26 * rt * t3 * t6 * n_heiii
+                       + 1.42e-27 * gaunt * rt * (n_hii + n_heii + 4.0 * n_heiii));
+    return lam;
+}
+
+// Ionisation fractions over time h with fixed rates.  Hydrogen: exact two-level
+// exponential (each fraction from its own value).  Helium: the three-level
+// chain's exact solution, x(h) = (1-c0) x_eq + c0 x0 + c1 M x0, where c0, c1
+// come from the two non-zero eigenvalues of the generator M.
+struct Frac { double hi, hii, hei, heii, heiii; };
+
+__device__ void evolve(Frac &x, const Frac &x0, const Rates &r, const double gam[3], double ne,
+                       double h, bool he) {
+    {
+        const double ion = gam[0] + r.col_hi * ne, rec = r.rec_hii * ne;
+        const double lam = ion + rec;
+        if (lam > 0.0) {
+            const double e = exp(-lam * h);
+            const double eq_hi = rec / lam, eq_hii = ion / lam;
+            x.hi = eq_hi + (x0.hi - eq_hi) * e;
+            x.hii = eq_hii + (x0.hii - eq_hii) * e;
+        } else {
+            x.hi = x0.hi;
+            x.hii = x0.hii;
+        }
+    }
+    x.hei = x0.hei; x.heii = x0.heii; x.heiii = x0.heiii;
+    if (!he) return;
+    const double i1 = gam[1] + r.col_hei * ne, r2 = r.rec_heii * ne;
+    const double i2 = gam[2] + r.col_heii * ne, r3 = r.rec_heiii * ne;
+    const double sum = i1 + r2 + i2 + r3;
+    if (!(sum > 0.0)) return;
+    const double det = i1 * i2 + i1 * r3 + r2 * r3;
+    const double half = -0.5 * sum;
+    const double disc = half * half - det;
+    const double lb = half - sqrt(disc > 0.0 ? disc : 0.0);   // most negative eigenvalue
+    const double la = det / lb;                              // the other one
+    const double ea = exp(la * h);
+    const double gap = la - lb;
+    double c1;
+    if (gap * h > 1.0e-3) {
+        c1 = (ea - exp(lb * h)) / gap;
+    } else {
+        const double u = gap * h;
+        c1 = h * exp(0.5 * (la + lb) * h) * (1.0 + u * u / 24.0);
+    }
+    const double c0 = ea - c1 * la;
+    double q1 = 0.0, q2 = 0.0, q3 = 0.0;
+    if (det > 0.0) { q1 = r2 * r3 / det; q2 = i1 * r3 / det; q3 = i1 * i2 / det; }
+    const double m1 = -i1 * x0.hei + r2 * x0.heii;
+    const double m2 = i1 * x0.hei - (r2 + i2) * x0.heii + r3 * x0.heiii;
+    const double m3 = i2 * x0.heii - r3 * x0.heiii;
+    x.hei = (1.0 - c0) * q1 + c0 * x0.hei + c1 * m1;
+    x.heii = (1.0 - c0) * q2 + c0 * x0.heii + c1 * m2;
+    x.heiii = (1.0 - c0) * q3 + c0 * x0.heiii + c1 * m3;
+}
+
+template <typename R, int S, bool TH>
+__global__ void __launch_bounds__(kCellBlock) k_update(GridGeom G, R *__restrict__ st, const double *__restrict__ acc,
+                                                       int acc_stride, double y_he, double cell_cm, double dt,
+                                                       double redshift, int n_chem, StepLedger *ledger) {
+    constexpr bool he = (S == 3);
+    const uint32_t np = G.ncell_pad;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    const double V = cell_cm * cell_cm * cell_cm;
+    const double kb = 1.380649e-16;
+    const bool compton = redshift >= 0.0;
+    const double tcmb = 2.725 * (1.0 + (redshift > 0.0 ? redshift : 0.0));
+    // 4 sigma_T a_rad k T_cmb^4 / (m_e c)
+    const double ccomp = compton ? 4.0 * 6.6524587321e-25 * 7.5657e-15 * kb * (tcmb * tcmb) * (tcmb * tcmb)
+                                       / (9.1093837015e-28 * 2.99792458e10)
+                                 : 0.0;
+    const double h = dt / n_chem;
+    unsigned int bad = 0;
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < np; s += stride) {
+        int i, j, k;
+        if (!slot_cell(G, s, i, j, k)) continue;
+        const double nh = (double)st[s];
+        const double nhe = he ? y_he * nh : 0.0;
+        Frac x;
+        x.hi = (double)st[(size_t)np + s];
+        x.hii = (double)st[2 * (size_t)np + s];
+        x.hei = (double)st[3 * (size_t)np + s];
+        x.heii = (double)st[4 * (size_t)np + s];
+        x.heiii = (double)st[5 * (size_t)np + s];
+        double T = (double)st[6 * (size_t)np + s];
+        const double *a = acc + (size_t)s * acc_stride;
+        const double dep[3] = {a[0], he ? a[1] : 0.0, he ? a[2] : 0.0};
+        const double qheat = TH ? a[he ? 3 : 1] : 0.0;
+        const double absorbers[3] = {nh * x.hi, nhe * x.hei, nhe * x.heii};
+        double gam[3];
+        for (int q = 0; q < 3; ++q)
+            gam[q] = (dep[q] > 0.0 && absorbers[q] > 0.0) ? dep[q] / (absorbers[q] * V * dt) : 0.0;
+        const double heat = qheat / (V * dt);
+        Rates r = rates_at(T);
+        for (int m = 0; m < n_chem; ++m) {
+            if (TH && m > 0) r = rates_at(T);
+            const double ne0 = nh * x.hii + nhe * (x.heii + 2.0 * x.heiii);
+            Frac xp, xn;
+            evolve(xp, x, r, gam, ne0, h, he);
+            const double ne_bar = 0.5 * (ne0 + (nh * xp.hii + nhe * (xp.heii + 2.0 * xp.heiii)));
+            evolve(xn, x, r, gam, ne_bar, h, he);
+            // clamp and renormalise each element's fractions
+            xn.hi = fmax(xn.hi, 0.0); xn.hii = fmax(xn.hii, 0.0);
+            const double sh = xn.hi + xn.hii;
+            if (sh > 0.0) { xn.hi = xn.hi / sh; xn.hii = xn.hii / sh; }
+            if (he) {
+                xn.hei = fmax(xn.hei, 0.0); xn.heii = fmax(xn.heii, 0.0); xn.heiii = fmax(xn.heiii, 0.0);
+                const double she = (xn.hei + xn.heii) + xn.heiii;
+                if (she > 0.0) { xn.hei = xn.hei / she; xn.heii = xn.heii / she; xn.heiii = xn.heiii / she; }
+            }
+            if (TH) {
+                const double ntot0 = nh * (1.0 + x.hii) + nhe * (1.0 + x.heii + 2.0 * x.heiii);
+                const double ntot1 = nh * (1.0 + xn.hii) + nhe * (1.0 + xn.heii + 2.0 * xn.heiii);
+                const double ne1 = nh * xn.hii + nhe * (xn.heii + 2.0 * xn.heiii);
+                const double lam = cooling_rate(T, ne1, nh * xn.hi, nh * xn.hii, nhe * xn.hei,
+                                                nhe * xn.heii, nhe * xn.heiii);
+                const double cne = ccomp * ne1;
+                double tn = (1.5 * kb * ntot0 * T + h * (heat + cne * tcmb))
+                          / (1.5 * kb * ntot1 + h * (lam / T + cne));
+                T = tn < tcmb ? tcmb : tn;
+            }
+            x = xn;
+        }
+        const double vals[6] = {x.hi, x.hii, x.hei, x.heii, x.heiii, T};
+        for (int q = 0; q < 6; ++q) {
+            if (!isfinite(vals[q])) bad = 1;
+            st[(size_t)(q + 1) * np + s] = (R)vals[q];
+        }
+    }
+    if (bad) atomicOr(&ledger->nonfinite, 1u);
+}
+
+// ---------------------------------------------------------------------------
+// Layout conversion (natural order <-> bricks)
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void k_fill_zero(R *p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = R(0);
+}
+
+template <typename R, typename In>
+__global__ void __launch_bounds__(kCellBlock) k_import(GridGeom G, R *__restrict__ st, const In *__restrict__ nh,
+                                                       const In *__restrict__ x, const In *__restrict__ t,
+                                                       uint32_t ncell) {
+    const uint32_t np = G.ncell_pad;
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += gridDim.x * blockDim.x) {
+        const int i = (int)(c % (uint32_t)G.n[0]);
+        const int j = (int)((c / (uint32_t)G.n[0]) % (uint32_t)G.n[1]);
+        const int k = (int)(c / ((uint32_t)G.n[0] * (uint32_t)G.n[1]));
+        const uint32_t s = cell_slot(G, i, j, k);
+        st[s] = (R)nh[c];
+        for (int f = 0; f < 5; ++f) st[(size_t)(f + 1) * np + s] = (R)x[(size_t)f * ncell + c];
+        st[6 * (size_t)np + s] = (R)t[c];
+    }
+}
+
+template <typename R, typename Out>
+__global__ void __launch_bounds__(kCellBlock) k_export(GridGeom G, const R *__restrict__ st,
+                                                       const double *__restrict__ acc, int acc_stride,
+                                                       int species, int thermal, uint32_t mask,
+                                                       Out *__restrict__ dst, uint32_t ncell) {
+    const uint32_t np = G.ncell_pad;
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += gridDim.x * blockDim.x) {
+        const int i = (int)(c % (uint32_t)G.n[0]);
+        const int j = (int)((c / (uint32_t)G.n[0]) % (uint32_t)G.n[1]);
+        const int k = (int)(c / ((uint32_t)G.n[0] * (uint32_t)G.n[1]));
+        const uint32_t s = cell_slot(G, i, j, k);
+        int out = 0;
+        for (int f = 0; f < 11; ++f) {
+            if (!(mask & (1u << f))) continue;
+            double v;
+            if (f < 7) {
+                v = (double)st[(size_t)f * np + s];
+            } else {
+                const double *a = acc + (size_t)s * acc_stride;
+                if (species == 3) v = (f < 10 || thermal) ? a[f - 7] : 0.0;
+                else v = (f == 7) ? a[0] : ((f == 10 && thermal) ? a[1] : 0.0);
+            }
+            dst[(size_t)out * ncell + c] = (Out)v;
+            ++out;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Ledger: per-block slots of the march summed (TwoSum) into the step ledger.
+// ---------------------------------------------------------------------------
+__global__ void k_ledger_zero(StepLedger *l) {
+    if (threadIdx.x == 0) {
+        StepLedger z;
+        for (int i = 0; i < 8; ++i) z.s[i] = 0.0;
+        for (int i = 0; i < 4; ++i) z.c[i] = 0ull;
+        z.substeps = 0ull;
+        z.nonfinite = 0u;
+        z.pad = 0u;
+        *l = z;
+    }
+}
+
+__global__ void __launch_bounds__(64) k_ledger_reduce(const LedgerSlot *slots, int n, StepLedger *l) {
+    // one wavefront: lane-strided partial sums, then a TwoSum tree
+    const int lane = threadIdx.x;
+    double s[8];
+    unsigned long long c[4] = {0, 0, 0, 0};
+    for (int i = 0; i < 8; ++i) s[i] = 0.0;
+    for (int b = lane; b < n; b += 64) {
+        for (int i = 0; i < 4; ++i) {
+            double t, e;
+            two_sum(s[2 * i], slots[b].s[2 * i], t, e);
+            s[2 * i] = t;
+            s[2 * i + 1] += slots[b].s[2 * i + 1] + e;
+        }
+        for (int i = 0; i < 4; ++i) c[i] += slots[b].c[i];
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        for (int i = 0; i < 4; ++i) {
+            const double so = __shfl_xor(s[2 * i], off), co = __shfl_xor(s[2 * i + 1], off);
+            double t, e;
+            two_sum(s[2 * i], so, t, e);
+            s[2 * i] = t;
+            s[2 * i + 1] += co + e;
+        }
+        for (int i = 0; i < 4; ++i) c[i] += __shfl_xor(c[i], off);
+    }
+    if (lane == 0) {
+        for (int i = 0; i < 4; ++i) {
+            double t, e;
+            two_sum(l->s[2 * i], s[2 * i], t, e);
+            l->s[2 * i] = t;
+            l->s[2 * i + 1] += s[2 * i + 1] + e;
+            l->c[i] += c[i];
+        }
+        l->substeps += 1ull;
+    }
+}
+
+// Sub-step without packets: only the sub-step counter of the ledger moves.
+__global__ void k_ledger_tick(StepLedger *l) {
+    if (threadIdx.x == 0) l->substeps += 1ull;
+}
+
+// ---------------------------------------------------------------------------
+// Geometric ray tracer: the march's traversal without the physics.
+// ---------------------------------------------------------------------------
+__global__ void k_trace_rays(GridGeom G, int m, const int32_t *o, const int32_t *c, int max_len,
+                             int32_t *cells, int32_t *count, int32_t *face) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    int k[3];
+    uint32_t d[3], a[3];
+    int sg[3];
+    bool bad = false;
+    for (int ax = 0; ax < 3; ++ax) {
+        const int oa = o[3 * r + ax], ca = c[3 * r + ax];
+        sg[ax] = (ca > 0) - (ca < 0);
+        a[ax] = (uint32_t)abs(ca);
+        k[ax] = (oa & 1) ? (oa - 1) / 2 : (ca >= 0 ? oa / 2 : oa / 2 - 1);
+        d[ax] = ca > 0 ? (uint32_t)(2 * (k[ax] + 1) - oa) : (ca < 0 ? (uint32_t)(oa - 2 * k[ax]) : 1u);
+        if (k[ax] < 0 || k[ax] >= G.n[ax]) bad = true;
+    }
+    if (bad || (a[0] | a[1] | a[2]) == 0u) { count[r] = 0; face[r] = -1; return; }
+    int n = 0;
+    for (;;) {
+        const uint32_t p01 = __umul24(d[0], a[1]), p10 = __umul24(d[1], a[0]);
+        const uint32_t p02 = __umul24(d[0], a[2]), p20 = __umul24(d[2], a[0]);
+        const uint32_t p12 = __umul24(d[1], a[2]), p21 = __umul24(d[2], a[1]);
+        const bool m0 = a[0] != 0u && p01 <= p10 && p02 <= p20;
+        const bool m1 = a[1] != 0u && p10 <= p01 && p12 <= p21;
+        const bool m2 = a[2] != 0u && p20 <= p02 && p21 <= p12;
+        if (n < max_len) cells[(size_t)r * max_len + n] = k[0] + G.n[0] * (k[1] + G.n[1] * k[2]);
+        ++n;
+        if (m0) { k[0] += sg[0]; d[0] += 2u; }
+        if (m1) { k[1] += sg[1]; d[1] += 2u; }
+        if (m2) { k[2] += sg[2]; d[2] += 2u; }
+        int f = 0;
+        for (int ax = 0; ax < 3; ++ax) {
+            if (k[ax] < 0) f |= 1 << ax;
+            if (k[ax] >= G.n[ax]) f |= (1 << ax) | (8 << ax);
+        }
+        if (f) { face[r] = f; break; }
+    }
+    count[r] = n;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_prep(const CellLaunch &c) {
+    const int nb = cell_blocks(c.geo.ncell_pad);
+    if (c.fp64) {
+        if (c.species == 1)
+            hipLaunchKernelGGL((k_prep<double, 1>), dim3(nb), dim3(kCellBlock), 0, c.stream, c.geo,
+                               (const double *)c.state, c.kappa, c.acc, c.acc_stride, c.y_he, c.queue);
+        else
+            hipLaunchKernelGGL((k_prep<double, 3>), dim3(nb), dim3(kCellBlock), 0, c.stream, c.geo,
+                               (const double *)c.state, c.kappa, c.acc, c.acc_stride, c.y_he, c.queue);
+    } else {
+        if (c.species == 1)
+            hipLaunchKernelGGL((k_prep<float, 1>), dim3(nb), dim3(kCellBlock), 0, c.stream, c.geo,
+                               (const float *)c.state, c.kappa, c.acc, c.acc_stride, c.y_he, c.queue);
+        else
+            hipLaunchKernelGGL((k_prep<float, 3>), dim3(nb), dim3(kCellBlock), 0, c.stream, c.geo,
+                               (const float *)c.state, c.kappa, c.acc, c.acc_stride, c.y_he, c.queue);
+    }
+    return hipGetLastError();
+}
+
+template <typename R, int S, bool TH>
+static void upd(const CellLaunch &c, int nb) {
+    hipLaunchKernelGGL((k_update<R, S, TH>), dim3(nb), dim3(kCellBlock), 0, c.stream, c.geo, (R *)c.state,
+                       c.acc, c.acc_stride, c.y_he, c.cell_cm, c.dt, c.redshift, c.n_chem, c.ledger);
+}
+
+hipError_t launch_update(const CellLaunch &c) {
+    const int nb = cell_blocks(c.geo.ncell_pad);
+    if (c.fp64) {
+        if (c.species == 1) { if (c.thermal) upd<double, 1, true>(c, nb); else upd<double, 1, false>(c, nb); }
+        else { if (c.thermal) upd<double, 3, true>(c, nb); else upd<double, 3, false>(c, nb); }
+    } else {
+        if (c.species == 1) { if (c.thermal) upd<float, 1, true>(c, nb); else upd<float, 1, false>(c, nb); }
+        else { if (c.thermal) upd<float, 3, true>(c, nb); else upd<float, 3, false>(c, nb); }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_import(const CellLaunch &c, const void *nh, const void *x, const void *t,
+                         int fields_fp64, int64_t ncell) {
+    const size_t nst = 7 * (size_t)c.geo.ncell_pad;
+    const int nb = cell_blocks((uint64_t)ncell);
+    if (c.fp64) {
+        hipLaunchKernelGGL((k_fill_zero<double>), dim3(cell_blocks(nst)), dim3(kCellBlock), 0, c.stream,
+                           (double *)c.state, nst);
+        if (fields_fp64)
+            hipLaunchKernelGGL((k_import<double, double>), dim3(nb), dim3(kCellBlock), 0, c.stream, c.geo,
+                               (double *)c.state, (const double *)nh, (const double *)x, (const double *)t,
+                               (uint32_t)ncell);
+        else
+            hipLaunchKernelGGL((k_import<double, float>), dim3(nb), dim3(kCellBlock), 0, c.stream, c.geo,
+                               (double *)c.state, (const float *)nh, (const float *)x, (const float *)t,
+                               (uint32_t)ncell);
+    } else {
+        hipLaunchKernelGGL((k_fill_zero<float>), dim3(cell_blocks(nst)), dim3(kCellBlock), 0, c.stream,
+                           (float *)c.state, nst);
+        if (fields_fp64)
+            hipLaunchKernelGGL((k_import<float, double>), dim3(nb), dim3(kCellBlock), 0, c.stream, c.geo,
+                               (float *)c.state, (const double *)nh, (const double *)x, (const double *)t,
+                               (uint32_t)ncell);
+        else
+            hipLaunchKernelGGL((k_import<float, float>), dim3(nb), dim3(kCellBlock), 0, c.stream, c.geo,
+                               (float *)c.state, (const float *)nh, (const float *)x, (const float *)t,
+                               (uint32_t)ncell);
+    }
+    // accumulators start at zero so a fetch before the first step is defined
+    hipLaunchKernelGGL((k_fill_zero<double>), dim3(cell_blocks((size_t)c.geo.ncell_pad * c.acc_stride)),
+                       dim3(kCellBlock), 0, c.stream, c.acc, (size_t)c.geo.ncell_pad * c.acc_stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_export(const CellLaunch &c, uint32_t mask, void *dst, int as_fp64, int64_t ncell) {
+    const int nb = cell_blocks((uint64_t)ncell);
+    if (c.fp64) {
+        if (as_fp64)
+            hipLaunchKernelGGL((k_export<double, double>), dim3(nb), dim3(kCellBlock), 0, c.stream, c.geo,
+                               (const double *)c.state, c.acc, c.acc_stride, c.species, c.thermal, mask,
+                               (double *)dst, (uint32_t)ncell);
+        else
+            hipLaunchKernelGGL((k_export<double, float>), dim3(nb), dim3(kCellBlock), 0, c.stream, c.geo,
+                               (const double *)c.state, c.acc, c.acc_stride, c.species, c.thermal, mask,
+                               (float *)dst, (uint32_t)ncell);
+    } else {
+        if (as_fp64)
+            hipLaunchKernelGGL((k_export<float, double>), dim3(nb), dim3(kCellBlock), 0, c.stream, c.geo,
+                               (const float *)c.state, c.acc, c.acc_stride, c.species, c.thermal, mask,
+                               (double *)dst, (uint32_t)ncell);
+        else
+            hipLaunchKernelGGL((k_export<float, float>), dim3(nb), dim3(kCellBlock), 0, c.stream, c.geo,
+                               (const float *)c.state, c.acc, c.acc_stride, c.species, c.thermal, mask,
+                               (float *)dst, (uint32_t)ncell);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ledger_zero(StepLedger *l, hipStream_t s) {
+    hipLaunchKernelGGL(k_ledger_zero, dim3(1), dim3(64), 0, s, l);
+    return hipGetLastError();
+}
+
+hipError_t launch_ledger_reduce(const LedgerSlot *slots, int nslots, StepLedger *l, hipStream_t s) {
+    if (nslots > 0) hipLaunchKernelGGL(k_ledger_reduce, dim3(1), dim3(64), 0, s, slots, nslots, l);
+    else hipLaunchKernelGGL(k_ledger_tick, dim3(1), dim3(64), 0, s, l);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_rays(const GridGeom &g, int m, const int32_t *o, const int32_t *c, int max_len,
+                             int32_t *cells, int32_t *count, int32_t *face, hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_trace_rays, dim3((m + 255) / 256), dim3(256), 0, s, g, m, o, c, max_len, cells, count,
+                       face);
+    return hipGetLastError();
+}
+
+}  // namespace rtk

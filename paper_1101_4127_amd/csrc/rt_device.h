@@ -1,0 +1,144 @@
+// rt_device.h -- device helpers of the packet march: counter-based generator,
+// isotropic integer directions, brick layout of the cell fields, float32
+// attenuation kernel.  Included by the HIP translation units only.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rt_internal.h"
+
+namespace rtk {
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11).  Each round multiplies
+// counter words 0 and 2 by fixed odd constants, xors the high halves with the
+// other two words and the key, and the key advances by a Weyl increment.
+// ---------------------------------------------------------------------------
+struct U64x4 { uint64_t v[4]; };
+
+__device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                               uint64_t k0, uint64_t k1) {
+#pragma unroll 1
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t a = 0xD2E7470EE14C6C93ull * c0;
+        const uint64_t ah = __umul64hi(0xD2E7470EE14C6C93ull, c0);
+        const uint64_t b = 0xCA5A826395121157ull * c2;
+        const uint64_t bh = __umul64hi(0xCA5A826395121157ull, c2);
+        const uint64_t n0 = bh ^ c1 ^ k0;
+        const uint64_t n2 = ah ^ c3 ^ k1;
+        c0 = n0; c1 = b; c2 = n2; c3 = a;
+        k0 += 0x9E3779B97F4A7C15ull;
+        k1 += 0xBB67AE8584CAA73Bull;
+    }
+    U64x4 o;
+    o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3;
+    return o;
+}
+
+// Isotropic integer direction of packet g in sub-step `step`: components are
+// the top 21 bits of Philox words 0..2 shifted to [-2^20, 2^20); the first
+// attempt whose squared length lies in [2^36, 2^40] is used (uniform on the
+// sphere); 64 failed attempts give the diagonal 2^19 (1,1,1).
+__device__ __forceinline__ void sample_direction(uint64_t seed, uint64_t solve_id, uint64_t g,
+                                                 uint64_t step, bool octant, int32_t c[3]) {
+    for (uint32_t attempt = 0; attempt < 64u; ++attempt) {
+        const U64x4 r = philox4x64_10(g, step, attempt, 0ull, seed, solve_id);
+        const int32_t x = (int32_t)(r.v[0] >> 43) - (1 << 20);
+        const int32_t y = (int32_t)(r.v[1] >> 43) - (1 << 20);
+        const int32_t z = (int32_t)(r.v[2] >> 43) - (1 << 20);
+        const int64_t q = (int64_t)x * x + (int64_t)y * y + (int64_t)z * z;
+        if (q >= (1ll << 36) && q <= (1ll << 40)) {
+            c[0] = octant ? abs(x) : x;
+            c[1] = octant ? abs(y) : y;
+            c[2] = octant ? abs(z) : z;
+            return;
+        }
+    }
+    c[0] = c[1] = c[2] = 1 << 19;
+}
+
+// ---------------------------------------------------------------------------
+// Brick layout: the grid is cut into bricks of 2^b cells per side, stored
+// brick after brick (x fastest); inside a brick cells follow the Morton
+// (bit-interleaved) order, so a ray's consecutive cells share cache lines for
+// any direction.  b = 0 is the natural order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {   // 3 low bits -> every third bit
+    return (v & 1u) | ((v & 2u) << 2) | ((v & 4u) << 4);
+}
+
+__device__ __forceinline__ uint32_t compact3(uint32_t m) {  // inverse of spread3
+    return (m & 1u) | ((m >> 2) & 2u) | ((m >> 4) & 4u);
+}
+
+__device__ __forceinline__ uint32_t cell_slot(const GridGeom &G, int i, int j, int k) {
+    if (G.bl == 0) return (uint32_t)i + (uint32_t)G.n[0] * ((uint32_t)j + (uint32_t)G.n[1] * (uint32_t)k);
+    const uint32_t m = (1u << G.bl) - 1u;
+    const uint32_t brick = ((uint32_t)(k >> G.bl) * (uint32_t)G.nb[1] + (uint32_t)(j >> G.bl)) * (uint32_t)G.nb[0]
+                         + (uint32_t)(i >> G.bl);
+    const uint32_t local = spread3((uint32_t)i & m) | (spread3((uint32_t)j & m) << 1)
+                         | (spread3((uint32_t)k & m) << 2);
+    return (brick << (3 * G.bl)) | local;
+}
+
+// Cell of a slot; returns false for padding slots outside the grid.
+__device__ __forceinline__ bool slot_cell(const GridGeom &G, uint32_t slot, int &i, int &j, int &k) {
+    if (G.bl == 0) {
+        i = (int)(slot % (uint32_t)G.n[0]);
+        const uint32_t r = slot / (uint32_t)G.n[0];
+        j = (int)(r % (uint32_t)G.n[1]);
+        k = (int)(r / (uint32_t)G.n[1]);
+        return k < G.n[2];
+    }
+    const uint32_t local = slot & ((1u << (3 * G.bl)) - 1u);
+    const uint32_t brick = slot >> (3 * G.bl);
+    const uint32_t bi = brick % (uint32_t)G.nb[0];
+    const uint32_t r = brick / (uint32_t)G.nb[0];
+    const uint32_t bj = r % (uint32_t)G.nb[1];
+    const uint32_t bk = r / (uint32_t)G.nb[1];
+    i = (int)((bi << G.bl) | compact3(local));
+    j = (int)((bj << G.bl) | compact3(local >> 1));
+    k = (int)((bk << G.bl) | compact3(local >> 2));
+    return i < G.n[0] && j < G.n[1] && k < G.n[2];
+}
+
+// ---------------------------------------------------------------------------
+// Attenuation factors of one cell in float32: em = 1 - exp(-tau) and
+// tr = exp(-tau), each with a small relative error at every tau >= 0.
+// 1 - expf(-tau) alone would lose all digits of em for tau ~ 1e-8, and
+// 1 - em would lose those of tr for tau >> 1 (the transmitted fraction of an
+// opaque cell), so each comes from the form that is accurate where it is used:
+// below tau = 0.25 em is the Taylor series of 1 - e^-t to t^7 (truncation
+// < 2e-9 relative) and tr = 1 - em; above, tr = 2^(-tau log2 e) from the
+// hardware exponential and em = 1 - tr.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void attenuation(float t, float &em, float &tr) {
+    float p = __builtin_fmaf(t, 1.0f / 5040.0f, -1.0f / 720.0f);
+    p = __builtin_fmaf(t, p, 1.0f / 120.0f);
+    p = __builtin_fmaf(t, p, -1.0f / 24.0f);
+    p = __builtin_fmaf(t, p, 1.0f / 6.0f);
+    p = __builtin_fmaf(t, p, -0.5f);
+    p = __builtin_fmaf(t, p, 1.0f);
+    const float small = t * p;
+    const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * t);
+    const bool lo = t < 0.25f;
+    em = lo ? small : 1.0f - e;
+    tr = lo ? 1.0f - small : e;
+}
+
+// Error-free sum a + b = s + e (Knuth's TwoSum).
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
+    s = a + b;
+    const double bp = s - a;
+    e = (a - (s - bp)) + (b - bp);
+}
+
+// Neumaier-compensated accumulation into (s, c).
+__device__ __forceinline__ void acc_comp(double &s, double &c, double v) {
+    double t, e;
+    two_sum(s, v, t, e);
+    s = t;
+    c += e;
+}
+
+}  // namespace rtk

@@ -1,0 +1,103 @@
+// rt_internal.h -- launch descriptions shared by the host ABI (rt_abi.cpp) and
+// the HIP kernels.  Not part of the public interface.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rtk {
+
+constexpr int kMaxBins = 16;
+constexpr int kMarchBlock = 256;          // threads per march block (4 wavefronts)
+#define RT_TRACE_HDR_DEV 8                // int32 header words of a trace record
+
+struct GridGeom {
+    int32_t n[3];        // cells per axis
+    int32_t bl;          // log2 of the brick side (0 = natural order)
+    int32_t nb[3];       // bricks per axis
+    uint32_t ncell_pad;  // slots, >= cells (bricks are padded)
+};
+
+// Per-block partial ledger written by the march (one slot per block).
+struct LedgerSlot {
+    double s[8];                 // (sum, compensation) of emitted, absorbed, escaped, truncated
+    unsigned long long c[4];     // crossings, packets, escaped count, truncated count
+};
+
+// Ledger of one rt_step, accumulated over its sub-steps on the device.
+struct StepLedger {
+    double s[8];
+    unsigned long long c[4];
+    unsigned long long substeps;
+    unsigned int nonfinite;
+    unsigned int pad;
+};
+
+struct SourceRec {
+    int32_t o[3];        // start point in half-cell units
+    int32_t octant;      // 1: directions folded into the + octant, 1/8 of L
+};
+
+// Everything one march launch needs (host side, type erased).
+struct MarchLaunch {
+    GridGeom geo;
+    double half_dl;                 // half the cell size [cm]
+    int32_t species;                // 1 (pure H) or 3 (H + He)
+    int32_t thermal;                // deposit photo-heating too
+    int32_t fp64;                   // plain float64 form
+    int32_t n_bins;
+    int32_t mb;                     // compiled bin capacity (1, 4, 8, 16)
+    const SourceRec *src;
+    const double *src_ndot;         // photons / s
+    const double *src_sedsum;       // sum of the source's SED row (float64)
+    const void *sed;                // [n_src][mb] float (float32 form) or double
+    int32_t n_src;
+    uint32_t packets;               // packets of this sub-step
+    double dt;                      // sub-step length [s]
+    uint64_t seed, solve_id, step_index;
+    const void *tab;                // [2][3][mb] of the march precision: cross-sections,
+                                    // heat factors (see rt_abi.cpp)
+    double tau_kill;
+    const void *kappa;              // absorbers per slot: R (pure H) or R4
+    double *acc;                    // accumulators per slot
+    int32_t acc_stride;             // doubles per slot
+    unsigned long long *queue;      // packet counter
+    LedgerSlot *slots;              // one per block
+    int32_t *trace;
+    int32_t trace_n, trace_len, trace_stride;
+    int32_t chunk;                  // packets claimed per wavefront grab
+    int32_t refill_min;
+    int32_t blocks;
+    hipStream_t stream;
+};
+
+struct CellLaunch {
+    GridGeom geo;
+    int32_t fp64;        // state stored as double
+    int32_t species;
+    int32_t thermal;
+    void *state;         // [7][ncell_pad]: n_H, x_HI, x_HII, x_HeI, x_HeII, x_HeIII, T
+    void *kappa;
+    double *acc;
+    int32_t acc_stride;
+    double y_he, cell_cm, dt, redshift;
+    int32_t n_chem;
+    unsigned long long *queue;
+    StepLedger *ledger;
+    hipStream_t stream;
+};
+
+hipError_t launch_march(const MarchLaunch &m);
+hipError_t march_occupancy(int species, int thermal, int fp64, int mb, int *blocks_per_cu);
+
+hipError_t launch_prep(const CellLaunch &c);
+hipError_t launch_update(const CellLaunch &c);
+hipError_t launch_import(const CellLaunch &c, const void *nh, const void *x, const void *t,
+                         int fields_fp64, int64_t ncell);
+hipError_t launch_export(const CellLaunch &c, uint32_t mask, void *dst, int as_fp64, int64_t ncell);
+hipError_t launch_ledger_zero(StepLedger *l, hipStream_t s);
+hipError_t launch_ledger_reduce(const LedgerSlot *slots, int nslots, StepLedger *l, hipStream_t s);
+hipError_t launch_trace_rays(const GridGeom &g, int m, const int32_t *o, const int32_t *c,
+                             int max_len, int32_t *cells, int32_t *count, int32_t *face,
+                             hipStream_t s);
+
+}  // namespace rtk

@@ -1,0 +1,289 @@
+"""Python binding of the C ABI in include/rt_mcrt.h (librt_mcrt.so).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+behind the ABI.  PyTorch provides device memory (the workspace and the input
+fields) and the stream.  Importing works without a GPU; any call that needs
+the library raises if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "librt_mcrt.so")
+
+RT_MAX_BINS = 16
+RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_ESTATE, RT_EOVERFLOW = 0, -1, -2, -3, -4, -5
+RT_ISOTHERMAL, RT_FP64, RT_TIME_MARCH = 0x1, 0x2, 0x4
+RT_SRC_CORNER_OCTANT = 0x1
+RT_TRACE_HDR = 8
+RT_FATE_TRUNC, RT_FATE_ESCAPE = 1, 2
+
+FIELDS = ("nh", "x_hi", "x_hii", "x_hei", "x_heii", "x_heiii", "temp", "d_hi", "d_hei", "d_heii", "q")
+F = {name: 1 << i for i, name in enumerate(FIELDS)}
+RT_F_ALL = (1 << len(FIELDS)) - 1
+
+
+class GridDesc(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32 * 3), ("cell_cm", C.c_double), ("y_he", C.c_double),
+        ("n_bins", C.c_int32), ("e_bin_ev", C.c_double * RT_MAX_BINS),
+        ("sigma_cm2", (C.c_double * RT_MAX_BINS) * 3), ("redshift", C.c_double),
+        ("tau_kill", C.c_double), ("n_sub", C.c_int32), ("n_chem", C.c_int32),
+        ("flags", C.c_uint32), ("solve_id", C.c_uint64), ("step_index0", C.c_uint64),
+        ("brick_log2", C.c_int32), ("wave_chunk", C.c_int32), ("refill_min", C.c_int32),
+        ("blocks_per_cu", C.c_int32), ("trace_packets", C.c_int32), ("trace_len", C.c_int32),
+        ("trace_stride", C.c_int32),
+    ]
+
+
+class StepStats(C.Structure):
+    _fields_ = [
+        ("emitted", C.c_double), ("absorbed", C.c_double), ("escaped", C.c_double),
+        ("truncated", C.c_double), ("crossings", C.c_int64), ("packets", C.c_int64),
+        ("n_escaped", C.c_int64), ("n_truncated", C.c_int64), ("substeps", C.c_int64),
+        ("nonfinite", C.c_uint32), ("pad", C.c_uint32), ("march_ms", C.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+# (name, restype, argtypes) of every exported entry point
+_VP, _I32, _I64, _U32, _U64, _D = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_double
+SIGNATURES = {
+    "rt_desc_defaults": (_I32, [C.POINTER(GridDesc)]),
+    "rt_workspace_bytes": (_I32, [C.POINTER(GridDesc), _I64, C.POINTER(C.c_size_t)]),
+    "rt_init_grid": (_I32, [C.POINTER(GridDesc), _VP, C.c_size_t, _I64, _VP, _VP, _VP, _I32, _VP,
+                            C.POINTER(_VP)]),
+    "rt_add_sources": (_I32, [_VP, _I32, _VP, _VP, _VP, _U32]),
+    "rt_step": (_I32, [_VP, _D, _I64, _U64, C.POINTER(StepStats)]),
+    "rt_read_stats": (_I32, [_VP, C.POINTER(StepStats)]),
+    "rt_fetch_fields": (_I32, [_VP, _U32, _VP, _I32, _I32]),
+    "rt_fetch_trace": (_I32, [_VP, _VP, _I64]),
+    "rt_trace_rays": (_I32, [_VP, _I32, _VP, _VP, _I32, _VP, _VP, _VP]),
+    "rt_get_step_index": (_I32, [_VP, C.POINTER(_U64)]),
+    "rt_release": (_I32, [_VP]),
+    "rt_strerror": (C.c_char_p, [_I32]),
+}
+
+_lib = None
+
+
+class RTError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        super().__init__(f"{fn}: {rt_strerror(status)} (status {status})")
+        self.status = status
+
+
+def lib():
+    """Load the HIP library; raise if it was not built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1101_4127_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(fn: str, status: int):
+    if status != RT_OK:
+        raise RTError(fn, status)
+
+
+def rt_strerror(status: int) -> str:
+    return lib().rt_strerror(int(status)).decode()
+
+
+def rt_desc_defaults() -> GridDesc:
+    d = GridDesc()
+    _check("rt_desc_defaults", lib().rt_desc_defaults(C.byref(d)))
+    return d
+
+
+def rt_workspace_bytes(desc: GridDesc, max_sources: int) -> int:
+    out = C.c_size_t(0)
+    _check("rt_workspace_bytes", lib().rt_workspace_bytes(C.byref(desc), int(max_sources), C.byref(out)))
+    return int(out.value)
+
+
+def _ptr(t) -> int:
+    return int(t.data_ptr())
+
+
+def _stream_ptr(stream) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def rt_init_grid(desc: GridDesc, workspace, max_sources: int, nh, x, temp, stream=None):
+    """workspace: uint8 device tensor; nh (ncell,), x (5, ncell), temp (ncell,) device
+    tensors of one dtype (float64 or float32), contiguous, natural order."""
+    import torch
+    f64 = nh.dtype == torch.float64
+    for t in (nh, x, temp):
+        if not (t.is_cuda and t.is_contiguous() and t.dtype == nh.dtype):
+            raise ValueError("fields must be contiguous device tensors of one dtype")
+    h = C.c_void_p()
+    st = lib().rt_init_grid(C.byref(desc), _ptr(workspace), workspace.numel() * workspace.element_size(),
+                            int(max_sources), _ptr(nh), _ptr(x), _ptr(temp), int(f64),
+                            _stream_ptr(stream), C.byref(h))
+    _check("rt_init_grid", st)
+    return h
+
+
+def rt_add_sources(h, ijk, ndot, sed, src_flags: int = 0):
+    ijk = np.ascontiguousarray(ijk, dtype=np.int32).reshape(-1, 3)
+    ndot = np.ascontiguousarray(ndot, dtype=np.float64).reshape(-1)
+    sed = np.ascontiguousarray(sed, dtype=np.float64).reshape(len(ndot), -1)
+    _check("rt_add_sources", lib().rt_add_sources(h, len(ndot), ijk.ctypes.data, ndot.ctypes.data,
+                                                  sed.ctypes.data, int(src_flags)))
+
+
+def rt_step(h, dt_s: float, n_packets: int, seed: int, stats: bool = True) -> Optional[dict]:
+    s = StepStats()
+    _check("rt_step", lib().rt_step(h, float(dt_s), int(n_packets), int(seed),
+                                    C.byref(s) if stats else None))
+    return s.as_dict() if stats else None
+
+
+def rt_read_stats(h) -> dict:
+    s = StepStats()
+    _check("rt_read_stats", lib().rt_read_stats(h, C.byref(s)))
+    return s.as_dict()
+
+
+def rt_fetch_fields(h, mask: int, ncell: int, as_fp64: bool = True, device_out=None) -> np.ndarray:
+    """Fields in mask bit order as an array (nfields, ncell); with device_out
+    (a device tensor of nfields*ncell elements) the copy stays on the device."""
+    nf = bin(mask).count("1")
+    if device_out is not None:
+        _check("rt_fetch_fields", lib().rt_fetch_fields(h, int(mask), _ptr(device_out), 1, int(as_fp64)))
+        return device_out.view(nf, ncell)
+    out = np.empty((nf, ncell), dtype=np.float64 if as_fp64 else np.float32)
+    _check("rt_fetch_fields", lib().rt_fetch_fields(h, int(mask), out.ctypes.data, 0, int(as_fp64)))
+    return out
+
+
+def rt_fetch_trace(h, count: int, trace_len: int) -> np.ndarray:
+    out = np.zeros((count, RT_TRACE_HDR + trace_len), dtype=np.int32)
+    _check("rt_fetch_trace", lib().rt_fetch_trace(h, out.ctypes.data, int(count)))
+    return out
+
+
+def rt_trace_rays(h, origins, dirs, max_len: int):
+    """origins, dirs: (m, 3) int32 device tensors; returns device tensors
+    (cells (m, max_len), count (m,), face (m,))."""
+    import torch
+    m = origins.shape[0]
+    dev = origins.device
+    cells = torch.full((m, max(max_len, 1)), -1, dtype=torch.int32, device=dev)
+    count = torch.zeros(m, dtype=torch.int32, device=dev)
+    face = torch.zeros(m, dtype=torch.int32, device=dev)
+    _check("rt_trace_rays", lib().rt_trace_rays(h, int(m), _ptr(origins.contiguous()), _ptr(dirs.contiguous()),
+                                                int(max_len), _ptr(cells), _ptr(count), _ptr(face)))
+    return cells, count, face
+
+
+def rt_get_step_index(h) -> int:
+    v = C.c_uint64(0)
+    _check("rt_get_step_index", lib().rt_get_step_index(h, C.byref(v)))
+    return int(v.value)
+
+
+def rt_release(h):
+    _check("rt_release", lib().rt_release(h))
+
+
+# ----------------------------------------------------------------------------
+# Convenience owner of one solve: torch device memory for the workspace and
+# the initial fields, built from a workload description.
+# ----------------------------------------------------------------------------
+def desc_from_workload(work, *, fp64: Optional[bool] = None, brick_log2: int = -1, wave_chunk: int = 0,
+                       refill_min: int = 0, blocks_per_cu: int = 0, trace_packets: int = 0,
+                       trace_len: int = 0, trace_stride: int = 1, time_march: bool = False) -> GridDesc:
+    d = rt_desc_defaults()
+    for a in range(3):
+        d.n[a] = int(work.n[a])
+    d.cell_cm = float(work.cell_cm)
+    d.y_he = float(work.y_he)
+    nb = work.bins.n_bins
+    d.n_bins = nb
+    for j in range(nb):
+        d.e_bin_ev[j] = float(work.bins.e_ev[j])
+        for s in range(3):
+            d.sigma_cm2[s][j] = float(work.bins.sigma[s, j])
+    d.redshift = float(work.redshift)
+    d.tau_kill = float(work.tau_kill)
+    d.n_sub = int(work.n_sub)
+    d.n_chem = int(work.n_chem)
+    f64 = bool(work.flags & 0x2) if fp64 is None else bool(fp64)
+    d.flags = ((RT_ISOTHERMAL if work.flags & 0x1 else 0) | (RT_FP64 if f64 else 0)
+               | (RT_TIME_MARCH if time_march else 0))
+    d.solve_id = int(work.solve_id)
+    d.brick_log2 = int(brick_log2)
+    d.wave_chunk = int(wave_chunk)
+    d.refill_min = int(refill_min)
+    d.blocks_per_cu = int(blocks_per_cu)
+    d.trace_packets = int(trace_packets)
+    d.trace_len = int(trace_len)
+    d.trace_stride = int(trace_stride)
+    return d
+
+
+class Solve:
+    """One solve on the current GPU: workspace and fields in torch device memory."""
+
+    def __init__(self, work, *, device: str = "cuda", stream=None, **tiles):
+        import torch
+        self.work = work
+        self.desc = desc_from_workload(work, **tiles)
+        self.ncell = work.ncell
+        self.fp64 = bool(self.desc.flags & RT_FP64)
+        self.stream = stream
+        nbytes = rt_workspace_bytes(self.desc, len(work.src_ndot))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        dt = torch.float64 if self.fp64 else torch.float32
+        nh = torch.as_tensor(np.asarray(work.n_h), dtype=dt, device=device).contiguous()
+        x = torch.as_tensor(np.asarray(work.x).reshape(5, -1), dtype=dt, device=device).contiguous()
+        t = torch.as_tensor(np.asarray(work.temp), dtype=dt, device=device).contiguous()
+        self.h = rt_init_grid(self.desc, self.workspace, len(work.src_ndot), nh, x, t, stream)
+        if len(work.src_ndot):
+            rt_add_sources(self.h, work.src_ijk, work.src_ndot, work.src_sed, work.src_flags)
+        # the import is stream-ordered: wait for it before the inputs are freed
+        (stream if stream is not None else torch.cuda.current_stream()).synchronize()
+        del nh, x, t
+
+    def step(self, dt: Optional[float] = None, packets: Optional[int] = None, seed: Optional[int] = None,
+             stats: bool = True):
+        w = self.work
+        return rt_step(self.h, w.dt_s if dt is None else dt, w.packets if packets is None else packets,
+                       w.seed if seed is None else seed, stats)
+
+    def fetch(self, mask: int = RT_F_ALL) -> np.ndarray:
+        return rt_fetch_fields(self.h, mask, self.ncell)
+
+    def trace(self, count: Optional[int] = None) -> np.ndarray:
+        n = self.desc.trace_packets if count is None else count
+        return rt_fetch_trace(self.h, n, self.desc.trace_len)
+
+    def release(self):
+        if self.h is not None:
+            rt_release(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass

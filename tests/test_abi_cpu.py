@@ -1,0 +1,114 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/rt_mcrt.h declares, its structs have the layout the
+binding assumes, and the host-only calls validate their arguments."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1101_4127_amd import rt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rt_mcrt.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(rt.LIB_PATH):
+        from paper_1101_4127_amd import build
+        build.build()
+    return rt.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rt_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert len(names) >= 12
+    out = subprocess.run(["nm", "-D", "--defined-only", rt.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (rt_\w+)", out))
+    for n in names:
+        assert n in exported, n
+        assert hasattr(L, n)
+    assert set(rt.SIGNATURES) == set(names)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(f"""
+#include <stdio.h>
+#include <stddef.h>
+#include "{HEADER}"
+int main(void) {{
+  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(rt_grid_desc), offsetof(rt_grid_desc, solve_id),
+         offsetof(rt_grid_desc, trace_stride), sizeof(rt_step_stats),
+         offsetof(rt_step_stats, crossings), offsetof(rt_step_stats, nonfinite),
+         offsetof(rt_step_stats, march_ms));
+  return 0;
+}}""")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-o", str(exe), str(src)])
+    vals = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    assert vals == [C.sizeof(rt.GridDesc), rt.GridDesc.solve_id.offset, rt.GridDesc.trace_stride.offset,
+                    C.sizeof(rt.StepStats), rt.StepStats.crossings.offset, rt.StepStats.nonfinite.offset,
+                    rt.StepStats.march_ms.offset]
+
+
+def test_defaults_and_strerror(L):
+    d = rt.rt_desc_defaults()
+    assert list(d.n) == [1, 1, 1] and d.n_bins == 1 and d.tau_kill == 30.0 and d.n_chem == 8
+    for st in (rt.RT_OK, rt.RT_EINVAL, rt.RT_ENOMEM, rt.RT_EDEVICE, rt.RT_ESTATE, rt.RT_EOVERFLOW):
+        assert rt.rt_strerror(st)
+    assert rt.rt_strerror(-99) == "unknown status"
+
+
+def test_workspace_bytes_scales_and_validates(L):
+    d = rt.rt_desc_defaults()
+    d.n[0] = d.n[1] = d.n[2] = 64
+    d.cell_cm = 1e21
+    b64 = rt.rt_workspace_bytes(d, 10)
+    d.n[0] = d.n[1] = d.n[2] = 128
+    b128 = rt.rt_workspace_bytes(d, 10)
+    assert 7.5 < b128 / b64 < 8.5
+    d.flags = rt.RT_FP64
+    assert rt.rt_workspace_bytes(d, 10) > b128
+    # invalid descriptions
+    for field, bad in (("n_bins", 0), ("n_bins", 9), ("n_bins", 17), ("tau_kill", 0.0), ("n_sub", 0), ("n_chem", 0),
+                       ("cell_cm", -1.0), ("brick_log2", 4), ("wave_chunk", 100), ("refill_min", 65),
+                       ("flags", 0x10), ("trace_stride", -1)):
+        e = rt.rt_desc_defaults()
+        setattr(e, field, bad)
+        with pytest.raises(rt.RTError) as ex:
+            rt.rt_workspace_bytes(e, 1)
+        assert ex.value.status == rt.RT_EINVAL, field
+    e = rt.rt_desc_defaults()
+    e.n[1] = 1025
+    with pytest.raises(rt.RTError):
+        rt.rt_workspace_bytes(e, 1)
+    # a cross-section above zero below its threshold is rejected
+    e = rt.rt_desc_defaults()
+    e.e_bin_ev[0] = 20.0
+    e.sigma_cm2[1][0] = 1e-18          # HeI below 24.6 eV
+    with pytest.raises(rt.RTError):
+        rt.rt_workspace_bytes(e, 1)
+
+
+def test_init_rejects_bad_arguments_before_touching_the_device(L):
+    d = rt.rt_desc_defaults()
+    h = C.c_void_p()
+    # misaligned or null workspace, null fields: EINVAL without a device call
+    assert L.rt_init_grid(C.byref(d), None, 1 << 20, 1, 1, 1, 1, 0, None, C.byref(h)) == rt.RT_EINVAL
+    assert L.rt_init_grid(C.byref(d), 0x1001, 1 << 20, 1, 256, 256, 256, 0, None, C.byref(h)) == rt.RT_EINVAL
+    assert L.rt_init_grid(C.byref(d), 0x1000, 1 << 20, 1, None, 256, 256, 0, None, C.byref(h)) == rt.RT_EINVAL
+    # too small a workspace
+    assert L.rt_init_grid(C.byref(d), 0x1000, 16, 1, 256, 256, 256, 0, None, C.byref(h)) == rt.RT_ENOMEM
+    # calls on a null handle
+    assert L.rt_step(None, 1.0, 1, 1, None) == rt.RT_EINVAL
+    assert L.rt_release(None) == rt.RT_EINVAL
+    assert L.rt_fetch_fields(None, 1, None, 0, 1) == rt.RT_EINVAL

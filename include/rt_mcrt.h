@@ -45,14 +45,23 @@ extern "C" {
 #define RT_EDEVICE (-3)     /* HIP error; the handle is unusable */
 #define RT_ESTATE (-4)      /* call not valid in the handle's state */
 #define RT_EOVERFLOW (-5)   /* a size exceeds what the library supports */
+#define RT_EINTERNAL (-6)   /* an internal consistency check of the march failed;
+                               the handle only accepts rt_release */
 
 /* rt_grid_desc.flags */
 #define RT_ISOTHERMAL 0x1u  /* temperature held fixed */
 #define RT_FP64 0x2u        /* plain form: march, absorber table and stored state
                                in float64 (default: float32 march and state,
                                float64 accumulators and float64 cell update) */
-#define RT_TIME_MARCH 0x4u  /* time every march launch with HIP events on the
-                               handle's stream (rt_step_stats.march_ms) */
+#define RT_TIME_MARCH 0x4u  /* time the march of every sub-step with HIP events
+                               on the handle's stream (rt_step_stats.march_ms) */
+#define RT_DIRECT_MARCH 0x8u /* per-packet march: every wavefront lane follows
+                               one packet from emission to its end and adds its
+                               deposits to the grid with float64 atomics.
+                               Default: the tiled march (tiles of 8^3 cells,
+                               deposits gathered per tile in on-chip memory,
+                               packets handed between tiles pass by pass).
+                               Both give the same packet histories. */
 
 /* rt_add_sources src_flags */
 #define RT_SRC_CORNER_OCTANT 0x1u /* source at the lowest corner of its cell,
@@ -101,8 +110,10 @@ typedef struct {
     uint32_t flags;               /* RT_ISOTHERMAL | RT_FP64 */
     uint64_t solve_id;            /* second word of the Philox key */
     uint64_t step_index0;         /* Philox sub-step counter to start from (resume) */
-    int32_t brick_log2;           /* brick side 2^b, b in 0..3 (0 = natural order); -1 = default */
-    int32_t wave_chunk;           /* packets a wavefront claims at a time; 0 = default */
+    int32_t brick_log2;           /* brick side 2^b, b in 0..3 (0 = natural order); -1 = default.
+                                     The tiled march needs b = 3 (or -1). */
+    int32_t wave_chunk;           /* per-packet march: packets a wavefront claims
+                                     at a time; 0 = default */
     int32_t refill_min;           /* dead lanes a wavefront gathers before it
                                      refills them; 0 = default */
     int32_t blocks_per_cu;        /* persistent march blocks per compute unit; 0 = default */
@@ -111,6 +122,14 @@ typedef struct {
                                      go to trace record r */
     int32_t trace_len;            /* cells recorded per traced packet */
     int32_t trace_stride;         /* spacing of traced packet ids; 0 = 1 */
+    int32_t run_len;              /* tiled march: packets of one tile one block
+                                     marches before it writes the tile's deposits
+                                     out; 0 = default (2048), else 64..2^20 */
+    int32_t reserved;             /* must be 0 */
+    int64_t inflight;             /* tiled march: packets propagated together (the
+                                     workspace holds one record each); a sub-step
+                                     with more packets runs in batches of this
+                                     size.  0 = default (2^24) */
 } rt_grid_desc;
 
 /* Photon ledger and counters of the most recent rt_step (all its sub-steps). */
@@ -125,7 +144,8 @@ typedef struct {
     int64_t n_truncated;
     int64_t substeps;
     uint32_t nonfinite; /* nonzero if the cell update produced a non-finite value */
-    uint32_t pad;
+    uint32_t errors;    /* nonzero if a consistency check of the march failed
+                           (rt_read_stats then returns RT_EINTERNAL) */
     double march_ms;    /* summed march kernel time (RT_TIME_MARCH), else 0 */
 } rt_step_stats;
 

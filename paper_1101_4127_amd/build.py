@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "librt_mcrt.so")
-SOURCES = ("rt_march.hip", "rt_cells.hip", "rt_abi.cpp")
+SOURCES = ("rt_march.hip", "rt_tiled.hip", "rt_cells.hip", "rt_abi.cpp")
 ARCH = "gfx950"
 
 FLAGS = [

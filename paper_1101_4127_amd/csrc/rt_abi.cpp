@@ -26,13 +26,22 @@ constexpr int kMaxSupportedBins = 8;   // widest compiled march instance
 
 int bin_capacity(int n_bins) { return n_bins <= 1 ? 1 : 8; }
 
+constexpr int64_t kDefaultInflight = (int64_t)1 << 24;   // packets in flight in the tiled march
+constexpr int kDefaultRun = 2048;                         // packets per tile run
+
 struct Plan {
     int species, thermal, fp64, mb, acc_stride, bl;
+    bool tiled;
     rtk::GridGeom geo;
     int64_t ncell;
     size_t real;
     size_t off_state, off_kappa, off_acc, off_src, off_ndot, off_sedsum, off_sed, off_tab, off_slots,
         off_ledger, off_queue, off_trace, off_stage, total;
+    // tiled march
+    uint32_t capacity, cmax, max_chunks, n_tiles, scan_blocks, passes;
+    size_t rec_bytes;
+    size_t off_rec, off_idx0, off_idx1, off_side, off_cnt, off_off, off_cbase, off_bsum, off_ch0, off_ch1,
+        off_ctrl;
 };
 
 bool finite_nonneg(double v) { return isfinite(v) && v >= 0.0; }
@@ -54,8 +63,13 @@ int32_t validate_desc(const rt_grid_desc *d) {
     if (!isfinite(d->redshift)) return RT_EINVAL;
     if (!(isfinite(d->tau_kill) && d->tau_kill > 0.0)) return RT_EINVAL;
     if (d->n_sub < 1 || d->n_chem < 1) return RT_EINVAL;
-    if (d->flags & ~(RT_ISOTHERMAL | RT_FP64 | RT_TIME_MARCH)) return RT_EINVAL;
+    if (d->flags & ~(RT_ISOTHERMAL | RT_FP64 | RT_TIME_MARCH | RT_DIRECT_MARCH)) return RT_EINVAL;
     if (d->brick_log2 < -1 || d->brick_log2 > 3) return RT_EINVAL;
+    // the tiled march's tiles are the bricks of side 8
+    if (!(d->flags & RT_DIRECT_MARCH) && d->brick_log2 != -1 && d->brick_log2 != 3) return RT_EINVAL;
+    if (d->run_len < 0 || d->run_len > (1 << 20) || (d->run_len > 0 && d->run_len < 64)) return RT_EINVAL;
+    if (d->inflight < 0 || d->inflight > ((int64_t)1 << 31) - 1) return RT_EINVAL;
+    if (d->reserved != 0) return RT_EINVAL;
     if (d->wave_chunk < 0 || d->wave_chunk % 64 != 0 || d->wave_chunk > (1 << 20)) return RT_EINVAL;
     if (d->refill_min < 0 || d->refill_min > 64) return RT_EINVAL;
     if (d->blocks_per_cu < 0 || d->blocks_per_cu > 32) return RT_EINVAL;
@@ -74,7 +88,8 @@ int32_t make_plan(const rt_grid_desc *d, int64_t max_sources, Plan *p) {
     p->fp64 = (d->flags & RT_FP64) ? 1 : 0;
     p->mb = bin_capacity(d->n_bins);
     p->acc_stride = p->species == 1 ? (p->thermal ? 2 : 1) : 4;
-    p->bl = d->brick_log2 < 0 ? 1 : d->brick_log2;
+    p->tiled = !(d->flags & RT_DIRECT_MARCH);
+    p->bl = p->tiled ? 3 : (d->brick_log2 < 0 ? 1 : d->brick_log2);
     rtk::GridGeom &g = p->geo;
     uint64_t np = 1;
     for (int a = 0; a < 3; ++a) {
@@ -105,6 +120,34 @@ int32_t make_plan(const rt_grid_desc *d, int64_t max_sources, Plan *p) {
     p->off_trace = o;
     o = align_up(o + (size_t)d->trace_packets * (RT_TRACE_HDR + (size_t)d->trace_len) * sizeof(int32_t));
     p->off_stage = o; o = align_up(o + (size_t)p->ncell * sizeof(double));
+    p->capacity = p->cmax = p->max_chunks = p->n_tiles = p->scan_blocks = p->passes = 0;
+    p->rec_bytes = 0;
+    p->off_rec = p->off_idx0 = p->off_idx1 = p->off_side = p->off_cnt = p->off_off = p->off_cbase = p->off_bsum =
+        p->off_ch0 = p->off_ch1 = p->off_ctrl = 0;
+    if (p->tiled) {
+        const uint64_t cap = (uint64_t)(d->inflight > 0 ? d->inflight : kDefaultInflight);
+        const uint64_t nt = (uint64_t)g.nb[0] * g.nb[1] * g.nb[2];
+        p->capacity = (uint32_t)cap;
+        p->cmax = (uint32_t)(d->run_len > 0 ? d->run_len : kDefaultRun);
+        const uint64_t mc = nt + cap / p->cmax + 1;
+        if (mc >= (1ull << 31)) return RT_EOVERFLOW;
+        p->max_chunks = (uint32_t)mc;
+        p->n_tiles = (uint32_t)nt;
+        p->scan_blocks = (uint32_t)((nt + 4095) / 4096);
+        p->passes = (uint32_t)(g.nb[0] + g.nb[1] + g.nb[2] - 2);
+        p->rec_bytes = rtk::tiled_record_bytes(p->fp64, p->species, p->mb);
+        p->off_rec = o; o = align_up(o + cap * p->rec_bytes);
+        p->off_idx0 = o; o = align_up(o + cap * sizeof(uint32_t));
+        p->off_idx1 = o; o = align_up(o + cap * sizeof(uint32_t));
+        p->off_side = o; o = align_up(o + cap * sizeof(uint32_t));
+        p->off_cnt = o; o = align_up(o + nt * sizeof(uint32_t));
+        p->off_off = o; o = align_up(o + nt * sizeof(uint32_t));
+        p->off_cbase = o; o = align_up(o + mc * rtk::kCodes * sizeof(uint32_t));
+        p->off_bsum = o; o = align_up(o + 2 * (size_t)p->scan_blocks * sizeof(uint32_t));
+        p->off_ch0 = o; o = align_up(o + mc * sizeof(rtk::TChunk));
+        p->off_ch1 = o; o = align_up(o + mc * sizeof(rtk::TChunk));
+        p->off_ctrl = o; o = align_up(o + sizeof(rtk::TCtrl));
+    }
     p->total = o;
     return RT_OK;
 }
@@ -155,6 +198,40 @@ bool valid(rt_solve_t h) { return h && h->magic == kMagic; }
 int32_t fail(rt_solve_t h) {
     if (h) h->dead = true;
     return RT_EDEVICE;
+}
+
+rtk::MarchLaunch tiled_base(rt_solve_t h) {
+    rtk::MarchLaunch m;
+    memset(&m, 0, sizeof(m));
+    m.blocks = h->blocks;
+    m.stream = h->stream;
+    return m;
+}
+
+rtk::TiledLaunch tiled_launch(rt_solve_t h, const rtk::MarchLaunch &m) {
+    const Plan &p = h->plan;
+    rtk::TiledLaunch t;
+    memset(&t, 0, sizeof(t));
+    t.m = m;
+    t.capacity = p.capacity;
+    t.cmax = p.cmax;
+    t.max_chunks = p.max_chunks;
+    t.n_tiles = p.n_tiles;
+    t.scan_blocks = p.scan_blocks;
+    t.passes = p.passes;
+    t.rec = h->ws + p.off_rec;
+    t.idx[0] = reinterpret_cast<uint32_t *>(h->ws + p.off_idx0);
+    t.idx[1] = reinterpret_cast<uint32_t *>(h->ws + p.off_idx1);
+    t.side = reinterpret_cast<uint32_t *>(h->ws + p.off_side);
+    t.cnt = reinterpret_cast<uint32_t *>(h->ws + p.off_cnt);
+    t.off = reinterpret_cast<uint32_t *>(h->ws + p.off_off);
+    t.cbase = reinterpret_cast<uint32_t *>(h->ws + p.off_cbase);
+    t.bsum = reinterpret_cast<uint32_t *>(h->ws + p.off_bsum);
+    t.chunks[0] = reinterpret_cast<rtk::TChunk *>(h->ws + p.off_ch0);
+    t.chunks[1] = reinterpret_cast<rtk::TChunk *>(h->ws + p.off_ch1);
+    t.ctrl = reinterpret_cast<rtk::TCtrl *>(h->ws + p.off_ctrl);
+    t.ledger = reinterpret_cast<rtk::StepLedger *>(h->ws + p.off_ledger);
+    return t;
 }
 
 rtk::CellLaunch cell_launch(rt_solve_t h, double dt) {
@@ -223,7 +300,9 @@ int32_t rt_init_grid(const rt_grid_desc *d, void *d_ws, size_t ws_bytes, int64_t
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return RT_EDEVICE;
     int bpcu = d->blocks_per_cu;
     if (bpcu == 0) {
-        if (rtk::march_occupancy(p.species, p.thermal, p.fp64, p.mb, &bpcu) != hipSuccess) return RT_EDEVICE;
+        const hipError_t e = p.tiled ? rtk::tiled_occupancy(p.species, p.thermal, p.fp64, p.mb, &bpcu)
+                                     : rtk::march_occupancy(p.species, p.thermal, p.fp64, p.mb, &bpcu);
+        if (e != hipSuccess) return RT_EDEVICE;
         if (bpcu < 1) bpcu = 1;
     }
     int blocks = cus * bpcu;
@@ -263,7 +342,8 @@ int32_t rt_init_grid(const rt_grid_desc *d, void *d_ws, size_t ws_bytes, int64_t
             hipSuccess ||
         hipStreamSynchronize(h->stream) != hipSuccess ||
         rtk::launch_import(c, d_nh, d_x, d_temp, fields_fp64, p.ncell) != hipSuccess ||
-        rtk::launch_ledger_zero(c.ledger, h->stream) != hipSuccess) {
+        rtk::launch_ledger_zero(c.ledger, h->stream) != hipSuccess ||
+        (p.tiled && rtk::launch_tiled_reset(tiled_launch(h, tiled_base(h))) != hipSuccess)) {
         for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
         delete h;
         return RT_EDEVICE;
@@ -292,12 +372,13 @@ int32_t rt_add_sources(rt_solve_t h, int32_t n, const int32_t *h_ijk, const doub
             if (v < 0 || v >= h->d.n[a]) return RT_EINVAL;
             rec[i].o[a] = 2 * v + (oct ? 0 : 1);
         }
-        rec[i].octant = oct ? 1 : 0;
+        rec[i].flags = oct ? rtk::kSrcOctant : 0u;
         if (!finite_nonneg(h_ndot[i])) return RT_EINVAL;
         double s = 0.0;
         for (int j = 0; j < nb; ++j) {
             const double v = h_sed[(size_t)i * nb + j];
             if (!finite_nonneg(v)) return RT_EINVAL;
+            if (v > 0.0) rec[i].flags |= 1u << (rtk::kSrcMaskShift + j);
             s += v;
             sed_d[(size_t)i * mb + j] = v;
             sed_f[(size_t)i * mb + j] = (float)v;
@@ -340,12 +421,16 @@ int32_t rt_read_stats(rt_solve_t h, rt_step_stats *stats) {
     stats->n_truncated = (int64_t)l.c[3];
     stats->substeps = (int64_t)l.substeps;
     stats->nonfinite = l.nonfinite;
-    stats->pad = 0;
+    stats->errors = l.errors;
     stats->march_ms = 0.0;
     for (int i = 0; i < h->timed; ++i) {
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]) != hipSuccess) return fail(h);
         stats->march_ms += ms;
+    }
+    if (l.errors) {
+        h->dead = true;
+        return RT_EINTERNAL;
     }
     return RT_OK;
 }
@@ -406,7 +491,17 @@ int32_t rt_step(rt_solve_t h, double dt_s, int64_t n_packets, uint64_t seed, rt_
             m.step_index = h->step_index;
             const bool timed = !h->ev.empty() && h->timed < kMaxTimedSubsteps;
             if (timed && hipEventRecord(h->ev[2 * h->timed], h->stream) != hipSuccess) return fail(h);
-            if (rtk::launch_march(m) != hipSuccess) return fail(h);
+            if (p.tiled) {
+                rtk::TiledLaunch t = tiled_launch(h, m);
+                if (rtk::launch_tiled_slots_zero(t) != hipSuccess) return fail(h);
+                for (int64_t g0 = 0; g0 < Pi; g0 += p.capacity) {
+                    t.g0 = (uint32_t)g0;
+                    t.nbatch = (uint32_t)(Pi - g0 < (int64_t)p.capacity ? Pi - g0 : p.capacity);
+                    if (rtk::launch_tiled_batch(t) != hipSuccess) return fail(h);
+                }
+            } else if (rtk::launch_march(m) != hipSuccess) {
+                return fail(h);
+            }
             if (timed) {
                 if (hipEventRecord(h->ev[2 * h->timed + 1], h->stream) != hipSuccess) return fail(h);
                 ++h->timed;
@@ -496,6 +591,7 @@ const char *rt_strerror(int32_t status) {
     case RT_EDEVICE: return "HIP device error; the handle is unusable";
     case RT_ESTATE: return "call not valid in the handle's state";
     case RT_EOVERFLOW: return "size beyond what the library supports";
+    case RT_EINTERNAL: return "internal consistency check of the march failed; the handle is unusable";
     default: return "unknown status";
     }
 }

@@ -299,7 +299,7 @@ __global__ void k_ledger_zero(StepLedger *l) {
         for (int i = 0; i < 4; ++i) z.c[i] = 0ull;
         z.substeps = 0ull;
         z.nonfinite = 0u;
-        z.pad = 0u;
+        z.errors = 0u;
         *l = z;
     }
 }

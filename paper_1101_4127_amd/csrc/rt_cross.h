@@ -1,0 +1,158 @@
+// rt_cross.h -- the arithmetic of one (packet, cell) crossing, shared by the
+// per-packet march and the tiled march so that both follow a packet through
+// bit-identical values: exact integer choice of the exit face, the chord, the
+// per-bin optical depth and Eq. (1) attenuation, the split of the absorbed
+// photons among HI, HeI and HeII in proportion to their optical depth, and
+// the extinction test (Partl et al. 2011, Sec. 2).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <type_traits>
+
+#include "rt_device.h"
+
+namespace rtk {
+
+template <typename R> struct Vec4;
+template <> struct Vec4<float> { using T = float4; };
+template <> struct Vec4<double> { using T = double4; };
+
+constexpr uint32_t kNeg = 0x80000000u;      // sign flag packed above |c| (|c| <= 2^20)
+constexpr uint32_t kMag = 0x00ffffffu;
+
+// Per-packet depth state.  float64 form: the accumulated optical depth of
+// every bin, T_j (bins the source does not populate start at +inf), exactly
+// as the oracle sums it.  float32 form: the column densities N_s = sum l kappa_s
+// of the three absorbers; T_j = sum_s sigma_s,j N_s is formed when the
+// extinction test needs it (the same quantity, one float32 rounding per
+// crossing and absorber instead of one per crossing and bin).
+template <typename R, int S, int MB>
+struct DepthState {
+    static constexpr bool F64 = std::is_same<R, double>::value;
+    static constexpr int N = F64 ? MB : (S == 1 ? 1 : 3);
+};
+
+// Exit face of the current cell by exact integer comparison of the ray
+// parameters d_a / |c_a| (all products < 2^32); ties cross several faces at
+// once.  Returns the lowest crossed axis.
+__device__ __forceinline__ int exit_face(uint32_t d0, uint32_t d1, uint32_t d2, uint32_t a0, uint32_t a1,
+                                         uint32_t a2, bool &m0, bool &m1, bool &m2) {
+    const uint32_t m0a = a0 & kMag, m1a = a1 & kMag, m2a = a2 & kMag;
+    const uint32_t p01 = __umul24(d0, m1a), p10 = __umul24(d1, m0a);
+    const uint32_t p02 = __umul24(d0, m2a), p20 = __umul24(d2, m0a);
+    const uint32_t p12 = __umul24(d1, m2a), p21 = __umul24(d2, m1a);
+    m0 = m0a != 0u && p01 <= p10 && p02 <= p20;
+    m1 = m1a != 0u && p10 <= p01 && p12 <= p21;
+    m2 = m2a != 0u && p20 <= p02 && p21 <= p12;
+    return m0 ? 0 : (m1 ? 1 : 2);
+}
+
+// Eq. (1) in every bin of one cell of chord length l (float32 form: l in
+// 1e18 cm, cross-sections in 1e-18 cm^2), with F the photons carried per bin
+// (updated to the transmitted part) and the depth state advanced.  Outputs,
+// in the march precision: the photons absorbed over all bins; per absorber,
+// kappa_s * sum_j sigma_s,j d_j / K_j (the photons the absorber takes); the
+// heat sum_s kappa_s sum_j h_s,j d_j / K_j (pure hydrogen: sum_j h_j d_j), in
+// eV per photon of the packet's weight; and the smallest accumulated optical
+// depth over the bins the source populates (bit j of `active`), which ends the
+// packet once it reaches tau_kill.
+template <typename R, int S, bool TH, int MB, typename KV>
+__device__ __forceinline__ void cross_cell(R l, const KV &kap, const typename Vec4<R>::T *s_sig,
+                                           const typename Vec4<R>::T *s_heat, uint32_t active, R (&F)[MB],
+                                           R (&D)[DepthState<R, S, MB>::N], R &absorbed, R &e0, R &e1,
+                                           R &e2, R &heat, R &tmin) {
+    constexpr bool F64 = std::is_same<R, double>::value;
+    using V4R = typename Vec4<R>::T;
+    R kH, kHe1 = R(0), kHe2 = R(0);
+    if constexpr (S == 1) kH = kap;
+    else { kH = kap.x; kHe1 = kap.y; kHe2 = kap.z; }
+    if constexpr (!F64) {
+        // column densities through the end of this cell
+        D[0] = __builtin_fmaf(l, kH, D[0]);
+        if (S == 3) {
+            D[1] = __builtin_fmaf(l, kHe1, D[1]);
+            D[2] = __builtin_fmaf(l, kHe2, D[2]);
+        }
+    }
+    R ab = R(0), g0 = R(0), g1 = R(0), g2 = R(0), h0 = R(0), h1 = R(0), h2 = R(0);
+    R tm = R(INFINITY);
+#pragma unroll
+    for (int j = 0; j < MB; ++j) {
+        const V4R sg = s_sig[j];
+        R K;
+        if (S == 1) K = kH * sg.x;
+        else if (F64) K = (kH * sg.x + kHe1 * sg.y) + kHe2 * sg.z;
+        else K = __builtin_fmaf(kHe2, sg.z, __builtin_fmaf(kHe1, sg.y, kH * sg.x));
+        const R tau = l * K;
+        R d;
+        if constexpr (F64) {
+            // transmitted = previous - absorbed, as the oracle defines it
+            d = F[j] * -expm1(-tau);
+            F[j] = F[j] - d;
+            D[j] = D[j] + tau;
+            tm = D[j] < tm ? D[j] : tm;
+        } else {
+            float em, tr;
+            attenuation(tau, em, tr);
+            d = F[j] * em;
+            F[j] = F[j] * tr;
+            R tj;
+            if (S == 1) tj = sg.x * D[0];
+            else tj = __builtin_fmaf(sg.z, D[2], __builtin_fmaf(sg.y, D[1], sg.x * D[0]));
+            tm = ((active >> j) & 1u) && tj < tm ? tj : tm;
+        }
+        ab += d;
+        if (S == 1) {
+            if (TH) h0 += d * s_heat[j].x;
+        } else {
+            R gk;
+            if (F64) gk = K > R(0) ? d / K : R(0);
+            else gk = K > R(0) ? d * __builtin_amdgcn_rcpf(K) : R(0);
+            g0 += sg.x * gk;
+            g1 += sg.y * gk;
+            g2 += sg.z * gk;
+            if (TH) {
+                const V4R ht = s_heat[j];
+                h0 += ht.x * gk;
+                h1 += ht.y * gk;
+                h2 += ht.z * gk;
+            }
+        }
+    }
+    absorbed = ab;
+    tmin = tm;
+    if (S == 1) {
+        e0 = ab;
+        e1 = e2 = R(0);
+        heat = h0;
+    } else {
+        e0 = kH * g0;
+        e1 = kHe1 * g1;
+        e2 = kHe2 * g2;
+        if (TH) {
+            if (F64) heat = (kH * h0 + kHe1 * h1) + kHe2 * h2;
+            else heat = __builtin_fmaf(kHe2, h2, __builtin_fmaf(kHe1, h1, kH * h0));
+        } else {
+            heat = R(0);
+        }
+    }
+}
+
+// Distance (half cells) from the start point o to the next face along one
+// axis, for a packet now in cell k: 1 for an axis the packet does not move
+// along; otherwise 2k + 2 - o (c > 0) or o - 2k (c < 0).
+__device__ __forceinline__ uint32_t next_face(int k, int32_t o, uint32_t a) {
+    if ((a & kMag) == 0u) return 1u;
+    return (a & kNeg) ? (uint32_t)(o - 2 * k) : (uint32_t)(2 * k + 2 - o);
+}
+
+__device__ __forceinline__ uint32_t pack_dir(int32_t c) {
+    return (uint32_t)abs(c) | (c < 0 ? kNeg : 0u);
+}
+
+__device__ __forceinline__ int32_t unpack_dir(uint32_t a) {
+    return (a & kNeg) ? -(int32_t)(a & kMag) : (int32_t)a;
+}
+
+}  // namespace rtk

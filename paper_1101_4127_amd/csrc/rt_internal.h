@@ -29,13 +29,15 @@ struct StepLedger {
     unsigned long long c[4];
     unsigned long long substeps;
     unsigned int nonfinite;
-    unsigned int pad;
+    unsigned int errors;         // an internal consistency check of the march failed
 };
 
 struct SourceRec {
     int32_t o[3];        // start point in half-cell units
-    int32_t octant;      // 1: directions folded into the + octant, 1/8 of L
+    uint32_t flags;      // kSrcOctant | (bins with SED > 0) << kSrcMaskShift
 };
+constexpr uint32_t kSrcOctant = 1u;       // directions folded into the + octant, 1/8 of L
+constexpr int kSrcMaskShift = 8;
 
 // Everything one march launch needs (host side, type erased).
 struct MarchLaunch {
@@ -87,6 +89,48 @@ struct CellLaunch {
 };
 
 hipError_t launch_march(const MarchLaunch &m);
+
+// ---------------------------------------------------------------------------
+// Tiled march: the grid is cut into tiles of 8^3 cells (the bricks of the
+// layout); packets are propagated pass by pass, each pass carrying every live
+// packet through one tile, with the deposits of a tile gathered in LDS.
+// ---------------------------------------------------------------------------
+constexpr int kTileLog2 = 3;
+constexpr int kTileCells = 1 << (3 * kTileLog2);
+constexpr int kCodes = 27;                // neighbour tiles a packet can move to (and itself)
+constexpr uint32_t kSideDead = 0xffffffffu;
+
+struct TChunk {          // a run of one tile's list of packets, marched by one block
+    uint32_t tile, start, len, shared;    // shared: the tile has more than one run this pass
+};
+
+struct TCtrl {
+    uint32_t n_chunks[2];   // runs in chunk table 0 / 1
+    uint32_t total[2];      // packets in list 0 / 1
+    uint32_t claim;         // next run of the current pass
+    uint32_t err;           // a bounds check failed
+    uint32_t pad[2];
+};
+
+struct TiledLaunch {
+    MarchLaunch m;          // physics, sources, accumulators, ledger slots, trace
+    uint32_t g0, nbatch;    // packet ids [g0, g0 + nbatch) of the sub-step
+    uint32_t capacity;      // packets in flight (records)
+    uint32_t cmax;          // packets per run
+    uint32_t max_chunks;
+    uint32_t n_tiles, scan_blocks, passes;
+    void *rec;
+    uint32_t *idx[2], *side, *cnt, *off, *cbase, *bsum;
+    TChunk *chunks[2];
+    TCtrl *ctrl;
+    StepLedger *ledger;
+};
+
+size_t tiled_record_bytes(int fp64, int species, int mb);
+hipError_t launch_tiled_reset(const TiledLaunch &t);
+hipError_t launch_tiled_slots_zero(const TiledLaunch &t);
+hipError_t launch_tiled_batch(const TiledLaunch &t);
+hipError_t tiled_occupancy(int species, int thermal, int fp64, int mb, int *blocks_per_cu);
 hipError_t march_occupancy(int species, int thermal, int fp64, int mb, int *blocks_per_cu);
 
 hipError_t launch_prep(const CellLaunch &c);

@@ -14,6 +14,7 @@
 #include <math.h>
 #include <type_traits>
 
+#include "rt_cross.h"
 #include "rt_device.h"
 #include "rt_internal.h"
 
@@ -45,10 +46,6 @@ struct MarchParams {
     uint32_t refill_min;
 };
 
-template <typename R> struct Vec4;
-template <> struct Vec4<float> { using T = float4; };
-template <> struct Vec4<double> { using T = double4; };
-
 __device__ __forceinline__ uint32_t uniform(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
@@ -77,8 +74,6 @@ template <typename R, int MB> struct MarchOcc { static constexpr int value = 2; 
 template <> struct MarchOcc<float, 1> { static constexpr int value = 4; };
 template <> struct MarchOcc<float, 8> { static constexpr int value = 3; };
 
-constexpr uint32_t kNeg = 0x80000000u;      // sign flag packed above |c| (|c| <= 2^20)
-constexpr uint32_t kMag = 0x00ffffffu;
 constexpr int kWaves = kMarchBlock / 64;
 
 template <typename R, int S, bool TH, int MB>
@@ -121,9 +116,13 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
     uint32_t slot = 0, count = 0, srcid = 0;
     int32_t tix = -1;                           // trace record of this packet, -1 if untraced
     KV kap{};                                   // absorbers of the current cell
-    R F[MB], T[MB];
+    constexpr int ND = DepthState<R, S, MB>::N;
+    R F[MB], D[ND];
+    uint32_t active = 0;                        // bins the packet's source populates
 #pragma unroll
-    for (int j = 0; j < MB; ++j) { F[j] = R(0); T[j] = R(0); }
+    for (int j = 0; j < MB; ++j) F[j] = R(0);
+#pragma unroll
+    for (int j = 0; j < ND; ++j) D[j] = R(0);
 
     // ---- ledger partials: updated only where every lane of the wave is active ----
     double l_emit = 0.0, l_abs = 0.0, l_esc = 0.0, l_trunc = 0.0;
@@ -162,7 +161,7 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
                         const uint32_t big = p.r * (p.q + 1u);
                         if (id < big) { sidx = id / (p.q + 1u); ns = p.q + 1u; }
                         else { sidx = p.r + (id - big) / p.q; ns = p.q; }
-                        const int32_t oct = p.src[sidx].octant;
+                        const int32_t oct = (int32_t)(p.src[sidx].flags & kSrcOctant);
                         double ww = p.src_ndot[sidx] * p.dt;
                         ww = ww / (double)ns;
                         if (oct) ww = ww * 0.125;
@@ -199,19 +198,20 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
                     const SourceRec sr = p.src[srcid];
                     if (F64) L = Ld; else Lf = (float)(Ld * p.len_scale);
                     k0 = sr.o[0] >> 1; k1 = sr.o[1] >> 1; k2 = sr.o[2] >> 1;
-                    a0 = (uint32_t)abs(c0) | (c0 < 0 ? kNeg : 0u);
-                    a1 = (uint32_t)abs(c1) | (c1 < 0 ? kNeg : 0u);
-                    a2 = (uint32_t)abs(c2) | (c2 < 0 ? kNeg : 0u);
+                    a0 = pack_dir(c0);
+                    a1 = pack_dir(c1);
+                    a2 = pack_dir(c2);
                     // distance to the first face: 1 from a cell centre, 2 from a corner
-                    d0 = (c0 > 0) ? (uint32_t)(2 * k0 + 2 - sr.o[0]) : (c0 < 0 ? (uint32_t)(sr.o[0] - 2 * k0) : 1u);
-                    d1 = (c1 > 0) ? (uint32_t)(2 * k1 + 2 - sr.o[1]) : (c1 < 0 ? (uint32_t)(sr.o[1] - 2 * k1) : 1u);
-                    d2 = (c2 > 0) ? (uint32_t)(2 * k2 + 2 - sr.o[2]) : (c2 < 0 ? (uint32_t)(sr.o[2] - 2 * k2) : 1u);
+                    d0 = next_face(k0, sr.o[0], a0);
+                    d1 = next_face(k1, sr.o[1], a1);
+                    d2 = next_face(k2, sr.o[2], a2);
+                    active = sr.flags >> kSrcMaskShift;
                     const R *sed = sedtab + (size_t)srcid * MB;
 #pragma unroll
-                    for (int j = 0; j < MB; ++j) {
-                        F[j] = sed[j];
-                        T[j] = F[j] > R(0) ? R(0) : R(INFINITY);
-                    }
+                    for (int j = 0; j < MB; ++j) F[j] = sed[j];
+#pragma unroll
+                    for (int j = 0; j < ND; ++j)
+                        D[j] = (!DepthState<R, S, MB>::F64 || ((active >> j) & 1u)) ? R(0) : R(INFINITY);
                     sprev = 0.0; pnum = 0; pden = 1;
                     absd = 0.0;
                     count = 0;
@@ -235,15 +235,10 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
         uint32_t it_cross = 0, it_fate = 0;
         if (alive) {
             // ---- geometry: nearest face by exact integer comparison ----
-            const uint32_t m0a = a0 & kMag, m1a = a1 & kMag, m2a = a2 & kMag;
-            const uint32_t p01 = __umul24(d0, m1a), p10 = __umul24(d1, m0a);
-            const uint32_t p02 = __umul24(d0, m2a), p20 = __umul24(d2, m0a);
-            const uint32_t p12 = __umul24(d1, m2a), p21 = __umul24(d2, m1a);
-            const bool m0 = m0a != 0u && p01 <= p10 && p02 <= p20;
-            const bool m1 = m1a != 0u && p10 <= p01 && p12 <= p21;
-            const bool m2 = m2a != 0u && p20 <= p02 && p21 <= p12;
-            const uint32_t num = m0 ? d0 : (m1 ? d1 : d2);
-            const uint32_t den = m0 ? m0a : (m1 ? m1a : m2a);
+            bool m0, m1, m2;
+            const int ax = exit_face(d0, d1, d2, a0, a1, a2, m0, m1, m2);
+            const uint32_t num = ax == 0 ? d0 : (ax == 1 ? d1 : d2);
+            const uint32_t den = (ax == 0 ? a0 : (ax == 1 ? a1 : a2)) & kMag;
             R l;
             double snew = 0.0;
             if (F64) {
@@ -274,48 +269,8 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
             // (the tables are re-read from LDS at every crossing rather than
             // held in registers across the loop)
             asm volatile("" ::: "memory");
-            R kH, kHe1 = R(0), kHe2 = R(0);
-            if constexpr (S == 1) kH = kap;
-            else { kH = kap.x; kHe1 = kap.y; kHe2 = kap.z; }
-            R absorbed = R(0), g0 = R(0), g1 = R(0), g2 = R(0), h0 = R(0), h1 = R(0), h2 = R(0);
-#pragma unroll
-            for (int j = 0; j < MB; ++j) {
-                const V4R sg = s_sig[j];
-                R K;
-                if (S == 1) K = kH * sg.x;
-                else if (F64) K = (kH * sg.x + kHe1 * sg.y) + kHe2 * sg.z;
-                else K = __builtin_fmaf(kHe2, sg.z, __builtin_fmaf(kHe1, sg.y, kH * sg.x));
-                const R tau = l * K;
-                R d;
-                if constexpr (F64) {
-                    // float64 form: transmitted = previous - absorbed, as the oracle defines it
-                    d = F[j] * -expm1(-tau);
-                    F[j] = F[j] - d;
-                } else {
-                    float em, tr;
-                    attenuation(tau, em, tr);
-                    d = F[j] * em;
-                    F[j] = F[j] * tr;
-                }
-                T[j] = T[j] + tau;
-                absorbed += d;
-                if (S == 1) {
-                    if (TH) h0 += d * s_heat[j].x;
-                } else {
-                    R gk;
-                    if (F64) gk = K > R(0) ? d / K : R(0);
-                    else gk = K > R(0) ? d * __builtin_amdgcn_rcpf(K) : R(0);
-                    g0 += sg.x * gk;
-                    g1 += sg.y * gk;
-                    g2 += sg.z * gk;
-                    if (TH) {
-                        const V4R ht = s_heat[j];
-                        h0 += ht.x * gk;
-                        h1 += ht.y * gk;
-                        h2 += ht.z * gk;
-                    }
-                }
-            }
+            R absorbed, e0, e1, e2, hs, tmin;
+            cross_cell<R, S, TH, MB>(l, kap, s_sig, s_heat, active, F, D, absorbed, e0, e1, e2, hs, tmin);
 
             // ---- deposit: float64 accumulators, hardware atomics at L2 ----
             double *cell = p.acc + (size_t)slot * ACC;
@@ -323,20 +278,17 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
                 const double v = w * (double)absorbed;
                 if (v != 0.0) unsafeAtomicAdd(cell, v);
                 if (TH) {
-                    const double q = w * ((double)h0 * kEvErg);
+                    const double q = w * ((double)hs * kEvErg);
                     if (q != 0.0) unsafeAtomicAdd(cell + 1, q);
                 }
             } else {
-                const double v0 = w * (double)(kH * g0);
-                const double v1 = w * (double)(kHe1 * g1);
-                const double v2 = w * (double)(kHe2 * g2);
+                const double v0 = w * (double)e0;
+                const double v1 = w * (double)e1;
+                const double v2 = w * (double)e2;
                 if (v0 != 0.0) unsafeAtomicAdd(cell, v0);
                 if (v1 != 0.0) unsafeAtomicAdd(cell + 1, v1);
                 if (v2 != 0.0) unsafeAtomicAdd(cell + 2, v2);
                 if (TH) {
-                    R hs;
-                    if (F64) hs = (kH * h0 + kHe1 * h1) + kHe2 * h2;
-                    else hs = __builtin_fmaf(kHe2, h2, __builtin_fmaf(kHe1, h1, kH * h0));
                     const double q = w * ((double)hs * kEvErg);
                     if (q != 0.0) unsafeAtomicAdd(cell + 3, q);
                 }
@@ -349,9 +301,6 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
             ++count;
 
             // ---- termination: extinguished (checked first) or out of the grid ----
-            R tmin = T[0];
-#pragma unroll
-            for (int j = 1; j < MB; ++j) tmin = T[j] < tmin ? T[j] : tmin;
             const uint32_t fate = (tmin >= (R)p.tau_kill) ? 1u : (out ? 2u : 0u);
             if (fate == 0) {
                 slot = nslot;
@@ -369,9 +318,9 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
                         : ((o0 ? 1 : 0) | (o1 ? 2 : 0) | (o2 ? 4 : 0)
                            | (k0 >= p.geo.n[0] ? 8 : 0) | (k1 >= p.geo.n[1] ? 16 : 0) | (k2 >= p.geo.n[2] ? 32 : 0));
                     rec[0] = (int32_t)count; rec[1] = (int32_t)fate; rec[2] = face; rec[3] = here;
-                    rec[4] = (a0 & kNeg) ? -(int32_t)(a0 & kMag) : (int32_t)a0;
-                    rec[5] = (a1 & kNeg) ? -(int32_t)(a1 & kMag) : (int32_t)a1;
-                    rec[6] = (a2 & kNeg) ? -(int32_t)(a2 & kMag) : (int32_t)a2;
+                    rec[4] = unpack_dir(a0);
+                    rec[5] = unpack_dir(a1);
+                    rec[6] = unpack_dir(a2);
                     rec[7] = (int32_t)srcid;
                 }
                 alive = false;

@@ -1,0 +1,888 @@
+// rt_tiled.hip -- the packet march organised by tiles of the grid.
+//
+// The physics per crossing is that of the per-packet march (rt_cross.h); what
+// changes is the order in which (packet, cell) pairs are visited.  Deposits of
+// many packets land in the same cells, and float64 atomics at L2 sustain only
+// ~2e10 updates/s on the whole chip, far below the crossing rate the march can
+// reach.  So the grid is cut into tiles of 8^3 cells (the bricks of the field
+// layout, contiguous in memory), and the propagation runs in passes:
+//
+//   emission   every packet of the batch is drawn (Philox direction, SED,
+//              weight) into a record of fixed size, and its source's tile
+//              counts it;
+//   pass       each block claims a run of one tile's packet list, stages the
+//              tile's absorbers in LDS, marches every packet of the run until
+//              it leaves the tile, dies or escapes, adding its deposits to
+//              float64 accumulators in LDS, then adds the tile's accumulators
+//              to the grid's once (plain read-add-write when the run is the
+//              tile's only one this pass, coalesced atomics otherwise).  A
+//              packet that moves on is written back to its record and ranked
+//              among the packets of its run bound for the same neighbour;
+//   sort       the per-tile counts of the next pass are scanned into list
+//              offsets and runs, and the record ids are scattered into the
+//              next pass's lists.
+//
+// The grid's partition into tiles is the GPU counterpart of the domain
+// decomposition of Sec. 3.2: a tile plays the part of a subdomain and the
+// hand-over of packets between passes that of the exchange between tasks.  A
+// ray's tile index changes monotonically along every axis, so a packet
+// visits at most tx + ty + tz - 2 tiles and that many passes empty every list.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <type_traits>
+
+#include "rt_cross.h"
+#include "rt_device.h"
+#include "rt_internal.h"
+
+namespace rtk {
+
+namespace {
+
+constexpr double kEvErg = 1.602176634e-12;
+constexpr int kTBlock = 256;              // threads of the emission, march and scatter blocks
+constexpr int kTWaves = kTBlock / 64;
+constexpr int kScanBlock = 1024;
+constexpr int kScanPer = 4;               // tiles per scan thread
+constexpr int kScanTiles = kScanBlock * kScanPer;
+
+struct TParams {
+    GridGeom geo;
+    double half_dl, len_scale;
+    const SourceRec *src;
+    const double *src_ndot, *src_sedsum;
+    const void *sed, *tab;
+    uint32_t q, r;                        // packets per source: q (+1 for the first r)
+    uint32_t n_src;
+    double dt;
+    uint64_t seed, solve_id, step;
+    double tau_kill;
+    const void *kappa;
+    double *acc;
+    LedgerSlot *slots;
+    int32_t *trace;
+    int32_t trace_n, trace_len;
+    uint32_t trace_stride;
+    uint32_t refill_min;
+    uint32_t g0, nbatch, capacity, cmax, max_chunks, n_tiles;
+    void *rec;
+    uint32_t *idx0, *idx1, *side, *cnt, *off, *cbase, *bsum;
+    TChunk *ch0, *ch1;
+    TCtrl *ctrl;
+    StepLedger *ledger;
+};
+
+// Record of a packet between passes (16-byte units).  Words: c[3] (integer
+// direction), the cell it is in or about to enter with the axis of the last
+// face it crossed (3: none yet), its source; then the depth state and the
+// photons per bin (float32 form: column densities, then F; float64 form: a
+// pad word, F, then T).
+template <typename R, int S, int MB>
+struct TRec {
+    static constexpr bool F64 = std::is_same<R, double>::value;
+    static constexpr int ND = DepthState<R, S, MB>::N;
+    static constexpr int BYTES = F64 ? 24 + 8 * (MB + ND) : 4 * (5 + ND + MB);
+    static constexpr int UNITS = (BYTES + 15) / 16;
+    static constexpr int WORDS = 4 * UNITS;
+};
+
+__device__ __forceinline__ uint32_t pack_cell(int k0, int k1, int k2, uint32_t axis) {
+    return (uint32_t)k0 | ((uint32_t)k1 << 10) | ((uint32_t)k2 << 20) | (axis << 30);
+}
+
+// Source of packet g under the equal share: the first r sources get q + 1.
+__device__ __forceinline__ uint32_t source_of(uint32_t g, uint32_t q, uint32_t r, uint32_t &ns) {
+    const uint32_t big = r * (q + 1u);
+    if (g < big) { ns = q + 1u; return g / (q + 1u); }
+    ns = q;
+    return r + (g - big) / q;
+}
+
+__device__ __forceinline__ double packet_weight(const TParams &p, uint32_t sidx, uint32_t ns, bool oct) {
+    double ww = p.src_ndot[sidx] * p.dt;
+    ww = ww / (double)ns;
+    if (oct) ww = ww * 0.125;
+    return ww;
+}
+
+__device__ __forceinline__ int32_t trace_slot(const TParams &p, uint32_t g) {
+    if (p.trace_n <= 0) return -1;
+    return (g % p.trace_stride == 0u && g / p.trace_stride < (uint32_t)p.trace_n) ? (int32_t)(g / p.trace_stride)
+                                                                                 : -1;
+}
+
+__device__ __forceinline__ uint32_t tile_of_cell(const GridGeom &G, int k0, int k1, int k2) {
+    return ((uint32_t)(k2 >> kTileLog2) * (uint32_t)G.nb[1] + (uint32_t)(k1 >> kTileLog2)) * (uint32_t)G.nb[0]
+         + (uint32_t)(k0 >> kTileLog2);
+}
+
+__device__ __forceinline__ uint32_t local_cell(int k0, int k1, int k2) {
+    return spread3((uint32_t)k0 & 7u) | (spread3((uint32_t)k1 & 7u) << 1) | (spread3((uint32_t)k2 & 7u) << 2);
+}
+
+// neighbour code (dx+1) + 3 (dy+1) + 9 (dz+1) -> tile id offset
+__device__ __forceinline__ int64_t code_offset(const GridGeom &G, uint32_t code) {
+    const int dx = (int)(code % 3u) - 1, dy = (int)((code / 3u) % 3u) - 1, dz = (int)(code / 9u) - 1;
+    return (int64_t)dx + (int64_t)G.nb[0] * ((int64_t)dy + (int64_t)G.nb[1] * (int64_t)dz);
+}
+
+__device__ __forceinline__ void wave_sum_pair(double &s, double &c) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double so = __shfl_xor(s, off), co = __shfl_xor(c, off);
+        double t, e;
+        two_sum(s, so, t, e);
+        s = t;
+        c = c + co + e;
+    }
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Add per-lane ledger partials (value, compensation pairs and counters) of the
+// whole block to the block's own slot (no other block writes it).
+__device__ void block_ledger_add(LedgerSlot *slot, double (&v)[8], unsigned long long (&c)[4]) {
+    __shared__ double sh_s[kTWaves][8];
+    __shared__ unsigned long long sh_c[kTWaves][4];
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) wave_sum_pair(v[2 * i], v[2 * i + 1]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) c[i] = wave_sum_u64(c[i]);
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) sh_s[wv][i] = v[i];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sh_c[wv][i] = c[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        LedgerSlot o = *slot;
+        for (int i = 0; i < 4; ++i) {
+            double s = o.s[2 * i], cc = o.s[2 * i + 1];
+            for (int u = 0; u < kTWaves; ++u) {
+                double t, e;
+                two_sum(s, sh_s[u][2 * i], t, e);
+                s = t;
+                cc += sh_s[u][2 * i + 1] + e;
+            }
+            o.s[2 * i] = s;
+            o.s[2 * i + 1] = cc;
+        }
+        for (int i = 0; i < 4; ++i)
+            for (int u = 0; u < kTWaves; ++u) o.c[i] += sh_c[u][i];
+        *slot = o;
+    }
+}
+
+template <typename R, int S, int MB>
+__device__ __forceinline__ void store_record(uint4 *dst, int32_t c0, int32_t c1, int32_t c2, uint32_t kw,
+                                             uint32_t srcid, const R (&F)[MB],
+                                             const R (&D)[DepthState<R, S, MB>::N]) {
+    using RL = TRec<R, S, MB>;
+    uint32_t w[RL::WORDS];
+#pragma unroll
+    for (int i = 0; i < RL::WORDS; ++i) w[i] = 0u;
+    w[0] = (uint32_t)c0; w[1] = (uint32_t)c1; w[2] = (uint32_t)c2; w[3] = kw; w[4] = srcid;
+    if constexpr (RL::F64) {
+#pragma unroll
+        for (int j = 0; j < MB; ++j) {
+            w[6 + 2 * j] = (uint32_t)__double2loint(F[j]);
+            w[7 + 2 * j] = (uint32_t)__double2hiint(F[j]);
+            w[6 + 2 * MB + 2 * j] = (uint32_t)__double2loint(D[j]);
+            w[7 + 2 * MB + 2 * j] = (uint32_t)__double2hiint(D[j]);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < RL::ND; ++j) w[5 + j] = __float_as_uint(D[j]);
+#pragma unroll
+        for (int j = 0; j < MB; ++j) w[5 + RL::ND + j] = __float_as_uint(F[j]);
+    }
+#pragma unroll
+    for (int u = 0; u < RL::UNITS; ++u) dst[u] = make_uint4(w[4 * u], w[4 * u + 1], w[4 * u + 2], w[4 * u + 3]);
+}
+
+// ---------------------------------------------------------------------------
+// Emission of one batch: source share, weight, direction, SED; the packet is
+// counted in its source's tile (wavefront-aggregated atomics) and its rank in
+// that tile's list kept for the scatter.
+// ---------------------------------------------------------------------------
+template <typename R, int S, bool TH, int MB>
+__global__ void __launch_bounds__(kTBlock) k_temit(const TParams p) {
+    using RL = TRec<R, S, MB>;
+    constexpr int ND = RL::ND;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
+    const uint32_t gw = (blockIdx.x * kTBlock + threadIdx.x) >> 6;
+    const uint32_t nw = gridDim.x * kTWaves;
+    double l_emit = 0.0;
+    uint32_t n_pk = 0;
+    const R *sedtab = reinterpret_cast<const R *>(p.sed);
+    uint4 *recs = reinterpret_cast<uint4 *>(p.rec);
+    for (uint32_t base = gw * 64u; base < p.nbatch; base += nw * 64u) {
+        const uint32_t i = base + lane;
+        const bool act = i < p.nbatch;
+        uint32_t tile = 0;
+        if (act) {
+            const uint32_t g = p.g0 + i;
+            uint32_t ns;
+            const uint32_t sidx = source_of(g, p.q, p.r, ns);
+            const SourceRec sr = p.src[sidx];
+            const bool oct = (sr.flags & kSrcOctant) != 0u;
+            const double ww = packet_weight(p, sidx, ns, oct);
+            l_emit += ww * p.src_sedsum[sidx];
+            n_pk += 1u;
+            int32_t c[3];
+            sample_direction(p.seed, p.solve_id, g, p.step, oct, c);
+            const int k0 = sr.o[0] >> 1, k1 = sr.o[1] >> 1, k2 = sr.o[2] >> 1;
+            const uint32_t active = sr.flags >> kSrcMaskShift;
+            R F[MB], D[ND];
+            const R *sed = sedtab + (size_t)sidx * MB;
+#pragma unroll
+            for (int j = 0; j < MB; ++j) F[j] = sed[j];
+#pragma unroll
+            for (int j = 0; j < ND; ++j) D[j] = (!RL::F64 || ((active >> j) & 1u)) ? R(0) : R(INFINITY);
+            store_record<R, S, MB>(recs + (size_t)i * RL::UNITS, c[0], c[1], c[2], pack_cell(k0, k1, k2, 3u), sidx,
+                                   F, D);
+            tile = tile_of_cell(p.geo, k0, k1, k2);
+            const int32_t tix = trace_slot(p, g);
+            if (tix >= 0) p.trace[(size_t)tix * (RT_TRACE_HDR_DEV + p.trace_len)] = 0;
+        }
+        // rank in the tile's list: one atomic per distinct tile of the wavefront
+        uint64_t pend = __ballot(act);
+        uint32_t rel = 0;
+        while (pend != 0ull) {
+            const int lead = __ffsll((unsigned long long)pend) - 1;
+            const uint32_t lt = (uint32_t)__shfl((int)tile, lead);
+            const uint64_t same = __ballot(act && tile == lt) & pend;
+            uint32_t b = 0;
+            if ((int)lane == lead) b = atomicAdd(p.cnt + lt, (uint32_t)__popcll(same));
+            b = (uint32_t)__shfl((int)b, lead);
+            if ((same >> lane) & 1ull) rel = b + (uint32_t)__popcll(same & lt_mask);
+            pend &= ~same;
+        }
+        if (act) p.side[i] = rel;
+    }
+    double v[8] = {l_emit, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    unsigned long long c[4] = {0ull, n_pk, 0ull, 0ull};
+    block_ledger_add(p.slots + blockIdx.x, v, c);
+}
+
+// List positions of the emitted packets: offset of the source's tile + rank.
+__global__ void __launch_bounds__(kTBlock) k_tscatter_emit(const TParams p) {
+    const uint32_t stride = gridDim.x * kTBlock;
+    for (uint32_t i = blockIdx.x * kTBlock + threadIdx.x; i < p.nbatch; i += stride) {
+        uint32_t ns;
+        const uint32_t sidx = source_of(p.g0 + i, p.q, p.r, ns);
+        const SourceRec sr = p.src[sidx];
+        const uint32_t tile = tile_of_cell(p.geo, sr.o[0] >> 1, sr.o[1] >> 1, sr.o[2] >> 1);
+        const uint32_t pos = p.off[tile] + p.side[i];
+        if (tile < p.n_tiles && pos < p.capacity) p.idx0[pos] = i;
+        else atomicOr(&p.ctrl->err, 1u);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Scan of the per-tile counts into list offsets and runs of at most cmax
+// packets (three launches: block sums, scan of the block sums, local scans).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void block_scan2(uint32_t &a, uint32_t &b, uint32_t &ta, uint32_t &tb) {
+    // exclusive scan of (a, b) over a block of kScanBlock threads; totals in (ta, tb)
+    __shared__ uint32_t sa[kScanBlock / 64], sb[kScanBlock / 64];
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    uint32_t ia = a, ib = b;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t ua = (uint32_t)__shfl_up((int)ia, d), ub = (uint32_t)__shfl_up((int)ib, d);
+        if (lane >= (uint32_t)d) { ia += ua; ib += ub; }
+    }
+    if (lane == 63u) { sa[wv] = ia; sb[wv] = ib; }
+    __syncthreads();
+    uint32_t pa = 0, pb = 0;
+    ta = 0; tb = 0;
+    for (uint32_t u = 0; u < kScanBlock / 64; ++u) {
+        if (u < wv) { pa += sa[u]; pb += sb[u]; }
+        ta += sa[u]; tb += sb[u];
+    }
+    __syncthreads();
+    a = pa + ia - a;
+    b = pb + ib - b;
+}
+
+__device__ __forceinline__ uint32_t runs_of(uint32_t n, uint32_t cmax) { return (n + cmax - 1u) / cmax; }
+
+__global__ void __launch_bounds__(kScanBlock) k_tscan_a(const TParams p) {
+    const uint32_t t0 = blockIdx.x * kScanTiles + threadIdx.x * kScanPer;
+    uint32_t a = 0, b = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        const uint32_t t = t0 + k;
+        const uint32_t n = t < p.n_tiles ? p.cnt[t] : 0u;
+        a += n;
+        b += runs_of(n, p.cmax);
+    }
+    uint32_t ta, tb;
+    block_scan2(a, b, ta, tb);
+    if (threadIdx.x == 0) {
+        p.bsum[2 * blockIdx.x] = ta;
+        p.bsum[2 * blockIdx.x + 1] = tb;
+    }
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_tscan_b(const TParams p, uint32_t nblk, int nxt) {
+    const uint32_t i = threadIdx.x;
+    uint32_t a = i < nblk ? p.bsum[2 * i] : 0u, b = i < nblk ? p.bsum[2 * i + 1] : 0u;
+    uint32_t ta, tb;
+    block_scan2(a, b, ta, tb);
+    if (i < nblk) {
+        p.bsum[2 * i] = a;
+        p.bsum[2 * i + 1] = b;
+    }
+    if (i == 0) {
+        const bool bad = ta > p.capacity || tb > p.max_chunks;
+        if (bad) p.ctrl->err |= 2u;
+        p.ctrl->total[nxt] = bad ? 0u : ta;
+        p.ctrl->n_chunks[nxt] = bad ? 0u : tb;
+        p.ctrl->claim = 0u;
+    }
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_tscan_c(const TParams p, int nxt) {
+    const uint32_t t0 = blockIdx.x * kScanTiles + threadIdx.x * kScanPer;
+    uint32_t n[kScanPer];
+    uint32_t a = 0, b = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        const uint32_t t = t0 + k;
+        n[k] = t < p.n_tiles ? p.cnt[t] : 0u;
+        a += n[k];
+        b += runs_of(n[k], p.cmax);
+    }
+    uint32_t ta, tb;
+    block_scan2(a, b, ta, tb);
+    a += p.bsum[2 * blockIdx.x];
+    b += p.bsum[2 * blockIdx.x + 1];
+    const uint32_t nch = p.ctrl->n_chunks[nxt];
+    TChunk *out = nxt ? p.ch1 : p.ch0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        const uint32_t t = t0 + k;
+        if (t >= p.n_tiles) break;
+        p.off[t] = a;
+        const uint32_t nr = runs_of(n[k], p.cmax);
+        for (uint32_t j = 0; j < nr; ++j) {
+            if (b + j >= nch) break;
+            TChunk c;
+            c.tile = t;
+            c.start = a + j * p.cmax;
+            c.len = min(p.cmax, n[k] - j * p.cmax);
+            c.shared = nr > 1u ? 1u : 0u;
+            out[b + j] = c;
+        }
+        a += n[k];
+        b += nr;
+        p.cnt[t] = 0u;
+    }
+}
+
+// Record ids of the packets that moved on, into the next pass's lists.
+__global__ void __launch_bounds__(kTBlock) k_tscatter(const TParams p, int cur) {
+    const uint32_t nch = p.ctrl->n_chunks[cur];
+    const TChunk *chs = cur ? p.ch1 : p.ch0;
+    const uint32_t *in = cur ? p.idx1 : p.idx0;
+    uint32_t *outl = cur ? p.idx0 : p.idx1;
+    for (uint32_t c = blockIdx.x; c < nch; c += gridDim.x) {
+        const TChunk ch = chs[c];
+        if (ch.start > p.capacity || ch.len > p.capacity - ch.start) continue;   // flagged by the march
+        for (uint32_t k = threadIdx.x; k < ch.len; k += kTBlock) {
+            const uint32_t pos = ch.start + k;
+            const uint32_t sd = p.side[pos];
+            if (sd == kSideDead) continue;
+            const uint32_t code = sd & 31u, rank = sd >> 5;
+            const int64_t y = (int64_t)ch.tile + code_offset(p.geo, code);
+            if (code >= (uint32_t)kCodes || y < 0 || y >= (int64_t)p.n_tiles) {
+                atomicOr(&p.ctrl->err, 4u);
+                continue;
+            }
+            const uint32_t dst = p.off[y] + p.cbase[(size_t)c * kCodes + code] + rank;
+            if (dst < p.capacity) outl[dst] = in[pos];
+            else atomicOr(&p.ctrl->err, 4u);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One pass of the march over the runs of every tile.
+// ---------------------------------------------------------------------------
+// Occupancy target (wavefronts per SIMD) the register allocation is held to.
+template <typename R, int MB> struct TOcc { static constexpr int value = 2; };
+template <> struct TOcc<float, 1> { static constexpr int value = 4; };
+template <> struct TOcc<float, 8> { static constexpr int value = 3; };
+
+template <typename R, int S, bool TH, int MB>
+__global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const TParams p, int cur) {
+    constexpr bool F64 = std::is_same<R, double>::value;
+    constexpr uint32_t ACC = (S == 1) ? (TH ? 2u : 1u) : 4u;
+    using KV = typename std::conditional<S == 1, R, typename Vec4<R>::T>::type;
+    using V4R = typename Vec4<R>::T;
+    using RL = TRec<R, S, MB>;
+    constexpr int ND = RL::ND;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
+
+    __shared__ V4R s_sig[MB];
+    __shared__ V4R s_heat[MB];
+    __shared__ KV s_kap[kTileCells];
+    __shared__ double s_acc[kTileCells * ACC];
+    __shared__ uint32_t s_cnt[kCodes];
+    __shared__ uint32_t s_next, s_claim;
+    if (threadIdx.x < MB) {
+        const R *t = reinterpret_cast<const R *>(p.tab);
+        const int j = threadIdx.x;
+        V4R a, b;
+        a.x = t[j]; a.y = t[MB + j]; a.z = t[2 * MB + j]; a.w = R(0);
+        b.x = t[3 * MB + j]; b.y = t[4 * MB + j]; b.z = t[5 * MB + j]; b.w = R(0);
+        s_sig[j] = a;
+        s_heat[j] = b;
+    }
+
+    const uint32_t nch = p.ctrl->n_chunks[cur];
+    const TChunk *chs = cur ? p.ch1 : p.ch0;
+    const uint32_t *list = cur ? p.idx1 : p.idx0;
+    uint4 *recs = reinterpret_cast<uint4 *>(p.rec);
+    const KV *kappa = reinterpret_cast<const KV *>(p.kappa);
+
+    double l_abs = 0.0, l_esc = 0.0, l_trunc = 0.0;
+    uint32_t n_cross = 0, n_esc = 0, n_trunc = 0;
+
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_claim = atomicAdd(&p.ctrl->claim, 1u);
+        __syncthreads();
+        const uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_claim);   // block-uniform
+        if (c >= nch) break;
+        const TChunk ch = chs[c];
+        if (ch.tile >= p.n_tiles || ch.start > p.capacity || ch.len > p.capacity - ch.start) {
+            if (threadIdx.x == 0) atomicOr(&p.ctrl->err, 8u);
+            continue;
+        }
+        const uint32_t tile = ch.tile;
+        const int tx = (int)(tile % (uint32_t)p.geo.nb[0]);
+        const int ty = (int)((tile / (uint32_t)p.geo.nb[0]) % (uint32_t)p.geo.nb[1]);
+        const int tz = (int)(tile / ((uint32_t)p.geo.nb[0] * (uint32_t)p.geo.nb[1]));
+
+        // stage the tile's absorbers, clear its accumulators
+        const KV *kt = kappa + ((size_t)tile << (3 * kTileLog2));
+        for (int i = threadIdx.x; i < kTileCells; i += kTBlock) s_kap[i] = kt[i];
+        for (int i = threadIdx.x; i < kTileCells * (int)ACC; i += kTBlock) s_acc[i] = 0.0;
+        if (threadIdx.x < kCodes) s_cnt[threadIdx.x] = 0u;
+        if (threadIdx.x == 0) s_next = 0u;
+        __syncthreads();
+
+        // ---- packet state (one per lane) ----
+        bool alive = false;
+        bool exhausted = false;                  // wave-uniform
+        uint32_t pos = 0, rid = 0;               // list position and record of the lane's packet
+        int k0 = 0, k1 = 0, k2 = 0;
+        uint32_t d0 = 1, d1 = 1, d2 = 1, a0 = 0, a1 = 0, a2 = 0, pnum = 0, pden = 1;
+        double sprev = 0.0, L = 0.0, w = 0.0, absd = 0.0;
+        float Lf = 0.0f;
+        uint32_t loc = 0, srcid = 0, count = 0, active = 0;
+        int32_t tix = -1;
+        KV kap{};
+        R F[MB], D[ND];
+#pragma unroll
+        for (int j = 0; j < MB; ++j) F[j] = R(0);
+#pragma unroll
+        for (int j = 0; j < ND; ++j) D[j] = R(0);
+
+        for (;;) {
+            const uint64_t dead = __ballot(!alive);
+            const uint32_t ndead = (uint32_t)__popcll(dead);
+            if (!exhausted && ndead != 0u && (ndead >= p.refill_min || ndead == 64u)) {
+                uint32_t b0 = 0;
+                if (lane == 0) b0 = atomicAdd(&s_next, ndead);
+                b0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)b0);
+                if (b0 >= ch.len) {
+                    exhausted = true;
+                } else {
+                    const uint32_t got = min(ndead, ch.len - b0);
+                    const uint32_t rank = (uint32_t)__popcll(dead & lt_mask);
+                    if (!alive && rank < got) {
+                        pos = ch.start + b0 + rank;
+                        const uint32_t ri = list[pos];
+                        if (ri >= p.capacity) {
+                            atomicOr(&p.ctrl->err, 16u);
+                            p.side[pos] = kSideDead;
+                        } else {
+                            rid = ri;
+                            const uint4 *rp = recs + (size_t)ri * RL::UNITS;
+                            uint32_t wd[RL::WORDS];
+#pragma unroll
+                            for (int u = 0; u < RL::UNITS; ++u) {
+                                const uint4 v = rp[u];
+                                wd[4 * u] = v.x; wd[4 * u + 1] = v.y; wd[4 * u + 2] = v.z; wd[4 * u + 3] = v.w;
+                            }
+                            const int32_t c0 = (int32_t)wd[0], c1 = (int32_t)wd[1], c2 = (int32_t)wd[2];
+                            const uint32_t kw = wd[3];
+                            srcid = wd[4];
+                            if constexpr (F64) {
+#pragma unroll
+                                for (int j = 0; j < MB; ++j) {
+                                    F[j] = __hiloint2double((int)wd[7 + 2 * j], (int)wd[6 + 2 * j]);
+                                    D[j] = __hiloint2double((int)wd[7 + 2 * MB + 2 * j], (int)wd[6 + 2 * MB + 2 * j]);
+                                }
+                            } else {
+#pragma unroll
+                                for (int j = 0; j < ND; ++j) D[j] = __uint_as_float(wd[5 + j]);
+#pragma unroll
+                                for (int j = 0; j < MB; ++j) F[j] = __uint_as_float(wd[5 + ND + j]);
+                            }
+                            k0 = (int)(kw & 1023u);
+                            k1 = (int)((kw >> 10) & 1023u);
+                            k2 = (int)((kw >> 20) & 1023u);
+                            const uint32_t ax = kw >> 30;
+                            // a record that is not a packet of this tile is an internal error
+                            const bool bad = srcid >= p.n_src || k0 >= p.geo.n[0] || k1 >= p.geo.n[1]
+                                || k2 >= p.geo.n[2] || (k0 >> kTileLog2) != tx || (k1 >> kTileLog2) != ty
+                                || (k2 >> kTileLog2) != tz || ((uint32_t)(c0 | c1 | c2) == 0u);
+                            if (bad) {
+                                atomicOr(&p.ctrl->err, 16u);
+                                p.side[pos] = kSideDead;
+                            } else {
+                                const SourceRec sr = p.src[srcid];
+                                a0 = pack_dir(c0);
+                                a1 = pack_dir(c1);
+                                a2 = pack_dir(c2);
+                                d0 = next_face(k0, sr.o[0], a0);
+                                d1 = next_face(k1, sr.o[1], a1);
+                                d2 = next_face(k2, sr.o[2], a2);
+                                // entry parameter of this cell: the last face crossed
+                                if (ax == 3u) { pnum = 0u; pden = 1u; }
+                                else {
+                                    pnum = (ax == 0u ? d0 : (ax == 1u ? d1 : d2)) - 2u;
+                                    pden = (ax == 0u ? a0 : (ax == 1u ? a1 : a2)) & kMag;
+                                }
+                                sprev = (ax == 3u) ? 0.0 : (double)pnum / (double)pden;
+                                const int64_t qq = (int64_t)c0 * c0 + (int64_t)c1 * c1 + (int64_t)c2 * c2;
+                                const double Ld = sqrt((double)qq) * p.half_dl;
+                                if (F64) L = Ld; else Lf = (float)(Ld * p.len_scale);
+                                const uint32_t ns = srcid < p.r ? p.q + 1u : p.q;
+                                const uint32_t g = p.g0 + ri;
+                                w = packet_weight(p, srcid, ns, (sr.flags & kSrcOctant) != 0u);
+                                active = sr.flags >> kSrcMaskShift;
+                                tix = trace_slot(p, g);
+                                count = tix >= 0 ? (uint32_t)p.trace[(size_t)tix * (RT_TRACE_HDR_DEV + p.trace_len)] : 0u;
+                                absd = 0.0;
+                                loc = local_cell(k0, k1, k2);
+                                kap = s_kap[loc];
+                                alive = true;
+                            }
+                        }
+                    }
+                }
+            }
+            if (__ballot(alive) == 0ull) {
+                if (exhausted) break;
+                continue;
+            }
+
+            double it_abs = 0.0, it_left = 0.0;
+            uint32_t it_cross = 0, it_fate = 0;
+            if (alive) {
+                bool m0, m1, m2;
+                const int ax = exit_face(d0, d1, d2, a0, a1, a2, m0, m1, m2);
+                const uint32_t num = ax == 0 ? d0 : (ax == 1 ? d1 : d2);
+                const uint32_t den = (ax == 0 ? a0 : (ax == 1 ? a1 : a2)) & kMag;
+                R l;
+                double snew = 0.0;
+                if (F64) {
+                    snew = (double)num / (double)den;
+                    l = (snew - sprev) * L;
+                } else {
+                    const uint32_t diff = num * pden - pnum * den;
+                    l = Lf * (float)diff * __builtin_amdgcn_rcpf((float)den * (float)pden);
+                }
+                const int here = k0 + p.geo.n[0] * (k1 + p.geo.n[1] * k2);
+                if (m0) { k0 += (a0 & kNeg) ? -1 : 1; d0 += 2u; }
+                if (m1) { k1 += (a1 & kNeg) ? -1 : 1; d1 += 2u; }
+                if (m2) { k2 += (a2 & kNeg) ? -1 : 1; d2 += 2u; }
+                const bool o0 = (uint32_t)k0 >= (uint32_t)p.geo.n[0];
+                const bool o1 = (uint32_t)k1 >= (uint32_t)p.geo.n[1];
+                const bool o2 = (uint32_t)k2 >= (uint32_t)p.geo.n[2];
+                const bool out = o0 | o1 | o2;
+                const int dx = (k0 >> kTileLog2) - tx, dy = (k1 >> kTileLog2) - ty, dz = (k2 >> kTileLog2) - tz;
+                const bool leave = !out && (dx | dy | dz) != 0;
+                uint32_t nloc = loc;
+                KV knext = kap;
+                if (!out && !leave) {
+                    nloc = local_cell(k0, k1, k2);
+                    knext = s_kap[nloc];
+                }
+
+                // (the tables are re-read from LDS at every crossing rather than
+                // held in registers across the loop)
+                asm volatile("" ::: "memory");
+                R absorbed, e0, e1, e2, hs, tmin;
+                cross_cell<R, S, TH, MB>(l, kap, s_sig, s_heat, active, F, D, absorbed, e0, e1, e2, hs, tmin);
+
+                // ---- deposit into the tile's float64 accumulators in LDS ----
+                double *cell = s_acc + loc * ACC;
+                if (S == 1) {
+                    const double v = w * (double)absorbed;
+                    if (v != 0.0) atomicAdd(cell, v);
+                    if (TH) {
+                        const double q = w * ((double)hs * kEvErg);
+                        if (q != 0.0) atomicAdd(cell + 1, q);
+                    }
+                } else {
+                    const double v0 = w * (double)e0;
+                    const double v1 = w * (double)e1;
+                    const double v2 = w * (double)e2;
+                    if (v0 != 0.0) atomicAdd(cell, v0);
+                    if (v1 != 0.0) atomicAdd(cell + 1, v1);
+                    if (v2 != 0.0) atomicAdd(cell + 2, v2);
+                    if (TH) {
+                        const double q = w * ((double)hs * kEvErg);
+                        if (q != 0.0) atomicAdd(cell + 3, q);
+                    }
+                }
+                absd += (double)absorbed;
+                it_cross = 1;
+                const bool traced = tix >= 0;
+                int32_t *rec = p.trace + (size_t)(traced ? tix : 0) * (RT_TRACE_HDR_DEV + p.trace_len);
+                if (traced && count < (uint32_t)p.trace_len) rec[RT_TRACE_HDR_DEV + count] = here;
+                ++count;
+
+                    const uint32_t fate = (tmin >= (R)p.tau_kill) ? 1u : (out ? 2u : (leave ? 3u : 0u));
+                if (fate == 0u) {
+                    loc = nloc;
+                    kap = knext;
+                    if (F64) sprev = snew; else { pnum = num; pden = den; }
+                } else {
+                    it_abs = w * absd;
+                    if (fate == 3u) {
+                        // moves on into a neighbour tile: record back, rank among the run's
+                        // packets bound for the same tile
+                        store_record<R, S, MB>(recs + (size_t)rid * RL::UNITS, unpack_dir(a0), unpack_dir(a1),
+                                               unpack_dir(a2), pack_cell(k0, k1, k2, (uint32_t)ax), srcid, F, D);
+                        const uint32_t code = (uint32_t)((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1));
+                        const uint32_t rank = atomicAdd(&s_cnt[code], 1u);
+                        p.side[pos] = code | (rank << 5);
+                        if (traced) rec[0] = (int32_t)count;
+                    } else {
+                        double left = 0.0;
+#pragma unroll
+                        for (int j = 0; j < MB; ++j) left += (double)F[j];
+                        it_left = w * left;
+                        it_fate = fate;
+                        p.side[pos] = kSideDead;
+                        if (traced) {
+                            const int face = fate == 1u ? 0
+                                : ((o0 ? 1 : 0) | (o1 ? 2 : 0) | (o2 ? 4 : 0)
+                                   | (k0 >= p.geo.n[0] ? 8 : 0) | (k1 >= p.geo.n[1] ? 16 : 0)
+                                   | (k2 >= p.geo.n[2] ? 32 : 0));
+                            rec[0] = (int32_t)count; rec[1] = (int32_t)fate; rec[2] = face; rec[3] = here;
+                            rec[4] = unpack_dir(a0);
+                            rec[5] = unpack_dir(a1);
+                            rec[6] = unpack_dir(a2);
+                            rec[7] = (int32_t)srcid;
+                        }
+                    }
+                    alive = false;
+                }
+            }
+            n_cross += it_cross;
+            l_abs += it_abs;
+            l_esc += (it_fate == 2u) ? it_left : 0.0;
+            l_trunc += (it_fate == 1u) ? it_left : 0.0;
+            n_esc += (it_fate == 2u) ? 1u : 0u;
+            n_trunc += (it_fate == 1u) ? 1u : 0u;
+        }
+        __syncthreads();
+
+        // ---- the tile's deposits into the grid's accumulators ----
+        double *ga = p.acc + ((size_t)tile << (3 * kTileLog2)) * ACC;
+        for (int i = threadIdx.x; i < kTileCells * (int)ACC; i += kTBlock) {
+            const double v = s_acc[i];
+            if (v != 0.0) {
+                if (ch.shared) unsafeAtomicAdd(ga + i, v);
+                else ga[i] += v;
+            }
+        }
+        // ---- reserve the run's places in the neighbours' next lists ----
+        if (threadIdx.x < kCodes) {
+            const uint32_t n = s_cnt[threadIdx.x];
+            if (n != 0u) {
+                const int64_t y = (int64_t)tile + code_offset(p.geo, threadIdx.x);
+                if (y >= 0 && y < (int64_t)p.n_tiles) p.cbase[(size_t)c * kCodes + threadIdx.x] = atomicAdd(p.cnt + y, n);
+                else atomicOr(&p.ctrl->err, 32u);
+            }
+        }
+    }
+
+    double v[8] = {0.0, 0.0, l_abs, 0.0, l_esc, 0.0, l_trunc, 0.0};
+    unsigned long long cc[4] = {n_cross, 0ull, n_esc, n_trunc};
+    block_ledger_add(p.slots + blockIdx.x, v, cc);
+}
+
+__global__ void k_tslots_zero(LedgerSlot *s, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        LedgerSlot z;
+        for (int k = 0; k < 8; ++k) z.s[k] = 0.0;
+        for (int k = 0; k < 4; ++k) z.c[k] = 0ull;
+        s[i] = z;
+    }
+}
+
+__global__ void k_tzero_u32(uint32_t *p, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+// End of a batch: every list must be empty; errors go to the step ledger.
+__global__ void k_tcheck(TCtrl *ctrl, int cur, StepLedger *l) {
+    if (threadIdx.x == 0) {
+        uint32_t e = ctrl->err;
+        if (ctrl->total[cur] != 0u) e |= 64u;
+        if (e) l->errors |= e;
+    }
+}
+
+TParams make_params(const TiledLaunch &t) {
+    const MarchLaunch &m = t.m;
+    TParams p;
+    const bool f64 = m.fp64 != 0;
+    p.geo = m.geo;
+    p.half_dl = m.half_dl;
+    p.len_scale = f64 ? 1.0 : 1.0e-18;
+    p.src = m.src;
+    p.src_ndot = m.src_ndot;
+    p.src_sedsum = m.src_sedsum;
+    p.sed = m.sed;
+    p.tab = m.tab;
+    p.q = m.n_src > 0 ? m.packets / (uint32_t)m.n_src : 0u;
+    p.r = m.n_src > 0 ? m.packets % (uint32_t)m.n_src : 0u;
+    p.n_src = (uint32_t)m.n_src;
+    p.dt = m.dt;
+    p.seed = m.seed;
+    p.solve_id = m.solve_id;
+    p.step = m.step_index;
+    p.tau_kill = m.tau_kill;
+    p.kappa = m.kappa;
+    p.acc = m.acc;
+    p.slots = m.slots;
+    p.trace = m.trace;
+    p.trace_n = m.trace ? m.trace_n : 0;
+    p.trace_len = m.trace_len;
+    p.trace_stride = (uint32_t)m.trace_stride;
+    p.refill_min = (uint32_t)m.refill_min;
+    p.g0 = t.g0;
+    p.nbatch = t.nbatch;
+    p.capacity = t.capacity;
+    p.cmax = t.cmax;
+    p.max_chunks = t.max_chunks;
+    p.n_tiles = t.n_tiles;
+    p.rec = t.rec;
+    p.idx0 = t.idx[0];
+    p.idx1 = t.idx[1];
+    p.side = t.side;
+    p.cnt = t.cnt;
+    p.off = t.off;
+    p.cbase = t.cbase;
+    p.bsum = t.bsum;
+    p.ch0 = t.chunks[0];
+    p.ch1 = t.chunks[1];
+    p.ctrl = t.ctrl;
+    p.ledger = t.ledger;
+    return p;
+}
+
+void scan(const TParams &p, const TiledLaunch &t, int nxt) {
+    hipLaunchKernelGGL(k_tscan_a, dim3(t.scan_blocks), dim3(kScanBlock), 0, t.m.stream, p);
+    hipLaunchKernelGGL(k_tscan_b, dim3(1), dim3(kScanBlock), 0, t.m.stream, p, t.scan_blocks, nxt);
+    hipLaunchKernelGGL(k_tscan_c, dim3(t.scan_blocks), dim3(kScanBlock), 0, t.m.stream, p, nxt);
+}
+
+template <typename R, int S, bool TH, int MB>
+hipError_t run_batch(const TiledLaunch &t) {
+    const TParams p = make_params(t);
+    const hipStream_t st = t.m.stream;
+    const dim3 grid(t.m.blocks), blk(kTBlock);
+    hipLaunchKernelGGL((k_temit<R, S, TH, MB>), grid, blk, 0, st, p);
+    scan(p, t, 0);
+    hipLaunchKernelGGL(k_tscatter_emit, grid, blk, 0, st, p);
+    int cur = 0;
+    for (uint32_t pass = 0; pass < t.passes; ++pass) {
+        hipLaunchKernelGGL((k_tmarch<R, S, TH, MB>), grid, blk, 0, st, p, cur);
+        scan(p, t, cur ^ 1);
+        hipLaunchKernelGGL(k_tscatter, grid, blk, 0, st, p, cur);
+        cur ^= 1;
+    }
+    hipLaunchKernelGGL(k_tcheck, dim3(1), dim3(64), 0, st, t.ctrl, cur, t.ledger);
+    return hipGetLastError();
+}
+
+template <typename R, int S, bool TH, int MB>
+hipError_t occ(int *n) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, reinterpret_cast<const void *>(&k_tmarch<R, S, TH, MB>),
+                                                        kTBlock, 0);
+}
+
+template <typename R, int S, bool TH>
+hipError_t pick_mb(const TiledLaunch *t, int mb, int *o) {
+    switch (mb) {
+    case 1: return t ? run_batch<R, S, TH, 1>(*t) : occ<R, S, TH, 1>(o);
+    case 8: return t ? run_batch<R, S, TH, 8>(*t) : occ<R, S, TH, 8>(o);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t dispatch(const TiledLaunch *t, int species, int thermal, int fp64, int mb, int *o) {
+    if (fp64) {
+        if (species == 1) return thermal ? pick_mb<double, 1, true>(t, mb, o) : pick_mb<double, 1, false>(t, mb, o);
+        return thermal ? pick_mb<double, 3, true>(t, mb, o) : pick_mb<double, 3, false>(t, mb, o);
+    }
+    if (species == 1) return thermal ? pick_mb<float, 1, true>(t, mb, o) : pick_mb<float, 1, false>(t, mb, o);
+    return thermal ? pick_mb<float, 3, true>(t, mb, o) : pick_mb<float, 3, false>(t, mb, o);
+}
+
+template <typename R, int S, int MB> constexpr size_t rec_bytes() { return 16u * TRec<R, S, MB>::UNITS; }
+
+}  // namespace
+
+size_t tiled_record_bytes(int fp64, int species, int mb) {
+    if (fp64) {
+        if (mb == 1) return species == 1 ? rec_bytes<double, 1, 1>() : rec_bytes<double, 3, 1>();
+        return species == 1 ? rec_bytes<double, 1, 8>() : rec_bytes<double, 3, 8>();
+    }
+    if (mb == 1) return species == 1 ? rec_bytes<float, 1, 1>() : rec_bytes<float, 3, 1>();
+    return species == 1 ? rec_bytes<float, 1, 8>() : rec_bytes<float, 3, 8>();
+}
+
+hipError_t launch_tiled_reset(const TiledLaunch &t) {
+    hipLaunchKernelGGL(k_tzero_u32, dim3(256), dim3(256), 0, t.m.stream, t.cnt, t.n_tiles);
+    hipLaunchKernelGGL(k_tzero_u32, dim3(1), dim3(64), 0, t.m.stream, reinterpret_cast<uint32_t *>(t.ctrl),
+                       (uint32_t)(sizeof(TCtrl) / sizeof(uint32_t)));
+    return hipGetLastError();
+}
+
+hipError_t launch_tiled_slots_zero(const TiledLaunch &t) {
+    hipLaunchKernelGGL(k_tslots_zero, dim3((t.m.blocks + 255) / 256), dim3(256), 0, t.m.stream, t.m.slots,
+                       t.m.blocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_tiled_batch(const TiledLaunch &t) {
+    return dispatch(&t, t.m.species, t.m.thermal, t.m.fp64, t.m.mb, nullptr);
+}
+
+hipError_t tiled_occupancy(int species, int thermal, int fp64, int mb, int *blocks_per_cu) {
+    return dispatch(nullptr, species, thermal, fp64, mb, blocks_per_cu);
+}
+
+}  // namespace rtk

@@ -17,8 +17,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "librt_mcrt.so")
 
 RT_MAX_BINS = 16
-RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_ESTATE, RT_EOVERFLOW = 0, -1, -2, -3, -4, -5
-RT_ISOTHERMAL, RT_FP64, RT_TIME_MARCH = 0x1, 0x2, 0x4
+RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_ESTATE, RT_EOVERFLOW, RT_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+RT_ISOTHERMAL, RT_FP64, RT_TIME_MARCH, RT_DIRECT_MARCH = 0x1, 0x2, 0x4, 0x8
 RT_SRC_CORNER_OCTANT = 0x1
 RT_TRACE_HDR = 8
 RT_FATE_TRUNC, RT_FATE_ESCAPE = 1, 2
@@ -37,7 +37,8 @@ class GridDesc(C.Structure):
         ("flags", C.c_uint32), ("solve_id", C.c_uint64), ("step_index0", C.c_uint64),
         ("brick_log2", C.c_int32), ("wave_chunk", C.c_int32), ("refill_min", C.c_int32),
         ("blocks_per_cu", C.c_int32), ("trace_packets", C.c_int32), ("trace_len", C.c_int32),
-        ("trace_stride", C.c_int32),
+        ("trace_stride", C.c_int32), ("run_len", C.c_int32), ("reserved", C.c_int32),
+        ("inflight", C.c_int64),
     ]
 
 
@@ -46,11 +47,11 @@ class StepStats(C.Structure):
         ("emitted", C.c_double), ("absorbed", C.c_double), ("escaped", C.c_double),
         ("truncated", C.c_double), ("crossings", C.c_int64), ("packets", C.c_int64),
         ("n_escaped", C.c_int64), ("n_truncated", C.c_int64), ("substeps", C.c_int64),
-        ("nonfinite", C.c_uint32), ("pad", C.c_uint32), ("march_ms", C.c_double),
+        ("nonfinite", C.c_uint32), ("errors", C.c_uint32), ("march_ms", C.c_double),
     ]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 # (name, restype, argtypes) of every exported entry point
@@ -211,7 +212,8 @@ def rt_release(h):
 # ----------------------------------------------------------------------------
 def desc_from_workload(work, *, fp64: Optional[bool] = None, brick_log2: int = -1, wave_chunk: int = 0,
                        refill_min: int = 0, blocks_per_cu: int = 0, trace_packets: int = 0,
-                       trace_len: int = 0, trace_stride: int = 1, time_march: bool = False) -> GridDesc:
+                       trace_len: int = 0, trace_stride: int = 1, time_march: bool = False,
+                       direct: bool = False, run_len: int = 0, inflight: int = 0) -> GridDesc:
     d = rt_desc_defaults()
     for a in range(3):
         d.n[a] = int(work.n[a])
@@ -229,7 +231,7 @@ def desc_from_workload(work, *, fp64: Optional[bool] = None, brick_log2: int = -
     d.n_chem = int(work.n_chem)
     f64 = bool(work.flags & 0x2) if fp64 is None else bool(fp64)
     d.flags = ((RT_ISOTHERMAL if work.flags & 0x1 else 0) | (RT_FP64 if f64 else 0)
-               | (RT_TIME_MARCH if time_march else 0))
+               | (RT_TIME_MARCH if time_march else 0) | (RT_DIRECT_MARCH if direct else 0))
     d.solve_id = int(work.solve_id)
     d.brick_log2 = int(brick_log2)
     d.wave_chunk = int(wave_chunk)
@@ -238,6 +240,8 @@ def desc_from_workload(work, *, fp64: Optional[bool] = None, brick_log2: int = -
     d.trace_packets = int(trace_packets)
     d.trace_len = int(trace_len)
     d.trace_stride = int(trace_stride)
+    d.run_len = int(run_len)
+    d.inflight = int(inflight)
     return d
 
 
@@ -247,6 +251,9 @@ class Solve:
     def __init__(self, work, *, device: str = "cuda", stream=None, **tiles):
         import torch
         self.work = work
+        if not tiles.get("inflight"):
+            # records for every packet of a sub-step, up to 2^24
+            tiles["inflight"] = int(min(1 << 24, max(1, -(-int(work.packets) // int(work.n_sub)))))
         self.desc = desc_from_workload(work, **tiles)
         self.ncell = work.ncell
         self.fp64 = bool(self.desc.flags & RT_FP64)

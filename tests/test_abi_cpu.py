@@ -46,42 +46,47 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "{HEADER}"
 int main(void) {{
-  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(rt_grid_desc), offsetof(rt_grid_desc, solve_id),
-         offsetof(rt_grid_desc, trace_stride), sizeof(rt_step_stats),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(rt_grid_desc), offsetof(rt_grid_desc, solve_id),
+         offsetof(rt_grid_desc, trace_stride), offsetof(rt_grid_desc, run_len),
+         offsetof(rt_grid_desc, inflight), sizeof(rt_step_stats),
          offsetof(rt_step_stats, crossings), offsetof(rt_step_stats, nonfinite),
-         offsetof(rt_step_stats, march_ms));
+         offsetof(rt_step_stats, errors), offsetof(rt_step_stats, march_ms));
   return 0;
 }}""")
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-std=c11", "-o", str(exe), str(src)])
     vals = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     assert vals == [C.sizeof(rt.GridDesc), rt.GridDesc.solve_id.offset, rt.GridDesc.trace_stride.offset,
+                    rt.GridDesc.run_len.offset, rt.GridDesc.inflight.offset,
                     C.sizeof(rt.StepStats), rt.StepStats.crossings.offset, rt.StepStats.nonfinite.offset,
-                    rt.StepStats.march_ms.offset]
+                    rt.StepStats.errors.offset, rt.StepStats.march_ms.offset]
 
 
 def test_defaults_and_strerror(L):
     d = rt.rt_desc_defaults()
     assert list(d.n) == [1, 1, 1] and d.n_bins == 1 and d.tau_kill == 30.0 and d.n_chem == 8
-    for st in (rt.RT_OK, rt.RT_EINVAL, rt.RT_ENOMEM, rt.RT_EDEVICE, rt.RT_ESTATE, rt.RT_EOVERFLOW):
+    for st in (rt.RT_OK, rt.RT_EINVAL, rt.RT_ENOMEM, rt.RT_EDEVICE, rt.RT_ESTATE, rt.RT_EOVERFLOW,
+               rt.RT_EINTERNAL):
         assert rt.rt_strerror(st)
     assert rt.rt_strerror(-99) == "unknown status"
 
 
 def test_workspace_bytes_scales_and_validates(L):
     d = rt.rt_desc_defaults()
+    d.flags = rt.RT_DIRECT_MARCH
     d.n[0] = d.n[1] = d.n[2] = 64
     d.cell_cm = 1e21
     b64 = rt.rt_workspace_bytes(d, 10)
     d.n[0] = d.n[1] = d.n[2] = 128
     b128 = rt.rt_workspace_bytes(d, 10)
     assert 7.5 < b128 / b64 < 8.5
-    d.flags = rt.RT_FP64
+    d.flags = rt.RT_FP64 | rt.RT_DIRECT_MARCH
     assert rt.rt_workspace_bytes(d, 10) > b128
     # invalid descriptions
     for field, bad in (("n_bins", 0), ("n_bins", 9), ("n_bins", 17), ("tau_kill", 0.0), ("n_sub", 0), ("n_chem", 0),
                        ("cell_cm", -1.0), ("brick_log2", 4), ("wave_chunk", 100), ("refill_min", 65),
-                       ("flags", 0x10), ("trace_stride", -1)):
+                       ("flags", 0x10), ("trace_stride", -1), ("brick_log2", 2), ("run_len", 10),
+                       ("run_len", (1 << 20) + 1), ("reserved", 1), ("inflight", -1), ("inflight", 1 << 31)):
         e = rt.rt_desc_defaults()
         setattr(e, field, bad)
         with pytest.raises(rt.RTError) as ex:
@@ -97,6 +102,30 @@ def test_workspace_bytes_scales_and_validates(L):
     e.sigma_cm2[1][0] = 1e-18          # HeI below 24.6 eV
     with pytest.raises(rt.RTError):
         rt.rt_workspace_bytes(e, 1)
+
+
+def test_tiled_workspace_holds_one_record_per_packet_in_flight(L):
+    """The tiled march's workspace grows by a fixed record size per packet in
+    flight (float32 H+He, 8 bins: 64-byte records plus three list words)."""
+    d = rt.rt_desc_defaults()
+    d.n[0] = d.n[1] = d.n[2] = 64
+    d.cell_cm = 1e21
+    d.y_he = 0.08
+    d.n_bins = 8
+    for j in range(8):
+        d.e_bin_ev[j] = 60.0 + j
+    d.inflight = 1 << 20
+    a = rt.rt_workspace_bytes(d, 10)
+    d.inflight = 1 << 21
+    b = rt.rt_workspace_bytes(d, 10)
+    per = (b - a) / (1 << 20)
+    assert 64 + 12 <= per <= 64 + 12 + 16 * 2        # record + lists (+ runs of 2048)
+    d.flags = rt.RT_FP64
+    c = rt.rt_workspace_bytes(d, 10)
+    assert c > b
+    # the direct march needs none of it
+    d.flags = rt.RT_DIRECT_MARCH
+    assert rt.rt_workspace_bytes(d, 10) < a
 
 
 def test_init_rejects_bad_arguments_before_touching_the_device(L):

@@ -85,10 +85,20 @@ def test_trace_rays_match_oracle(gpu):
     s.release()
 
 
-@pytest.mark.parametrize("brick", [0, 1, 2, 3])
-def test_fp64_bitexact_traces_deposits_state(gpu, brick):
+MARCHES = {
+    "tiled": dict(),
+    "tiled-short-runs-batches": dict(run_len=64, inflight=1000, refill_min=1, blocks_per_cu=1),
+    "direct-b0": dict(direct=True, brick_log2=0),
+    "direct-b1": dict(direct=True, brick_log2=1),
+    "direct-b2": dict(direct=True, brick_log2=2),
+    "direct-b3": dict(direct=True, brick_log2=3),
+}
+
+
+@pytest.mark.parametrize("march", list(MARCHES))
+def test_fp64_bitexact_traces_deposits_state(gpu, march):
     w = ragged_case(tau_kill=4.0)
-    o, stats, fields, tr = PT.run_both(w, fp64=True, trace_n=w.packets, trace_len=96, brick_log2=brick)
+    o, stats, fields, tr = PT.run_both(w, fp64=True, trace_n=w.packets, trace_len=96, **MARCHES[march])
     g, r = stats[0]
     assert g["crossings"] == r["crossings"] and g["n_truncated"] == r["n_truncated"]
     assert r["n_truncated"] > 0 and r["n_escaped"] > 0
@@ -176,7 +186,8 @@ def test_single_cell_grid(gpu):
 
 
 def test_tiles_do_not_change_results(gpu):
-    """Brick size, claim chunk, refill threshold and grid size change the
+    """March organisation (per packet or by tiles), brick size, claim chunk,
+    run length, packets in flight, refill threshold and grid size change the
     schedule only: traces identical, deposits equal up to summation order,
     and every ledger counter equal to the oracle's."""
     from paper_1101_4127_amd import rt
@@ -184,10 +195,13 @@ def test_tiles_do_not_change_results(gpu):
     o = O.OracleSolve(w)
     r = o.step()
     ref = None
-    for tiles in (dict(brick_log2=0, wave_chunk=64, refill_min=1, blocks_per_cu=1),
-                  dict(brick_log2=2, wave_chunk=1024, refill_min=32),
-                  dict(brick_log2=3, wave_chunk=256, refill_min=8, blocks_per_cu=2),
-                  dict(refill_min=64)):
+    for tiles in (dict(direct=True, brick_log2=0, wave_chunk=64, refill_min=1, blocks_per_cu=1),
+                  dict(direct=True, brick_log2=2, wave_chunk=1024, refill_min=32),
+                  dict(direct=True, brick_log2=3, wave_chunk=256, refill_min=8, blocks_per_cu=2),
+                  dict(refill_min=64),
+                  dict(),
+                  dict(run_len=64, inflight=3000, refill_min=1),
+                  dict(run_len=1 << 20, blocks_per_cu=1)):
         s = rt.Solve(w, trace_packets=5000, trace_len=96, **tiles)
         st = s.step()
         f = s.fetch()
@@ -214,8 +228,11 @@ def test_ledger_counts_under_every_schedule(gpu, fp64, n, packets):
     from paper_1101_4127_amd import rt
     w = ragged_case(n=n, n_src=3, packets=packets, fp64=fp64)
     r = O.OracleSolve(w).step()
-    for tiles in (dict(), dict(wave_chunk=64), dict(refill_min=64), dict(wave_chunk=1024),
-                  dict(wave_chunk=1024, refill_min=1), dict(blocks_per_cu=1)):
+    for tiles in (dict(), dict(run_len=64), dict(refill_min=64), dict(inflight=packets // 7 + 1),
+                  dict(run_len=64, refill_min=1, blocks_per_cu=1),
+                  dict(direct=True), dict(direct=True, wave_chunk=64), dict(direct=True, refill_min=64),
+                  dict(direct=True, wave_chunk=1024), dict(direct=True, wave_chunk=1024, refill_min=1),
+                  dict(direct=True, blocks_per_cu=1)):
         s = rt.Solve(w, **tiles)
         st = s.step()
         s.release()
@@ -251,7 +268,9 @@ def test_checkpoint_resume(gpu):
     tc = rt.rt_fetch_trace(h, 1000, 64)
     rt.rt_release(h)
     assert PT.traces_equal(ta, tc)
-    assert np.max(np.abs(fc - fa) / np.maximum(np.abs(fa), 1e-300)) < 1e-12
+    # same packets; float64 deposits summed in a different order (atomics) feed
+    # through the cell update at the 1e-16 level
+    assert np.max(np.abs(fc - fa) / np.maximum(np.abs(fa), 1e-300)) < 1e-10
 
 
 def test_error_paths(gpu):

@@ -124,7 +124,7 @@ typedef struct {
     int32_t trace_stride;         /* spacing of traced packet ids; 0 = 1 */
     int32_t run_len;              /* tiled march: packets of one tile one block
                                      marches before it writes the tile's deposits
-                                     out; 0 = default (2048), else 64..2^20 */
+                                     out; 0 = default (2048), else 64..2048 */
     int32_t reserved;             /* must be 0 */
     int64_t inflight;             /* tiled march: packets propagated together (the
                                      workspace holds one record each); a sub-step

@@ -67,7 +67,7 @@ int32_t validate_desc(const rt_grid_desc *d) {
     if (d->brick_log2 < -1 || d->brick_log2 > 3) return RT_EINVAL;
     // the tiled march's tiles are the bricks of side 8
     if (!(d->flags & RT_DIRECT_MARCH) && d->brick_log2 != -1 && d->brick_log2 != 3) return RT_EINVAL;
-    if (d->run_len < 0 || d->run_len > (1 << 20) || (d->run_len > 0 && d->run_len < 64)) return RT_EINVAL;
+    if (d->run_len < 0 || d->run_len > 2048 || (d->run_len > 0 && d->run_len < 64)) return RT_EINVAL;
     if (d->inflight < 0 || d->inflight > ((int64_t)1 << 31) - 1) return RT_EINVAL;
     if (d->reserved != 0) return RT_EINVAL;
     if (d->wave_chunk < 0 || d->wave_chunk % 64 != 0 || d->wave_chunk > (1 << 20)) return RT_EINVAL;

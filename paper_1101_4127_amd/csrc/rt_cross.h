@@ -18,6 +18,11 @@ template <typename R> struct Vec4;
 template <> struct Vec4<float> { using T = float4; };
 template <> struct Vec4<double> { using T = double4; };
 
+// Per-bin table of the march precision, [2][3][MB]: cross-sections of HI,
+// HeI, HeII, then their heat factors.  Read through the constant address
+// space: the indices are uniform, so the values live in scalar registers.
+template <typename R> using CTab = const __attribute__((address_space(4))) R *;
+
 constexpr uint32_t kNeg = 0x80000000u;      // sign flag packed above |c| (|c| <= 2^20)
 constexpr uint32_t kMag = 0x00ffffffu;
 
@@ -58,12 +63,10 @@ __device__ __forceinline__ int exit_face(uint32_t d0, uint32_t d1, uint32_t d2, 
 // depth over the bins the source populates (bit j of `active`), which ends the
 // packet once it reaches tau_kill.
 template <typename R, int S, bool TH, int MB, typename KV>
-__device__ __forceinline__ void cross_cell(R l, const KV &kap, const typename Vec4<R>::T *s_sig,
-                                           const typename Vec4<R>::T *s_heat, uint32_t active, R (&F)[MB],
+__device__ __forceinline__ void cross_cell(R l, const KV &kap, CTab<R> tab, uint32_t active, R (&F)[MB],
                                            R (&D)[DepthState<R, S, MB>::N], R &absorbed, R &e0, R &e1,
                                            R &e2, R &heat, R &tmin) {
     constexpr bool F64 = std::is_same<R, double>::value;
-    using V4R = typename Vec4<R>::T;
     R kH, kHe1 = R(0), kHe2 = R(0);
     if constexpr (S == 1) kH = kap;
     else { kH = kap.x; kHe1 = kap.y; kHe2 = kap.z; }
@@ -79,7 +82,7 @@ __device__ __forceinline__ void cross_cell(R l, const KV &kap, const typename Ve
     R tm = R(INFINITY);
 #pragma unroll
     for (int j = 0; j < MB; ++j) {
-        const V4R sg = s_sig[j];
+        struct { R x, y, z; } sg = {tab[j], tab[MB + j], tab[2 * MB + j]};
         R K;
         if (S == 1) K = kH * sg.x;
         else if (F64) K = (kH * sg.x + kHe1 * sg.y) + kHe2 * sg.z;
@@ -104,7 +107,7 @@ __device__ __forceinline__ void cross_cell(R l, const KV &kap, const typename Ve
         }
         ab += d;
         if (S == 1) {
-            if (TH) h0 += d * s_heat[j].x;
+            if (TH) h0 += d * tab[3 * MB + j];
         } else {
             R gk;
             if (F64) gk = K > R(0) ? d / K : R(0);
@@ -113,10 +116,9 @@ __device__ __forceinline__ void cross_cell(R l, const KV &kap, const typename Ve
             g1 += sg.y * gk;
             g2 += sg.z * gk;
             if (TH) {
-                const V4R ht = s_heat[j];
-                h0 += ht.x * gk;
-                h1 += ht.y * gk;
-                h2 += ht.z * gk;
+                h0 += tab[3 * MB + j] * gk;
+                h1 += tab[4 * MB + j] * gk;
+                h2 += tab[5 * MB + j] * gk;
             }
         }
     }

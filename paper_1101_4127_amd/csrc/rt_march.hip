@@ -88,20 +88,10 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
     // per-bin tables shared by all lanes (one 4-vector of cross-sections and
     // one of heat factors per bin), and the wave-private emission batch
     using V4R = typename Vec4<R>::T;
-    __shared__ V4R s_sig[MB];
-    __shared__ V4R s_heat[MB];
     __shared__ int32_t sb_c[kWaves][3][64];
     __shared__ uint32_t sb_g[kWaves][64], sb_src[kWaves][64];
     __shared__ double sb_w[kWaves][64], sb_L[kWaves][64];
-    if (threadIdx.x < MB) {
-        const R *t = reinterpret_cast<const R *>(p.tab);
-        const int j = threadIdx.x;
-        V4R a, b;
-        a.x = t[j]; a.y = t[MB + j]; a.z = t[2 * MB + j]; a.w = R(0);
-        b.x = t[3 * MB + j]; b.y = t[4 * MB + j]; b.z = t[5 * MB + j]; b.w = R(0);
-        s_sig[j] = a;
-        s_heat[j] = b;
-    }
+    const CTab<R> tab = (CTab<R>)p.tab;
     __syncthreads();
 
     // ---- packet state (one per lane; only touched while the lane holds a packet) ----
@@ -257,20 +247,14 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
             const bool o1 = (uint32_t)k1 >= (uint32_t)p.geo.n[1];
             const bool o2 = (uint32_t)k2 >= (uint32_t)p.geo.n[2];
             const bool out = o0 | o1 | o2;
-            // issue the next cell's gather before this cell's arithmetic
-            uint32_t nslot = slot;
-            KV knext = kap;
-            if (!out) {
-                nslot = cell_slot(p.geo, k0, k1, k2);
-                knext = kappa[nslot];
-            }
+            // issue the next cell's gather before this cell's arithmetic (a packet
+            // that left re-reads its last cell: the value is unused)
+            const uint32_t nslot = out ? slot : cell_slot(p.geo, k0, k1, k2);
+            const KV knext = kappa[nslot];
 
             // ---- Eq. (1) per bin and the split among absorbers ----
-            // (the tables are re-read from LDS at every crossing rather than
-            // held in registers across the loop)
-            asm volatile("" ::: "memory");
             R absorbed, e0, e1, e2, hs, tmin;
-            cross_cell<R, S, TH, MB>(l, kap, s_sig, s_heat, active, F, D, absorbed, e0, e1, e2, hs, tmin);
+            cross_cell<R, S, TH, MB>(l, kap, tab, active, F, D, absorbed, e0, e1, e2, hs, tmin);
 
             // ---- deposit: float64 accumulators, hardware atomics at L2 ----
             double *cell = p.acc + (size_t)slot * ACC;

@@ -72,19 +72,29 @@ struct TParams {
     StepLedger *ledger;
 };
 
-// Record of a packet between passes (16-byte units).  Words: c[3] (integer
-// direction), the cell it is in or about to enter with the axis of the last
-// face it crossed (3: none yet), its source; then the depth state and the
-// photons per bin (float32 form: column densities, then F; float64 form: a
-// pad word, F, then T).
+// Record of a packet between passes (16-byte units), holding everything the
+// march needs to resume it without touching the source tables.  Words:
+//   0-2  c[3], the integer direction
+//   3    the cell it is in (or about to enter) | axis of the last face crossed
+//        (3: none yet) << 30
+//   4    next-face distances d0 | d1 << 16 (half cells)
+//   5    d2 | bins the source populates << 16
+//   6-7  packet weight (photons per unit of the SED), float64
+//   8    source
+// float32 form: then the column densities N_s and the photons per bin F_j;
+// float64 form: a pad word, then F_j and the optical depths T_j.
 template <typename R, int S, int MB>
 struct TRec {
     static constexpr bool F64 = std::is_same<R, double>::value;
     static constexpr int ND = DepthState<R, S, MB>::N;
-    static constexpr int BYTES = F64 ? 24 + 8 * (MB + ND) : 4 * (5 + ND + MB);
+    static constexpr int HDR = F64 ? 10 : 9;
+    static constexpr int BYTES = 4 * HDR + (int)sizeof(R) * (MB + ND);
     static constexpr int UNITS = (BYTES + 15) / 16;
     static constexpr int WORDS = 4 * UNITS;
 };
+
+// Longest run of a tile's list one block marches (its record ids are staged in LDS).
+constexpr int kMaxRun = 2048;
 
 __device__ __forceinline__ uint32_t pack_cell(int k0, int k1, int k2, uint32_t axis) {
     return (uint32_t)k0 | ((uint32_t)k1 << 10) | ((uint32_t)k2 << 20) | (axis << 30);
@@ -181,29 +191,35 @@ __device__ void block_ledger_add(LedgerSlot *slot, double (&v)[8], unsigned long
 
 template <typename R, int S, int MB>
 __device__ __forceinline__ void store_record(uint4 *dst, int32_t c0, int32_t c1, int32_t c2, uint32_t kw,
+                                             uint32_t d0, uint32_t d1, uint32_t d2, uint32_t active, double w,
                                              uint32_t srcid, const R (&F)[MB],
                                              const R (&D)[DepthState<R, S, MB>::N]) {
     using RL = TRec<R, S, MB>;
-    uint32_t w[RL::WORDS];
+    uint32_t x[RL::WORDS];
 #pragma unroll
-    for (int i = 0; i < RL::WORDS; ++i) w[i] = 0u;
-    w[0] = (uint32_t)c0; w[1] = (uint32_t)c1; w[2] = (uint32_t)c2; w[3] = kw; w[4] = srcid;
+    for (int i = 0; i < RL::WORDS; ++i) x[i] = 0u;
+    x[0] = (uint32_t)c0; x[1] = (uint32_t)c1; x[2] = (uint32_t)c2; x[3] = kw;
+    x[4] = d0 | (d1 << 16);
+    x[5] = d2 | (active << 16);
+    x[6] = (uint32_t)__double2loint(w);
+    x[7] = (uint32_t)__double2hiint(w);
+    x[8] = srcid;
     if constexpr (RL::F64) {
 #pragma unroll
         for (int j = 0; j < MB; ++j) {
-            w[6 + 2 * j] = (uint32_t)__double2loint(F[j]);
-            w[7 + 2 * j] = (uint32_t)__double2hiint(F[j]);
-            w[6 + 2 * MB + 2 * j] = (uint32_t)__double2loint(D[j]);
-            w[7 + 2 * MB + 2 * j] = (uint32_t)__double2hiint(D[j]);
+            x[RL::HDR + 2 * j] = (uint32_t)__double2loint(F[j]);
+            x[RL::HDR + 1 + 2 * j] = (uint32_t)__double2hiint(F[j]);
+            x[RL::HDR + 2 * MB + 2 * j] = (uint32_t)__double2loint(D[j]);
+            x[RL::HDR + 2 * MB + 1 + 2 * j] = (uint32_t)__double2hiint(D[j]);
         }
     } else {
 #pragma unroll
-        for (int j = 0; j < RL::ND; ++j) w[5 + j] = __float_as_uint(D[j]);
+        for (int j = 0; j < RL::ND; ++j) x[RL::HDR + j] = __float_as_uint(D[j]);
 #pragma unroll
-        for (int j = 0; j < MB; ++j) w[5 + RL::ND + j] = __float_as_uint(F[j]);
+        for (int j = 0; j < MB; ++j) x[RL::HDR + RL::ND + j] = __float_as_uint(F[j]);
     }
 #pragma unroll
-    for (int u = 0; u < RL::UNITS; ++u) dst[u] = make_uint4(w[4 * u], w[4 * u + 1], w[4 * u + 2], w[4 * u + 3]);
+    for (int u = 0; u < RL::UNITS; ++u) dst[u] = make_uint4(x[4 * u], x[4 * u + 1], x[4 * u + 2], x[4 * u + 3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -246,8 +262,10 @@ __global__ void __launch_bounds__(kTBlock) k_temit(const TParams p) {
             for (int j = 0; j < MB; ++j) F[j] = sed[j];
 #pragma unroll
             for (int j = 0; j < ND; ++j) D[j] = (!RL::F64 || ((active >> j) & 1u)) ? R(0) : R(INFINITY);
-            store_record<R, S, MB>(recs + (size_t)i * RL::UNITS, c[0], c[1], c[2], pack_cell(k0, k1, k2, 3u), sidx,
-                                   F, D);
+            const uint32_t a0 = pack_dir(c[0]), a1 = pack_dir(c[1]), a2 = pack_dir(c[2]);
+            store_record<R, S, MB>(recs + (size_t)i * RL::UNITS, c[0], c[1], c[2], pack_cell(k0, k1, k2, 3u),
+                                   next_face(k0, sr.o[0], a0), next_face(k1, sr.o[1], a1),
+                                   next_face(k2, sr.o[2], a2), active, ww, sidx, F, D);
             tile = tile_of_cell(p.geo, k0, k1, k2);
             const int32_t tix = trace_slot(p, g);
             if (tix >= 0) p.trace[(size_t)tix * (RT_TRACE_HDR_DEV + p.trace_len)] = 0;
@@ -421,7 +439,7 @@ __global__ void __launch_bounds__(kTBlock) k_tscatter(const TParams p, int cur) 
 // Occupancy target (wavefronts per SIMD) the register allocation is held to.
 template <typename R, int MB> struct TOcc { static constexpr int value = 2; };
 template <> struct TOcc<float, 1> { static constexpr int value = 4; };
-template <> struct TOcc<float, 8> { static constexpr int value = 3; };
+template <> struct TOcc<float, 8> { static constexpr int value = 4; };
 
 template <typename R, int S, bool TH, int MB>
 __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const TParams p, int cur) {
@@ -434,21 +452,12 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
 
-    __shared__ V4R s_sig[MB];
-    __shared__ V4R s_heat[MB];
     __shared__ KV s_kap[kTileCells];
     __shared__ double s_acc[kTileCells * ACC];
     __shared__ uint32_t s_cnt[kCodes];
+    __shared__ uint32_t s_list[kMaxRun];
     __shared__ uint32_t s_next, s_claim;
-    if (threadIdx.x < MB) {
-        const R *t = reinterpret_cast<const R *>(p.tab);
-        const int j = threadIdx.x;
-        V4R a, b;
-        a.x = t[j]; a.y = t[MB + j]; a.z = t[2 * MB + j]; a.w = R(0);
-        b.x = t[3 * MB + j]; b.y = t[4 * MB + j]; b.z = t[5 * MB + j]; b.w = R(0);
-        s_sig[j] = a;
-        s_heat[j] = b;
-    }
+    const CTab<R> tab = (CTab<R>)p.tab;
 
     const uint32_t nch = p.ctrl->n_chunks[cur];
     const TChunk *chs = cur ? p.ch1 : p.ch0;
@@ -466,7 +475,8 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
         const uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_claim);   // block-uniform
         if (c >= nch) break;
         const TChunk ch = chs[c];
-        if (ch.tile >= p.n_tiles || ch.start > p.capacity || ch.len > p.capacity - ch.start) {
+        if (ch.tile >= p.n_tiles || ch.start > p.capacity || ch.len > p.capacity - ch.start
+            || ch.len > (uint32_t)kMaxRun) {
             if (threadIdx.x == 0) atomicOr(&p.ctrl->err, 8u);
             continue;
         }
@@ -479,6 +489,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
         const KV *kt = kappa + ((size_t)tile << (3 * kTileLog2));
         for (int i = threadIdx.x; i < kTileCells; i += kTBlock) s_kap[i] = kt[i];
         for (int i = threadIdx.x; i < kTileCells * (int)ACC; i += kTBlock) s_acc[i] = 0.0;
+        for (uint32_t i = threadIdx.x; i < ch.len; i += kTBlock) s_list[i] = list[ch.start + i];
         if (threadIdx.x < kCodes) s_cnt[threadIdx.x] = 0u;
         if (threadIdx.x == 0) s_next = 0u;
         __syncthreads();
@@ -514,7 +525,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                     const uint32_t rank = (uint32_t)__popcll(dead & lt_mask);
                     if (!alive && rank < got) {
                         pos = ch.start + b0 + rank;
-                        const uint32_t ri = list[pos];
+                        const uint32_t ri = s_list[b0 + rank];
                         if (ri >= p.capacity) {
                             atomicOr(&p.ctrl->err, 16u);
                             p.side[pos] = kSideDead;
@@ -529,18 +540,24 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                             }
                             const int32_t c0 = (int32_t)wd[0], c1 = (int32_t)wd[1], c2 = (int32_t)wd[2];
                             const uint32_t kw = wd[3];
-                            srcid = wd[4];
+                            d0 = wd[4] & 0xffffu;
+                            d1 = wd[4] >> 16;
+                            d2 = wd[5] & 0xffffu;
+                            active = wd[5] >> 16;
+                            w = __hiloint2double((int)wd[7], (int)wd[6]);
+                            srcid = wd[8];
                             if constexpr (F64) {
 #pragma unroll
                                 for (int j = 0; j < MB; ++j) {
-                                    F[j] = __hiloint2double((int)wd[7 + 2 * j], (int)wd[6 + 2 * j]);
-                                    D[j] = __hiloint2double((int)wd[7 + 2 * MB + 2 * j], (int)wd[6 + 2 * MB + 2 * j]);
+                                    F[j] = __hiloint2double((int)wd[RL::HDR + 1 + 2 * j], (int)wd[RL::HDR + 2 * j]);
+                                    D[j] = __hiloint2double((int)wd[RL::HDR + 2 * MB + 1 + 2 * j],
+                                                            (int)wd[RL::HDR + 2 * MB + 2 * j]);
                                 }
                             } else {
 #pragma unroll
-                                for (int j = 0; j < ND; ++j) D[j] = __uint_as_float(wd[5 + j]);
+                                for (int j = 0; j < ND; ++j) D[j] = __uint_as_float(wd[RL::HDR + j]);
 #pragma unroll
-                                for (int j = 0; j < MB; ++j) F[j] = __uint_as_float(wd[5 + ND + j]);
+                                for (int j = 0; j < MB; ++j) F[j] = __uint_as_float(wd[RL::HDR + ND + j]);
                             }
                             k0 = (int)(kw & 1023u);
                             k1 = (int)((kw >> 10) & 1023u);
@@ -554,13 +571,9 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                                 atomicOr(&p.ctrl->err, 16u);
                                 p.side[pos] = kSideDead;
                             } else {
-                                const SourceRec sr = p.src[srcid];
                                 a0 = pack_dir(c0);
                                 a1 = pack_dir(c1);
                                 a2 = pack_dir(c2);
-                                d0 = next_face(k0, sr.o[0], a0);
-                                d1 = next_face(k1, sr.o[1], a1);
-                                d2 = next_face(k2, sr.o[2], a2);
                                 // entry parameter of this cell: the last face crossed
                                 if (ax == 3u) { pnum = 0u; pden = 1u; }
                                 else {
@@ -571,11 +584,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                                 const int64_t qq = (int64_t)c0 * c0 + (int64_t)c1 * c1 + (int64_t)c2 * c2;
                                 const double Ld = sqrt((double)qq) * p.half_dl;
                                 if (F64) L = Ld; else Lf = (float)(Ld * p.len_scale);
-                                const uint32_t ns = srcid < p.r ? p.q + 1u : p.q;
-                                const uint32_t g = p.g0 + ri;
-                                w = packet_weight(p, srcid, ns, (sr.flags & kSrcOctant) != 0u);
-                                active = sr.flags >> kSrcMaskShift;
-                                tix = trace_slot(p, g);
+                                tix = trace_slot(p, p.g0 + ri);
                                 count = tix >= 0 ? (uint32_t)p.trace[(size_t)tix * (RT_TRACE_HDR_DEV + p.trace_len)] : 0u;
                                 absd = 0.0;
                                 loc = local_cell(k0, k1, k2);
@@ -617,18 +626,13 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                 const bool out = o0 | o1 | o2;
                 const int dx = (k0 >> kTileLog2) - tx, dy = (k1 >> kTileLog2) - ty, dz = (k2 >> kTileLog2) - tz;
                 const bool leave = !out && (dx | dy | dz) != 0;
-                uint32_t nloc = loc;
-                KV knext = kap;
-                if (!out && !leave) {
-                    nloc = local_cell(k0, k1, k2);
-                    knext = s_kap[nloc];
-                }
+                // next cell's absorbers, read before this cell's arithmetic (the
+                // masked index stays inside the tile; unused when the packet leaves)
+                const uint32_t nloc = local_cell(k0, k1, k2);
+                const KV knext = s_kap[nloc];
 
-                // (the tables are re-read from LDS at every crossing rather than
-                // held in registers across the loop)
-                asm volatile("" ::: "memory");
                 R absorbed, e0, e1, e2, hs, tmin;
-                cross_cell<R, S, TH, MB>(l, kap, s_sig, s_heat, active, F, D, absorbed, e0, e1, e2, hs, tmin);
+                cross_cell<R, S, TH, MB>(l, kap, tab, active, F, D, absorbed, e0, e1, e2, hs, tmin);
 
                 // ---- deposit into the tile's float64 accumulators in LDS ----
                 double *cell = s_acc + loc * ACC;
@@ -669,7 +673,8 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                         // moves on into a neighbour tile: record back, rank among the run's
                         // packets bound for the same tile
                         store_record<R, S, MB>(recs + (size_t)rid * RL::UNITS, unpack_dir(a0), unpack_dir(a1),
-                                               unpack_dir(a2), pack_cell(k0, k1, k2, (uint32_t)ax), srcid, F, D);
+                                               unpack_dir(a2), pack_cell(k0, k1, k2, (uint32_t)ax), d0, d1, d2,
+                                               active, w, srcid, F, D);
                         const uint32_t code = (uint32_t)((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1));
                         const uint32_t rank = atomicAdd(&s_cnt[code], 1u);
                         p.side[pos] = code | (rank << 5);

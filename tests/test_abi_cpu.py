@@ -86,7 +86,7 @@ def test_workspace_bytes_scales_and_validates(L):
     for field, bad in (("n_bins", 0), ("n_bins", 9), ("n_bins", 17), ("tau_kill", 0.0), ("n_sub", 0), ("n_chem", 0),
                        ("cell_cm", -1.0), ("brick_log2", 4), ("wave_chunk", 100), ("refill_min", 65),
                        ("flags", 0x10), ("trace_stride", -1), ("brick_log2", 2), ("run_len", 10),
-                       ("run_len", (1 << 20) + 1), ("reserved", 1), ("inflight", -1), ("inflight", 1 << 31)):
+                       ("run_len", 2049), ("reserved", 1), ("inflight", -1), ("inflight", 1 << 31)):
         e = rt.rt_desc_defaults()
         setattr(e, field, bad)
         with pytest.raises(rt.RTError) as ex:
@@ -106,7 +106,7 @@ def test_workspace_bytes_scales_and_validates(L):
 
 def test_tiled_workspace_holds_one_record_per_packet_in_flight(L):
     """The tiled march's workspace grows by a fixed record size per packet in
-    flight (float32 H+He, 8 bins: 64-byte records plus three list words)."""
+    flight (float32 H+He, 8 bins: 80-byte records plus three list words)."""
     d = rt.rt_desc_defaults()
     d.n[0] = d.n[1] = d.n[2] = 64
     d.cell_cm = 1e21
@@ -119,7 +119,7 @@ def test_tiled_workspace_holds_one_record_per_packet_in_flight(L):
     d.inflight = 1 << 21
     b = rt.rt_workspace_bytes(d, 10)
     per = (b - a) / (1 << 20)
-    assert 64 + 12 <= per <= 64 + 12 + 16 * 2        # record + lists (+ runs of 2048)
+    assert 80 + 12 <= per <= 80 + 12 + 16 * 2        # record + lists (+ runs of 2048)
     d.flags = rt.RT_FP64
     c = rt.rt_workspace_bytes(d, 10)
     assert c > b

@@ -321,7 +321,7 @@ int32_t rt_init_grid(const rt_grid_desc *d, void *d_ws, size_t ws_bytes, int64_t
     h->step_index = d->step_index0;
     h->blocks = blocks;
     h->chunk = d->wave_chunk > 0 ? d->wave_chunk : 256;
-    h->refill_min = d->refill_min > 0 ? d->refill_min : 8;
+    h->refill_min = d->refill_min > 0 ? d->refill_min : (p.tiled ? 16 : 8);
     h->dead = false;
     h->timed = 0;
     if (d->flags & RT_TIME_MARCH) {

@@ -59,11 +59,12 @@ __device__ __forceinline__ int exit_face(uint32_t d0, uint32_t d1, uint32_t d2, 
 // in the march precision: the photons absorbed over all bins; per absorber,
 // kappa_s * sum_j sigma_s,j d_j / K_j (the photons the absorber takes); the
 // heat sum_s kappa_s sum_j h_s,j d_j / K_j (pure hydrogen: sum_j h_j d_j), in
-// eV per photon of the packet's weight; and the smallest accumulated optical
-// depth over the bins the source populates (bit j of `active`), which ends the
-// packet once it reaches tau_kill.
+// eV per photon of the packet's weight; and, in the float64 form, the
+// smallest accumulated optical depth over the bins (those the source does
+// not populate hold +inf), which ends the packet once it reaches tau_kill
+// (float32 form: see Extinction).
 template <typename R, int S, bool TH, int MB, typename KV>
-__device__ __forceinline__ void cross_cell(R l, const KV &kap, CTab<R> tab, uint32_t active, R (&F)[MB],
+__device__ __forceinline__ void cross_cell(R l, const KV &kap, CTab<R> tab, R (&F)[MB],
                                            R (&D)[DepthState<R, S, MB>::N], R &absorbed, R &e0, R &e1,
                                            R &e2, R &heat, R &tmin) {
     constexpr bool F64 = std::is_same<R, double>::value;
@@ -100,25 +101,37 @@ __device__ __forceinline__ void cross_cell(R l, const KV &kap, CTab<R> tab, uint
             attenuation(tau, em, tr);
             d = F[j] * em;
             F[j] = F[j] * tr;
-            R tj;
-            if (S == 1) tj = sg.x * D[0];
-            else tj = __builtin_fmaf(sg.z, D[2], __builtin_fmaf(sg.y, D[1], sg.x * D[0]));
-            tm = ((active >> j) & 1u) && tj < tm ? tj : tm;
         }
         ab += d;
-        if (S == 1) {
-            if (TH) h0 += d * tab[3 * MB + j];
+        if constexpr (F64) {
+            // float64 form: the oracle's order, no contraction
+            if (S == 1) {
+                if (TH) h0 += d * tab[3 * MB + j];
+            } else {
+                const R gk = K > R(0) ? d / K : R(0);
+                g0 += sg.x * gk;
+                g1 += sg.y * gk;
+                g2 += sg.z * gk;
+                if (TH) {
+                    h0 += tab[3 * MB + j] * gk;
+                    h1 += tab[4 * MB + j] * gk;
+                    h2 += tab[5 * MB + j] * gk;
+                }
+            }
         } else {
-            R gk;
-            if (F64) gk = K > R(0) ? d / K : R(0);
-            else gk = K > R(0) ? d * __builtin_amdgcn_rcpf(K) : R(0);
-            g0 += sg.x * gk;
-            g1 += sg.y * gk;
-            g2 += sg.z * gk;
-            if (TH) {
-                h0 += tab[3 * MB + j] * gk;
-                h1 += tab[4 * MB + j] * gk;
-                h2 += tab[5 * MB + j] * gk;
+            if (S == 1) {
+                if (TH) h0 = __builtin_fmaf(d, tab[3 * MB + j], h0);
+            } else {
+                // d_j / K_j; K_j = 0 only where d_j = 0
+                const float gk = d * __builtin_amdgcn_rcpf(fmaxf(K, 1e-30f));
+                g0 = __builtin_fmaf(sg.x, gk, g0);
+                g1 = __builtin_fmaf(sg.y, gk, g1);
+                g2 = __builtin_fmaf(sg.z, gk, g2);
+                if (TH) {
+                    h0 = __builtin_fmaf(tab[3 * MB + j], gk, h0);
+                    h1 = __builtin_fmaf(tab[4 * MB + j], gk, h1);
+                    h2 = __builtin_fmaf(tab[5 * MB + j], gk, h2);
+                }
             }
         }
     }
@@ -140,6 +153,74 @@ __device__ __forceinline__ void cross_cell(R l, const KV &kap, CTab<R> tab, uint
         }
     }
 }
+
+// Extinction test of the float32 form: a packet ends once every bin the
+// source populates has T_j = sum_s sigma_s,j N_s >= tau_kill.  The packet
+// keeps a witness bin whose T_j was below tau_kill at the last full check;
+// as long as the witness stays below, some bin is (so the packet lives) and
+// one T_j is formed per crossing instead of all of them.  When the witness
+// reaches tau_kill the full minimum decides, and a new witness is taken.  The
+// decision equals the one of the full minimum at every crossing (T_j only
+// grows, and the witness's T_j is formed exactly as in the full minimum).
+template <int S, int MB>
+struct Extinction {
+    float wH = 0.0f, wHe1 = 0.0f, wHe2 = 0.0f;    // cross-sections of the witness bin
+    uint32_t jw = 0;                              // the witness bin
+
+    __device__ __forceinline__ static float depth(float sH, float sHe1, float sHe2, const float (&N)[S == 1 ? 1 : 3]) {
+        if (S == 1) return sH * N[0];
+        return __builtin_fmaf(sHe2, N[2], __builtin_fmaf(sHe1, N[1], sH * N[0]));
+    }
+
+    // full check: true if extinguished; else the witness is the first bin of
+    // smallest depth
+    __device__ __forceinline__ bool full(CTab<float> tab, uint32_t active, float tau_kill,
+                                         const float (&N)[S == 1 ? 1 : 3]) {
+        float tm = INFINITY;
+#pragma unroll
+        for (int j = 0; j < MB; ++j) {
+            const float sH = tab[j], sHe1 = S == 1 ? 0.0f : tab[MB + j], sHe2 = S == 1 ? 0.0f : tab[2 * MB + j];
+            const float t = depth(sH, sHe1, sHe2, N);
+            const bool take = ((active >> j) & 1u) && t < tm;
+            tm = take ? t : tm;
+            wH = take ? sH : wH;
+            wHe1 = take ? sHe1 : wHe1;
+            wHe2 = take ? sHe2 : wHe2;
+            jw = take ? (uint32_t)j : jw;
+        }
+        return tm >= tau_kill;
+    }
+
+    // resume with a known witness bin (cross-sections from a per-lane table)
+    __device__ __forceinline__ void resume(uint32_t j, const float *sig) {
+        jw = j;
+        wH = sig[j];
+        wHe1 = S == 1 ? 0.0f : sig[MB + j];
+        wHe2 = S == 1 ? 0.0f : sig[2 * MB + j];
+    }
+
+    __device__ __forceinline__ bool extinguished(CTab<float> tab, uint32_t active, float tau_kill,
+                                                 const float (&N)[S == 1 ? 1 : 3]) {
+        if (depth(wH, wHe1, wHe2, N) < tau_kill) return false;
+        return full(tab, active, tau_kill, N);
+    }
+};
+
+// Extinction state of either form: the float64 form tests the minimum of its
+// per-bin depths (returned by cross_cell), the float32 form a witness.
+template <typename R, int S, int MB>
+struct DepthTest {
+    static constexpr bool F64 = std::is_same<R, double>::value;
+    Extinction<S, MB> ext;
+    __device__ __forceinline__ void start(CTab<R> tab, uint32_t active, const R (&D)[DepthState<R, S, MB>::N]) {
+        if constexpr (!F64) (void)ext.full(tab, active, 0.0f, D);
+    }
+    __device__ __forceinline__ bool extinguished(CTab<R> tab, uint32_t active, double tau_kill, R tmin,
+                                                 const R (&D)[DepthState<R, S, MB>::N]) {
+        if constexpr (F64) return tmin >= tau_kill;
+        else return ext.extinguished(tab, active, (float)tau_kill, D);
+    }
+};
 
 // Distance (half cells) from the start point o to the next face along one
 // axis, for a packet now in cell k: 1 for an axis the packet does not move

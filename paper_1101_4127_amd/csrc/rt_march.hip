@@ -109,6 +109,7 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
     constexpr int ND = DepthState<R, S, MB>::N;
     R F[MB], D[ND];
     uint32_t active = 0;                        // bins the packet's source populates
+    DepthTest<R, S, MB> dtest;
 #pragma unroll
     for (int j = 0; j < MB; ++j) F[j] = R(0);
 #pragma unroll
@@ -202,6 +203,7 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
 #pragma unroll
                     for (int j = 0; j < ND; ++j)
                         D[j] = (!DepthState<R, S, MB>::F64 || ((active >> j) & 1u)) ? R(0) : R(INFINITY);
+                    dtest.start(tab, active, D);
                     sprev = 0.0; pnum = 0; pden = 1;
                     absd = 0.0;
                     count = 0;
@@ -254,7 +256,7 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
 
             // ---- Eq. (1) per bin and the split among absorbers ----
             R absorbed, e0, e1, e2, hs, tmin;
-            cross_cell<R, S, TH, MB>(l, kap, tab, active, F, D, absorbed, e0, e1, e2, hs, tmin);
+            cross_cell<R, S, TH, MB>(l, kap, tab, F, D, absorbed, e0, e1, e2, hs, tmin);
 
             // ---- deposit: float64 accumulators, hardware atomics at L2 ----
             double *cell = p.acc + (size_t)slot * ACC;
@@ -285,7 +287,7 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
             ++count;
 
             // ---- termination: extinguished (checked first) or out of the grid ----
-            const uint32_t fate = (tmin >= (R)p.tau_kill) ? 1u : (out ? 2u : 0u);
+            const uint32_t fate = dtest.extinguished(tab, active, p.tau_kill, tmin, D) ? 1u : (out ? 2u : 0u);
             if (fate == 0) {
                 slot = nslot;
                 kap = knext;

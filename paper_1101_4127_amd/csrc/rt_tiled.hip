@@ -77,12 +77,14 @@ struct TParams {
 //   0-2  c[3], the integer direction
 //   3    the cell it is in (or about to enter) | axis of the last face crossed
 //        (3: none yet) << 30
-//   4    next-face distances d0 | d1 << 16 (half cells)
+//   4    next-face distances d0 | d1 << 16 (half cells), with the witness
+//        bin of the float32 extinction test in bits 12-15
 //   5    d2 | bins the source populates << 16
 //   6-7  packet weight (photons per unit of the SED), float64
-//   8    source
+//   8    length scale |c| dx / 2 of the chord (float32 form, in 1e18 cm);
+//        float64 form: words 8-9, float64 in cm
 // float32 form: then the column densities N_s and the photons per bin F_j;
-// float64 form: a pad word, then F_j and the optical depths T_j.
+// float64 form: F_j and the optical depths T_j.
 template <typename R, int S, int MB>
 struct TRec {
     static constexpr bool F64 = std::is_same<R, double>::value;
@@ -126,8 +128,15 @@ __device__ __forceinline__ uint32_t tile_of_cell(const GridGeom &G, int k0, int 
          + (uint32_t)(k0 >> kTileLog2);
 }
 
+// Cell of a tile in LDS: linear order x + 8 y + 64 z (two bit operations per
+// crossing); the grid's accumulators and absorbers keep the Morton order of
+// the brick, so staging and write-out permute within the tile.
 __device__ __forceinline__ uint32_t local_cell(int k0, int k1, int k2) {
-    return spread3((uint32_t)k0 & 7u) | (spread3((uint32_t)k1 & 7u) << 1) | (spread3((uint32_t)k2 & 7u) << 2);
+    return ((uint32_t)k0 & 7u) | (((uint32_t)k1 & 7u) << 3) | (((uint32_t)k2 & 7u) << 6);
+}
+
+__device__ __forceinline__ uint32_t local_to_morton(uint32_t i) {
+    return spread3(i & 7u) | (spread3((i >> 3) & 7u) << 1) | (spread3(i >> 6) << 2);
 }
 
 // neighbour code (dx+1) + 3 (dy+1) + 9 (dz+1) -> tile id offset
@@ -191,20 +200,22 @@ __device__ void block_ledger_add(LedgerSlot *slot, double (&v)[8], unsigned long
 
 template <typename R, int S, int MB>
 __device__ __forceinline__ void store_record(uint4 *dst, int32_t c0, int32_t c1, int32_t c2, uint32_t kw,
-                                             uint32_t d0, uint32_t d1, uint32_t d2, uint32_t active, double w,
-                                             uint32_t srcid, const R (&F)[MB],
+                                             uint32_t d0, uint32_t jw, uint32_t d1, uint32_t d2, uint32_t active,
+                                             double w,
+                                             R len, const R (&F)[MB],
                                              const R (&D)[DepthState<R, S, MB>::N]) {
     using RL = TRec<R, S, MB>;
     uint32_t x[RL::WORDS];
 #pragma unroll
     for (int i = 0; i < RL::WORDS; ++i) x[i] = 0u;
     x[0] = (uint32_t)c0; x[1] = (uint32_t)c1; x[2] = (uint32_t)c2; x[3] = kw;
-    x[4] = d0 | (d1 << 16);
+    x[4] = d0 | (jw << 12) | (d1 << 16);
     x[5] = d2 | (active << 16);
     x[6] = (uint32_t)__double2loint(w);
     x[7] = (uint32_t)__double2hiint(w);
-    x[8] = srcid;
     if constexpr (RL::F64) {
+        x[8] = (uint32_t)__double2loint(len);
+        x[9] = (uint32_t)__double2hiint(len);
 #pragma unroll
         for (int j = 0; j < MB; ++j) {
             x[RL::HDR + 2 * j] = (uint32_t)__double2loint(F[j]);
@@ -213,6 +224,7 @@ __device__ __forceinline__ void store_record(uint4 *dst, int32_t c0, int32_t c1,
             x[RL::HDR + 2 * MB + 1 + 2 * j] = (uint32_t)__double2hiint(D[j]);
         }
     } else {
+        x[8] = __float_as_uint(len);
 #pragma unroll
         for (int j = 0; j < RL::ND; ++j) x[RL::HDR + j] = __float_as_uint(D[j]);
 #pragma unroll
@@ -220,6 +232,33 @@ __device__ __forceinline__ void store_record(uint4 *dst, int32_t c0, int32_t c1,
     }
 #pragma unroll
     for (int u = 0; u < RL::UNITS; ++u) dst[u] = make_uint4(x[4 * u], x[4 * u + 1], x[4 * u + 2], x[4 * u + 3]);
+}
+
+// Write back what a crossing changes (cell, face distances, witness, depth
+// state, photons); direction, weight, chord scale and SED mask stay.
+template <typename R, int S, int MB>
+__device__ __forceinline__ void store_moving(uint4 *dst, uint32_t kw, uint32_t d0, uint32_t jw, uint32_t d1,
+                                             uint32_t d2, uint32_t active, const R (&F)[MB],
+                                             const R (&D)[DepthState<R, S, MB>::N]) {
+    using RL = TRec<R, S, MB>;
+    uint32_t *w = reinterpret_cast<uint32_t *>(dst);
+    w[3] = kw;
+    w[4] = d0 | (jw << 12) | (d1 << 16);
+    w[5] = d2 | (active << 16);
+    if constexpr (RL::F64) {
+#pragma unroll
+        for (int j = 0; j < MB; ++j) {
+            w[RL::HDR + 2 * j] = (uint32_t)__double2loint(F[j]);
+            w[RL::HDR + 1 + 2 * j] = (uint32_t)__double2hiint(F[j]);
+            w[RL::HDR + 2 * MB + 2 * j] = (uint32_t)__double2loint(D[j]);
+            w[RL::HDR + 2 * MB + 1 + 2 * j] = (uint32_t)__double2hiint(D[j]);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < RL::ND; ++j) w[RL::HDR + j] = __float_as_uint(D[j]);
+#pragma unroll
+        for (int j = 0; j < MB; ++j) w[RL::HDR + RL::ND + j] = __float_as_uint(F[j]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -263,9 +302,13 @@ __global__ void __launch_bounds__(kTBlock) k_temit(const TParams p) {
 #pragma unroll
             for (int j = 0; j < ND; ++j) D[j] = (!RL::F64 || ((active >> j) & 1u)) ? R(0) : R(INFINITY);
             const uint32_t a0 = pack_dir(c[0]), a1 = pack_dir(c[1]), a2 = pack_dir(c[2]);
+            const int64_t qq = (int64_t)c[0] * c[0] + (int64_t)c[1] * c[1] + (int64_t)c[2] * c[2];
+            const double Ld = sqrt((double)qq) * p.half_dl;
+            const R len = RL::F64 ? (R)Ld : (R)(Ld * p.len_scale);
+            const uint32_t jw = active ? (uint32_t)__builtin_ctz(active) : 0u;   // all depths 0: first bin
             store_record<R, S, MB>(recs + (size_t)i * RL::UNITS, c[0], c[1], c[2], pack_cell(k0, k1, k2, 3u),
-                                   next_face(k0, sr.o[0], a0), next_face(k1, sr.o[1], a1),
-                                   next_face(k2, sr.o[2], a2), active, ww, sidx, F, D);
+                                   next_face(k0, sr.o[0], a0), jw, next_face(k1, sr.o[1], a1),
+                                   next_face(k2, sr.o[2], a2), active, ww, len, F, D);
             tile = tile_of_cell(p.geo, k0, k1, k2);
             const int32_t tix = trace_slot(p, g);
             if (tix >= 0) p.trace[(size_t)tix * (RT_TRACE_HDR_DEV + p.trace_len)] = 0;
@@ -457,7 +500,9 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
     __shared__ uint32_t s_cnt[kCodes];
     __shared__ uint32_t s_list[kMaxRun];
     __shared__ uint32_t s_next, s_claim;
+    __shared__ float s_sigf[3 * MB];          // float32 form: cross-sections, indexed per lane
     const CTab<R> tab = (CTab<R>)p.tab;
+    if (!F64 && threadIdx.x < 3 * MB) s_sigf[threadIdx.x] = (float)tab[threadIdx.x];
 
     const uint32_t nch = p.ctrl->n_chunks[cur];
     const TChunk *chs = cur ? p.ch1 : p.ch0;
@@ -487,7 +532,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
 
         // stage the tile's absorbers, clear its accumulators
         const KV *kt = kappa + ((size_t)tile << (3 * kTileLog2));
-        for (int i = threadIdx.x; i < kTileCells; i += kTBlock) s_kap[i] = kt[i];
+        for (int i = threadIdx.x; i < kTileCells; i += kTBlock) s_kap[i] = kt[local_to_morton(i)];
         for (int i = threadIdx.x; i < kTileCells * (int)ACC; i += kTBlock) s_acc[i] = 0.0;
         for (uint32_t i = threadIdx.x; i < ch.len; i += kTBlock) s_list[i] = list[ch.start + i];
         if (threadIdx.x < kCodes) s_cnt[threadIdx.x] = 0u;
@@ -502,7 +547,8 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
         uint32_t d0 = 1, d1 = 1, d2 = 1, a0 = 0, a1 = 0, a2 = 0, pnum = 0, pden = 1;
         double sprev = 0.0, L = 0.0, w = 0.0, absd = 0.0;
         float Lf = 0.0f;
-        uint32_t loc = 0, srcid = 0, count = 0, active = 0;
+        uint32_t loc = 0, count = 0, active = 0;
+        DepthTest<R, S, MB> dtest;
         int32_t tix = -1;
         KV kap{};
         R F[MB], D[ND];
@@ -540,12 +586,14 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                             }
                             const int32_t c0 = (int32_t)wd[0], c1 = (int32_t)wd[1], c2 = (int32_t)wd[2];
                             const uint32_t kw = wd[3];
-                            d0 = wd[4] & 0xffffu;
+                            d0 = wd[4] & 0xfffu;
+                            const uint32_t jw = (wd[4] >> 12) & 0xfu;
                             d1 = wd[4] >> 16;
                             d2 = wd[5] & 0xffffu;
                             active = wd[5] >> 16;
                             w = __hiloint2double((int)wd[7], (int)wd[6]);
-                            srcid = wd[8];
+                            if constexpr (F64) L = __hiloint2double((int)wd[9], (int)wd[8]);
+                            else Lf = __uint_as_float(wd[8]);
                             if constexpr (F64) {
 #pragma unroll
                                 for (int j = 0; j < MB; ++j) {
@@ -564,7 +612,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                             k2 = (int)((kw >> 20) & 1023u);
                             const uint32_t ax = kw >> 30;
                             // a record that is not a packet of this tile is an internal error
-                            const bool bad = srcid >= p.n_src || k0 >= p.geo.n[0] || k1 >= p.geo.n[1]
+                            const bool bad = k0 >= p.geo.n[0] || k1 >= p.geo.n[1]
                                 || k2 >= p.geo.n[2] || (k0 >> kTileLog2) != tx || (k1 >> kTileLog2) != ty
                                 || (k2 >> kTileLog2) != tz || ((uint32_t)(c0 | c1 | c2) == 0u);
                             if (bad) {
@@ -581,9 +629,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                                     pden = (ax == 0u ? a0 : (ax == 1u ? a1 : a2)) & kMag;
                                 }
                                 sprev = (ax == 3u) ? 0.0 : (double)pnum / (double)pden;
-                                const int64_t qq = (int64_t)c0 * c0 + (int64_t)c1 * c1 + (int64_t)c2 * c2;
-                                const double Ld = sqrt((double)qq) * p.half_dl;
-                                if (F64) L = Ld; else Lf = (float)(Ld * p.len_scale);
+                                if constexpr (!F64) dtest.ext.resume(jw < (uint32_t)MB ? jw : 0u, s_sigf);
                                 tix = trace_slot(p, p.g0 + ri);
                                 count = tix >= 0 ? (uint32_t)p.trace[(size_t)tix * (RT_TRACE_HDR_DEV + p.trace_len)] : 0u;
                                 absd = 0.0;
@@ -616,7 +662,8 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                     const uint32_t diff = num * pden - pnum * den;
                     l = Lf * (float)diff * __builtin_amdgcn_rcpf((float)den * (float)pden);
                 }
-                const int here = k0 + p.geo.n[0] * (k1 + p.geo.n[1] * k2);
+                int here = 0;                          // natural index, for traces only
+                if (p.trace_n > 0) here = k0 + p.geo.n[0] * (k1 + p.geo.n[1] * k2);
                 if (m0) { k0 += (a0 & kNeg) ? -1 : 1; d0 += 2u; }
                 if (m1) { k1 += (a1 & kNeg) ? -1 : 1; d1 += 2u; }
                 if (m2) { k2 += (a2 & kNeg) ? -1 : 1; d2 += 2u; }
@@ -632,28 +679,19 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                 const KV knext = s_kap[nloc];
 
                 R absorbed, e0, e1, e2, hs, tmin;
-                cross_cell<R, S, TH, MB>(l, kap, tab, active, F, D, absorbed, e0, e1, e2, hs, tmin);
+                cross_cell<R, S, TH, MB>(l, kap, tab, F, D, absorbed, e0, e1, e2, hs, tmin);
 
                 // ---- deposit into the tile's float64 accumulators in LDS ----
+                // (zero deposits are added too: an LDS add is cheaper than the branch)
                 double *cell = s_acc + loc * ACC;
                 if (S == 1) {
-                    const double v = w * (double)absorbed;
-                    if (v != 0.0) atomicAdd(cell, v);
-                    if (TH) {
-                        const double q = w * ((double)hs * kEvErg);
-                        if (q != 0.0) atomicAdd(cell + 1, q);
-                    }
+                    atomicAdd(cell, w * (double)absorbed);
+                    if (TH) atomicAdd(cell + 1, w * ((double)hs * kEvErg));
                 } else {
-                    const double v0 = w * (double)e0;
-                    const double v1 = w * (double)e1;
-                    const double v2 = w * (double)e2;
-                    if (v0 != 0.0) atomicAdd(cell, v0);
-                    if (v1 != 0.0) atomicAdd(cell + 1, v1);
-                    if (v2 != 0.0) atomicAdd(cell + 2, v2);
-                    if (TH) {
-                        const double q = w * ((double)hs * kEvErg);
-                        if (q != 0.0) atomicAdd(cell + 3, q);
-                    }
+                    atomicAdd(cell, w * (double)e0);
+                    atomicAdd(cell + 1, w * (double)e1);
+                    atomicAdd(cell + 2, w * (double)e2);
+                    if (TH) atomicAdd(cell + 3, w * ((double)hs * kEvErg));
                 }
                 absd += (double)absorbed;
                 it_cross = 1;
@@ -662,7 +700,8 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                 if (traced && count < (uint32_t)p.trace_len) rec[RT_TRACE_HDR_DEV + count] = here;
                 ++count;
 
-                    const uint32_t fate = (tmin >= (R)p.tau_kill) ? 1u : (out ? 2u : (leave ? 3u : 0u));
+                const uint32_t fate = dtest.extinguished(tab, active, p.tau_kill, tmin, D) ? 1u
+                                      : (out ? 2u : (leave ? 3u : 0u));
                 if (fate == 0u) {
                     loc = nloc;
                     kap = knext;
@@ -672,9 +711,10 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                     if (fate == 3u) {
                         // moves on into a neighbour tile: record back, rank among the run's
                         // packets bound for the same tile
-                        store_record<R, S, MB>(recs + (size_t)rid * RL::UNITS, unpack_dir(a0), unpack_dir(a1),
-                                               unpack_dir(a2), pack_cell(k0, k1, k2, (uint32_t)ax), d0, d1, d2,
-                                               active, w, srcid, F, D);
+                        uint32_t jw = 0;
+                        if constexpr (!F64) jw = dtest.ext.jw;
+                        store_moving<R, S, MB>(recs + (size_t)rid * RL::UNITS, pack_cell(k0, k1, k2, (uint32_t)ax),
+                                               d0, jw, d1, d2, active, F, D);
                         const uint32_t code = (uint32_t)((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1));
                         const uint32_t rank = atomicAdd(&s_cnt[code], 1u);
                         p.side[pos] = code | (rank << 5);
@@ -695,7 +735,8 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                             rec[4] = unpack_dir(a0);
                             rec[5] = unpack_dir(a1);
                             rec[6] = unpack_dir(a2);
-                            rec[7] = (int32_t)srcid;
+                            uint32_t ns;
+                            rec[7] = (int32_t)source_of(p.g0 + rid, p.q, p.r, ns);
                         }
                     }
                     alive = false;
@@ -715,8 +756,9 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
         for (int i = threadIdx.x; i < kTileCells * (int)ACC; i += kTBlock) {
             const double v = s_acc[i];
             if (v != 0.0) {
-                if (ch.shared) unsafeAtomicAdd(ga + i, v);
-                else ga[i] += v;
+                double *g = ga + local_to_morton((uint32_t)i / ACC) * ACC + (uint32_t)i % ACC;
+                if (ch.shared) unsafeAtomicAdd(g, v);
+                else *g += v;
             }
         }
         // ---- reserve the run's places in the neighbours' next lists ----

@@ -9,9 +9,11 @@ the densest 1 % of cells, 8 frequency bins, 1e8 packets per step; inputs are
 seeded and synthetic and already resident in HBM when timing starts.
 
 Prints one JSON line: whole-step cell crossings/s of the float32-march /
-float64-accumulate form, the march kernel's roofline (algorithmic bytes per
-crossing over its HIP-event duration), the plain float64 form measured the
-same way, and the float64 CPU oracle timed on a bounded sample.
+float64-accumulate form (tiled march, every packet of the step in flight),
+the march kernel's roofline (algorithmic bytes per crossing over the
+HIP-event duration of its launches on the library's stream), the plain
+float64 form measured the same way, and the float64 CPU oracle timed on a
+bounded sample.
 """
 from __future__ import annotations
 
@@ -31,8 +33,8 @@ HBM_PEAK_GBS = 8000.0
 # accumulator updates (H+He with heating)
 BYTES_F32 = 3 * 4 + 4 * 8
 BYTES_F64 = 3 * 8 + 4 * 8
-MARCH_SRC = os.path.join(ROOT, "paper_1101_4127_amd", "csrc", "rt_march.hip")
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "march_traffic.json")
+KERNELS = {False: "k_tmarch<float, 3, true, 8>", True: "k_march<float, 3, true, 8>"}
 
 
 def log(*a):
@@ -41,7 +43,7 @@ def log(*a):
 
 def march_hash() -> str:
     h = hashlib.sha256()
-    for name in ("rt_march.hip", "rt_device.h", "rt_internal.h"):
+    for name in ("rt_tiled.hip", "rt_march.hip", "rt_cross.h", "rt_device.h", "rt_internal.h"):
         with open(os.path.join(ROOT, "paper_1101_4127_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -61,12 +63,15 @@ def workload(name: str, packets):
 def time_form(work, *, fp64: bool, steps: int, warmup: int, tiles: dict):
     import torch
     from paper_1101_4127_amd import rt
+    tiles = dict(tiles)
+    if not tiles.get("direct") and not tiles.get("inflight"):
+        tiles["inflight"] = -(-work.packets // work.n_sub)        # every packet of a sub-step in flight
     s = rt.Solve(work, fp64=fp64, time_march=True, **tiles)
     for i in range(warmup):
         s.step(seed=1000 + i)
     torch.cuda.synchronize()
     cross = 0
-    march_ms = 0.0
+    march_ms = kernel_ms = 0.0
     launches = 0
     resid = 0.0
     t0 = time.perf_counter()
@@ -74,14 +79,30 @@ def time_form(work, *, fp64: bool, steps: int, warmup: int, tiles: dict):
         st = s.step(seed=1 + i)
         cross += st["crossings"]
         march_ms += st["march_ms"]
-        launches += st["substeps"]
+        kernel_ms += st["kernel_ms"]
+        launches += st["kernel_launches"]
         resid = max(resid, abs(st["emitted"] - st["absorbed"] - st["escaped"] - st["truncated"]) / st["emitted"])
         if st["nonfinite"]:
             raise SystemExit("non-finite cell state")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     s.release()
-    return dict(crossings=cross, wall_s=wall, march_ms=march_ms, launches=launches, resid=resid)
+    return dict(crossings=cross, wall_s=wall, march_ms=march_ms, kernel_ms=kernel_ms, launches=launches,
+                resid=resid)
+
+
+def copy_calibration(mib: int):
+    """A plain device copy of known size, for scaling HBM counters (run under
+    rocprofv3 --pmc next to the march)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy calibration: {mib} MiB read + {mib} MiB written")
+    del a, b
 
 
 def cpu_baseline(work, target_s: float):
@@ -151,10 +172,13 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2, help="timed steps of the plain float64 form")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--brick", type=int, default=-1)
-    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--direct", action="store_true", help="per-packet march instead of the tiled one")
+    ap.add_argument("--inflight", type=int, default=0)
+    ap.add_argument("--run-len", type=int, default=0)
     ap.add_argument("--refill", type=int, default=0)
     ap.add_argument("--bpcu", type=int, default=0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run a device copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
@@ -167,8 +191,10 @@ def main():
     from paper_1101_4127_amd import rt
     rt.lib()
 
-    tiles = dict(brick_log2=args.brick, wave_chunk=args.chunk, refill_min=args.refill,
+    tiles = dict(direct=args.direct, inflight=args.inflight, run_len=args.run_len, refill_min=args.refill,
                  blocks_per_cu=args.bpcu)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
     t0 = time.perf_counter()
     work = workload(args.workload, args.packets)
     log(f"workload {work.name}: {work.ncell} cells, {len(work.src_ndot)} sources, "
@@ -176,11 +202,13 @@ def main():
 
     f32 = time_form(work, fp64=False, steps=args.steps, warmup=args.warmup, tiles=tiles)
     value = f32["crossings"] / f32["wall_s"]
-    per_launch = f32["crossings"] / max(f32["launches"], 1)
-    avg_ms = f32["march_ms"] / max(f32["launches"], 1)
+    launches = max(f32["launches"], 1)
+    per_launch = f32["crossings"] / launches
+    avg_ms = f32["kernel_ms"] / launches
     achieved = BYTES_F32 * per_launch / (avg_ms * 1e-3) / 1e9
-    log(f"float32 march: {value:.4g} crossings/s, march {avg_ms:.2f} ms/launch, {achieved:.0f} GB/s "
-        f"algorithmic, conservation residual {f32['resid']:.2e}")
+    log(f"float32 march: {value:.4g} crossings/s, march kernel {f32['kernel_ms'] / args.steps:.1f} ms/step "
+        f"in {launches // args.steps} launches, {achieved:.0f} GB/s algorithmic, whole march "
+        f"{f32['march_ms'] / args.steps:.1f} ms/step, conservation residual {f32['resid']:.2e}")
     out = {
         "metric": METRIC, "value": value, "unit": "crossings/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * f32["wall_s"] / args.steps, "higher_is_better": True,
@@ -188,21 +216,27 @@ def main():
         "config": {"workload": work.name, "grid": list(work.n), "sources": len(work.src_ndot),
                    "packets_per_step": work.packets, "bins": work.bins.n_bins,
                    "form": "float32 march, float64 accumulators and cell update",
+                   "march": "per-packet" if args.direct else "tiled",
                    "crossings_per_step": f32["crossings"] / args.steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(per_launch),
-                     "kernel": "k_march<float,3,true,8>", "bytes_per_crossing": BYTES_F32,
-                     "march_ms_per_launch": avg_ms},
+                     "kernel": KERNELS[args.direct], "bytes_per_crossing": BYTES_F32,
+                     "crossings_per_launch": per_launch, "avg_launch_ms": avg_ms,
+                     "whole_march_ms_per_step": f32["march_ms"] / args.steps,
+                     "whole_march_gcross_per_s": f32["crossings"] / (f32["march_ms"] * 1e-3) / 1e9},
         "conservation_residual": f32["resid"],
     }
     if args.fp64_steps > 0:
         f64 = time_form(work, fp64=True, steps=args.fp64_steps, warmup=1, tiles=tiles)
         v64 = f64["crossings"] / f64["wall_s"]
-        ms64 = f64["march_ms"] / max(f64["launches"], 1)
-        a64 = BYTES_F64 * (f64["crossings"] / max(f64["launches"], 1)) / (ms64 * 1e-3) / 1e9
-        log(f"float64 plain: {v64:.4g} crossings/s, march {ms64:.2f} ms/launch, {a64:.0f} GB/s")
-        out["fp64_plain"] = {"value": v64, "unit": "crossings/s", "march_ms_per_launch": ms64,
+        l64 = max(f64["launches"], 1)
+        ms64 = f64["kernel_ms"] / l64
+        a64 = BYTES_F64 * (f64["crossings"] / l64) / (ms64 * 1e-3) / 1e9
+        log(f"float64 plain: {v64:.4g} crossings/s, march kernel {f64['kernel_ms'] / args.fp64_steps:.1f} "
+            f"ms/step, {a64:.0f} GB/s algorithmic")
+        out["fp64_plain"] = {"value": v64, "unit": "crossings/s", "avg_launch_ms": ms64,
                              "achieved_gbs": a64, "bytes_per_crossing": BYTES_F64,
+                             "ms_per_step": 1e3 * f64["wall_s"] / args.fp64_steps,
                              "speedup_of_fp32_form": value / v64, "conservation_residual": f64["resid"]}
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()

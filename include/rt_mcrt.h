@@ -146,7 +146,11 @@ typedef struct {
     uint32_t nonfinite; /* nonzero if the cell update produced a non-finite value */
     uint32_t errors;    /* nonzero if a consistency check of the march failed
                            (rt_read_stats then returns RT_EINTERNAL) */
-    double march_ms;    /* summed march kernel time (RT_TIME_MARCH), else 0 */
+    double march_ms;    /* RT_TIME_MARCH: time of the whole march of every sub-step
+                           (tiled march: emission, passes, sorts), else 0 */
+    double kernel_ms;   /* RT_TIME_MARCH: summed time of the march kernel's own
+                           launches (tiled march: one per pass), else 0 */
+    int64_t kernel_launches; /* launches timed in kernel_ms */
 } rt_step_stats;
 
 /* Fill *d with defaults: 1 bin, tau_kill 30, n_sub 1, n_chem 8, redshift -1,

@@ -182,13 +182,17 @@ struct rt_solve {
     uint64_t step_index;
     int blocks, chunk, refill_min;
     bool dead;
-    // march timing (RT_TIME_MARCH): one event pair per timed sub-step of the last rt_step
+    // march timing (RT_TIME_MARCH): one event pair per timed sub-step of the last rt_step,
+    // and one per launch of the march kernel itself (tiled march: one per pass)
     std::vector<hipEvent_t> ev;
     int timed;
+    std::vector<hipEvent_t> kev;
+    int ktimed;
 };
 
 namespace {
 constexpr int kMaxTimedSubsteps = 1024;
+constexpr int kMaxTimedKernels = 16384;
 }
 
 namespace {
@@ -324,14 +328,20 @@ int32_t rt_init_grid(const rt_grid_desc *d, void *d_ws, size_t ws_bytes, int64_t
     h->refill_min = d->refill_min > 0 ? d->refill_min : (p.tiled ? 16 : 8);
     h->dead = false;
     h->timed = 0;
+    h->ktimed = 0;
     if (d->flags & RT_TIME_MARCH) {
         h->ev.resize(2 * kMaxTimedSubsteps);
-        for (size_t i = 0; i < h->ev.size(); ++i)
-            if (hipEventCreate(&h->ev[i]) != hipSuccess) {
-                for (size_t k = 0; k < i; ++k) (void)hipEventDestroy(h->ev[k]);
-                delete h;
-                return RT_EDEVICE;
-            }
+        h->kev.resize(p.tiled ? 2 * kMaxTimedKernels : 0);
+        bool ok = true;
+        for (size_t i = 0; i < h->ev.size() && ok; ++i) ok = hipEventCreate(&h->ev[i]) == hipSuccess;
+        for (size_t i = 0; i < h->kev.size() && ok; ++i) ok = hipEventCreate(&h->kev[i]) == hipSuccess;
+        if (!ok) {
+            // events are created in order; destroy the ones that exist
+            for (hipEvent_t e : h->ev) if (e) (void)hipEventDestroy(e);
+            for (hipEvent_t e : h->kev) if (e) (void)hipEventDestroy(e);
+            delete h;
+            return RT_EDEVICE;
+        }
     }
 
     rtk::CellLaunch c = cell_launch(h, 0.0);
@@ -345,6 +355,7 @@ int32_t rt_init_grid(const rt_grid_desc *d, void *d_ws, size_t ws_bytes, int64_t
         rtk::launch_ledger_zero(c.ledger, h->stream) != hipSuccess ||
         (p.tiled && rtk::launch_tiled_reset(tiled_launch(h, tiled_base(h))) != hipSuccess)) {
         for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+        for (hipEvent_t e : h->kev) (void)hipEventDestroy(e);
         delete h;
         return RT_EDEVICE;
     }
@@ -428,6 +439,19 @@ int32_t rt_read_stats(rt_solve_t h, rt_step_stats *stats) {
         if (hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]) != hipSuccess) return fail(h);
         stats->march_ms += ms;
     }
+    stats->kernel_ms = 0.0;
+    stats->kernel_launches = 0;
+    if (h->plan.tiled) {
+        for (int i = 0; i < h->ktimed; ++i) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, h->kev[2 * i], h->kev[2 * i + 1]) != hipSuccess) return fail(h);
+            stats->kernel_ms += ms;
+        }
+        stats->kernel_launches = h->ktimed;
+    } else {
+        stats->kernel_ms = stats->march_ms;      // one march launch per sub-step
+        stats->kernel_launches = h->timed;
+    }
     if (l.errors) {
         h->dead = true;
         return RT_EINTERNAL;
@@ -482,6 +506,7 @@ int32_t rt_step(rt_solve_t h, double dt_s, int64_t n_packets, uint64_t seed, rt_
     m.stream = h->stream;
 
     h->timed = 0;
+    h->ktimed = 0;
     for (int32_t i = 0; i < nsub; ++i) {
         const int64_t Pi = base + (i < extra ? 1 : 0);
         if (rtk::launch_prep(c) != hipSuccess) return fail(h);
@@ -493,6 +518,11 @@ int32_t rt_step(rt_solve_t h, double dt_s, int64_t n_packets, uint64_t seed, rt_
             if (timed && hipEventRecord(h->ev[2 * h->timed], h->stream) != hipSuccess) return fail(h);
             if (p.tiled) {
                 rtk::TiledLaunch t = tiled_launch(h, m);
+                if (!h->kev.empty()) {
+                    t.ev = h->kev.data();
+                    t.ev_cap = kMaxTimedKernels;
+                    t.ev_used = &h->ktimed;
+                }
                 if (rtk::launch_tiled_slots_zero(t) != hipSuccess) return fail(h);
                 for (int64_t g0 = 0; g0 < Pi; g0 += p.capacity) {
                     t.g0 = (uint32_t)g0;
@@ -578,6 +608,7 @@ int32_t rt_release(rt_solve_t h) {
     if (!valid(h)) return RT_EINVAL;
     const bool ok = h->dead || hipStreamSynchronize(h->stream) == hipSuccess;
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : h->kev) (void)hipEventDestroy(e);
     h->magic = 0;
     delete h;
     return ok ? RT_OK : RT_EDEVICE;

@@ -124,6 +124,10 @@ struct TiledLaunch {
     TChunk *chunks[2];
     TCtrl *ctrl;
     StepLedger *ledger;
+    // optional timing of every march-kernel launch: event pairs ev[2i], ev[2i+1]
+    hipEvent_t *ev;
+    int ev_cap;           // pairs available
+    int *ev_used;         // pairs recorded so far (host counter)
 };
 
 size_t tiled_record_bytes(int fp64, int species, int mb);

@@ -865,7 +865,13 @@ hipError_t run_batch(const TiledLaunch &t) {
     hipLaunchKernelGGL(k_tscatter_emit, grid, blk, 0, st, p);
     int cur = 0;
     for (uint32_t pass = 0; pass < t.passes; ++pass) {
+        const bool timed = t.ev && *t.ev_used < t.ev_cap;
+        if (timed) (void)hipEventRecord(t.ev[2 * *t.ev_used], st);
         hipLaunchKernelGGL((k_tmarch<R, S, TH, MB>), grid, blk, 0, st, p, cur);
+        if (timed) {
+            (void)hipEventRecord(t.ev[2 * *t.ev_used + 1], st);
+            ++*t.ev_used;
+        }
         scan(p, t, cur ^ 1);
         hipLaunchKernelGGL(k_tscatter, grid, blk, 0, st, p, cur);
         cur ^= 1;

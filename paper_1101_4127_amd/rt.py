@@ -48,6 +48,7 @@ class StepStats(C.Structure):
         ("truncated", C.c_double), ("crossings", C.c_int64), ("packets", C.c_int64),
         ("n_escaped", C.c_int64), ("n_truncated", C.c_int64), ("substeps", C.c_int64),
         ("nonfinite", C.c_uint32), ("errors", C.c_uint32), ("march_ms", C.c_double),
+        ("kernel_ms", C.c_double), ("kernel_launches", C.c_int64),
     ]
 
     def as_dict(self) -> dict:

@@ -46,11 +46,12 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "{HEADER}"
 int main(void) {{
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(rt_grid_desc), offsetof(rt_grid_desc, solve_id),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(rt_grid_desc), offsetof(rt_grid_desc, solve_id),
          offsetof(rt_grid_desc, trace_stride), offsetof(rt_grid_desc, run_len),
          offsetof(rt_grid_desc, inflight), sizeof(rt_step_stats),
          offsetof(rt_step_stats, crossings), offsetof(rt_step_stats, nonfinite),
-         offsetof(rt_step_stats, errors), offsetof(rt_step_stats, march_ms));
+         offsetof(rt_step_stats, errors), offsetof(rt_step_stats, march_ms),
+         offsetof(rt_step_stats, kernel_launches));
   return 0;
 }}""")
     exe = tmp_path / "layout"
@@ -59,7 +60,8 @@ int main(void) {{
     assert vals == [C.sizeof(rt.GridDesc), rt.GridDesc.solve_id.offset, rt.GridDesc.trace_stride.offset,
                     rt.GridDesc.run_len.offset, rt.GridDesc.inflight.offset,
                     C.sizeof(rt.StepStats), rt.StepStats.crossings.offset, rt.StepStats.nonfinite.offset,
-                    rt.StepStats.errors.offset, rt.StepStats.march_ms.offset]
+                    rt.StepStats.errors.offset, rt.StepStats.march_ms.offset,
+                    rt.StepStats.kernel_launches.offset]
 
 
 def test_defaults_and_strerror(L):

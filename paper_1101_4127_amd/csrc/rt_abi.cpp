@@ -169,6 +169,18 @@ std::vector<double> march_table(const rt_grid_desc *d, const Plan &p) {
     return t;
 }
 
+// 1 when the 8-bin H+He table has the threshold-aligned layout the tiled
+// march has a specialisation for: HeI and HeII cross-sections zero in bins
+// 0-2, HeII zero in bins 3-4.
+int32_t bin_layout(const rt_grid_desc *d, const Plan &p) {
+    if (p.species != 3 || p.mb != 8) return 0;
+    for (int j = 0; j < 5 && j < d->n_bins; ++j) {
+        if (d->sigma_cm2[2][j] != 0.0) return 0;
+        if (j < 3 && d->sigma_cm2[1][j] != 0.0) return 0;
+    }
+    return 1;
+}
+
 }  // namespace
 
 struct rt_solve {
@@ -481,6 +493,7 @@ int32_t rt_step(rt_solve_t h, double dt_s, int64_t n_packets, uint64_t seed, rt_
     m.fp64 = p.fp64;
     m.n_bins = h->d.n_bins;
     m.mb = p.mb;
+    m.layout = bin_layout(&h->d, p);
     m.src = reinterpret_cast<const rtk::SourceRec *>(h->ws + p.off_src);
     m.src_ndot = reinterpret_cast<const double *>(h->ws + p.off_ndot);
     m.src_sedsum = reinterpret_cast<const double *>(h->ws + p.off_sedsum);

@@ -63,7 +63,7 @@ __device__ __forceinline__ int exit_face(uint32_t d0, uint32_t d1, uint32_t d2, 
 // smallest accumulated optical depth over the bins (those the source does
 // not populate hold +inf), which ends the packet once it reaches tau_kill
 // (float32 form: see Extinction).
-template <typename R, int S, bool TH, int MB, typename KV>
+template <typename R, int S, bool TH, int MB, int NA = 0, int NB = 0, typename KV>
 __device__ __forceinline__ void cross_cell(R l, const KV &kap, CTab<R> tab, R (&F)[MB],
                                            R (&D)[DepthState<R, S, MB>::N], R &absorbed, R &e0, R &e1,
                                            R &e2, R &heat, R &tmin) {
@@ -84,10 +84,22 @@ __device__ __forceinline__ void cross_cell(R l, const KV &kap, CTab<R> tab, R (&
 #pragma unroll
     for (int j = 0; j < MB; ++j) {
         struct { R x, y, z; } sg = {tab[j], tab[MB + j], tab[2 * MB + j]};
+        // helium terms of a bin below a helium threshold are zero: with a bin
+        // layout known at compile time (the first NA bins hydrogen only, the
+        // next NB without HeII; checked on the table by the host) they are
+        // skipped, which adds nothing and changes no bit
+        const bool he1 = S == 3 && j >= NA, he2 = S == 3 && j >= NA + NB;   // constant once unrolled
         R K;
         if (S == 1) K = kH * sg.x;
-        else if (F64) K = (kH * sg.x + kHe1 * sg.y) + kHe2 * sg.z;
-        else K = __builtin_fmaf(kHe2, sg.z, __builtin_fmaf(kHe1, sg.y, kH * sg.x));
+        else if (F64) {
+            K = kH * sg.x;
+            if (he1) K = K + kHe1 * sg.y;
+            if (he2) K = K + kHe2 * sg.z;
+        } else {
+            K = kH * sg.x;
+            if (he1) K = __builtin_fmaf(kHe1, sg.y, K);
+            if (he2) K = __builtin_fmaf(kHe2, sg.z, K);
+        }
         const R tau = l * K;
         R d;
         if constexpr (F64) {
@@ -110,12 +122,12 @@ __device__ __forceinline__ void cross_cell(R l, const KV &kap, CTab<R> tab, R (&
             } else {
                 const R gk = K > R(0) ? d / K : R(0);
                 g0 += sg.x * gk;
-                g1 += sg.y * gk;
-                g2 += sg.z * gk;
+                if (he1) g1 += sg.y * gk;
+                if (he2) g2 += sg.z * gk;
                 if (TH) {
                     h0 += tab[3 * MB + j] * gk;
-                    h1 += tab[4 * MB + j] * gk;
-                    h2 += tab[5 * MB + j] * gk;
+                    if (he1) h1 += tab[4 * MB + j] * gk;
+                    if (he2) h2 += tab[5 * MB + j] * gk;
                 }
             }
         } else {
@@ -125,12 +137,12 @@ __device__ __forceinline__ void cross_cell(R l, const KV &kap, CTab<R> tab, R (&
                 // d_j / K_j; K_j = 0 only where d_j = 0
                 const float gk = d * __builtin_amdgcn_rcpf(fmaxf(K, 1e-30f));
                 g0 = __builtin_fmaf(sg.x, gk, g0);
-                g1 = __builtin_fmaf(sg.y, gk, g1);
-                g2 = __builtin_fmaf(sg.z, gk, g2);
+                if (he1) g1 = __builtin_fmaf(sg.y, gk, g1);
+                if (he2) g2 = __builtin_fmaf(sg.z, gk, g2);
                 if (TH) {
                     h0 = __builtin_fmaf(tab[3 * MB + j], gk, h0);
-                    h1 = __builtin_fmaf(tab[4 * MB + j], gk, h1);
-                    h2 = __builtin_fmaf(tab[5 * MB + j], gk, h2);
+                    if (he1) h1 = __builtin_fmaf(tab[4 * MB + j], gk, h1);
+                    if (he2) h2 = __builtin_fmaf(tab[5 * MB + j], gk, h2);
                 }
             }
         }

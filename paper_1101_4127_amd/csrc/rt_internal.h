@@ -47,7 +47,8 @@ struct MarchLaunch {
     int32_t thermal;                // deposit photo-heating too
     int32_t fp64;                   // plain float64 form
     int32_t n_bins;
-    int32_t mb;                     // compiled bin capacity (1, 4, 8, 16)
+    int32_t mb;                     // compiled bin capacity (1 or 8)
+    int32_t layout;                 // 1: bins 0-2 hydrogen only, 3-4 without HeII (8 bins, H+He)
     const SourceRec *src;
     const double *src_ndot;         // photons / s
     const double *src_sedsum;       // sum of the source's SED row (float64)

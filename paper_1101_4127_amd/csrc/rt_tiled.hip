@@ -484,7 +484,7 @@ template <typename R, int MB> struct TOcc { static constexpr int value = 2; };
 template <> struct TOcc<float, 1> { static constexpr int value = 4; };
 template <> struct TOcc<float, 8> { static constexpr int value = 4; };
 
-template <typename R, int S, bool TH, int MB>
+template <typename R, int S, bool TH, int MB, int NA, int NB>
 __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const TParams p, int cur) {
     constexpr bool F64 = std::is_same<R, double>::value;
     constexpr uint32_t ACC = (S == 1) ? (TH ? 2u : 1u) : 4u;
@@ -679,7 +679,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                 const KV knext = s_kap[nloc];
 
                 R absorbed, e0, e1, e2, hs, tmin;
-                cross_cell<R, S, TH, MB>(l, kap, tab, F, D, absorbed, e0, e1, e2, hs, tmin);
+                cross_cell<R, S, TH, MB, NA, NB>(l, kap, tab, F, D, absorbed, e0, e1, e2, hs, tmin);
 
                 // ---- deposit into the tile's float64 accumulators in LDS ----
                 // (zero deposits are added too: an LDS add is cheaper than the branch)
@@ -855,7 +855,7 @@ void scan(const TParams &p, const TiledLaunch &t, int nxt) {
     hipLaunchKernelGGL(k_tscan_c, dim3(t.scan_blocks), dim3(kScanBlock), 0, t.m.stream, p, nxt);
 }
 
-template <typename R, int S, bool TH, int MB>
+template <typename R, int S, bool TH, int MB, int NA, int NB>
 hipError_t run_batch(const TiledLaunch &t) {
     const TParams p = make_params(t);
     const hipStream_t st = t.m.stream;
@@ -867,7 +867,7 @@ hipError_t run_batch(const TiledLaunch &t) {
     for (uint32_t pass = 0; pass < t.passes; ++pass) {
         const bool timed = t.ev && *t.ev_used < t.ev_cap;
         if (timed) (void)hipEventRecord(t.ev[2 * *t.ev_used], st);
-        hipLaunchKernelGGL((k_tmarch<R, S, TH, MB>), grid, blk, 0, st, p, cur);
+        hipLaunchKernelGGL((k_tmarch<R, S, TH, MB, NA, NB>), grid, blk, 0, st, p, cur);
         if (timed) {
             (void)hipEventRecord(t.ev[2 * *t.ev_used + 1], st);
             ++*t.ev_used;
@@ -882,15 +882,18 @@ hipError_t run_batch(const TiledLaunch &t) {
 
 template <typename R, int S, bool TH, int MB>
 hipError_t occ(int *n) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, reinterpret_cast<const void *>(&k_tmarch<R, S, TH, MB>),
-                                                        kTBlock, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        n, reinterpret_cast<const void *>(&k_tmarch<R, S, TH, MB, 0, 0>), kTBlock, 0);
 }
 
 template <typename R, int S, bool TH>
 hipError_t pick_mb(const TiledLaunch *t, int mb, int *o) {
     switch (mb) {
-    case 1: return t ? run_batch<R, S, TH, 1>(*t) : occ<R, S, TH, 1>(o);
-    case 8: return t ? run_batch<R, S, TH, 8>(*t) : occ<R, S, TH, 8>(o);
+    case 1: return t ? run_batch<R, S, TH, 1, 0, 0>(*t) : occ<R, S, TH, 1>(o);
+    case 8:
+        if (!t) return occ<R, S, TH, 8>(o);
+        if (S == 3 && t->m.layout == 1) return run_batch<R, S, TH, 8, 3, 2>(*t);
+        return run_batch<R, S, TH, 8, 0, 0>(*t);
     default: return hipErrorInvalidValue;
     }
 }

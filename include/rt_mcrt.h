@@ -125,7 +125,12 @@ typedef struct {
     int32_t run_len;              /* tiled march: packets of one tile one block
                                      marches before it writes the tile's deposits
                                      out; 0 = default (2048), else 64..2048 */
-    int32_t reserved;             /* must be 0 */
+    int32_t park_lanes;           /* tiled march: once a run of a tile is used up,
+                                     a wavefront with at most this many packets
+                                     still marching writes them back; they resume
+                                     in the same tile in the next pass (their
+                                     histories do not change).  0..64; 0 = never
+                                     (default: march them to the tile's edge) */
     int64_t inflight;             /* tiled march: packets propagated together (the
                                      workspace holds one record each); a sub-step
                                      with more packets runs in batches of this

@@ -38,7 +38,7 @@ struct Plan {
     size_t off_state, off_kappa, off_acc, off_src, off_ndot, off_sedsum, off_sed, off_tab, off_slots,
         off_ledger, off_queue, off_trace, off_stage, total;
     // tiled march
-    uint32_t capacity, cmax, max_chunks, n_tiles, scan_blocks, passes;
+    uint32_t capacity, cmax, max_chunks, n_tiles, scan_blocks, passes, park_passes, park_lanes;
     size_t rec_bytes;
     size_t off_rec, off_idx0, off_idx1, off_side, off_cnt, off_off, off_cbase, off_bsum, off_ch0, off_ch1,
         off_ctrl;
@@ -69,7 +69,7 @@ int32_t validate_desc(const rt_grid_desc *d) {
     if (!(d->flags & RT_DIRECT_MARCH) && d->brick_log2 != -1 && d->brick_log2 != 3) return RT_EINVAL;
     if (d->run_len < 0 || d->run_len > 2048 || (d->run_len > 0 && d->run_len < 64)) return RT_EINVAL;
     if (d->inflight < 0 || d->inflight > ((int64_t)1 << 31) - 1) return RT_EINVAL;
-    if (d->reserved != 0) return RT_EINVAL;
+    if (d->park_lanes < 0 || d->park_lanes > 64) return RT_EINVAL;
     if (d->wave_chunk < 0 || d->wave_chunk % 64 != 0 || d->wave_chunk > (1 << 20)) return RT_EINVAL;
     if (d->refill_min < 0 || d->refill_min > 64) return RT_EINVAL;
     if (d->blocks_per_cu < 0 || d->blocks_per_cu > 32) return RT_EINVAL;
@@ -121,6 +121,7 @@ int32_t make_plan(const rt_grid_desc *d, int64_t max_sources, Plan *p) {
     o = align_up(o + (size_t)d->trace_packets * (RT_TRACE_HDR + (size_t)d->trace_len) * sizeof(int32_t));
     p->off_stage = o; o = align_up(o + (size_t)p->ncell * sizeof(double));
     p->capacity = p->cmax = p->max_chunks = p->n_tiles = p->scan_blocks = p->passes = 0;
+    p->park_passes = p->park_lanes = 0;
     p->rec_bytes = 0;
     p->off_rec = p->off_idx0 = p->off_idx1 = p->off_side = p->off_cnt = p->off_off = p->off_cbase = p->off_bsum =
         p->off_ch0 = p->off_ch1 = p->off_ctrl = 0;
@@ -134,7 +135,13 @@ int32_t make_plan(const rt_grid_desc *d, int64_t max_sources, Plan *p) {
         p->max_chunks = (uint32_t)mc;
         p->n_tiles = (uint32_t)nt;
         p->scan_blocks = (uint32_t)((nt + 4095) / 4096);
-        p->passes = (uint32_t)(g.nb[0] + g.nb[1] + g.nb[2] - 2);
+        // a packet visits at most tx + ty + tz - 2 tiles.  Parking is allowed in
+        // that many passes and the same number follow without it, so a packet
+        // parked in the last parking pass still reaches the end of its path.
+        const uint32_t visits = (uint32_t)(g.nb[0] + g.nb[1] + g.nb[2] - 2);
+        p->park_lanes = (uint32_t)d->park_lanes;
+        p->park_passes = p->park_lanes ? visits : 0u;
+        p->passes = visits + p->park_passes;
         p->rec_bytes = rtk::tiled_record_bytes(p->fp64, p->species, p->mb);
         p->off_rec = o; o = align_up(o + cap * p->rec_bytes);
         p->off_idx0 = o; o = align_up(o + cap * sizeof(uint32_t));
@@ -235,6 +242,8 @@ rtk::TiledLaunch tiled_launch(rt_solve_t h, const rtk::MarchLaunch &m) {
     t.n_tiles = p.n_tiles;
     t.scan_blocks = p.scan_blocks;
     t.passes = p.passes;
+    t.park_passes = p.park_passes;
+    t.park_lanes = p.park_lanes;
     t.rec = h->ws + p.off_rec;
     t.idx[0] = reinterpret_cast<uint32_t *>(h->ws + p.off_idx0);
     t.idx[1] = reinterpret_cast<uint32_t *>(h->ws + p.off_idx1);

@@ -119,7 +119,10 @@ struct TiledLaunch {
     uint32_t capacity;      // packets in flight (records)
     uint32_t cmax;          // packets per run
     uint32_t max_chunks;
-    uint32_t n_tiles, scan_blocks, passes;
+    uint32_t n_tiles, scan_blocks;
+    uint32_t passes;        // passes launched per batch
+    uint32_t park_passes;   // passes (from the first) in which packets may be parked
+    uint32_t park_lanes;    // park when at most this many lanes still march (0: never)
     void *rec;
     uint32_t *idx[2], *side, *cnt, *off, *cbase, *bsum;
     TChunk *chunks[2];

@@ -64,6 +64,7 @@ struct TParams {
     int32_t trace_n, trace_len;
     uint32_t trace_stride;
     uint32_t refill_min;
+    uint32_t park;                        // park at most this many marching lanes (0: never)
     uint32_t g0, nbatch, capacity, cmax, max_chunks, n_tiles;
     void *rec;
     uint32_t *idx0, *idx1, *side, *cnt, *off, *cbase, *bsum;
@@ -545,6 +546,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
         uint32_t pos = 0, rid = 0;               // list position and record of the lane's packet
         int k0 = 0, k1 = 0, k2 = 0;
         uint32_t d0 = 1, d1 = 1, d2 = 1, a0 = 0, a1 = 0, a2 = 0, pnum = 0, pden = 1;
+        uint32_t lax = 3;                        // axis of the last face crossed (3: none)
         double sprev = 0.0, L = 0.0, w = 0.0, absd = 0.0;
         float Lf = 0.0f;
         uint32_t loc = 0, count = 0, active = 0;
@@ -611,6 +613,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                             k1 = (int)((kw >> 10) & 1023u);
                             k2 = (int)((kw >> 20) & 1023u);
                             const uint32_t ax = kw >> 30;
+                            lax = ax;
                             // a record that is not a packet of this tile is an internal error
                             const bool bad = k0 >= p.geo.n[0] || k1 >= p.geo.n[1]
                                 || k2 >= p.geo.n[2] || (k0 >> kTileLog2) != tx || (k1 >> kTileLog2) != ty
@@ -705,6 +708,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                 if (fate == 0u) {
                     loc = nloc;
                     kap = knext;
+                    lax = (uint32_t)ax;
                     if (F64) sprev = snew; else { pnum = num; pden = den; }
                 } else {
                     it_abs = w * absd;
@@ -748,6 +752,28 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
             l_trunc += (it_fate == 1u) ? it_left : 0.0;
             n_esc += (it_fate == 2u) ? 1u : 0u;
             n_trunc += (it_fate == 1u) ? 1u : 0u;
+
+            // ---- run used up and few lanes left: park them for the next pass ----
+            // (every parked packet has crossed a cell in this pass, so it progresses)
+            if (exhausted && p.park != 0u) {
+                const uint64_t am = __ballot(alive);
+                if (am != 0ull && (uint32_t)__popcll(am) <= p.park) {
+                    double pk_abs = 0.0;
+                    if (alive) {
+                        uint32_t jw = 0;
+                        if constexpr (!F64) jw = dtest.ext.jw;
+                        store_moving<R, S, MB>(recs + (size_t)rid * RL::UNITS, pack_cell(k0, k1, k2, lax), d0, jw,
+                                               d1, d2, active, F, D);
+                        const uint32_t stay = 13u;                 // code of the tile itself
+                        const uint32_t rank = atomicAdd(&s_cnt[stay], 1u);
+                        p.side[pos] = stay | (rank << 5);
+                        if (tix >= 0) p.trace[(size_t)tix * (RT_TRACE_HDR_DEV + p.trace_len)] = (int32_t)count;
+                        pk_abs = w * absd;
+                        alive = false;
+                    }
+                    l_abs += pk_abs;
+                }
+            }
         }
         __syncthreads();
 
@@ -828,6 +854,7 @@ TParams make_params(const TiledLaunch &t) {
     p.trace_len = m.trace_len;
     p.trace_stride = (uint32_t)m.trace_stride;
     p.refill_min = (uint32_t)m.refill_min;
+    p.park = 0u;
     p.g0 = t.g0;
     p.nbatch = t.nbatch;
     p.capacity = t.capacity;
@@ -864,10 +891,12 @@ hipError_t run_batch(const TiledLaunch &t) {
     scan(p, t, 0);
     hipLaunchKernelGGL(k_tscatter_emit, grid, blk, 0, st, p);
     int cur = 0;
+    TParams pp = p;
     for (uint32_t pass = 0; pass < t.passes; ++pass) {
+        pp.park = pass < t.park_passes ? t.park_lanes : 0u;
         const bool timed = t.ev && *t.ev_used < t.ev_cap;
         if (timed) (void)hipEventRecord(t.ev[2 * *t.ev_used], st);
-        hipLaunchKernelGGL((k_tmarch<R, S, TH, MB, NA, NB>), grid, blk, 0, st, p, cur);
+        hipLaunchKernelGGL((k_tmarch<R, S, TH, MB, NA, NB>), grid, blk, 0, st, pp, cur);
         if (timed) {
             (void)hipEventRecord(t.ev[2 * *t.ev_used + 1], st);
             ++*t.ev_used;

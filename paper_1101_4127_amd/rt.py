@@ -37,7 +37,7 @@ class GridDesc(C.Structure):
         ("flags", C.c_uint32), ("solve_id", C.c_uint64), ("step_index0", C.c_uint64),
         ("brick_log2", C.c_int32), ("wave_chunk", C.c_int32), ("refill_min", C.c_int32),
         ("blocks_per_cu", C.c_int32), ("trace_packets", C.c_int32), ("trace_len", C.c_int32),
-        ("trace_stride", C.c_int32), ("run_len", C.c_int32), ("reserved", C.c_int32),
+        ("trace_stride", C.c_int32), ("run_len", C.c_int32), ("park_lanes", C.c_int32),
         ("inflight", C.c_int64),
     ]
 
@@ -214,7 +214,8 @@ def rt_release(h):
 def desc_from_workload(work, *, fp64: Optional[bool] = None, brick_log2: int = -1, wave_chunk: int = 0,
                        refill_min: int = 0, blocks_per_cu: int = 0, trace_packets: int = 0,
                        trace_len: int = 0, trace_stride: int = 1, time_march: bool = False,
-                       direct: bool = False, run_len: int = 0, inflight: int = 0) -> GridDesc:
+                       direct: bool = False, run_len: int = 0, inflight: int = 0,
+                       park_lanes: int = 0) -> GridDesc:
     d = rt_desc_defaults()
     for a in range(3):
         d.n[a] = int(work.n[a])
@@ -242,6 +243,7 @@ def desc_from_workload(work, *, fp64: Optional[bool] = None, brick_log2: int = -
     d.trace_len = int(trace_len)
     d.trace_stride = int(trace_stride)
     d.run_len = int(run_len)
+    d.park_lanes = int(park_lanes)
     d.inflight = int(inflight)
     return d
 

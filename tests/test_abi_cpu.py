@@ -88,7 +88,7 @@ def test_workspace_bytes_scales_and_validates(L):
     for field, bad in (("n_bins", 0), ("n_bins", 9), ("n_bins", 17), ("tau_kill", 0.0), ("n_sub", 0), ("n_chem", 0),
                        ("cell_cm", -1.0), ("brick_log2", 4), ("wave_chunk", 100), ("refill_min", 65),
                        ("flags", 0x10), ("trace_stride", -1), ("brick_log2", 2), ("run_len", 10),
-                       ("run_len", 2049), ("reserved", 1), ("inflight", -1), ("inflight", 1 << 31)):
+                       ("run_len", 2049), ("park_lanes", -1), ("park_lanes", 65), ("inflight", -1), ("inflight", 1 << 31)):
         e = rt.rt_desc_defaults()
         setattr(e, field, bad)
         with pytest.raises(rt.RTError) as ex:

@@ -1,0 +1,127 @@
+"""Parity at the full benchmark size: the 256^3 lognormal H+He workload (1e4
+sources, 8 bins, 1e8 packets per step) in the launch configuration bench.py
+times (tiled march, every packet of the step in flight, default runs and
+grid), checked on outputs the oracle can compute one by one:
+
+* packet histories of a sample of packet ids (every 50 000th), each marched
+  alone by the oracle over the same frozen state: cell sequences, directions
+  and sources identical; fates identical (float64 form) or identical outside
+  the extinction guard band (float32 form);
+* the cell update of a sample of cells, driven by the deposits the GPU
+  accumulated, against the oracle's update of the same cells;
+* properties that hold at any size: photon conservation, every packet ending
+  once, fractions in [0, 1] summing to one, finite non-negative deposits."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1101_4127_amd import workloads as W
+
+import parity as PT
+
+pytestmark = pytest.mark.gpu
+
+STRIDE = 50_000
+TRACE_LEN = 1024            # > 3 * 256 cells, the longest path through the grid
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1101_4127_amd import rt
+    rt.lib()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def work():
+    return W.lognormal_256()
+
+
+@pytest.fixture(scope="module")
+def oracle_state(work):
+    o = O.OracleSolve(work)
+    o.absorbers()
+    return o
+
+
+def oracle_traces(o, work, ids):
+    """Histories of the sampled packets, one oracle march per packet (the
+    record of packet g is written at index g / stride = 1 with stride g)."""
+    acc = np.zeros((4, work.ncell))
+    out = []
+    for g in ids:
+        g = int(g)
+        stride = g if g > 0 else 1
+        _, _, tr = o.march(g, g + 1, dt=work.dt_s / work.n_sub, packets=work.packets, seed=1,
+                           step_index=0, trace_n=2, trace_len=TRACE_LEN, trace_stride=stride, acc=acc,
+                           absorbers=False)
+        out.append(tr[1 if g > 0 else 0])
+    return np.array(out)
+
+
+def run_gpu(work, fp64):
+    from paper_1101_4127_amd import rt
+    n = work.packets // STRIDE
+    s = rt.Solve(work, fp64=fp64, inflight=work.packets, trace_packets=n, trace_len=TRACE_LEN,
+                 trace_stride=STRIDE)
+    st = s.step(seed=1)
+    fields = s.fetch()
+    tr = s.trace()
+    s.release()
+    return st, fields, tr
+
+
+def check_properties(st, fields, work, resid_tol, sum_tol):
+    assert st["errors"] == 0 and st["nonfinite"] == 0
+    assert st["packets"] == work.packets
+    assert st["n_escaped"] + st["n_truncated"] == work.packets
+    resid = abs(st["emitted"] - (st["absorbed"] + st["escaped"] + st["truncated"])) / st["emitted"]
+    assert resid <= resid_tol, resid
+    x = fields[1:6]
+    assert np.all(x >= 0.0) and np.all(x <= 1.0 + 1e-6)
+    assert np.max(np.abs(x[0] + x[1] - 1.0)) < 1e-5
+    assert np.max(np.abs(x[2] + x[3] + x[4] - 1.0)) < 1e-5
+    dep = fields[7:11]
+    assert np.all(np.isfinite(dep)) and np.all(dep >= 0.0)
+    # every photon absorbed in a cell is in the accumulators: their sum is
+    # the ledger's absorbed count (the species split sums to the absorbed
+    # photons up to the march precision's rounding)
+    assert abs(dep[0:3].sum() - st["absorbed"]) <= sum_tol * st["absorbed"]
+
+
+def check_sampled_updates(work, fields, tol):
+    rng = np.random.default_rng(11)
+    idx = np.sort(rng.choice(work.ncell, 2000, replace=False))
+    # include the cells with the largest deposits (the ionised and heated ones)
+    idx = np.unique(np.concatenate([idx, np.argsort(fields[7])[-500:]]))
+    o = O.OracleSolve(work)
+    acc = np.zeros((4, work.ncell))
+    acc[:, idx] = fields[7:11][:, idx]
+    o.update_cells(work.dt_s / work.n_sub, acc, idx)
+    fe = np.max(PT.frac_err(fields[1:6][:, idx], o.x[:, idx]))
+    te = np.max(PT.temp_err(fields[6][idx], o.T[idx]))
+    assert fe <= tol and te <= tol, (fe, te)
+
+
+def test_fullsize_fp32_bench_configuration(gpu, work, oracle_state):
+    st, fields, tr = run_gpu(work, fp64=False)
+    check_properties(st, fields, work, resid_tol=1e-6, sum_tol=1e-6)
+    ids = np.arange(0, work.packets, STRIDE)
+    otr = oracle_traces(oracle_state, work, ids)
+    assert np.all(otr[:, 0] > 0) and {1, 2} <= set(np.unique(otr[:, 1]).tolist())
+    mism = PT.compare_traces(work, oracle_state.kappa, tr, otr, exact=False)
+    assert mism <= len(ids) // 100, mism
+    check_sampled_updates(work, fields, 1e-5)
+
+
+def test_fullsize_fp64_plain(gpu, work, oracle_state):
+    st, fields, tr = run_gpu(work, fp64=True)
+    check_properties(st, fields, work, resid_tol=1e-12, sum_tol=1e-12)
+    ids = np.arange(0, work.packets, STRIDE)
+    otr = oracle_traces(oracle_state, work, ids)
+    assert np.all(otr[:, 0] > 0) and {1, 2} <= set(np.unique(otr[:, 1]).tolist())
+    PT.compare_traces(work, oracle_state.kappa, tr, otr, exact=True)
+    check_sampled_updates(work, fields, 1e-9)

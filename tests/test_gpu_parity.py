@@ -88,6 +88,8 @@ def test_trace_rays_match_oracle(gpu):
 MARCHES = {
     "tiled": dict(),
     "tiled-short-runs-batches": dict(run_len=64, inflight=1000, refill_min=1, blocks_per_cu=1),
+    "tiled-park-at-once": dict(park_lanes=64, run_len=128),
+    "tiled-park-some": dict(park_lanes=24),
     "direct-b0": dict(direct=True, brick_log2=0),
     "direct-b1": dict(direct=True, brick_log2=1),
     "direct-b2": dict(direct=True, brick_log2=2),
@@ -201,7 +203,8 @@ def test_tiles_do_not_change_results(gpu):
                   dict(refill_min=64),
                   dict(),
                   dict(run_len=64, inflight=3000, refill_min=1),
-                  dict(run_len=2048, blocks_per_cu=1)):
+                  dict(run_len=2048, blocks_per_cu=1),
+                  dict(park_lanes=64, run_len=64), dict(park_lanes=24)):
         s = rt.Solve(w, trace_packets=5000, trace_len=96, **tiles)
         st = s.step()
         f = s.fetch()

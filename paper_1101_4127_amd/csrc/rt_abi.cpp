@@ -113,7 +113,7 @@ int32_t make_plan(const rt_grid_desc *d, int64_t max_sources, Plan *p) {
     p->off_ndot = o; o = align_up(o + ms * sizeof(double));
     p->off_sedsum = o; o = align_up(o + ms * sizeof(double));
     p->off_sed = o; o = align_up(o + ms * p->mb * p->real);
-    p->off_tab = o; o = align_up(o + 6 * (size_t)p->mb * p->real);
+    p->off_tab = o; o = align_up(o + 7 * (size_t)p->mb * p->real);
     p->off_slots = o; o = align_up(o + kMaxMarchBlocks * sizeof(rtk::LedgerSlot));
     p->off_ledger = o; o = align_up(o + sizeof(rtk::StepLedger));
     p->off_queue = o; o = align_up(o + sizeof(unsigned long long));
@@ -159,12 +159,13 @@ int32_t make_plan(const rt_grid_desc *d, int64_t max_sources, Plan *p) {
     return RT_OK;
 }
 
-// Per-bin march table, [2][3][mb] in the march precision.  Row 0: the
-// cross-sections (float32 form: in units of 1e-18 cm^2, lengths then in 1e18
-// cm, so optical depths stay far from the float32 range limits).  Row 1: heat
-// factors in eV: pure hydrogen E_j - E_th,HI; H+He sigma_s,j (E_j - E_th,s).
+// Per-bin march table, [7][mb] in the march precision.  Rows 0-2: the
+// cross-sections of HI, HeI, HeII (float32 form: in units of 1e-18 cm^2,
+// lengths then in 1e18 cm, so optical depths stay far from the float32 range
+// limits).  Rows 3-5: heat factors in eV: pure hydrogen E_j - E_th,HI; H+He
+// sigma_s,j (E_j - E_th,s).  Row 6: E_j - E_th,HI.
 std::vector<double> march_table(const rt_grid_desc *d, const Plan &p) {
-    std::vector<double> t(6 * (size_t)p.mb, 0.0);
+    std::vector<double> t(7 * (size_t)p.mb, 0.0);
     const double scale = p.fp64 ? 1.0 : 1.0e18;
     for (int s = 0; s < 3; ++s)
         for (int j = 0; j < d->n_bins; ++j) {
@@ -172,6 +173,7 @@ std::vector<double> march_table(const rt_grid_desc *d, const Plan &p) {
             const double de = sig > 0.0 ? d->e_bin_ev[j] - kThresholdEv[s] : 0.0;
             t[(size_t)s * p.mb + j] = sig * scale;
             t[(size_t)(3 + s) * p.mb + j] = p.species == 1 ? de : sig * scale * de;
+            if (s == 0) t[(size_t)6 * p.mb + j] = de;
         }
     return t;
 }

@@ -18,8 +18,8 @@ template <typename R> struct Vec4;
 template <> struct Vec4<float> { using T = float4; };
 template <> struct Vec4<double> { using T = double4; };
 
-// Per-bin table of the march precision, [2][3][MB]: cross-sections of HI,
-// HeI, HeII, then their heat factors.  Read through the constant address
+// Per-bin table of the march precision, [7][MB]: cross-sections of HI, HeI,
+// HeII, their heat factors, then E_j - E_th,HI.  Read through the constant address
 // space: the indices are uniform, so the values live in scalar registers.
 template <typename R> using CTab = const __attribute__((address_space(4))) R *;
 
@@ -80,6 +80,7 @@ __device__ __forceinline__ void cross_cell(R l, const KV &kap, CTab<R> tab, R (&
         }
     }
     R ab = R(0), g0 = R(0), g1 = R(0), g2 = R(0), h0 = R(0), h1 = R(0), h2 = R(0);
+    R dH = R(0), qH = R(0);     // bins absorbed by hydrogen alone (j < NA): photons, heat
     R tm = R(INFINITY);
 #pragma unroll
     for (int j = 0; j < MB; ++j) {
@@ -115,7 +116,14 @@ __device__ __forceinline__ void cross_cell(R l, const KV &kap, CTab<R> tab, R (&
             F[j] = F[j] * tr;
         }
         ab += d;
-        if constexpr (F64) {
+        if (S == 3 && j < NA) {
+            // hydrogen alone absorbs here: its share is 1, its heat E_j - E_th,HI
+            dH += d;
+            if (TH) {
+                if constexpr (F64) qH += d * tab[6 * MB + j];
+                else qH = __builtin_fmaf(d, tab[6 * MB + j], qH);
+            }
+        } else if constexpr (F64) {
             // float64 form: the oracle's order, no contraction
             if (S == 1) {
                 if (TH) h0 += d * tab[3 * MB + j];
@@ -154,12 +162,12 @@ __device__ __forceinline__ void cross_cell(R l, const KV &kap, CTab<R> tab, R (&
         e1 = e2 = R(0);
         heat = h0;
     } else {
-        e0 = kH * g0;
+        e0 = kH * g0 + dH;
         e1 = kHe1 * g1;
         e2 = kHe2 * g2;
         if (TH) {
-            if (F64) heat = (kH * h0 + kHe1 * h1) + kHe2 * h2;
-            else heat = __builtin_fmaf(kHe2, h2, __builtin_fmaf(kHe1, h1, kH * h0));
+            if (F64) heat = ((kH * h0 + kHe1 * h1) + kHe2 * h2) + qH;
+            else heat = __builtin_fmaf(kHe2, h2, __builtin_fmaf(kHe1, h1, __builtin_fmaf(kH, h0, qH)));
         } else {
             heat = R(0);
         }

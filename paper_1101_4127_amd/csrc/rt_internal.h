@@ -57,8 +57,8 @@ struct MarchLaunch {
     uint32_t packets;               // packets of this sub-step
     double dt;                      // sub-step length [s]
     uint64_t seed, solve_id, step_index;
-    const void *tab;                // [2][3][mb] of the march precision: cross-sections,
-                                    // heat factors (see rt_abi.cpp)
+    const void *tab;                // [7][mb] of the march precision: cross-sections,
+                                    // heat factors, E_j - E_th,HI (see rt_abi.cpp)
     double tau_kill;
     const void *kappa;              // absorbers per slot: R (pure H) or R4
     double *acc;                    // accumulators per slot

@@ -76,7 +76,7 @@ template <> struct MarchOcc<float, 8> { static constexpr int value = 3; };
 
 constexpr int kWaves = kMarchBlock / 64;
 
-template <typename R, int S, bool TH, int MB>
+template <typename R, int S, bool TH, int MB, int NA, int NB>
 __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march(const MarchParams p) {
     constexpr bool F64 = std::is_same<R, double>::value;
     constexpr uint32_t ACC = (S == 1) ? (TH ? 2u : 1u) : 4u;
@@ -256,7 +256,7 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
 
             // ---- Eq. (1) per bin and the split among absorbers ----
             R absorbed, e0, e1, e2, hs, tmin;
-            cross_cell<R, S, TH, MB>(l, kap, tab, F, D, absorbed, e0, e1, e2, hs, tmin);
+            cross_cell<R, S, TH, MB, NA, NB>(l, kap, tab, F, D, absorbed, e0, e1, e2, hs, tmin);
 
             // ---- deposit: float64 accumulators, hardware atomics at L2 ----
             double *cell = p.acc + (size_t)slot * ACC;
@@ -362,7 +362,7 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
 // ---------------------------------------------------------------------------
 // host-side dispatch over (precision, species, thermal, bin capacity)
 // ---------------------------------------------------------------------------
-template <typename R, int S, bool TH, int MB>
+template <typename R, int S, bool TH, int MB, int NA, int NB>
 static hipError_t run(const MarchLaunch &m) {
     MarchParams p;
     constexpr bool F64 = std::is_same<R, double>::value;
@@ -393,14 +393,14 @@ static hipError_t run(const MarchLaunch &m) {
     p.trace_stride = (uint32_t)m.trace_stride;
     p.chunk = (uint32_t)m.chunk;
     p.refill_min = (uint32_t)m.refill_min;
-    hipLaunchKernelGGL((k_march<R, S, TH, MB>), dim3(m.blocks), dim3(kMarchBlock), 0, m.stream, p);
+    hipLaunchKernelGGL((k_march<R, S, TH, MB, NA, NB>), dim3(m.blocks), dim3(kMarchBlock), 0, m.stream, p);
     return hipGetLastError();
 }
 
 template <typename R, int S, bool TH, int MB>
 static hipError_t occ(int *n) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, reinterpret_cast<const void *>(&k_march<R, S, TH, MB>),
-                                                        kMarchBlock, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        n, reinterpret_cast<const void *>(&k_march<R, S, TH, MB, 0, 0>), kMarchBlock, 0);
 }
 
 // Compiled bin capacities: 1 (monochromatic) and 8 (up to 8 bins, unused bins
@@ -408,8 +408,11 @@ static hipError_t occ(int *n) {
 template <typename R, int S, bool TH>
 static hipError_t pick_mb(const MarchLaunch *m, int mb, int *occ_out) {
     switch (mb) {
-    case 1: return m ? run<R, S, TH, 1>(*m) : occ<R, S, TH, 1>(occ_out);
-    case 8: return m ? run<R, S, TH, 8>(*m) : occ<R, S, TH, 8>(occ_out);
+    case 1: return m ? run<R, S, TH, 1, 0, 0>(*m) : occ<R, S, TH, 1>(occ_out);
+    case 8:
+        if (!m) return occ<R, S, TH, 8>(occ_out);
+        if (S == 3 && m->layout == 1) return run<R, S, TH, 8, 3, 2>(*m);
+        return run<R, S, TH, 8, 0, 0>(*m);
     default: return hipErrorInvalidValue;
     }
 }

@@ -451,29 +451,36 @@ __global__ void __launch_bounds__(kScanBlock) k_tscan_c(const TParams p, int nxt
     }
 }
 
-// Record ids of the packets that moved on, into the next pass's lists.
+// Record ids of the packets that moved on, into the next pass's lists.  The
+// run's 27 destination bases (neighbour's list offset + the run's reservation
+// in it) are formed once per run in LDS.
 __global__ void __launch_bounds__(kTBlock) k_tscatter(const TParams p, int cur) {
     const uint32_t nch = p.ctrl->n_chunks[cur];
     const TChunk *chs = cur ? p.ch1 : p.ch0;
     const uint32_t *in = cur ? p.idx1 : p.idx0;
     uint32_t *outl = cur ? p.idx0 : p.idx1;
+    __shared__ uint32_t s_dst[kCodes];
     for (uint32_t c = blockIdx.x; c < nch; c += gridDim.x) {
         const TChunk ch = chs[c];
         if (ch.start > p.capacity || ch.len > p.capacity - ch.start) continue;   // flagged by the march
+        if (threadIdx.x < kCodes) {
+            // bases of codes this run did not use are never read
+            const int64_t y = (int64_t)ch.tile + code_offset(p.geo, threadIdx.x);
+            s_dst[threadIdx.x] = (y >= 0 && y < (int64_t)p.n_tiles)
+                                     ? p.off[y] + p.cbase[(size_t)c * kCodes + threadIdx.x] : 0xffffffffu;
+        }
+        __syncthreads();
         for (uint32_t k = threadIdx.x; k < ch.len; k += kTBlock) {
             const uint32_t pos = ch.start + k;
             const uint32_t sd = p.side[pos];
             if (sd == kSideDead) continue;
             const uint32_t code = sd & 31u, rank = sd >> 5;
-            const int64_t y = (int64_t)ch.tile + code_offset(p.geo, code);
-            if (code >= (uint32_t)kCodes || y < 0 || y >= (int64_t)p.n_tiles) {
-                atomicOr(&p.ctrl->err, 4u);
-                continue;
-            }
-            const uint32_t dst = p.off[y] + p.cbase[(size_t)c * kCodes + code] + rank;
-            if (dst < p.capacity) outl[dst] = in[pos];
+            const uint32_t base = code < (uint32_t)kCodes ? s_dst[code] : 0xffffffffu;
+            const uint32_t dst = base + rank;
+            if (base != 0xffffffffu && dst < p.capacity) outl[dst] = in[pos];
             else atomicOr(&p.ctrl->err, 4u);
         }
+        __syncthreads();
     }
 }
 
@@ -724,10 +731,10 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                         p.side[pos] = code | (rank << 5);
                         if (traced) rec[0] = (int32_t)count;
                     } else {
-                        double left = 0.0;
+                        R left = R(0);
 #pragma unroll
-                        for (int j = 0; j < MB; ++j) left += (double)F[j];
-                        it_left = w * left;
+                        for (int j = 0; j < MB; ++j) left += F[j];
+                        it_left = w * (double)left;
                         it_fate = fate;
                         p.side[pos] = kSideDead;
                         if (traced) {

@@ -244,6 +244,60 @@ def stromgren_c1(n: int = 32, packets: int = 100000, steps: int = 10, n_sub: int
         flags=ISOTHERMAL | (FP64_MARCH if fp64 else 0), seed=1)
 
 
+def thermal_test2(n: int = 32, packets: int = 100000, steps: int = 5, n_sub: int = 50,
+                  fp64: bool = False, box_kpc: float = 15.0) -> Workload:
+    """The thermal H II region of Sec. 4.2 (Test 2): Test 0's set-up (uniform
+    pure H, n_H = 1e-3, one corner source of 5e48 ph/s) with a 1e5 K black body
+    in 8 bins, the gas initially neutral at 100 K and its temperature followed;
+    box 15 kpc (the comparison project's box; the paper only says larger),
+    10 Myr steps."""
+    box = box_kpc * KPC_CM
+    ncell = n ** 3
+    x, t = _neutral_state(ncell, 100.0)
+    bins = blackbody_table(1.0e5)
+    return Workload(
+        name=f"thermal_test2_{n}^3", n=(n, n, n), cell_cm=box / n, y_he=0.0, bins=bins,
+        redshift=-1.0, n_h=np.full(ncell, float(np.float32(1.0e-3))), x=x, temp=t,
+        src_ijk=np.zeros((1, 3), np.int32), src_ndot=np.array([5.0e48]),
+        src_sed=bins.sed[None, :].copy(), src_flags=SRC_CORNER_OCTANT,
+        dt_s=10.0 * MYR_S, packets=packets, steps=steps, n_sub=n_sub, n_chem=8,
+        flags=(FP64_MARCH if fp64 else 0), seed=1)
+
+
+def blackbody_photon_rate(luminosity_erg_s: float, t_bb: float, lo_ev: float = 13.6,
+                          hi_ev: float = 200.0) -> float:
+    """Photons/s in [lo_ev, hi_ev] of a black body of total luminosity L."""
+    from scipy.integrate import quad
+    kt = K_B * t_bb / EV_ERG
+    energy = quad(lambda e: e ** 3 / math.expm1(e / kt), 1e-8 * kt, 60.0 * kt, epsabs=0.0, epsrel=1e-12,
+                  limit=400)[0]
+    photons = quad(lambda e: e * e / math.expm1(e / kt), lo_ev, hi_ev, epsabs=0.0, epsrel=1e-12,
+                   limit=400)[0]
+    return luminosity_erg_s / EV_ERG * photons / energy
+
+
+def hhe_test3(n: int = 32, packets: int = 200000, steps: int = 6, n_sub: int = 50,
+              fp64: bool = False) -> Workload:
+    """The H+He H II region of Sec. 4.2 (Test 3, the CLOUDY94 comparison): a
+    6e4 K black body of 1e38 erg/s (its photons in 13.6-200 eV, 8 bins) in a
+    uniform medium of 1 particle/cm^3, 90 % hydrogen by number (n_H = 0.9,
+    y = 1/9), initially neutral at 100 K, temperature followed; box 128 pc with
+    the source at its corner (the paper does not place it); 6e5 yr in steps of
+    1e5 yr."""
+    box = 128.0e-3 * KPC_CM
+    ncell = n ** 3
+    x, t = _neutral_state(ncell, 100.0)
+    bins = blackbody_table(6.0e4)
+    ndot = blackbody_photon_rate(1.0e38, 6.0e4)
+    return Workload(
+        name=f"hhe_test3_{n}^3", n=(n, n, n), cell_cm=box / n, y_he=1.0 / 9.0, bins=bins,
+        redshift=-1.0, n_h=np.full(ncell, float(np.float32(0.9))), x=x, temp=t,
+        src_ijk=np.zeros((1, 3), np.int32), src_ndot=np.array([ndot]),
+        src_sed=bins.sed[None, :].copy(), src_flags=SRC_CORNER_OCTANT,
+        dt_s=1.0e5 * YR_S, packets=packets, steps=steps, n_sub=n_sub, n_chem=8,
+        flags=(FP64_MARCH if fp64 else 0), seed=1)
+
+
 def cosmo_cell_cm(n: int, box_mpc_h: float = 10.0, z: float = 9.0) -> float:
     """Proper cell size of an n^3 grid on a comoving box of box_mpc_h Mpc/h."""
     return box_mpc_h / HUBBLE_H * MPC_CM / (1.0 + z) / n

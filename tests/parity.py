@@ -15,8 +15,8 @@ def deposit_err(g, o):
     return np.abs(g - o) / np.maximum(np.abs(o), floor)
 
 
-def frac_err(g, o):
-    return np.abs(g - o) / np.maximum(o, 1e-8)
+def frac_err(g, o, floor=1e-8):
+    return np.abs(g - o) / np.maximum(o, floor)
 
 
 def temp_err(g, o):
@@ -40,12 +40,12 @@ def run_both(work, *, fp64, steps=1, trace_n=0, trace_len=0, stride=1, seeds=Non
     return o, stats, fields, trace
 
 
-def compare_state(o, fields, work, *, frac_tol, temp_tol, dep_tol):
+def compare_state(o, fields, work, *, frac_tol, temp_tol, dep_tol, frac_floor=1e-8):
     """Per-field maximum errors; asserts them against the tolerances."""
     rep = {}
     iso = bool(work.flags & W.ISOTHERMAL)
     for f in range(5):
-        rep[f"x{f}"] = float(np.max(frac_err(fields[1 + f], o.x[f])))
+        rep[f"x{f}"] = float(np.max(frac_err(fields[1 + f], o.x[f], frac_floor)))
     rep["T"] = float(np.max(temp_err(fields[6], o.T)))
     for f in range(3):
         rep[f"D{f}"] = float(np.max(deposit_err(fields[7 + f], o.acc[f])))

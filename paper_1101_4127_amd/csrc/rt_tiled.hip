@@ -94,6 +94,9 @@ struct TRec {
     static constexpr int BYTES = 4 * HDR + (int)sizeof(R) * (MB + ND);
     static constexpr int UNITS = (BYTES + 15) / 16;
     static constexpr int WORDS = 4 * UNITS;
+    // records sit on a power-of-two stride (whole 128-byte lines from 128 bytes
+    // up), so a record read or written back never straddles a line boundary
+    static constexpr int STRIDE = UNITS <= 2 ? 2 : (UNITS <= 4 ? 4 : (UNITS <= 8 ? 8 : 16));
 };
 
 // Longest run of a tile's list one block marches (its record ids are staged in LDS).
@@ -307,7 +310,7 @@ __global__ void __launch_bounds__(kTBlock) k_temit(const TParams p) {
             const double Ld = sqrt((double)qq) * p.half_dl;
             const R len = RL::F64 ? (R)Ld : (R)(Ld * p.len_scale);
             const uint32_t jw = active ? (uint32_t)__builtin_ctz(active) : 0u;   // all depths 0: first bin
-            store_record<R, S, MB>(recs + (size_t)i * RL::UNITS, c[0], c[1], c[2], pack_cell(k0, k1, k2, 3u),
+            store_record<R, S, MB>(recs + (size_t)i * RL::STRIDE, c[0], c[1], c[2], pack_cell(k0, k1, k2, 3u),
                                    next_face(k0, sr.o[0], a0), jw, next_face(k1, sr.o[1], a1),
                                    next_face(k2, sr.o[2], a2), active, ww, len, F, D);
             tile = tile_of_cell(p.geo, k0, k1, k2);
@@ -586,7 +589,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                             p.side[pos] = kSideDead;
                         } else {
                             rid = ri;
-                            const uint4 *rp = recs + (size_t)ri * RL::UNITS;
+                            const uint4 *rp = recs + (size_t)ri * RL::STRIDE;
                             uint32_t wd[RL::WORDS];
 #pragma unroll
                             for (int u = 0; u < RL::UNITS; ++u) {
@@ -724,7 +727,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                         // packets bound for the same tile
                         uint32_t jw = 0;
                         if constexpr (!F64) jw = dtest.ext.jw;
-                        store_moving<R, S, MB>(recs + (size_t)rid * RL::UNITS, pack_cell(k0, k1, k2, (uint32_t)ax),
+                        store_moving<R, S, MB>(recs + (size_t)rid * RL::STRIDE, pack_cell(k0, k1, k2, (uint32_t)ax),
                                                d0, jw, d1, d2, active, F, D);
                         const uint32_t code = (uint32_t)((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1));
                         const uint32_t rank = atomicAdd(&s_cnt[code], 1u);
@@ -769,7 +772,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                     if (alive) {
                         uint32_t jw = 0;
                         if constexpr (!F64) jw = dtest.ext.jw;
-                        store_moving<R, S, MB>(recs + (size_t)rid * RL::UNITS, pack_cell(k0, k1, k2, lax), d0, jw,
+                        store_moving<R, S, MB>(recs + (size_t)rid * RL::STRIDE, pack_cell(k0, k1, k2, lax), d0, jw,
                                                d1, d2, active, F, D);
                         const uint32_t stay = 13u;                 // code of the tile itself
                         const uint32_t rank = atomicAdd(&s_cnt[stay], 1u);
@@ -943,7 +946,7 @@ hipError_t dispatch(const TiledLaunch *t, int species, int thermal, int fp64, in
     return thermal ? pick_mb<float, 3, true>(t, mb, o) : pick_mb<float, 3, false>(t, mb, o);
 }
 
-template <typename R, int S, int MB> constexpr size_t rec_bytes() { return 16u * TRec<R, S, MB>::UNITS; }
+template <typename R, int S, int MB> constexpr size_t rec_bytes() { return 16u * TRec<R, S, MB>::STRIDE; }
 
 }  // namespace
 

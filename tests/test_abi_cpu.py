@@ -108,7 +108,8 @@ def test_workspace_bytes_scales_and_validates(L):
 
 def test_tiled_workspace_holds_one_record_per_packet_in_flight(L):
     """The tiled march's workspace grows by a fixed record size per packet in
-    flight (float32 H+He, 8 bins: 80-byte records plus three list words)."""
+    flight (float32 H+He, 8 bins: 80-byte records on a 128-byte stride, so no
+    record straddles a cache line, plus three list words)."""
     d = rt.rt_desc_defaults()
     d.n[0] = d.n[1] = d.n[2] = 64
     d.cell_cm = 1e21
@@ -121,7 +122,7 @@ def test_tiled_workspace_holds_one_record_per_packet_in_flight(L):
     d.inflight = 1 << 21
     b = rt.rt_workspace_bytes(d, 10)
     per = (b - a) / (1 << 20)
-    assert 80 + 12 <= per <= 80 + 12 + 16 * 2        # record + lists (+ runs of 2048)
+    assert 128 + 12 <= per <= 128 + 12 + 16 * 2      # record + lists (+ runs of 2048)
     d.flags = rt.RT_FP64
     c = rt.rt_workspace_bytes(d, 10)
     assert c > b

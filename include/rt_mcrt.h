@@ -227,6 +227,53 @@ int32_t rt_get_step_index(rt_solve_t h, uint64_t *out);
 /* Synchronise and destroy the handle (the workspace may then be freed). */
 int32_t rt_release(rt_solve_t h);
 
+/* ---- Fused steps of many independent solves (serving) ----
+ * rt_step_many advances n solves by one rt_step each, with the same operation
+ * per solve as rt_step (Sec. 2 march and cell update; Sec. 3.2 packet shares)
+ * and the same packet ids, Philox counters and crossing arithmetic, so every
+ * solve's result is the one rt_step gives alone, up to the order in which
+ * float64 deposits are added.  Per sub-step the solves share three kernel
+ * launches (absorbers, march, cell update; one packet id space over all
+ * solves) plus a ledger reduction, instead of four per solve; with
+ * RT_BATCH_GRAPH the whole call is captured once as a hipGraph and replayed
+ * (the launches read the solves from a device table, so the graph does not
+ * depend on which solves are in the batch).
+ *
+ * Solves of one call: pure hydrogen (y_he = 0), one bin, all float32 or all
+ * float64, all thermal or all isothermal, no tracing, on the batch's device,
+ * each at most once.  They may use any march flags (the fused march is the
+ * per-packet one); their own streams are ordered around the call with events,
+ * so rt_fetch_fields and rt_read_stats on a solve see its result. */
+typedef struct rt_batch *rt_batch_t;
+
+#define RT_MAX_BATCH 64      /* solves per rt_step_many */
+#define RT_BATCH_GRAPH 0x1u  /* capture each call shape (sub-step count, precision,
+                                thermal) once as a hipGraph and replay it */
+
+/* Device workspace bytes of a batch of at most max_solves (1..RT_MAX_BATCH)
+ * solves: the solve table, per-(solve, block) ledger slots, a counter. */
+int32_t rt_batch_workspace_bytes(int32_t max_solves, size_t *bytes_out);
+
+/* Create a batch in the caller's device workspace (256-byte aligned, at least
+ * rt_batch_workspace_bytes).  hip_stream: the stream the fused launches go to;
+ * it must not be NULL with RT_BATCH_GRAPH (the legacy stream cannot be
+ * captured).  Allocates pinned host memory for the table it stages. */
+int32_t rt_batch_init(int32_t max_solves, void *d_ws, size_t ws_bytes, void *hip_stream, uint32_t flags,
+                      rt_batch_t *out);
+
+/* Advance solves[0..n) by one step each: solve i by dt_s[i] with n_packets[i]
+ * packets and Philox seed seeds[i], exactly as rt_step(solves[i], ...) would
+ * (its n_sub sub-steps; the call runs max n_sub fused rounds).  Returns
+ * RT_EINVAL (nothing enqueued) if a solve breaks the rules above or a step
+ * argument would be rejected by rt_step.  Stream-ordered; if stats is not
+ * NULL (n entries) the call synchronises and fills each solve's ledger. */
+int32_t rt_step_many(rt_batch_t b, const rt_solve_t *solves, int32_t n, const double *dt_s,
+                     const int64_t *n_packets, const uint64_t *seeds, rt_step_stats *stats);
+
+/* Synchronise the batch's stream, destroy its graphs and events and free its
+ * pinned staging memory (the workspace may then be freed). */
+int32_t rt_batch_release(rt_batch_t b);
+
 /* Static description of a status code. */
 const char *rt_strerror(int32_t status);
 

@@ -638,6 +638,289 @@ int32_t rt_release(rt_solve_t h) {
     return ok ? RT_OK : RT_EDEVICE;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Fused steps of many solves
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr uint64_t kBatchMagic = 0x52544d4342415443ull;
+constexpr int kMaxBatchBlocks = 2048;     // march blocks the ledger slots are sized for
+
+struct BatchLayout {
+    size_t off_head, off_table, off_slots, off_queue, total;
+};
+
+BatchLayout batch_layout(int32_t max_solves) {
+    BatchLayout l;
+    size_t o = 0;
+    // the table follows the head directly, as in the staging memory it is copied from
+    l.off_head = o;
+    l.off_table = o + sizeof(rtk::BatchHead);
+    o = align_up(l.off_table + (size_t)max_solves * sizeof(rtk::BatchSolve));
+    l.off_slots = o; o = align_up(o + (size_t)max_solves * kMaxBatchBlocks * sizeof(rtk::LedgerSlot));
+    l.off_queue = o; o = align_up(o + sizeof(unsigned long long));
+    l.total = o;
+    return l;
+}
+
+struct BatchGraph {
+    int rounds, fp64, thermal;
+    hipGraphExec_t exec;
+};
+
+}  // namespace
+
+struct rt_batch {
+    uint64_t magic;
+    int32_t max_solves;
+    uint32_t flags;
+    hipStream_t stream;
+    int device, cus;
+    char *ws;
+    BatchLayout lay;
+    int occ[2][2];                 // march blocks per CU by [fp64][thermal]
+    void *staging;                 // pinned: head then table
+    hipEvent_t staged;             // the last table copy has been read
+    bool staged_pending;
+    hipEvent_t done;               // end of the last fused call
+    std::vector<hipEvent_t> ev_in; // one per solve slot: its stream's work before the call
+    std::vector<BatchGraph> graphs;
+};
+
+namespace {
+
+bool batch_valid(rt_batch_t b) { return b && b->magic == kBatchMagic; }
+
+rtk::BatchLaunch batch_launch(rt_batch_t b, int fp64, int thermal) {
+    rtk::BatchLaunch l;
+    l.head = reinterpret_cast<const rtk::BatchHead *>(b->ws + b->lay.off_head);
+    l.table = reinterpret_cast<const rtk::BatchSolve *>(b->ws + b->lay.off_table);
+    l.slots = reinterpret_cast<rtk::LedgerSlot *>(b->ws + b->lay.off_slots);
+    l.queue = reinterpret_cast<unsigned long long *>(b->ws + b->lay.off_queue);
+    l.fp64 = fp64;
+    l.thermal = thermal;
+    int blocks = b->cus * b->occ[fp64][thermal];
+    if (blocks > kMaxBatchBlocks) blocks = kMaxBatchBlocks;
+    l.blocks = blocks < 1 ? 1 : blocks;
+    l.chunk = 256;
+    l.refill_min = 8;
+    l.cell_blocks = b->cus * 8;
+    l.stream = b->stream;
+    return l;
+}
+
+// Every launch of one call: ledgers cleared, then per round absorbers, march,
+// ledger reduction and cell update of every solve that still has sub-steps.
+hipError_t batch_enqueue(const rtk::BatchLaunch &l, int rounds) {
+    hipError_t e = rtk::launch_batch_begin(l);
+    for (int r = 0; r < rounds && e == hipSuccess; ++r) {
+        e = rtk::launch_batch_prep(l, r);
+        if (e == hipSuccess) e = rtk::launch_batch_march(l, r);
+        if (e == hipSuccess) e = rtk::launch_batch_ledger(l, r);
+        if (e == hipSuccess) e = rtk::launch_batch_update(l, r);
+    }
+    return e;
+}
+
+hipError_t batch_graph(rt_batch_t b, const rtk::BatchLaunch &l, int rounds, hipGraphExec_t *out) {
+    for (const BatchGraph &g : b->graphs)
+        if (g.rounds == rounds && g.fp64 == l.fp64 && g.thermal == l.thermal) {
+            *out = g.exec;
+            return hipSuccess;
+        }
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const hipError_t el = batch_enqueue(l, rounds);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(b->stream, &graph);
+    if (el != hipSuccess || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return el != hipSuccess ? el : e;
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return e;
+    b->graphs.push_back(BatchGraph{rounds, l.fp64, l.thermal, exec});
+    *out = exec;
+    return hipSuccess;
+}
+
+void batch_destroy(rt_batch_t b) {
+    for (BatchGraph &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+    for (hipEvent_t e : b->ev_in) if (e) (void)hipEventDestroy(e);
+    if (b->staged) (void)hipEventDestroy(b->staged);
+    if (b->done) (void)hipEventDestroy(b->done);
+    if (b->staging) (void)hipHostFree(b->staging);
+    b->magic = 0;
+    delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t rt_batch_workspace_bytes(int32_t max_solves, size_t *bytes_out) {
+    if (!bytes_out || max_solves < 1 || max_solves > RT_MAX_BATCH) return RT_EINVAL;
+    *bytes_out = batch_layout(max_solves).total;
+    return RT_OK;
+}
+
+int32_t rt_batch_init(int32_t max_solves, void *d_ws, size_t ws_bytes, void *hip_stream, uint32_t flags,
+                      rt_batch_t *out) {
+    if (!out) return RT_EINVAL;
+    *out = nullptr;
+    if (max_solves < 1 || max_solves > RT_MAX_BATCH || (flags & ~RT_BATCH_GRAPH)) return RT_EINVAL;
+    if ((flags & RT_BATCH_GRAPH) && !hip_stream) return RT_EINVAL;
+    if (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0) return RT_EINVAL;
+    const BatchLayout lay = batch_layout(max_solves);
+    if (ws_bytes < lay.total) return RT_ENOMEM;
+    rt_batch *b = new (std::nothrow) rt_batch;
+    if (!b) return RT_ENOMEM;
+    b->magic = kBatchMagic;
+    b->max_solves = max_solves;
+    b->flags = flags;
+    b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    b->ws = reinterpret_cast<char *>(d_ws);
+    b->lay = lay;
+    b->staging = nullptr;
+    b->staged = nullptr;
+    b->done = nullptr;
+    b->staged_pending = false;
+    bool ok = hipGetDevice(&b->device) == hipSuccess &&
+              hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->device) == hipSuccess;
+    for (int f = 0; f < 2 && ok; ++f)
+        for (int t = 0; t < 2 && ok; ++t) {
+            ok = rtk::batch_march_occupancy(f, t, &b->occ[f][t]) == hipSuccess;
+            if (ok && b->occ[f][t] < 1) b->occ[f][t] = 1;
+        }
+    ok = ok && hipHostMalloc(&b->staging, sizeof(rtk::BatchHead) + (size_t)max_solves * sizeof(rtk::BatchSolve),
+                             hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&b->done, hipEventDisableTiming) == hipSuccess;
+    b->ev_in.assign(max_solves, nullptr);
+    for (int i = 0; i < max_solves && ok; ++i)
+        ok = hipEventCreateWithFlags(&b->ev_in[i], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        batch_destroy(b);
+        return RT_EDEVICE;
+    }
+    *out = b;
+    return RT_OK;
+}
+
+int32_t rt_step_many(rt_batch_t b, const rt_solve_t *solves, int32_t n, const double *dt_s,
+                     const int64_t *n_packets, const uint64_t *seeds, rt_step_stats *stats) {
+    if (!batch_valid(b) || !solves || !dt_s || !n_packets || !seeds) return RT_EINVAL;
+    if (n < 1 || n > b->max_solves) return RT_EINVAL;
+    int fp64 = -1, thermal = -1, rounds = 0;
+    for (int i = 0; i < n; ++i) {
+        const rt_solve_t h = solves[i];
+        if (!valid(h)) return RT_EINVAL;
+        if (h->dead) return RT_ESTATE;
+        for (int k = 0; k < i; ++k)
+            if (solves[k] == h) return RT_EINVAL;
+        const Plan &p = h->plan;
+        if (h->device != b->device || p.species != 1 || p.mb != 1 || h->d.trace_packets > 0) return RT_EINVAL;
+        if ((fp64 >= 0 && p.fp64 != fp64) || (thermal >= 0 && p.thermal != thermal)) return RT_EINVAL;
+        fp64 = p.fp64;
+        thermal = p.thermal;
+        if (!(isfinite(dt_s[i]) && dt_s[i] > 0.0) || n_packets[i] < 0) return RT_EINVAL;
+        const int64_t base = n_packets[i] / h->d.n_sub;
+        if (h->n_src > 0 && base < h->n_src) return RT_EINVAL;
+        if (base + 1 > ((int64_t)1 << 31)) return RT_EOVERFLOW;
+        if (h->d.n_sub > rounds) rounds = h->d.n_sub;
+    }
+    const rtk::BatchLaunch l = batch_launch(b, fp64, thermal);
+
+    // the table: the previous copy out of the staging memory must have happened
+    if (b->staged_pending && hipEventSynchronize(b->staged) != hipSuccess) return RT_EDEVICE;
+    rtk::BatchHead *hd = reinterpret_cast<rtk::BatchHead *>(b->staging);
+    rtk::BatchSolve *tb = reinterpret_cast<rtk::BatchSolve *>(hd + 1);
+    uint64_t cells = 0;
+    for (int i = 0; i < n; ++i) {
+        const rt_solve_t h = solves[i];
+        const Plan &p = h->plan;
+        rtk::BatchSolve &t = tb[i];
+        memset(&t, 0, sizeof(t));
+        t.geo = p.geo;
+        t.half_dl = 0.5 * h->d.cell_cm;
+        t.dt = dt_s[i] / h->d.n_sub;
+        t.tau_kill = h->d.tau_kill;
+        t.y_he = h->d.y_he;
+        t.cell_cm = h->d.cell_cm;
+        t.redshift = h->d.redshift;
+        t.seed = seeds[i];
+        t.solve_id = h->d.solve_id;
+        t.step0 = h->step_index;
+        t.packets = h->n_src > 0 ? n_packets[i] : 0;     // without sources only the update runs
+        t.src = reinterpret_cast<const rtk::SourceRec *>(h->ws + p.off_src);
+        t.src_ndot = reinterpret_cast<const double *>(h->ws + p.off_ndot);
+        t.src_sedsum = reinterpret_cast<const double *>(h->ws + p.off_sedsum);
+        t.sed = h->ws + p.off_sed;
+        t.tab = h->ws + p.off_tab;
+        t.state = h->ws + p.off_state;
+        t.kappa = h->ws + p.off_kappa;
+        t.acc = reinterpret_cast<double *>(h->ws + p.off_acc);
+        t.ledger = reinterpret_cast<rtk::StepLedger *>(h->ws + p.off_ledger);
+        t.n_sub = h->d.n_sub;
+        t.n_src = (int32_t)h->n_src;
+        t.n_chem = h->d.n_chem;
+        t.acc_stride = p.acc_stride;
+        t.cell0 = cells;
+        cells += p.geo.ncell_pad;
+    }
+    memset(hd, 0, sizeof(*hd));
+    hd->n = n;
+    hd->cells = cells;
+
+    // order: each solve's earlier work, the table copy, the fused launches
+    for (int i = 0; i < n; ++i) {
+        const hipStream_t s = solves[i]->stream;
+        if (s == b->stream) continue;
+        if (hipEventRecord(b->ev_in[i], s) != hipSuccess || hipStreamWaitEvent(b->stream, b->ev_in[i], 0) != hipSuccess)
+            return RT_EDEVICE;
+    }
+    if (hipMemcpyAsync(b->ws + b->lay.off_head, b->staging,
+                       sizeof(rtk::BatchHead) + (size_t)n * sizeof(rtk::BatchSolve), hipMemcpyHostToDevice,
+                       b->stream) != hipSuccess)
+        return RT_EDEVICE;
+    static_assert(sizeof(rtk::BatchHead) % alignof(rtk::BatchSolve) == 0, "table after the head is misaligned");
+    if (hipEventRecord(b->staged, b->stream) != hipSuccess) return RT_EDEVICE;
+    b->staged_pending = true;
+    if (b->flags & RT_BATCH_GRAPH) {
+        hipGraphExec_t exec = nullptr;
+        if (batch_graph(b, l, rounds, &exec) != hipSuccess || hipGraphLaunch(exec, b->stream) != hipSuccess)
+            return RT_EDEVICE;
+    } else if (batch_enqueue(l, rounds) != hipSuccess) {
+        return RT_EDEVICE;
+    }
+    if (hipEventRecord(b->done, b->stream) != hipSuccess) return RT_EDEVICE;
+    for (int i = 0; i < n; ++i) {
+        rt_solve_t h = solves[i];
+        h->step_index += (uint64_t)h->d.n_sub;
+        h->timed = 0;
+        h->ktimed = 0;
+        if (h->stream != b->stream && hipStreamWaitEvent(h->stream, b->done, 0) != hipSuccess) return fail(h);
+    }
+    if (stats) {
+        for (int i = 0; i < n; ++i) {
+            const int32_t r = rt_read_stats(solves[i], &stats[i]);
+            if (r != RT_OK) return r;
+        }
+    }
+    return RT_OK;
+}
+
+int32_t rt_batch_release(rt_batch_t b) {
+    if (!batch_valid(b)) return RT_EINVAL;
+    const bool ok = hipStreamSynchronize(b->stream) == hipSuccess;
+    batch_destroy(b);
+    return ok ? RT_OK : RT_EDEVICE;
+}
+
 const char *rt_strerror(int32_t status) {
     switch (status) {
     case RT_OK: return "ok";

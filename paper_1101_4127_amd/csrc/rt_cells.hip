@@ -28,29 +28,34 @@ static inline int cell_blocks(uint64_t n) {
 // reset: kappa = (n_H x_HI, (y n_H) x_HeI, (y n_H) x_HeII).
 // ---------------------------------------------------------------------------
 template <typename R, int S>
+__device__ __forceinline__ void prep_slot(uint32_t np, const R *__restrict__ st, void *__restrict__ kappa,
+                                          double *__restrict__ acc, int acc_stride, double y_he, uint32_t s) {
+    const double nh = (double)st[s];
+    const double xhi = (double)st[(size_t)np + s];
+    if (S == 1) {
+        reinterpret_cast<R *>(kappa)[s] = (R)(nh * xhi);
+    } else {
+        const double yn = y_he * nh;
+        typename V4<R>::T v;
+        v.x = (R)(nh * xhi);
+        v.y = (R)(yn * (double)st[3 * (size_t)np + s]);
+        v.z = (R)(yn * (double)st[4 * (size_t)np + s]);
+        v.w = R(0);
+        reinterpret_cast<typename V4<R>::T *>(kappa)[s] = v;
+    }
+    double *a = acc + (size_t)s * acc_stride;
+    for (int i = 0; i < acc_stride; ++i) a[i] = 0.0;
+}
+
+template <typename R, int S>
 __global__ void __launch_bounds__(kCellBlock) k_prep(GridGeom G, const R *__restrict__ st,
                                                      void *__restrict__ kappa, double *__restrict__ acc,
                                                      int acc_stride, double y_he, unsigned long long *queue) {
     const uint32_t np = G.ncell_pad;
     const uint32_t step = gridDim.x * blockDim.x;
     if (blockIdx.x == 0 && threadIdx.x == 0) *queue = 0ull;
-    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < np; s += step) {
-        const double nh = (double)st[s];
-        const double xhi = (double)st[(size_t)np + s];
-        if (S == 1) {
-            reinterpret_cast<R *>(kappa)[s] = (R)(nh * xhi);
-        } else {
-            const double yn = y_he * nh;
-            typename V4<R>::T v;
-            v.x = (R)(nh * xhi);
-            v.y = (R)(yn * (double)st[3 * (size_t)np + s]);
-            v.z = (R)(yn * (double)st[4 * (size_t)np + s]);
-            v.w = R(0);
-            reinterpret_cast<typename V4<R>::T *>(kappa)[s] = v;
-        }
-        double *a = acc + (size_t)s * acc_stride;
-        for (int i = 0; i < acc_stride; ++i) a[i] = 0.0;
-    }
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < np; s += step)
+        prep_slot<R, S>(np, st, kappa, acc, acc_stride, y_he, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -160,26 +165,34 @@ __device__ void evolve(Frac &x, const Frac &x0, const Rates &r, const double gam
     x.heiii = (1.0 - c0) * q3 + c0 * x0.heiii + c1 * m3;
 }
 
+// Constants of one solve's cell update for a sub-step of length dt.
+struct UpdateConst {
+    double V, kb, tcmb, ccomp, h;
+    __device__ __forceinline__ UpdateConst(double cell_cm, double dt, double redshift, int n_chem) {
+        V = cell_cm * cell_cm * cell_cm;
+        kb = 1.380649e-16;
+        const bool compton = redshift >= 0.0;
+        tcmb = 2.725 * (1.0 + (redshift > 0.0 ? redshift : 0.0));
+        // 4 sigma_T a_rad k T_cmb^4 / (m_e c)
+        ccomp = compton ? 4.0 * 6.6524587321e-25 * 7.5657e-15 * kb * (tcmb * tcmb) * (tcmb * tcmb)
+                              / (9.1093837015e-28 * 2.99792458e10)
+                        : 0.0;
+        h = dt / n_chem;
+    }
+};
+
+// The update of slot s (padding slots outside the grid are left alone); bad is
+// set when a result is not finite.
 template <typename R, int S, bool TH>
-__global__ void __launch_bounds__(kCellBlock) k_update(GridGeom G, R *__restrict__ st, const double *__restrict__ acc,
-                                                       int acc_stride, double y_he, double cell_cm, double dt,
-                                                       double redshift, int n_chem, StepLedger *ledger) {
+__device__ __forceinline__ void update_slot(const GridGeom &G, R *__restrict__ st, const double *__restrict__ acc,
+                                            int acc_stride, double y_he, double dt, int n_chem,
+                                            const UpdateConst &u, uint32_t s, unsigned int &bad) {
     constexpr bool he = (S == 3);
     const uint32_t np = G.ncell_pad;
-    const uint32_t stride = gridDim.x * blockDim.x;
-    const double V = cell_cm * cell_cm * cell_cm;
-    const double kb = 1.380649e-16;
-    const bool compton = redshift >= 0.0;
-    const double tcmb = 2.725 * (1.0 + (redshift > 0.0 ? redshift : 0.0));
-    // 4 sigma_T a_rad k T_cmb^4 / (m_e c)
-    const double ccomp = compton ? 4.0 * 6.6524587321e-25 * 7.5657e-15 * kb * (tcmb * tcmb) * (tcmb * tcmb)
-                                       / (9.1093837015e-28 * 2.99792458e10)
-                                 : 0.0;
-    const double h = dt / n_chem;
-    unsigned int bad = 0;
-    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < np; s += stride) {
+    const double V = u.V, kb = u.kb, tcmb = u.tcmb, ccomp = u.ccomp, h = u.h;
+    {
         int i, j, k;
-        if (!slot_cell(G, s, i, j, k)) continue;
+        if (!slot_cell(G, s, i, j, k)) return;
         const double nh = (double)st[s];
         const double nhe = he ? y_he * nh : 0.0;
         Frac x;
@@ -233,6 +246,18 @@ __global__ void __launch_bounds__(kCellBlock) k_update(GridGeom G, R *__restrict
             st[(size_t)(q + 1) * np + s] = (R)vals[q];
         }
     }
+}
+
+template <typename R, int S, bool TH>
+__global__ void __launch_bounds__(kCellBlock) k_update(GridGeom G, R *__restrict__ st, const double *__restrict__ acc,
+                                                       int acc_stride, double y_he, double cell_cm, double dt,
+                                                       double redshift, int n_chem, StepLedger *ledger) {
+    const uint32_t np = G.ncell_pad;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    const UpdateConst u(cell_cm, dt, redshift, n_chem);
+    unsigned int bad = 0;
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < np; s += stride)
+        update_slot<R, S, TH>(G, st, acc, acc_stride, y_he, dt, n_chem, u, s, bad);
     if (bad) atomicOr(&ledger->nonfinite, 1u);
 }
 
@@ -292,21 +317,24 @@ __global__ void __launch_bounds__(kCellBlock) k_export(GridGeom G, const R *__re
 // ---------------------------------------------------------------------------
 // Ledger: per-block slots of the march summed (TwoSum) into the step ledger.
 // ---------------------------------------------------------------------------
-__global__ void k_ledger_zero(StepLedger *l) {
-    if (threadIdx.x == 0) {
-        StepLedger z;
-        for (int i = 0; i < 8; ++i) z.s[i] = 0.0;
-        for (int i = 0; i < 4; ++i) z.c[i] = 0ull;
-        z.substeps = 0ull;
-        z.nonfinite = 0u;
-        z.errors = 0u;
-        *l = z;
-    }
+__device__ __forceinline__ void zero_ledger(StepLedger *l) {
+    StepLedger z;
+    for (int i = 0; i < 8; ++i) z.s[i] = 0.0;
+    for (int i = 0; i < 4; ++i) z.c[i] = 0ull;
+    z.substeps = 0ull;
+    z.nonfinite = 0u;
+    z.errors = 0u;
+    *l = z;
 }
 
-__global__ void __launch_bounds__(64) k_ledger_reduce(const LedgerSlot *slots, int n, StepLedger *l) {
-    // one wavefront: lane-strided partial sums, then a TwoSum tree
-    const int lane = threadIdx.x;
+__global__ void k_ledger_zero(StepLedger *l) {
+    if (threadIdx.x == 0) zero_ledger(l);
+}
+
+// One wavefront adds n per-block slots into a step ledger: lane-strided
+// partial sums, then a TwoSum tree; the sub-step counter moves by one.
+__device__ __forceinline__ void reduce_slots(const LedgerSlot *slots, int n, StepLedger *l) {
+    const int lane = threadIdx.x & 63;
     double s[8];
     unsigned long long c[4] = {0, 0, 0, 0};
     for (int i = 0; i < 8; ++i) s[i] = 0.0;
@@ -339,6 +367,10 @@ __global__ void __launch_bounds__(64) k_ledger_reduce(const LedgerSlot *slots, i
         }
         l->substeps += 1ull;
     }
+}
+
+__global__ void __launch_bounds__(64) k_ledger_reduce(const LedgerSlot *slots, int n, StepLedger *l) {
+    reduce_slots(slots, n, l);
 }
 
 // Sub-step without packets: only the sub-step counter of the ledger moves.
@@ -390,8 +422,101 @@ __global__ void k_trace_rays(GridGeom G, int m, const int32_t *o, const int32_t 
 }
 
 // ---------------------------------------------------------------------------
+// Fused sub-steps of many solves: the cell kernels walk the concatenation of
+// the solves' slots; each thread finds its solve in the table (first slots
+// ascending, staged in LDS).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int batch_solve_of(const uint64_t *first, int n, uint64_t g) {
+    int lo = 0, hi = n - 1;                 // the last solve whose first slot is <= g
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(64) k_bbegin(const BatchHead *hd, const BatchSolve *tb) {
+    if (threadIdx.x == 0 && (int)blockIdx.x < hd->n) zero_ledger(tb[blockIdx.x].ledger);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kCellBlock) k_bprep(const BatchHead *hd, const BatchSolve *tb, int round,
+                                                      unsigned long long *queue) {
+    __shared__ uint64_t s_first[kMaxBatch];
+    const int n = hd->n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s_first[i] = tb[i].cell0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *queue = 0ull;
+    __syncthreads();
+    const uint64_t total = hd->cells;
+    for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < total;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const int b = batch_solve_of(s_first, n, g);
+        const BatchSolve &sv = tb[b];
+        if (round >= sv.n_sub) continue;
+        prep_slot<R, 1>(sv.geo.ncell_pad, reinterpret_cast<const R *>(sv.state), sv.kappa, sv.acc, sv.acc_stride,
+                        sv.y_he, (uint32_t)(g - s_first[b]));
+    }
+}
+
+__global__ void __launch_bounds__(64) k_bledger(const BatchHead *hd, const BatchSolve *tb, int round,
+                                                const LedgerSlot *slots, int nslots) {
+    const int b = blockIdx.x;
+    if (b >= hd->n || round >= tb[b].n_sub) return;
+    reduce_slots(slots + (size_t)b * nslots, nslots, tb[b].ledger);
+}
+
+template <typename R, bool TH>
+__global__ void __launch_bounds__(kCellBlock) k_bupdate(const BatchHead *hd, const BatchSolve *tb, int round) {
+    __shared__ uint64_t s_first[kMaxBatch];
+    const int n = hd->n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s_first[i] = tb[i].cell0;
+    __syncthreads();
+    const uint64_t total = hd->cells;
+    for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < total;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const int b = batch_solve_of(s_first, n, g);
+        const BatchSolve &sv = tb[b];
+        if (round >= sv.n_sub) continue;
+        const UpdateConst u(sv.cell_cm, sv.dt, sv.redshift, sv.n_chem);
+        unsigned int bad = 0;
+        update_slot<R, 1, TH>(sv.geo, reinterpret_cast<R *>(sv.state), sv.acc, sv.acc_stride, sv.y_he, sv.dt,
+                              sv.n_chem, u, (uint32_t)(g - s_first[b]), bad);
+        if (bad) atomicOr(&sv.ledger->nonfinite, 1u);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+hipError_t launch_batch_begin(const BatchLaunch &b) {
+    hipLaunchKernelGGL(k_bbegin, dim3(kMaxBatch), dim3(64), 0, b.stream, b.head, b.table);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_prep(const BatchLaunch &b, int round) {
+    if (b.fp64) hipLaunchKernelGGL(k_bprep<double>, dim3(b.cell_blocks), dim3(kCellBlock), 0, b.stream, b.head,
+                                   b.table, round, b.queue);
+    else hipLaunchKernelGGL(k_bprep<float>, dim3(b.cell_blocks), dim3(kCellBlock), 0, b.stream, b.head, b.table,
+                            round, b.queue);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_ledger(const BatchLaunch &b, int round) {
+    hipLaunchKernelGGL(k_bledger, dim3(kMaxBatch), dim3(64), 0, b.stream, b.head, b.table, round, b.slots, b.blocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_update(const BatchLaunch &b, int round) {
+    const dim3 g(b.cell_blocks), t(kCellBlock);
+    if (b.fp64) {
+        if (b.thermal) hipLaunchKernelGGL((k_bupdate<double, true>), g, t, 0, b.stream, b.head, b.table, round);
+        else hipLaunchKernelGGL((k_bupdate<double, false>), g, t, 0, b.stream, b.head, b.table, round);
+    } else {
+        if (b.thermal) hipLaunchKernelGGL((k_bupdate<float, true>), g, t, 0, b.stream, b.head, b.table, round);
+        else hipLaunchKernelGGL((k_bupdate<float, false>), g, t, 0, b.stream, b.head, b.table, round);
+    }
+    return hipGetLastError();
+}
 hipError_t launch_prep(const CellLaunch &c) {
     const int nb = cell_blocks(c.geo.ncell_pad);
     if (c.fp64) {

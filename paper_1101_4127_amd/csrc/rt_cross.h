@@ -23,6 +23,17 @@ template <> struct Vec4<double> { using T = double4; };
 // space: the indices are uniform, so the values live in scalar registers.
 template <typename R> using CTab = const __attribute__((address_space(4))) R *;
 
+// The per-bin table of one monochromatic solve held in registers, indexed like
+// the [7][1] table in memory (rows 0-2 cross-sections, 3-5 heat factors, 6 the
+// hydrogen heat factor); a march whose lanes carry packets of different solves
+// passes this instead of a pointer.  Indices are compile-time constants once
+// the bin loops are unrolled, so the lookup folds away.
+template <typename R>
+struct LaneTab1 {
+    R sig, heat;
+    __device__ __forceinline__ R operator[](int i) const { return i == 0 ? sig : (i == 3 || i == 6 ? heat : R(0)); }
+};
+
 constexpr uint32_t kNeg = 0x80000000u;      // sign flag packed above |c| (|c| <= 2^20)
 constexpr uint32_t kMag = 0x00ffffffu;
 
@@ -63,8 +74,8 @@ __device__ __forceinline__ int exit_face(uint32_t d0, uint32_t d1, uint32_t d2, 
 // smallest accumulated optical depth over the bins (those the source does
 // not populate hold +inf), which ends the packet once it reaches tau_kill
 // (float32 form: see Extinction).
-template <typename R, int S, bool TH, int MB, int NA = 0, int NB = 0, typename KV>
-__device__ __forceinline__ void cross_cell(R l, const KV &kap, CTab<R> tab, R (&F)[MB],
+template <typename R, int S, bool TH, int MB, int NA = 0, int NB = 0, typename KV, typename TT>
+__device__ __forceinline__ void cross_cell(R l, const KV &kap, TT tab, R (&F)[MB],
                                            R (&D)[DepthState<R, S, MB>::N], R &absorbed, R &e0, R &e1,
                                            R &e2, R &heat, R &tmin) {
     constexpr bool F64 = std::is_same<R, double>::value;
@@ -194,7 +205,8 @@ struct Extinction {
 
     // full check: true if extinguished; else the witness is the first bin of
     // smallest depth
-    __device__ __forceinline__ bool full(CTab<float> tab, uint32_t active, float tau_kill,
+    template <typename TT>
+    __device__ __forceinline__ bool full(TT tab, uint32_t active, float tau_kill,
                                          const float (&N)[S == 1 ? 1 : 3]) {
         float tm = INFINITY;
 #pragma unroll
@@ -219,7 +231,8 @@ struct Extinction {
         wHe2 = S == 1 ? 0.0f : sig[2 * MB + j];
     }
 
-    __device__ __forceinline__ bool extinguished(CTab<float> tab, uint32_t active, float tau_kill,
+    template <typename TT>
+    __device__ __forceinline__ bool extinguished(TT tab, uint32_t active, float tau_kill,
                                                  const float (&N)[S == 1 ? 1 : 3]) {
         if (depth(wH, wHe1, wHe2, N) < tau_kill) return false;
         return full(tab, active, tau_kill, N);
@@ -232,10 +245,12 @@ template <typename R, int S, int MB>
 struct DepthTest {
     static constexpr bool F64 = std::is_same<R, double>::value;
     Extinction<S, MB> ext;
-    __device__ __forceinline__ void start(CTab<R> tab, uint32_t active, const R (&D)[DepthState<R, S, MB>::N]) {
+    template <typename TT>
+    __device__ __forceinline__ void start(TT tab, uint32_t active, const R (&D)[DepthState<R, S, MB>::N]) {
         if constexpr (!F64) (void)ext.full(tab, active, 0.0f, D);
     }
-    __device__ __forceinline__ bool extinguished(CTab<R> tab, uint32_t active, double tau_kill, R tmin,
+    template <typename TT>
+    __device__ __forceinline__ bool extinguished(TT tab, uint32_t active, double tau_kill, R tmin,
                                                  const R (&D)[DepthState<R, S, MB>::N]) {
         if constexpr (F64) return tmin >= tau_kill;
         else return ext.extinguished(tab, active, (float)tau_kill, D);

@@ -141,6 +141,60 @@ hipError_t launch_tiled_batch(const TiledLaunch &t);
 hipError_t tiled_occupancy(int species, int thermal, int fp64, int mb, int *blocks_per_cu);
 hipError_t march_occupancy(int species, int thermal, int fp64, int mb, int *blocks_per_cu);
 
+// ---------------------------------------------------------------------------
+// Fused steps of many independent solves (pure hydrogen, one bin).  Every
+// kernel of a fused sub-step reads the solves from one device table, so the
+// launch shapes do not depend on the batch and one captured graph serves any
+// set of solves; round r of a call is every solve's sub-step r.
+// ---------------------------------------------------------------------------
+constexpr int kMaxBatch = 64;              // solves per fused call
+
+struct BatchSolve {
+    GridGeom geo;
+    double half_dl, dt, tau_kill, y_he, cell_cm, redshift;
+    uint64_t seed, solve_id, step0;        // step index of the call's first sub-step
+    int64_t packets;                       // packets of the call, split over n_sub as rt_step does
+    const SourceRec *src;
+    const double *src_ndot, *src_sedsum;
+    const void *sed, *tab;
+    void *state, *kappa;
+    double *acc;
+    StepLedger *ledger;
+    int32_t n_sub, n_src, n_chem, acc_stride;
+    uint64_t cell0;                        // first fused cell index of this solve
+};
+
+struct BatchHead {
+    int32_t n;                             // solves in the table
+    int32_t pad;
+    uint64_t cells;                        // fused cells: the solves' padded slot counts summed
+};
+
+// Packets of sub-step `round` of a solve (zero once its sub-steps are done).
+__host__ __device__ inline uint32_t round_packets(const BatchSolve &s, int round) {
+    if (round >= s.n_sub) return 0u;
+    const int64_t base = s.packets / s.n_sub, extra = s.packets % s.n_sub;
+    return (uint32_t)(base + (round < extra ? 1 : 0));
+}
+
+struct BatchLaunch {
+    const BatchHead *head;
+    const BatchSolve *table;
+    LedgerSlot *slots;                     // [kMaxBatch][blocks] per-block partial ledgers
+    unsigned long long *queue;             // packet counter of the round
+    int32_t fp64, thermal;
+    int32_t blocks, chunk, refill_min;     // march grid and claim parameters
+    int32_t cell_blocks;                   // grid of the cell kernels
+    hipStream_t stream;
+};
+
+hipError_t launch_batch_begin(const BatchLaunch &b);
+hipError_t launch_batch_prep(const BatchLaunch &b, int round);
+hipError_t launch_batch_march(const BatchLaunch &b, int round);
+hipError_t launch_batch_ledger(const BatchLaunch &b, int round);
+hipError_t launch_batch_update(const BatchLaunch &b, int round);
+hipError_t batch_march_occupancy(int fp64, int thermal, int *blocks_per_cu);
+
 hipError_t launch_prep(const CellLaunch &c);
 hipError_t launch_update(const CellLaunch &c);
 hipError_t launch_import(const CellLaunch &c, const void *nh, const void *x, const void *t,

@@ -552,11 +552,14 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
 
         // ---- packet state (one per lane) ----
         bool alive = false;
+        bool pend = false;                       // segment over, fate not yet settled (implies alive)
+        bool kill = false;                       // extinction candidate at the last crossing
         bool exhausted = false;                  // wave-uniform
         uint32_t pos = 0, rid = 0;               // list position and record of the lane's packet
         int k0 = 0, k1 = 0, k2 = 0;
         uint32_t d0 = 1, d1 = 1, d2 = 1, a0 = 0, a1 = 0, a2 = 0, pnum = 0, pden = 1;
         uint32_t lax = 3;                        // axis of the last face crossed (3: none)
+        int hlast = 0;                           // natural index of the last cell crossed (traces)
         double sprev = 0.0, L = 0.0, w = 0.0, absd = 0.0;
         float Lf = 0.0f;
         uint32_t loc = 0, count = 0, active = 0;
@@ -570,9 +573,67 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
         for (int j = 0; j < ND; ++j) D[j] = R(0);
 
         for (;;) {
+            // Lanes whose segment ended wait, like dead lanes, until enough lanes
+            // are idle; then the wave settles their fates together (extinction
+            // check over every bin, record write-back, ledger) and refills the
+            // dead lanes, so that code runs once per refill, not per crossing.
+            const uint32_t npend = (uint32_t)__popcll(__ballot(pend));
+            const uint32_t nidle = (uint32_t)__popcll(__ballot(!alive)) + npend;
+            const bool trigger = nidle != 0u
+                && (nidle == 64u || (exhausted ? npend >= p.refill_min : nidle >= p.refill_min));
+            if (trigger && npend != 0u && pend) {
+                bool ex = kill;
+                if constexpr (!F64) ex = kill && dtest.ext.full(tab, active, (float)p.tau_kill, D);
+                const bool o0 = (uint32_t)k0 >= (uint32_t)p.geo.n[0];
+                const bool o1 = (uint32_t)k1 >= (uint32_t)p.geo.n[1];
+                const bool o2 = (uint32_t)k2 >= (uint32_t)p.geo.n[2];
+                const bool out = o0 | o1 | o2;
+                const int dx = (k0 >> kTileLog2) - tx, dy = (k1 >> kTileLog2) - ty, dz = (k2 >> kTileLog2) - tz;
+                const bool leave = !out && (dx | dy | dz) != 0;
+                const uint32_t fate = ex ? 1u : (out ? 2u : (leave ? 3u : 0u));
+                if (fate != 0u) {                  // fate 0: a new witness bin, the packet marches on
+                    const bool traced = tix >= 0;
+                    int32_t *rec = p.trace + (size_t)(traced ? tix : 0) * (RT_TRACE_HDR_DEV + p.trace_len);
+                    l_abs += w * absd;
+                    if (fate == 3u) {
+                        // moves on into a neighbour tile: record back, rank among the run's
+                        // packets bound for the same tile
+                        uint32_t jw = 0;
+                        if constexpr (!F64) jw = dtest.ext.jw;
+                        store_moving<R, S, MB>(recs + (size_t)rid * RL::STRIDE, pack_cell(k0, k1, k2, lax),
+                                               d0, jw, d1, d2, active, F, D);
+                        const uint32_t code = (uint32_t)((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1));
+                        const uint32_t rank = atomicAdd(&s_cnt[code], 1u);
+                        p.side[pos] = code | (rank << 5);
+                        if (traced) rec[0] = (int32_t)count;
+                    } else {
+                        R left = R(0);
+#pragma unroll
+                        for (int j = 0; j < MB; ++j) left += F[j];
+                        const double wl = w * (double)left;
+                        if (fate == 2u) { l_esc += wl; ++n_esc; } else { l_trunc += wl; ++n_trunc; }
+                        p.side[pos] = kSideDead;
+                        if (traced) {
+                            const int face = fate == 1u ? 0
+                                : ((o0 ? 1 : 0) | (o1 ? 2 : 0) | (o2 ? 4 : 0)
+                                   | (k0 >= p.geo.n[0] ? 8 : 0) | (k1 >= p.geo.n[1] ? 16 : 0)
+                                   | (k2 >= p.geo.n[2] ? 32 : 0));
+                            rec[0] = (int32_t)count; rec[1] = (int32_t)fate; rec[2] = face; rec[3] = hlast;
+                            rec[4] = unpack_dir(a0);
+                            rec[5] = unpack_dir(a1);
+                            rec[6] = unpack_dir(a2);
+                            uint32_t ns;
+                            rec[7] = (int32_t)source_of(p.g0 + rid, p.q, p.r, ns);
+                        }
+                    }
+                    alive = false;
+                }
+                pend = false;
+                kill = false;
+            }
             const uint64_t dead = __ballot(!alive);
             const uint32_t ndead = (uint32_t)__popcll(dead);
-            if (!exhausted && ndead != 0u && (ndead >= p.refill_min || ndead == 64u)) {
+            if (trigger && !exhausted && ndead != 0u) {
                 uint32_t b0 = 0;
                 if (lane == 0) b0 = atomicAdd(&s_next, ndead);
                 b0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)b0);
@@ -654,14 +715,13 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                     }
                 }
             }
-            if (__ballot(alive) == 0ull) {
-                if (exhausted) break;
+            if (__ballot(alive && !pend) == 0ull) {
+                if (exhausted && __ballot(alive) == 0ull) break;
                 continue;
             }
 
-            double it_abs = 0.0, it_left = 0.0;
-            uint32_t it_cross = 0, it_fate = 0;
-            if (alive) {
+            uint32_t it_cross = 0;
+            if (alive && !pend) {
                 bool m0, m1, m2;
                 const int ax = exit_face(d0, d1, d2, a0, a1, a2, m0, m1, m2);
                 const uint32_t num = ax == 0 ? d0 : (ax == 1 ? d1 : d2);
@@ -713,63 +773,27 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                 if (traced && count < (uint32_t)p.trace_len) rec[RT_TRACE_HDR_DEV + count] = here;
                 ++count;
 
-                const uint32_t fate = dtest.extinguished(tab, active, p.tau_kill, tmin, D) ? 1u
-                                      : (out ? 2u : (leave ? 3u : 0u));
-                if (fate == 0u) {
-                    loc = nloc;
-                    kap = knext;
-                    lax = (uint32_t)ax;
-                    if (F64) sprev = snew; else { pnum = num; pden = den; }
-                } else {
-                    it_abs = w * absd;
-                    if (fate == 3u) {
-                        // moves on into a neighbour tile: record back, rank among the run's
-                        // packets bound for the same tile
-                        uint32_t jw = 0;
-                        if constexpr (!F64) jw = dtest.ext.jw;
-                        store_moving<R, S, MB>(recs + (size_t)rid * RL::STRIDE, pack_cell(k0, k1, k2, (uint32_t)ax),
-                                               d0, jw, d1, d2, active, F, D);
-                        const uint32_t code = (uint32_t)((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1));
-                        const uint32_t rank = atomicAdd(&s_cnt[code], 1u);
-                        p.side[pos] = code | (rank << 5);
-                        if (traced) rec[0] = (int32_t)count;
-                    } else {
-                        R left = R(0);
-#pragma unroll
-                        for (int j = 0; j < MB; ++j) left += F[j];
-                        it_left = w * (double)left;
-                        it_fate = fate;
-                        p.side[pos] = kSideDead;
-                        if (traced) {
-                            const int face = fate == 1u ? 0
-                                : ((o0 ? 1 : 0) | (o1 ? 2 : 0) | (o2 ? 4 : 0)
-                                   | (k0 >= p.geo.n[0] ? 8 : 0) | (k1 >= p.geo.n[1] ? 16 : 0)
-                                   | (k2 >= p.geo.n[2] ? 32 : 0));
-                            rec[0] = (int32_t)count; rec[1] = (int32_t)fate; rec[2] = face; rec[3] = here;
-                            rec[4] = unpack_dir(a0);
-                            rec[5] = unpack_dir(a1);
-                            rec[6] = unpack_dir(a2);
-                            uint32_t ns;
-                            rec[7] = (int32_t)source_of(p.g0 + rid, p.q, p.r, ns);
-                        }
-                    }
-                    alive = false;
-                }
+                // the state moves on to the next cell; a packet that left the tile,
+                // the grid, or whose witness depth reached the cut is settled later
+                loc = nloc;
+                kap = knext;
+                lax = (uint32_t)ax;
+                if (F64) sprev = snew; else { pnum = num; pden = den; }
+                if (p.trace_n > 0) hlast = here;
+                if constexpr (F64) kill = tmin >= p.tau_kill;
+                else kill = Extinction<S, MB>::depth(dtest.ext.wH, dtest.ext.wHe1, dtest.ext.wHe2, D)
+                            >= (float)p.tau_kill;
+                pend = kill || out || leave;
             }
             n_cross += it_cross;
-            l_abs += it_abs;
-            l_esc += (it_fate == 2u) ? it_left : 0.0;
-            l_trunc += (it_fate == 1u) ? it_left : 0.0;
-            n_esc += (it_fate == 2u) ? 1u : 0u;
-            n_trunc += (it_fate == 1u) ? 1u : 0u;
 
             // ---- run used up and few lanes left: park them for the next pass ----
             // (every parked packet has crossed a cell in this pass, so it progresses)
             if (exhausted && p.park != 0u) {
-                const uint64_t am = __ballot(alive);
+                const uint64_t am = __ballot(alive && !pend);
                 if (am != 0ull && (uint32_t)__popcll(am) <= p.park) {
                     double pk_abs = 0.0;
-                    if (alive) {
+                    if (alive && !pend) {
                         uint32_t jw = 0;
                         if constexpr (!F64) jw = dtest.ext.jw;
                         store_moving<R, S, MB>(recs + (size_t)rid * RL::STRIDE, pack_cell(k0, k1, k2, lax), d0, jw,

@@ -22,6 +22,8 @@ RT_ISOTHERMAL, RT_FP64, RT_TIME_MARCH, RT_DIRECT_MARCH = 0x1, 0x2, 0x4, 0x8
 RT_SRC_CORNER_OCTANT = 0x1
 RT_TRACE_HDR = 8
 RT_FATE_TRUNC, RT_FATE_ESCAPE = 1, 2
+RT_MAX_BATCH = 64
+RT_BATCH_GRAPH = 0x1
 
 FIELDS = ("nh", "x_hi", "x_hii", "x_hei", "x_heii", "x_heiii", "temp", "d_hi", "d_hei", "d_heii", "q")
 F = {name: 1 << i for i, name in enumerate(FIELDS)}
@@ -70,6 +72,11 @@ SIGNATURES = {
     "rt_trace_rays": (_I32, [_VP, _I32, _VP, _VP, _I32, _VP, _VP, _VP]),
     "rt_get_step_index": (_I32, [_VP, C.POINTER(_U64)]),
     "rt_release": (_I32, [_VP]),
+    "rt_batch_workspace_bytes": (_I32, [_I32, C.POINTER(C.c_size_t)]),
+    "rt_batch_init": (_I32, [_I32, _VP, C.c_size_t, _VP, _U32, C.POINTER(_VP)]),
+    "rt_step_many": (_I32, [_VP, C.POINTER(_VP), _I32, C.POINTER(_D), C.POINTER(_I64), C.POINTER(_U64),
+                            C.POINTER(StepStats)]),
+    "rt_batch_release": (_I32, [_VP]),
     "rt_strerror": (C.c_char_p, [_I32]),
 }
 
@@ -207,6 +214,37 @@ def rt_release(h):
     _check("rt_release", lib().rt_release(h))
 
 
+def rt_batch_workspace_bytes(max_solves: int) -> int:
+    out = C.c_size_t(0)
+    _check("rt_batch_workspace_bytes", lib().rt_batch_workspace_bytes(int(max_solves), C.byref(out)))
+    return int(out.value)
+
+
+def rt_batch_init(max_solves: int, workspace, stream, flags: int = RT_BATCH_GRAPH):
+    b = C.c_void_p()
+    _check("rt_batch_init", lib().rt_batch_init(int(max_solves), _ptr(workspace),
+                                                workspace.numel() * workspace.element_size(),
+                                                _stream_ptr(stream), int(flags), C.byref(b)))
+    return b
+
+
+def rt_step_many(b, handles, dt_s, n_packets, seeds, stats: bool = False):
+    """One step of every solve in handles (fused); returns a list of ledger
+    dicts when stats is true."""
+    n = len(handles)
+    hs = (_VP * n)(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    dts = (_D * n)(*[float(v) for v in dt_s])
+    pks = (_I64 * n)(*[int(v) for v in n_packets])
+    sds = (_U64 * n)(*[int(v) for v in seeds])
+    st = (StepStats * n)() if stats else None
+    _check("rt_step_many", lib().rt_step_many(b, hs, int(n), dts, pks, sds, st))
+    return [x.as_dict() for x in st] if stats else None
+
+
+def rt_batch_release(b):
+    _check("rt_batch_release", lib().rt_batch_release(b))
+
+
 # ----------------------------------------------------------------------------
 # Convenience owner of one solve: torch device memory for the workspace and
 # the initial fields, built from a workload description.
@@ -291,6 +329,39 @@ class Solve:
         if self.h is not None:
             rt_release(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Fused steps of up to max_solves solves on their own stream (torch device
+    memory for the workspace); graph=True captures each call shape once."""
+
+    def __init__(self, max_solves: int = RT_MAX_BATCH, *, graph: bool = True, stream=None, device: str = "cuda"):
+        import torch
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        self.workspace = torch.empty(rt_batch_workspace_bytes(max_solves), dtype=torch.uint8, device=device)
+        self.b = rt_batch_init(max_solves, self.workspace, self.stream, RT_BATCH_GRAPH if graph else 0)
+
+    def step(self, solves, dt_s=None, packets=None, seeds=None, stats: bool = False):
+        """One step of every Solve in solves; per-solve values default to the
+        solve's workload (dt, packets per step, seed)."""
+        dt_s = [s.work.dt_s for s in solves] if dt_s is None else dt_s
+        packets = [s.work.packets for s in solves] if packets is None else packets
+        seeds = [s.work.seed for s in solves] if seeds is None else seeds
+        return rt_step_many(self.b, [s.h for s in solves], dt_s, packets, seeds, stats)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def release(self):
+        if self.b is not None:
+            rt_batch_release(self.b)
+            self.b = None
 
     def __del__(self):
         try:

@@ -1,0 +1,182 @@
+"""Continuous-batching server of independent small solves.
+
+Requests (a workload each, with an arrival time) are admitted in arrival
+order while a slot of the fused batch and device memory are free.  An
+admitted solve keeps its fields and workspace on the device until it has run
+all its steps.  Each fused call (rt_step_many) advances every admitted solve
+by one step; requests that arrive meanwhile join at the next call, and a
+solve that has finished leaves its slot and memory to the next request.
+Latency is completion minus arrival.
+
+Host-side scheduling only: every step of every solve runs in the library's
+kernels.  The baseline is the same requests run one at a time through rt_step.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Callable, List, Optional
+
+import numpy as np
+
+from . import rt
+
+
+@dataclasses.dataclass
+class Served:
+    rid: int
+    arrival_s: float
+    admit_s: float
+    done_s: float
+    steps: int
+    crossings: int
+    packets: int
+    emitted: float
+    residual: float                 # max over steps of |emitted - absorbed - escaped - truncated| / emitted
+    fields: Optional[np.ndarray]    # rt.FIELDS order, natural cell order, float64
+
+    @property
+    def latency_s(self) -> float:
+        return self.done_s - self.arrival_s
+
+
+def workspace_bytes(work, fp64: bool, direct: bool = True) -> int:
+    """Device bytes a request holds while admitted (its workspace)."""
+    d = rt.desc_from_workload(work, fp64=fp64, direct=direct)
+    return rt.rt_workspace_bytes(d, max(1, len(work.src_ndot)))
+
+
+def percentile(values, q: float) -> float:
+    return float(np.percentile(np.asarray(values, dtype=np.float64), q)) if len(values) else float("nan")
+
+
+def admissible(need: int, used: int, n_active: int, max_slots: int, budget: int) -> bool:
+    """A request is admitted when a slot is free and its workspace fits."""
+    return n_active < max_slots and used + need <= budget
+
+
+class GpuExecutor:
+    """Solves on the current GPU, stepped together by rt_step_many on the
+    batch's stream (their fields and workspaces stay on the device)."""
+
+    def __init__(self, max_slots: int, *, fp64: bool, graph: bool, device: str = "cuda"):
+        self.fp64 = fp64
+        self.device = device
+        self.batch = rt.Batch(max_slots, graph=graph, device=device)
+
+    def open(self, work):
+        return rt.Solve(work, fp64=self.fp64, direct=True, stream=self.batch.stream, device=self.device)
+
+    def step(self, solves):
+        return self.batch.step(solves, stats=True)       # synchronises
+
+    def fetch(self, solve):
+        return solve.fetch()
+
+    def close(self, solve):
+        solve.release()
+
+    def release(self):
+        self.batch.release()
+
+
+class Server:
+    """Admits requests into one fused batch of at most max_slots solves and a
+    device-memory budget (bytes of solve workspaces; default half the free
+    device memory when the server starts)."""
+
+    def __init__(self, *, max_slots: int = rt.RT_MAX_BATCH, hbm_budget: Optional[int] = None,
+                 fp64: bool = False, graph: bool = True, keep_fields: bool = True, device: str = "cuda",
+                 executor=None):
+        if not 1 <= max_slots <= rt.RT_MAX_BATCH:
+            raise ValueError(f"max_slots must be in 1..{rt.RT_MAX_BATCH}")
+        self.max_slots = max_slots
+        self.fp64 = fp64
+        self.keep_fields = keep_fields
+        if hbm_budget is None:
+            import torch
+            free, _ = torch.cuda.mem_get_info()
+            hbm_budget = free // 2
+        self.hbm_budget = int(hbm_budget)
+        self.ex = executor if executor is not None else GpuExecutor(max_slots, fp64=fp64, graph=graph,
+                                                                    device=device)
+        self.calls = 0
+        self.call_solves = []          # solves per fused call
+        self.peak_bytes = 0            # most workspace bytes admitted at once
+
+    def run(self, requests, *, realtime: bool = True,
+            clock: Callable[[], float] = time.perf_counter) -> List[Served]:
+        """Serve every request; arrivals follow request.arrival_s from the
+        start of the run when realtime, else all are present at once."""
+        pending = collections.deque(sorted(requests, key=lambda r: (r.arrival_s, r.rid)))
+        need = {r.rid: workspace_bytes(r.work, self.fp64) for r in pending}
+        for r in pending:
+            if need[r.rid] > self.hbm_budget:
+                raise ValueError(f"request {r.rid} needs {need[r.rid]} bytes, above the budget")
+        active = []                    # [request, solve, admit time, steps done, ledgers]
+        used = 0
+        out: List[Served] = []
+        t0 = clock()
+        while pending or active:
+            now = clock() - t0
+            while pending and (not realtime or pending[0].arrival_s <= now):
+                r = pending[0]
+                if not admissible(need[r.rid], used, len(active), self.max_slots, self.hbm_budget):
+                    break
+                pending.popleft()
+                s = self.ex.open(r.work)
+                used += need[r.rid]
+                self.peak_bytes = max(self.peak_bytes, used)
+                active.append([r, s, clock() - t0, 0, []])
+            if not active:
+                wait = pending[0].arrival_s - (clock() - t0)
+                if wait > 0:
+                    time.sleep(min(wait, 0.05))
+                continue
+            ledgers = self.ex.step([a[1] for a in active])
+            self.calls += 1
+            self.call_solves.append(len(active))
+            done_t = clock() - t0
+            still = []
+            for a, st in zip(active, ledgers):
+                a[3] += 1
+                a[4].append(st)
+                if a[3] < a[0].work.steps:
+                    still.append(a)
+                    continue
+                r, s = a[0], a[1]
+                fields = self.ex.fetch(s) if self.keep_fields else None
+                self.ex.close(s)
+                used -= need[r.rid]
+                led = a[4]
+                res = max(abs(x["emitted"] - (x["absorbed"] + x["escaped"] + x["truncated"])) / x["emitted"]
+                          if x["emitted"] > 0 else 0.0 for x in led)
+                out.append(Served(r.rid, r.arrival_s, a[2], done_t, a[3], sum(x["crossings"] for x in led),
+                                  sum(x["packets"] for x in led), sum(x["emitted"] for x in led), res, fields))
+            active = still
+        return sorted(out, key=lambda x: x.rid)
+
+    def release(self):
+        self.ex.release()
+
+
+def run_alone(requests, *, fp64: bool = True, direct: bool = True, keep_fields: bool = True,
+              device: str = "cuda", clock: Callable[[], float] = time.perf_counter):
+    """The requests one at a time, each with rt_step on its own solve (all
+    present at once: no arrival times).  Returns (results, seconds)."""
+    import torch
+    out = []
+    t0 = clock()
+    for r in sorted(requests, key=lambda q: q.rid):
+        s = rt.Solve(r.work, fp64=fp64, direct=direct, device=device)
+        led = [s.step() for _ in range(r.work.steps)]
+        fields = s.fetch() if keep_fields else None
+        s.release()
+        res = max(abs(x["emitted"] - (x["absorbed"] + x["escaped"] + x["truncated"])) / x["emitted"]
+                  if x["emitted"] > 0 else 0.0 for x in led)
+        t = clock() - t0
+        out.append(Served(r.rid, 0.0, 0.0, t, len(led), sum(x["crossings"] for x in led),
+                          sum(x["packets"] for x in led), sum(x["emitted"] for x in led), res, fields))
+    torch.cuda.synchronize()
+    return out, clock() - t0

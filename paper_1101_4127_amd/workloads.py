@@ -390,13 +390,15 @@ class Request:
 
 
 def serving_stream(count: int = 512, rate_per_s: float = 200.0, seed: int = 4,
-                   steps: int = 5, n_sub: int = 10) -> List[Request]:
+                   steps: int = 5, n_sub: int = 10, sides=(16, 24, 32, 48, 64),
+                   log_packets=(4.0, 6.0), max_sources: int = 16) -> List[Request]:
     """Independent pure-H isothermal solves with uneven sizes: side from
     {16,24,32,48,64}, uniform or lognormal gas (50/50), 1-16 monochromatic
     13.6 eV sources of 5e48 ph/s at cell centres, 1e4-1e6 packets per step
-    (log-uniform), 5 steps of 1 Myr; cell size as in the Stroemgren case."""
+    (log-uniform), 5 steps of 1 Myr; cell size as in the Stroemgren case.
+    Arrivals are a Poisson process of the given mean rate."""
     rng = np.random.default_rng(seed)
-    sides = (16, 24, 32, 48, 64)
+    sides = tuple(sides)
     bins = monochromatic_table(13.6)
     dl = 6.6 * KPC_CM / 32
     t = 0.0
@@ -409,9 +411,9 @@ def serving_stream(count: int = 512, rate_per_s: float = 200.0, seed: int = 4,
             nh = np.full(ncell, 1.0e-3)
         else:
             nh = lognormal_field(n, 1.0, 1.0e-3, int(rng.integers(1 << 31)))
-        n_src = int(rng.integers(1, 17))
+        n_src = int(rng.integers(1, max_sources + 1))
         cells = rng.choice(ncell, size=n_src, replace=False)
-        packets = int(round(10.0 ** rng.uniform(4.0, 6.0)))
+        packets = int(round(10.0 ** rng.uniform(*log_packets)))
         packets = max(packets - packets % n_sub, n_sub * n_src)
         x, temp = _neutral_state(ncell, 1.0e4)
         w = Workload(

@@ -144,3 +144,26 @@ def test_init_rejects_bad_arguments_before_touching_the_device(L):
     assert L.rt_step(None, 1.0, 1, 1, None) == rt.RT_EINVAL
     assert L.rt_release(None) == rt.RT_EINVAL
     assert L.rt_fetch_fields(None, 1, None, 0, 1) == rt.RT_EINVAL
+
+
+def test_batch_arguments_are_checked_before_the_device(L):
+    out = C.c_size_t(0)
+    for bad in (0, 65):
+        assert L.rt_batch_workspace_bytes(bad, C.byref(out)) == rt.RT_EINVAL
+    assert L.rt_batch_workspace_bytes(1, None) == rt.RT_EINVAL
+    assert L.rt_batch_workspace_bytes(64, C.byref(out)) == rt.RT_OK
+    big = out.value
+    assert L.rt_batch_workspace_bytes(1, C.byref(out)) == rt.RT_OK
+    assert 0 < out.value < big
+    b = C.c_void_p()
+    assert L.rt_batch_init(0, 0x1000, 1 << 30, 0x10, 0, C.byref(b)) == rt.RT_EINVAL
+    assert L.rt_batch_init(65, 0x1000, 1 << 30, 0x10, 0, C.byref(b)) == rt.RT_EINVAL
+    assert L.rt_batch_init(4, 0x1000, 1 << 30, None, rt.RT_BATCH_GRAPH, C.byref(b)) == rt.RT_EINVAL
+    assert L.rt_batch_init(4, 0x1000, 1 << 30, 0x10, 0x2, C.byref(b)) == rt.RT_EINVAL
+    assert L.rt_batch_init(4, 0x1001, 1 << 30, 0x10, 0, C.byref(b)) == rt.RT_EINVAL
+    assert L.rt_batch_init(4, None, 1 << 30, 0x10, 0, C.byref(b)) == rt.RT_EINVAL
+    assert L.rt_batch_init(4, 0x1000, 16, 0x10, 0, C.byref(b)) == rt.RT_ENOMEM
+    assert L.rt_batch_init(4, 0x1000, 1 << 30, 0x10, 0, None) == rt.RT_EINVAL
+    assert L.rt_step_many(None, None, 1, None, None, None, None) == rt.RT_EINVAL
+    assert L.rt_batch_release(None) == rt.RT_EINVAL
+

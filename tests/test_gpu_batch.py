@@ -1,0 +1,190 @@
+"""Fused steps of many solves (rt_step_many) and the continuous-batching
+server, on the serving workload's kind of solves (pure hydrogen, one 13.6 eV
+bin, isothermal, uneven grid sides, uniform or lognormal gas).
+
+* every solve's result in a fused batch is the one rt_step gives alone, up to
+  the order of float64 deposit additions: packets and crossings equal,
+  deposits and fractions (relative to max(x, 1e-6)) within 1e-9 (float64) /
+  fractions within 1e-4 and deposits within 1e-5 (float32 march), the stated
+  bars of the two forms;
+* a captured graph, replayed several times with eager work and
+  synchronisations between the replays and with a different set of solves,
+  gives what the eager launches give;
+* against the float64 oracle, solve by solve;
+* served requests (admission by free slots, joins between fused calls) end
+  where the same requests end alone."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1101_4127_amd import workloads as W
+
+import parity as PT
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1101_4127_amd import rt
+    rt.lib()
+    return torch
+
+
+def stream(count=8, seed=41, steps=2, n_sub=4, sides=(16, 24, 32), log_packets=(3.5, 4.3), rate=2000.0):
+    return W.serving_stream(count=count, rate_per_s=rate, seed=seed, steps=steps, n_sub=n_sub, sides=sides,
+                            log_packets=log_packets, max_sources=6)
+
+
+def alone(reqs, fp64):
+    from paper_1101_4127_amd import rt
+    out = []
+    for r in reqs:
+        s = rt.Solve(r.work, fp64=fp64, direct=True)
+        led = [s.step() for _ in range(r.work.steps)]
+        out.append((s.fetch(), led))
+        s.release()
+    return out
+
+
+def batched(reqs, fp64, graph):
+    from paper_1101_4127_amd import rt
+    b = rt.Batch(len(reqs), graph=graph)
+    solves = [rt.Solve(r.work, fp64=fp64, direct=True, stream=b.stream) for r in reqs]
+    leds = [[] for _ in reqs]
+    for _ in range(reqs[0].work.steps):
+        for i, st in enumerate(b.step(solves, stats=True)):
+            leds[i].append(st)
+    out = [(s.fetch(), led) for s, led in zip(solves, leds)]
+    for s in solves:
+        s.release()
+    b.release()
+    return out
+
+
+def assert_same(a, m, fp64, work):
+    fa, la = a
+    fm, lm = m
+    for x, y in zip(la, lm):
+        assert x["packets"] == y["packets"]
+        assert x["substeps"] == y["substeps"] == work.n_sub
+        assert abs(x["crossings"] - y["crossings"]) <= 1e-6 * x["crossings"]
+        assert abs(x["emitted"] - y["emitted"]) <= 1e-12 * x["emitted"]
+        for k in ("absorbed", "escaped", "truncated"):
+            assert abs(x[k] - y[k]) <= 1e-9 * x["emitted"], k
+        assert y["nonfinite"] == 0 and y["errors"] == 0
+    # float64: the two runs differ only in the order of float64 deposit
+    # additions, i.e. by rounding; fractions are compared relative to
+    # max(x, 1e-6) (a rounding-level absolute difference of 1e-16 on a
+    # fraction of 1e-10 is not a 1e-6 relative error)
+    ft, dt, floor = (1e-9, 1e-9, 1e-6) if fp64 else (1e-4, 1e-5, 1e-8)
+    assert np.array_equal(fa[0], fm[0])
+    for f in (1, 2):
+        assert np.max(PT.frac_err(fm[f], fa[f], floor)) <= ft, f
+    assert np.max(PT.deposit_err(fm[7], fa[7])) <= dt
+    assert np.array_equal(fa[6], fm[6])          # isothermal
+
+
+@pytest.mark.parametrize("graph", [True, False], ids=["graph", "eager"])
+@pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
+def test_fused_step_equals_alone(fp64, graph):
+    reqs = stream()
+    a = alone(reqs, fp64)
+    m = batched(reqs, fp64, graph)
+    for r, x, y in zip(reqs, a, m):
+        assert_same(x, y, fp64, r.work)
+
+
+def test_graph_replays_match_eager_launches():
+    """Three fused calls of the same solves through a captured graph and
+    through eager launches, the fields fetched (eager copies, synchronising)
+    after every call; then the graph again with another set of solves."""
+    from paper_1101_4127_amd import rt
+    reqs = stream(count=6, seed=43, steps=3)
+    be, bg = rt.Batch(6, graph=False), rt.Batch(6, graph=True)
+    se = [rt.Solve(r.work, fp64=True, direct=True, stream=be.stream) for r in reqs]
+    sg = [rt.Solve(r.work, fp64=True, direct=True, stream=bg.stream) for r in reqs]
+    for _ in range(3):
+        le = be.step(se, stats=True)
+        lg = bg.step(sg, stats=True)
+        for x, y in zip(le, lg):
+            assert x["packets"] == y["packets"] and x["crossings"] == y["crossings"]
+        for a, b in zip(se, sg):
+            fa, fb = a.fetch(), b.fetch()
+            assert np.max(PT.frac_err(fb[1], fa[1], 1e-6)) <= 1e-9
+            assert np.max(PT.deposit_err(fb[7], fa[7])) <= 1e-9
+    # the same graph shape with three of the solves, in another order
+    sub_e, sub_g = [se[4], se[1], se[2]], [sg[4], sg[1], sg[2]]
+    be.step(sub_e, stats=True)
+    bg.step(sub_g, stats=True)
+    for a, b in zip(sub_e, sub_g):
+        fa, fb = a.fetch(), b.fetch()
+        assert np.max(PT.frac_err(fb[1], fa[1], 1e-6)) <= 1e-9
+    for s in se + sg:
+        s.release()
+    be.release()
+    bg.release()
+
+
+def test_fused_step_against_oracle():
+    """Float64 fused steps of three small solves against the oracle run on
+    each alone (multi-step float64 bar: 1e-6 on fractions and deposits)."""
+    from paper_1101_4127_amd import rt
+    reqs = stream(count=3, seed=44, steps=2, n_sub=3, sides=(16,), log_packets=(3.3, 3.6))
+    b = rt.Batch(3, graph=True)
+    solves = [rt.Solve(r.work, fp64=True, direct=True, stream=b.stream) for r in reqs]
+    oracles = [O.OracleSolve(r.work) for r in reqs]
+    for _ in range(2):
+        led = b.step(solves, stats=True)
+        for o, g in zip(oracles, led):
+            ost = o.step()
+            assert g["packets"] == ost["packets"]
+            assert abs(g["crossings"] - ost["crossings"]) <= 1e-6 * ost["crossings"]
+            assert abs(g["emitted"] - ost["emitted"]) <= 1e-12 * ost["emitted"]
+            res = abs(g["emitted"] - (g["absorbed"] + g["escaped"] + g["truncated"])) / g["emitted"]
+            assert res <= 1e-12
+    for r, s, o in zip(reqs, solves, oracles):
+        PT.compare_state(o, s.fetch(), r.work, frac_tol=1e-6, temp_tol=1e-12, dep_tol=1e-6)
+        s.release()
+    b.release()
+
+
+def test_fused_step_rejects_what_it_cannot_fuse():
+    from paper_1101_4127_amd import rt
+    reqs = stream(count=2, seed=45)
+    b = rt.Batch(2, graph=False)
+    s64 = rt.Solve(reqs[0].work, fp64=True, direct=True, stream=b.stream)
+    s32 = rt.Solve(reqs[1].work, fp64=False, direct=True, stream=b.stream)
+    hhe = rt.Solve(W.small_mixed(n=8, n_src=2, packets=2000), fp64=True, direct=True, stream=b.stream)
+    for bad in ([s64, s32], [s64, s64], [hhe], [s64, s64, s64]):
+        with pytest.raises(rt.RTError) as e:
+            b.step(bad)
+        assert e.value.status == rt.RT_EINVAL
+    # nothing was enqueued: the solves still step alone
+    assert s64.step()["packets"] == reqs[0].work.packets
+    for s in (s64, s32, hhe):
+        s.release()
+    b.release()
+
+
+def test_served_results_equal_results_alone():
+    """Twelve requests arriving faster than they are served, at most five
+    admitted at once: each served result equals the request run alone."""
+    from paper_1101_4127_amd import serve
+    reqs = stream(count=12, seed=46, steps=3, rate=400.0)
+    srv = serve.Server(max_slots=5, fp64=False, graph=True)
+    got = srv.run(reqs)
+    srv.release()
+    assert [g.rid for g in got] == [r.rid for r in reqs]
+    assert max(srv.call_solves) <= 5 and srv.calls >= 3 * 12 / 5
+    ref, _ = serve.run_alone(reqs, fp64=False)
+    for g, a, r in zip(got, ref, reqs):
+        assert g.steps == r.work.steps and g.packets == a.packets
+        assert g.latency_s > 0 and g.admit_s >= 0
+        assert abs(g.crossings - a.crossings) <= 1e-6 * a.crossings
+        assert np.max(PT.frac_err(g.fields[1], a.fields[1])) <= 1e-4
+        assert np.max(PT.deposit_err(g.fields[7], a.fields[7])) <= 1e-5
+        assert g.residual <= 1e-6

@@ -12,8 +12,11 @@ Prints one JSON line: whole-step cell crossings/s of the float32-march /
 float64-accumulate form (tiled march, every packet of the step in flight),
 the march kernel's roofline (algorithmic bytes per crossing over the
 HIP-event duration of its launches on the library's stream), the plain
-float64 form measured the same way, and the float64 CPU oracle timed on a
-bounded sample.
+float64 form measured the same way, the float64 CPU oracle timed on a
+bounded sample, and the serving workload: 512 independent pure-hydrogen
+solves (sides 16-64, 5 steps each) arriving as a Poisson stream of 200/s,
+served by continuous batching of fused steps (p50/p99 latency, throughput),
+against the same solves run one at a time in the plain float64 form.
 """
 from __future__ import annotations
 
@@ -162,6 +165,71 @@ def traffic_for(launch_crossings: float):
     return t.get("bytes_per_launch")
 
 
+def serving_leg(count: int, accuracy_requests: int = 32):
+    """The serving workload through the continuous-batching server (float32
+    march, fused steps replayed as a hipGraph), in real time and with every
+    request present at once, and the same requests one at a time in the plain
+    float64 form; the served results of the first requests against their
+    float64 results."""
+    import numpy as np
+    from paper_1101_4127_amd import serve
+    from paper_1101_4127_amd import workloads as W
+    t0 = time.perf_counter()
+    reqs = W.serving_stream(count=count)
+    log(f"serving: {count} requests ({time.perf_counter() - t0:.1f} s to generate), "
+        f"arrivals over {reqs[-1].arrival_s:.2f} s")
+    srv = serve.Server(max_slots=64, fp64=False, graph=True, keep_fields=False)
+    srv.run(W.serving_stream(count=8, seed=99), realtime=False)           # capture and first launches
+    srv.calls, srv.call_solves = 0, []
+    t = time.perf_counter()
+    got = srv.run(reqs)
+    wall = time.perf_counter() - t
+    calls, mean_batch = srv.calls, float(np.mean(srv.call_solves))
+    t = time.perf_counter()
+    sat = srv.run(reqs, realtime=False)
+    wall_sat = time.perf_counter() - t
+    srv.release()
+    lat = [g.latency_s for g in got]
+    cross = sum(g.crossings for g in got)
+    cross_sat = sum(g.crossings for g in sat)
+    base, wall_base = serve.run_alone(reqs, fp64=True, direct=True, keep_fields=False)
+    cross_base = sum(g.crossings for g in base)
+    # accuracy of the served form against the plain float64 form
+    sub = reqs[:accuracy_requests]
+    srv = serve.Server(max_slots=64, fp64=False, graph=True, keep_fields=True)
+    acc32 = srv.run(sub, realtime=False)
+    srv.release()
+    acc64, _ = serve.run_alone(sub, fp64=True, direct=True, keep_fields=True)
+    fx, dep = [], []
+    for a, b in zip(acc32, acc64):
+        for f in (1, 2):
+            fx.append(np.abs(a.fields[f] - b.fields[f]) / np.maximum(b.fields[f], 1e-8))
+        mean = float(np.mean(np.abs(b.fields[7])))
+        dep.append(np.abs(a.fields[7] - b.fields[7]) / np.maximum(np.abs(b.fields[7]), 1e-12 * max(mean, 1e-300)))
+    fx = np.concatenate(fx)
+    dep = np.concatenate(dep)
+    out = {
+        "workload": f"poisson_{count}_pure_H_16-64^3", "requests": count, "rate_per_s": 200.0,
+        "form": "float32 march, float64 accumulators; fused steps of up to 64 solves replayed as a hipGraph",
+        "p50_latency_ms": 1e3 * serve.percentile(lat, 50), "p99_latency_ms": 1e3 * serve.percentile(lat, 99),
+        "wall_s": wall, "solves_per_s": count / wall, "crossings_per_s": cross / wall,
+        "fused_calls": calls, "mean_solves_per_call": mean_batch,
+        "max_conservation_residual": max(g.residual for g in got),
+        "all_present": {"wall_s": wall_sat, "solves_per_s": count / wall_sat, "crossings_per_s": cross_sat / wall_sat},
+        "baseline_fp64_one_at_a_time": {"wall_s": wall_base, "solves_per_s": count / wall_base,
+                                        "crossings_per_s": cross_base / wall_base, "march": "per-packet"},
+        "speedup_all_present_vs_baseline": (cross_sat / wall_sat) / (cross_base / wall_base),
+        "accuracy_vs_fp64": {"requests": len(sub), "fraction_err_max": float(fx.max()),
+                             "fraction_err_p99": float(np.percentile(fx, 99)),
+                             "deposit_err_max": float(dep.max()), "deposit_err_p99": float(np.percentile(dep, 99))},
+    }
+    log(f"serving: p50 {out['p50_latency_ms']:.1f} ms, p99 {out['p99_latency_ms']:.1f} ms, "
+        f"{out['solves_per_s']:.0f} solves/s at 200/s arrivals; all present: {out['all_present']['crossings_per_s']:.3g} "
+        f"crossings/s vs {out['baseline_fp64_one_at_a_time']['crossings_per_s']:.3g} one at a time in float64 "
+        f"({out['speedup_all_present_vs_baseline']:.1f}x); fractions vs float64 max {fx.max():.2e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,6 +245,7 @@ def main():
     ap.add_argument("--run-len", type=int, default=0)
     ap.add_argument("--refill", type=int, default=0)
     ap.add_argument("--bpcu", type=int, default=0)
+    ap.add_argument("--serving-requests", type=int, default=512, help="0 skips the serving workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -238,6 +307,8 @@ def main():
                              "achieved_gbs": a64, "bytes_per_crossing": BYTES_F64,
                              "ms_per_step": 1e3 * f64["wall_s"] / args.fp64_steps,
                              "speedup_of_fp32_form": value / v64, "conservation_residual": f64["resid"]}
+    if args.serving_requests > 0:
+        out["serving"] = serving_leg(args.serving_requests)
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(work, args.cpu_seconds)

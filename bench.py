@@ -246,6 +246,8 @@ def main():
     ap.add_argument("--refill", type=int, default=0)
     ap.add_argument("--bpcu", type=int, default=0)
     ap.add_argument("--serving-requests", type=int, default=512, help="0 skips the serving workload")
+    ap.add_argument("--autotune", action="store_true",
+                    help="choose the march's launch parameters by measurement first (tiled march)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -269,6 +271,14 @@ def main():
     log(f"workload {work.name}: {work.ncell} cells, {len(work.src_ndot)} sources, "
         f"{work.packets} packets/step ({time.perf_counter() - t0:.1f} s to generate)")
 
+    tuned = None
+    if args.autotune:
+        from paper_1101_4127_amd import autotune
+        t0 = time.perf_counter()
+        tuned = autotune.tune(work, fp64=False, kinds=("direct",) if args.direct else ("tiled",))
+        tiles.update(tuned["config"])
+        log(f"autotune: {tuned['config']} ({tuned['march_ms']:.1f} ms march, {len(tuned['trials'])} trials, "
+            f"{time.perf_counter() - t0:.0f} s)")
     f32 = time_form(work, fp64=False, steps=args.steps, warmup=args.warmup, tiles=tiles)
     value = f32["crossings"] / f32["wall_s"]
     launches = max(f32["launches"], 1)
@@ -295,6 +305,9 @@ def main():
                      "whole_march_gcross_per_s": f32["crossings"] / (f32["march_ms"] * 1e-3) / 1e9},
         "conservation_residual": f32["resid"],
     }
+    if tuned is not None:
+        out["config"]["autotuned"] = tuned["config"]
+        out["config"]["autotune_trials"] = len(tuned["trials"])
     if args.fp64_steps > 0:
         f64 = time_form(work, fp64=True, steps=args.fp64_steps, warmup=1, tiles=tiles)
         v64 = f64["crossings"] / f64["wall_s"]

@@ -188,3 +188,25 @@ def test_served_results_equal_results_alone():
         assert np.max(PT.frac_err(g.fields[1], a.fields[1])) <= 1e-4
         assert np.max(PT.deposit_err(g.fields[7], a.fields[7])) <= 1e-5
         assert g.residual <= 1e-6
+
+
+def test_autotuned_parameters_leave_results_unchanged():
+    """The tuner on a small H+He case (both march kinds, one sweep), then the
+    chosen parameters against the defaults: same ledger, same deposits."""
+    from paper_1101_4127_amd import autotune, rt
+    w = W.small_mixed(n=24, n_src=4, packets=20000, fp64=True)
+    r = autotune.tune(w, fp64=True, steps=1, sweeps=1)
+    assert len(r["trials"]) >= 10 and r["march_ms"] > 0
+    cfg = dict(r["config"])
+    a = rt.Solve(w, fp64=True)
+    sa = a.step()
+    fa = a.fetch()
+    a.release()
+    b = rt.Solve(w, fp64=True, **cfg)
+    sb = b.step()
+    fb = b.fetch()
+    b.release()
+    assert sa["crossings"] == sb["crossings"] and sa["packets"] == sb["packets"]
+    assert sa["n_escaped"] == sb["n_escaped"] and sa["n_truncated"] == sb["n_truncated"]
+    for f in range(7, 11):
+        assert np.max(PT.deposit_err(fb[f], fa[f])) <= 1e-9

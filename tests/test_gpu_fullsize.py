@@ -1,7 +1,8 @@
-"""Parity at the full benchmark size: the 256^3 lognormal H+He workload (1e4
-sources, 8 bins, 1e8 packets per step) in the launch configuration bench.py
-times (tiled march, every packet of the step in flight, default runs and
-grid), checked on outputs the oracle can compute one by one:
+"""Parity at full size: the 256^3 lognormal H+He workload (1e4 sources, 8
+bins, 1e8 packets per step) in the launch configuration bench.py times (tiled
+march, every packet of the step in flight, default runs and grid), both
+forms, and the 512^3 one (sigma_ln 1.5, 1e5 sources, 5e8 packets per step)
+in the float32 form, checked on outputs the oracle can compute one by one:
 
 * packet histories of a sample of packet ids (every 50 000th), each marched
   alone by the oracle over the same frozen state: cell sequences, directions
@@ -23,6 +24,8 @@ pytestmark = pytest.mark.gpu
 
 STRIDE = 50_000
 TRACE_LEN = 1024            # > 3 * 256 cells, the longest path through the grid
+STRIDE_512 = 1_000_000
+TRACE_LEN_512 = 1600        # > 3 * 512
 
 
 @pytest.fixture(scope="module")
@@ -47,7 +50,7 @@ def oracle_state(work):
     return o
 
 
-def oracle_traces(o, work, ids):
+def oracle_traces(o, work, ids, trace_len=TRACE_LEN):
     """Histories of the sampled packets, one oracle march per packet (the
     record of packet g is written at index g / stride = 1 with stride g)."""
     acc = np.zeros((4, work.ncell))
@@ -56,17 +59,17 @@ def oracle_traces(o, work, ids):
         g = int(g)
         stride = g if g > 0 else 1
         _, _, tr = o.march(g, g + 1, dt=work.dt_s / work.n_sub, packets=work.packets, seed=1,
-                           step_index=0, trace_n=2, trace_len=TRACE_LEN, trace_stride=stride, acc=acc,
+                           step_index=0, trace_n=2, trace_len=trace_len, trace_stride=stride, acc=acc,
                            absorbers=False)
         out.append(tr[1 if g > 0 else 0])
     return np.array(out)
 
 
-def run_gpu(work, fp64):
+def run_gpu(work, fp64, stride=STRIDE, trace_len=TRACE_LEN):
     from paper_1101_4127_amd import rt
-    n = work.packets // STRIDE
-    s = rt.Solve(work, fp64=fp64, inflight=work.packets, trace_packets=n, trace_len=TRACE_LEN,
-                 trace_stride=STRIDE)
+    n = work.packets // stride
+    s = rt.Solve(work, fp64=fp64, inflight=work.packets, trace_packets=n, trace_len=trace_len,
+                 trace_stride=stride)
     st = s.step(seed=1)
     fields = s.fetch()
     tr = s.trace()
@@ -92,18 +95,23 @@ def check_properties(st, fields, work, resid_tol, sum_tol):
     assert abs(dep[0:3].sum() - st["absorbed"]) <= sum_tol * st["absorbed"]
 
 
-def check_sampled_updates(work, fields, tol):
+def check_sampled_updates(work, fields, tol, o=None):
+    """Cell updates of a sample of cells driven by the GPU's deposits, against
+    the oracle's update of the same cells; returns the per-field maxima."""
     rng = np.random.default_rng(11)
     idx = np.sort(rng.choice(work.ncell, 2000, replace=False))
     # include the cells with the largest deposits (the ionised and heated ones)
-    idx = np.unique(np.concatenate([idx, np.argsort(fields[7])[-500:]]))
-    o = O.OracleSolve(work)
+    idx = np.unique(np.concatenate([idx, np.argpartition(fields[7], -500)[-500:]]))
+    o = O.OracleSolve(work) if o is None else o
     acc = np.zeros((4, work.ncell))
     acc[:, idx] = fields[7:11][:, idx]
     o.update_cells(work.dt_s / work.n_sub, acc, idx)
-    fe = np.max(PT.frac_err(fields[1:6][:, idx], o.x[:, idx]))
-    te = np.max(PT.temp_err(fields[6][idx], o.T[idx]))
-    assert fe <= tol and te <= tol, (fe, te)
+    rep = {name: float(np.max(PT.frac_err(fields[1 + f][idx], o.x[f][idx])))
+           for f, name in enumerate(("x_HI", "x_HII", "x_HeI", "x_HeII", "x_HeIII"))}
+    rep["T"] = float(np.max(PT.temp_err(fields[6][idx], o.T[idx])))
+    print("sampled cell updates, max error per field:", rep)
+    assert max(rep.values()) <= tol, rep
+    return rep
 
 
 def test_fullsize_fp32_bench_configuration(gpu, work, oracle_state):
@@ -125,3 +133,27 @@ def test_fullsize_fp64_plain(gpu, work, oracle_state):
     assert np.all(otr[:, 0] > 0) and {1, 2} <= set(np.unique(otr[:, 1]).tolist())
     PT.compare_traces(work, oracle_state.kappa, tr, otr, exact=True)
     check_sampled_updates(work, fields, 1e-9)
+
+
+def test_fullsize_512_fp32():
+    """512^3, 5e8 packets in flight (about 80 GB of records and lists)."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1101_4127_amd import rt
+    rt.lib()
+    torch.cuda.empty_cache()
+    work = W.lognormal_512()
+    st, fields, tr = run_gpu(work, fp64=False, stride=STRIDE_512, trace_len=TRACE_LEN_512)
+    check_properties(st, fields, work, resid_tol=1e-6, sum_tol=1e-6)
+    o = O.OracleSolve(work)
+    o.absorbers()
+    ids = np.arange(0, work.packets, STRIDE_512)
+    otr = oracle_traces(o, work, ids, TRACE_LEN_512)
+    assert np.all(otr[:, 0] > 0)
+    mism = PT.compare_traces(work, o.kappa, tr, otr, exact=False)
+    print(f"512^3: {len(ids)} sampled packet histories, {mism} fates in the extinction guard band")
+    assert mism <= len(ids) // 100, mism
+    del o
+    check_sampled_updates(work, fields, 1e-5)
+

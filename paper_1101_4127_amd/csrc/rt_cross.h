@@ -64,6 +64,46 @@ __device__ __forceinline__ int exit_face(uint32_t d0, uint32_t d1, uint32_t d2, 
     return m0 ? 0 : (m1 ? 1 : 2);
 }
 
+// A per-bin table copied into registers once per kernel: with the bins of a
+// crossing in branches of their own, table reads through memory would sit in
+// (and wait inside) every branch; the copy keeps them out of the loop.
+template <typename R, int N>
+struct RegTab {
+    R v[N];
+    __device__ __forceinline__ R operator[](int i) const { return v[i]; }
+};
+
+// The table a march passes to the crossing: registers in the float32 form,
+// the constant-address-space pointer in the float64 form (its 7 x 8 doubles
+// would not fit the scalar registers).
+template <typename R, int MB, bool F64 = std::is_same<R, double>::value>
+struct MarchTab {
+    using type = RegTab<R, 7 * MB>;
+    __device__ __forceinline__ static type make(CTab<R> t) {
+        type r;
+#pragma unroll
+        for (int i = 0; i < 7 * MB; ++i) r.v[i] = t[i];
+        return r;
+    }
+};
+template <typename R, int MB>
+struct MarchTab<R, MB, true> {
+    using type = CTab<R>;
+    __device__ __forceinline__ static type make(CTab<R> t) { return t; }
+};
+
+// Depth below which the float32 form keeps computing a bin whatever tau_kill.
+constexpr float kDropDepth = 30.0f;
+
+// Optical depth T = sigma_HI N_HI + sigma_HeI N_HeI + sigma_HeII N_HeII of one
+// bin from a packet's column densities (float32 form), in one fixed order of
+// operations used by every test that compares it with tau_kill.
+template <int S>
+__device__ __forceinline__ float column_depth(float sH, float sHe1, float sHe2, const float (&N)[S == 1 ? 1 : 3]) {
+    if (S == 1) return sH * N[0];
+    return __builtin_fmaf(sHe2, N[2], __builtin_fmaf(sHe1, N[1], sH * N[0]));
+}
+
 // Eq. (1) in every bin of one cell of chord length l (float32 form: l in
 // 1e18 cm, cross-sections in 1e-18 cm^2), with F the photons carried per bin
 // (updated to the transmitted part) and the depth state advanced.  Outputs,
@@ -74,10 +114,21 @@ __device__ __forceinline__ int exit_face(uint32_t d0, uint32_t d1, uint32_t d2, 
 // smallest accumulated optical depth over the bins (those the source does
 // not populate hold +inf), which ends the packet once it reaches tau_kill
 // (float32 form: see Extinction).
+//
+// Float32 form with several bins: a bin whose optical depth T_j reaches
+// tau_drop after this cell is dropped from the packet (its bit cleared in
+// `active`, its remaining photons added to `dropped` for the truncated
+// ledger).  The caller passes tau_drop = max(tau_kill, kDropDepth): the
+// extinction rule applied bin by bin, at a depth where a bin keeps at most
+// e^-30 (9.4e-14) of its share.  A bin no lane of the wavefront still
+// carries is skipped; the lanes then all hold exactly 0 photons in it, so
+// skipping changes nothing.
 template <typename R, int S, bool TH, int MB, int NA = 0, int NB = 0, typename KV, typename TT>
 __device__ __forceinline__ void cross_cell(R l, const KV &kap, TT tab, R (&F)[MB],
                                            R (&D)[DepthState<R, S, MB>::N], R &absorbed, R &e0, R &e1,
-                                           R &e2, R &heat, R &tmin) {
+                                           R &e2, R &heat, R &tmin, uint32_t &active, float tau_drop,
+                                           R &dropped) {
+    constexpr bool DROP = !std::is_same<R, double>::value && MB > 1;
     constexpr bool F64 = std::is_same<R, double>::value;
     R kH, kHe1 = R(0), kHe2 = R(0);
     if constexpr (S == 1) kH = kap;
@@ -93,8 +144,12 @@ __device__ __forceinline__ void cross_cell(R l, const KV &kap, TT tab, R (&F)[MB
     R ab = R(0), g0 = R(0), g1 = R(0), g2 = R(0), h0 = R(0), h1 = R(0), h2 = R(0);
     R dH = R(0), qH = R(0);     // bins absorbed by hydrogen alone (j < NA): photons, heat
     R tm = R(INFINITY);
+    R drop = R(0);
 #pragma unroll
     for (int j = 0; j < MB; ++j) {
+        if constexpr (DROP) {
+            if (__ballot((active >> j) & 1u) == 0ull) continue;
+        }
         struct { R x, y, z; } sg = {tab[j], tab[MB + j], tab[2 * MB + j]};
         // helium terms of a bin below a helium threshold are zero: with a bin
         // layout known at compile time (the first NA bins hydrogen only, the
@@ -125,6 +180,19 @@ __device__ __forceinline__ void cross_cell(R l, const KV &kap, TT tab, R (&F)[MB
             attenuation(tau, em, tr);
             d = F[j] * em;
             F[j] = F[j] * tr;
+            if constexpr (DROP) {
+                // the same T_j as the extinction test forms (zero helium
+                // cross-sections add exact zeros)
+                float Tj;
+                if constexpr (S == 1) Tj = sg.x * D[0];
+                else if (j < NA) Tj = sg.x * D[0];
+                else if (j < NA + NB) Tj = __builtin_fmaf(sg.y, D[1], sg.x * D[0]);
+                else Tj = column_depth<S>(sg.x, sg.y, sg.z, D);
+                const bool gone = ((active >> j) & 1u) && Tj >= tau_drop;
+                drop += gone ? F[j] : R(0);
+                F[j] = gone ? R(0) : F[j];
+                active = gone ? (active & ~(1u << j)) : active;
+            }
         }
         ab += d;
         if (S == 3 && j < NA) {
@@ -168,6 +236,7 @@ __device__ __forceinline__ void cross_cell(R l, const KV &kap, TT tab, R (&F)[MB
     }
     absorbed = ab;
     tmin = tm;
+    dropped = drop;
     if (S == 1) {
         e0 = ab;
         e1 = e2 = R(0);
@@ -199,8 +268,7 @@ struct Extinction {
     uint32_t jw = 0;                              // the witness bin
 
     __device__ __forceinline__ static float depth(float sH, float sHe1, float sHe2, const float (&N)[S == 1 ? 1 : 3]) {
-        if (S == 1) return sH * N[0];
-        return __builtin_fmaf(sHe2, N[2], __builtin_fmaf(sHe1, N[1], sH * N[0]));
+        return column_depth<S>(sH, sHe1, sHe2, N);
     }
 
     // full check: true if extinguished; else the witness is the first bin of

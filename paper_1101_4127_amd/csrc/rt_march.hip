@@ -103,6 +103,7 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
     double sprev = 0.0, L = 0.0;                // float64 form: entry parameter, length scale
     float Lf = 0.0f;                            // float32 form: length scale (1e18 cm units)
     double w = 0.0, absd = 0.0;
+    float dropf = 0.0f;                         // float32 form: photons of bins dropped so far
     uint32_t slot = 0, count = 0, srcid = 0;
     int32_t tix = -1;                           // trace record of this packet, -1 if untraced
     KV kap{};                                   // absorbers of the current cell
@@ -206,6 +207,7 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
                     dtest.start(tab, active, D);
                     sprev = 0.0; pnum = 0; pden = 1;
                     absd = 0.0;
+                    dropf = 0.0f;
                     count = 0;
                     slot = cell_slot(p.geo, k0, k1, k2);
                     kap = kappa[slot];
@@ -223,7 +225,7 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
         }
 
         // what this iteration adds to the ledger (zero for lanes without a packet)
-        double it_abs = 0.0, it_left = 0.0;
+        double it_abs = 0.0, it_left = 0.0, it_drop = 0.0;
         uint32_t it_cross = 0, it_fate = 0;
         if (alive) {
             // ---- geometry: nearest face by exact integer comparison ----
@@ -255,8 +257,10 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
             const KV knext = kappa[nslot];
 
             // ---- Eq. (1) per bin and the split among absorbers ----
-            R absorbed, e0, e1, e2, hs, tmin;
-            cross_cell<R, S, TH, MB, NA, NB>(l, kap, tab, F, D, absorbed, e0, e1, e2, hs, tmin);
+            R absorbed, e0, e1, e2, hs, tmin, dropped;
+            cross_cell<R, S, TH, MB, NA, NB>(l, kap, tab, F, D, absorbed, e0, e1, e2, hs, tmin, active,
+                                             fmaxf((float)p.tau_kill, kDropDepth), dropped);
+            if constexpr (!F64) dropf += dropped;
 
             // ---- deposit: float64 accumulators, hardware atomics at L2 ----
             double *cell = p.acc + (size_t)slot * ACC;
@@ -298,6 +302,7 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
                 for (int j = 0; j < MB; ++j) left += (double)F[j];
                 it_abs = w * absd;
                 it_left = w * left;
+                it_drop = w * (double)dropf;
                 it_fate = fate;
                 if (traced) {
                     const int face = fate == 1 ? 0
@@ -316,7 +321,7 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
         n_cross += it_cross;
         l_abs += it_abs;
         l_esc += (it_fate == 2u) ? it_left : 0.0;
-        l_trunc += (it_fate == 1u) ? it_left : 0.0;
+        l_trunc += ((it_fate == 1u) ? it_left : 0.0) + it_drop;
         n_esc += (it_fate == 2u) ? 1u : 0u;
         n_trunc += (it_fate == 1u) ? 1u : 0u;
     }
@@ -550,8 +555,9 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, 1>::value))
             const uint32_t nslot = out ? slot : cell_slot(geo, k0, k1, k2);
             const R knext = kappa[nslot];
 
-            R absorbed, e0, e1, e2, hs, tmin;
-            cross_cell<R, 1, TH, 1>(l, kap, tab, F, D, absorbed, e0, e1, e2, hs, tmin);
+            R absorbed, e0, e1, e2, hs, tmin, dropped;
+            cross_cell<R, 1, TH, 1>(l, kap, tab, F, D, absorbed, e0, e1, e2, hs, tmin, active, (float)tau_kill,
+                                    dropped);
 
             double *cell = acc + (size_t)slot * ACC;
             const double v = w * (double)absorbed;

@@ -512,8 +512,9 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
     __shared__ uint32_t s_list[kMaxRun];
     __shared__ uint32_t s_next, s_claim;
     __shared__ float s_sigf[3 * MB];          // float32 form: cross-sections, indexed per lane
-    const CTab<R> tab = (CTab<R>)p.tab;
-    if (!F64 && threadIdx.x < 3 * MB) s_sigf[threadIdx.x] = (float)tab[threadIdx.x];
+    const CTab<R> ctab = (CTab<R>)p.tab;
+    if (!F64 && threadIdx.x < 3 * MB) s_sigf[threadIdx.x] = (float)ctab[threadIdx.x];
+    const typename MarchTab<R, MB>::type tab = MarchTab<R, MB>::make(ctab);
 
     const uint32_t nch = p.ctrl->n_chunks[cur];
     const TChunk *chs = cur ? p.ch1 : p.ch0;
@@ -562,6 +563,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
         int hlast = 0;                           // natural index of the last cell crossed (traces)
         double sprev = 0.0, L = 0.0, w = 0.0, absd = 0.0;
         float Lf = 0.0f;
+        float dropf = 0.0f;                      // float32 form: photons of bins dropped in this segment
         uint32_t loc = 0, count = 0, active = 0;
         DepthTest<R, S, MB> dtest;
         int32_t tix = -1;
@@ -581,6 +583,9 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
             const uint32_t nidle = (uint32_t)__popcll(__ballot(!alive)) + npend;
             const bool trigger = nidle != 0u
                 && (nidle == 64u || (exhausted ? npend >= p.refill_min : nidle >= p.refill_min));
+            // what the settled packets add to the ledger (added below in uniform control flow)
+            double st_abs = 0.0, st_esc = 0.0, st_trunc = 0.0;
+            uint32_t st_nesc = 0, st_ntrunc = 0;
             if (trigger && npend != 0u && pend) {
                 bool ex = kill;
                 if constexpr (!F64) ex = kill && dtest.ext.full(tab, active, (float)p.tau_kill, D);
@@ -594,7 +599,8 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                 if (fate != 0u) {                  // fate 0: a new witness bin, the packet marches on
                     const bool traced = tix >= 0;
                     int32_t *rec = p.trace + (size_t)(traced ? tix : 0) * (RT_TRACE_HDR_DEV + p.trace_len);
-                    l_abs += w * absd;
+                    st_abs = w * absd;
+                    st_trunc = w * (double)dropf;
                     if (fate == 3u) {
                         // moves on into a neighbour tile: record back, rank among the run's
                         // packets bound for the same tile
@@ -611,7 +617,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
 #pragma unroll
                         for (int j = 0; j < MB; ++j) left += F[j];
                         const double wl = w * (double)left;
-                        if (fate == 2u) { l_esc += wl; ++n_esc; } else { l_trunc += wl; ++n_trunc; }
+                        if (fate == 2u) { st_esc = wl; st_nesc = 1u; } else { st_trunc += wl; st_ntrunc = 1u; }
                         p.side[pos] = kSideDead;
                         if (traced) {
                             const int face = fate == 1u ? 0
@@ -631,6 +637,11 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                 pend = false;
                 kill = false;
             }
+            l_abs += st_abs;
+            l_esc += st_esc;
+            l_trunc += st_trunc;
+            n_esc += st_nesc;
+            n_trunc += st_ntrunc;
             const uint64_t dead = __ballot(!alive);
             const uint32_t ndead = (uint32_t)__popcll(dead);
             if (trigger && !exhausted && ndead != 0u) {
@@ -707,6 +718,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                                 tix = trace_slot(p, p.g0 + ri);
                                 count = tix >= 0 ? (uint32_t)p.trace[(size_t)tix * (RT_TRACE_HDR_DEV + p.trace_len)] : 0u;
                                 absd = 0.0;
+                                dropf = 0.0f;
                                 loc = local_cell(k0, k1, k2);
                                 kap = s_kap[loc];
                                 alive = true;
@@ -715,11 +727,10 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                     }
                 }
             }
-            if (__ballot(alive && !pend) == 0ull) {
-                if (exhausted && __ballot(alive) == 0ull) break;
-                continue;
-            }
+            if (exhausted && __ballot(alive) == 0ull) break;
 
+            // (with no lane marching this iteration only settles and refills: one
+            // path through the loop body keeps the packet state in its registers)
             uint32_t it_cross = 0;
             if (alive && !pend) {
                 bool m0, m1, m2;
@@ -751,8 +762,10 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                 const uint32_t nloc = local_cell(k0, k1, k2);
                 const KV knext = s_kap[nloc];
 
-                R absorbed, e0, e1, e2, hs, tmin;
-                cross_cell<R, S, TH, MB, NA, NB>(l, kap, tab, F, D, absorbed, e0, e1, e2, hs, tmin);
+                R absorbed, e0, e1, e2, hs, tmin, dropped;
+                cross_cell<R, S, TH, MB, NA, NB>(l, kap, tab, F, D, absorbed, e0, e1, e2, hs, tmin, active,
+                                                 fmaxf((float)p.tau_kill, kDropDepth), dropped);
+                if constexpr (!F64) dropf += dropped;
 
                 // ---- deposit into the tile's float64 accumulators in LDS ----
                 // (zero deposits are added too: an LDS add is cheaper than the branch)
@@ -792,7 +805,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
             if (exhausted && p.park != 0u) {
                 const uint64_t am = __ballot(alive && !pend);
                 if (am != 0ull && (uint32_t)__popcll(am) <= p.park) {
-                    double pk_abs = 0.0;
+                    double pk_abs = 0.0, pk_drop = 0.0;
                     if (alive && !pend) {
                         uint32_t jw = 0;
                         if constexpr (!F64) jw = dtest.ext.jw;
@@ -803,9 +816,11 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                         p.side[pos] = stay | (rank << 5);
                         if (tix >= 0) p.trace[(size_t)tix * (RT_TRACE_HDR_DEV + p.trace_len)] = (int32_t)count;
                         pk_abs = w * absd;
+                        pk_drop = w * (double)dropf;
                         alive = false;
                     }
                     l_abs += pk_abs;
+                    l_trunc += pk_drop;
                 }
             }
         }

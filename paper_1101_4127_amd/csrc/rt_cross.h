@@ -92,6 +92,17 @@ struct MarchTab<R, MB, true> {
     __device__ __forceinline__ static type make(CTab<R> t) { return t; }
 };
 
+// Bins any lane of the wavefront with lane_on set still carries (bit j: some
+// such lane has bit j of `active`).  Wave-uniform.
+template <int MB>
+__device__ __forceinline__ uint32_t wave_bins(bool lane_on, uint32_t active) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int j = 0; j < MB; ++j)
+        if (__ballot(lane_on && ((active >> j) & 1u)) != 0ull) m |= 1u << j;
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)m);
+}
+
 // Depth below which the float32 form keeps computing a bin whatever tau_kill.
 constexpr float kDropDepth = 30.0f;
 
@@ -120,14 +131,15 @@ __device__ __forceinline__ float column_depth(float sH, float sHe1, float sHe2, 
 // `active`, its remaining photons added to `dropped` for the truncated
 // ledger).  The caller passes tau_drop = max(tau_kill, kDropDepth): the
 // extinction rule applied bin by bin, at a depth where a bin keeps at most
-// e^-30 (9.4e-14) of its share.  A bin no lane of the wavefront still
-// carries is skipped; the lanes then all hold exactly 0 photons in it, so
-// skipping changes nothing.
+// e^-30 (9.4e-14) of its share.  Bins outside `wbins` (wave-uniform; a
+// superset of the bins the wavefront's crossing lanes still carry, e.g. from
+// wave_bins) are skipped: every crossing lane holds exactly 0 photons in them,
+// so skipping changes nothing.
 template <typename R, int S, bool TH, int MB, int NA = 0, int NB = 0, typename KV, typename TT>
 __device__ __forceinline__ void cross_cell(R l, const KV &kap, TT tab, R (&F)[MB],
                                            R (&D)[DepthState<R, S, MB>::N], R &absorbed, R &e0, R &e1,
                                            R &e2, R &heat, R &tmin, uint32_t &active, float tau_drop,
-                                           R &dropped) {
+                                           R &dropped, uint32_t wbins = ~0u) {
     constexpr bool DROP = !std::is_same<R, double>::value && MB > 1;
     constexpr bool F64 = std::is_same<R, double>::value;
     R kH, kHe1 = R(0), kHe2 = R(0);
@@ -148,7 +160,7 @@ __device__ __forceinline__ void cross_cell(R l, const KV &kap, TT tab, R (&F)[MB
 #pragma unroll
     for (int j = 0; j < MB; ++j) {
         if constexpr (DROP) {
-            if (__ballot((active >> j) & 1u) == 0ull) continue;
+            if (!((wbins >> j) & 1u)) continue;
         }
         struct { R x, y, z; } sg = {tab[j], tab[MB + j], tab[2 * MB + j]};
         // helium terms of a bin below a helium threshold are zero: with a bin

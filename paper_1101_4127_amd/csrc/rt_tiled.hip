@@ -565,6 +565,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
         float Lf = 0.0f;
         float dropf = 0.0f;                      // float32 form: photons of bins dropped in this segment
         uint32_t loc = 0, count = 0, active = 0;
+        uint32_t wbins = 0;                      // wave-uniform: bins some crossing lane may carry
         DepthTest<R, S, MB> dtest;
         int32_t tix = -1;
         KV kap{};
@@ -728,6 +729,11 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                 }
             }
             if (exhausted && __ballot(alive) == 0ull) break;
+            // lanes change packets or bins only at a settle or refill (bins are
+            // also dropped while crossing, which only clears bits)
+            if constexpr (!F64 && MB > 1) {
+                if (trigger) wbins = wave_bins<MB>(alive && !pend, active);
+            }
 
             // (with no lane marching this iteration only settles and refills: one
             // path through the loop body keeps the packet state in its registers)
@@ -764,7 +770,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
 
                 R absorbed, e0, e1, e2, hs, tmin, dropped;
                 cross_cell<R, S, TH, MB, NA, NB>(l, kap, tab, F, D, absorbed, e0, e1, e2, hs, tmin, active,
-                                                 fmaxf((float)p.tau_kill, kDropDepth), dropped);
+                                                 fmaxf((float)p.tau_kill, kDropDepth), dropped, wbins);
                 if constexpr (!F64) dropf += dropped;
 
                 // ---- deposit into the tile's float64 accumulators in LDS ----

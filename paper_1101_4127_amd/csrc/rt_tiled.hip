@@ -944,7 +944,7 @@ hipError_t run_batch(const TiledLaunch &t) {
     const dim3 grid(t.m.blocks), blk(kTBlock);
     hipLaunchKernelGGL((k_temit<R, S, TH, MB>), grid, blk, 0, st, p);
     scan(p, t, 0);
-    hipLaunchKernelGGL(k_tscatter_emit, grid, blk, 0, st, p);
+    hipLaunchKernelGGL(k_tscatter_emit, dim3(8 * t.m.blocks), blk, 0, st, p);
     int cur = 0;
     TParams pp = p;
     for (uint32_t pass = 0; pass < t.passes; ++pass) {
@@ -957,7 +957,9 @@ hipError_t run_batch(const TiledLaunch &t) {
             ++*t.ev_used;
         }
         scan(p, t, cur ^ 1);
-        hipLaunchKernelGGL(k_tscatter, grid, blk, 0, st, p, cur);
+        // each run's scatter waits on two dependent reads before its copies:
+        // many more blocks than the march keep enough runs in flight
+        hipLaunchKernelGGL(k_tscatter, dim3(8 * t.m.blocks), blk, 0, st, p, cur);
         cur ^= 1;
     }
     hipLaunchKernelGGL(k_tcheck, dim3(1), dim3(64), 0, st, t.ctrl, cur, t.ledger);

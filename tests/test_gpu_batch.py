@@ -210,3 +210,28 @@ def test_autotuned_parameters_leave_results_unchanged():
     assert sa["n_escaped"] == sb["n_escaped"] and sa["n_truncated"] == sb["n_truncated"]
     for f in range(7, 11):
         assert np.max(PT.deposit_err(fb[f], fa[f])) <= 1e-9
+
+
+def test_fused_step_single_solve_and_solve_without_sources():
+    """A batch of one, and a batch holding a solve without sources (its cell
+    update still runs, with no packets), each against the same solves alone."""
+    from paper_1101_4127_amd import rt
+    reqs = stream(count=2, seed=47)
+    empty = reqs[1].work.with_(src_ijk=np.zeros((0, 3), np.int32), src_ndot=np.zeros(0), src_sed=np.zeros((0, 1)))
+    works = [reqs[0].work, empty]
+    for batch in ([0], [0, 1]):
+        b = rt.Batch(2, graph=True)
+        fused = [rt.Solve(works[i], fp64=True, direct=True, stream=b.stream) for i in batch]
+        alone = [rt.Solve(works[i], fp64=True, direct=True) for i in batch]
+        for _ in range(2):
+            led = b.step(fused, stats=True)
+            ref = [s.step() for s in alone]
+            for x, y in zip(ref, led):
+                assert x["packets"] == y["packets"] and x["substeps"] == y["substeps"]
+        for a, f in zip(alone, fused):
+            fa, fm = a.fetch(), f.fetch()
+            assert np.max(PT.frac_err(fm[1], fa[1], 1e-6)) <= 1e-9
+            assert np.max(PT.deposit_err(fm[7], fa[7])) <= 1e-9
+            a.release()
+            f.release()
+        b.release()

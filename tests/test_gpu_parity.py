@@ -381,3 +381,32 @@ def test_test3_whole_run_plain_fp64(gpu):
             assert np.max(PT.frac_err(f[1 + i], o.x[i])) < 1e-6, (k, i)
         assert np.max(PT.temp_err(f[6], o.T)) < 1e-6, k
     s.release()
+
+
+@pytest.mark.parametrize("n", [(1024, 2, 3), (3, 1024, 2), (2, 3, 1024)], ids=["x", "y", "z"])
+def test_longest_axis_grids(gpu, n):
+    """Grids at the per-axis maximum (1024 cells) in each direction, one cell
+    or a few wide: tiles of one partial row, passes along the long axis;
+    float64 traces, deposits and state bit-exact against the oracle."""
+    w = ragged_case(n=n, n_src=3, packets=3000, cell_cm=2e21)
+    o, stats, fields, tr = PT.run_both(w, fp64=True, trace_n=300, trace_len=1100, stride=10)
+    PT.compare_traces(w, o.kappa, tr, o.trace, exact=True)
+    PT.compare_state(o, fields, w, frac_tol=1e-9, temp_tol=1e-9, dep_tol=1e-9)
+    assert PT.ledger_close(*stats[0], 1e-12) <= 1e-12
+
+
+def test_one_packet_per_source_and_zero_packets(gpu):
+    """The smallest valid step (one packet per source per sub-step) matches the
+    oracle; a step with sources but no packets is rejected and leaves the
+    handle usable."""
+    from paper_1101_4127_amd import rt
+    w = ragged_case(n=(9, 7, 5), n_src=4, packets=4, fp64=True)
+    o, stats, fields, tr = PT.run_both(w, fp64=True, trace_n=4, trace_len=64)
+    PT.compare_traces(w, o.kappa, tr, o.trace, exact=True)
+    PT.compare_state(o, fields, w, frac_tol=1e-9, temp_tol=1e-9, dep_tol=1e-9)
+    s = rt.Solve(w, fp64=True)
+    with pytest.raises(rt.RTError) as e:
+        rt.rt_step(s.h, w.dt_s, 0, 1)
+    assert e.value.status == rt.RT_EINVAL
+    assert s.step()["packets"] == 4
+    s.release()

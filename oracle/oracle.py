@@ -43,6 +43,11 @@ class Grid(C.Structure):
                 ("tau_kill", C.c_double), ("n_chem", C.c_int32), ("flags", C.c_uint32)]
 
 
+class Reemit(C.Structure):
+    _fields_ = [("f_rec", C.c_double), ("n_t", C.c_int32), ("log10_t0", C.c_double),
+                ("dlog10_t", C.c_double), ("milne", C.POINTER(C.c_double))]
+
+
 class Rates(C.Structure):
     _fields_ = [("a_hii", C.c_double), ("a_heii", C.c_double), ("a_heiii", C.c_double),
                 ("b_hi", C.c_double), ("b_hei", C.c_double), ("b_heii", C.c_double)]
@@ -80,6 +85,17 @@ def lib():
                                    C.c_double, C.c_int64, C.c_int32, C.c_uint64, C.c_uint64,
                                    u64p, dp, dp, dp, C.c_int32, C.c_int32, C.c_int32, ip]
             L.orc_step.restype = C.c_int
+            L.orc_step_rx.argtypes = L.orc_step.argtypes + [_P(Reemit), dp]
+            L.orc_step_rx.restype = C.c_int
+            L.orc_rates_case_a.argtypes = [C.c_double, _P(Rates)]
+            L.orc_ground_fraction.argtypes = [C.c_double, dp]
+            L.orc_update_cell_rx.argtypes = [gp, C.c_double, C.c_double, dp, dp, dp,
+                                             _P(Rates), C.c_int, C.c_int, dp]
+            L.orc_hii_time.argtypes = [C.c_double] * 5
+            L.orc_hii_time.restype = C.c_double
+            L.orc_he_ion_time.argtypes = [dp, dp] + [C.c_double] * 5 + [dp]
+            L.orc_direction_ex.argtypes = [C.c_uint64] * 4 + [C.c_int, C.c_uint64, ip]
+            L.orc_direction_ex.restype = C.c_int
             _lib = L
     return _lib
 
@@ -148,6 +164,50 @@ def rates_at(T: float) -> Rates:
     return r
 
 
+def rates_case_a(T: float) -> Rates:
+    r = Rates()
+    lib().orc_rates_case_a(float(T), C.byref(r))
+    return r
+
+
+def ground_fraction(T: float) -> np.ndarray:
+    """Share of HII, HeII, HeIII recombinations that reach the ground state."""
+    p = np.zeros(3)
+    lib().orc_ground_fraction(float(T), _ptr(p, C.c_double))
+    return p
+
+
+def hii_time(x0: float, xh: float, I: float, R: float, h: float) -> float:
+    return lib().orc_hii_time(float(x0), float(xh), float(I), float(R), float(h))
+
+
+def he_ion_time(x0, xh, I1, R2, I2, R3, h) -> np.ndarray:
+    a, b, out = _c64(x0), _c64(xh), np.zeros(2)
+    lib().orc_he_ion_time(_ptr(a, C.c_double), _ptr(b, C.c_double), float(I1), float(R2), float(I2),
+                          float(R3), float(h), _ptr(out, C.c_double))
+    return out
+
+
+def direction_ex(seed: int, solve_id: int, g: int, step_index: int, octant: bool, stream: int):
+    c = np.zeros(3, np.int32)
+    att = lib().orc_direction_ex(seed, solve_id, g, step_index, int(octant), stream, _ptr(c, C.c_int32))
+    return c, att
+
+
+def update_cell_rx(grid: Grid, dt: float, nh: float, x, T: float, acc, rc,
+                   fixed: Optional[Rates] = None, case_a: bool = True):
+    """Advance one cell with recombination counting; returns (x[5], T, rc[3])."""
+    xv = _c64(np.array(x, dtype=np.float64).copy())
+    tv = np.array([T], np.float64)
+    av = _c64(acc)
+    rv = _c64(np.array(rc, dtype=np.float64).copy())
+    lib().orc_update_cell_rx(C.byref(grid), float(dt), float(nh), _ptr(xv, C.c_double),
+                             _ptr(tv, C.c_double), _ptr(av, C.c_double),
+                             C.byref(fixed) if fixed is not None else None, 0, int(case_a),
+                             _ptr(rv, C.c_double))
+    return xv, float(tv[0]), rv
+
+
 def cooling(T, ne, n_hi, n_hii, n_hei, n_heii, n_heiii) -> float:
     return lib().orc_cooling(*(float(v) for v in (T, ne, n_hi, n_hii, n_hei, n_heii, n_heiii)))
 
@@ -174,7 +234,8 @@ LEDGER_KEYS = ("emitted", "absorbed", "escaped", "truncated")
 def ledger_dict(led: np.ndarray) -> dict:
     d = {k: float(led[2 * i] + led[2 * i + 1]) for i, k in enumerate(LEDGER_KEYS)}
     d.update(crossings=int(led[8]), n_escaped=int(led[9]), n_truncated=int(led[10]),
-             packets=int(led[11]))
+             packets=int(led[11]), diffuse_emitted=float(led[12] + led[13]),
+             diffuse_packets=int(led[14]))
     return d
 
 
@@ -197,6 +258,14 @@ class OracleSolve:
         self.step_index = np.zeros(1, np.uint64)
         self.seed = work.seed if seed is None else seed
         self.trace = None
+        # recombination counters (per atom, HII, HeII, HeIII) and the emission inputs
+        self.rc = np.zeros((3, nc))
+        self._reemit = None
+        if work.recomb is not None:
+            r = work.recomb
+            self._milne = _c64(r.milne).copy()
+            self._reemit = Reemit(float(r.f_rec), int(r.n_t), float(r.log10_t0), float(r.dlog10_t),
+                                  _ptr(self._milne, C.c_double))
 
     def step(self, dt: Optional[float] = None, packets: Optional[int] = None,
              seed: Optional[int] = None, trace_n: int = 0, trace_len: int = 0,
@@ -207,14 +276,16 @@ class OracleSolve:
         seed = self.seed if seed is None else seed
         led = np.zeros(16)
         tr = np.zeros((max(trace_n, 0), TRACE_HDR + trace_len), np.int32) if trace_n else None
-        rc = lib().orc_step(C.byref(self.grid), _ptr(self.nh, C.c_double), _ptr(self.x, C.c_double),
-                            _ptr(self.T, C.c_double), len(self.src_ndot),
-                            _ptr(self.src_ijk, C.c_int32), _ptr(self.src_ndot, C.c_double),
-                            _ptr(self.src_sed, C.c_double), self.src_flags, float(dt),
-                            int(packets), int(w.n_sub), int(seed), int(w.solve_id),
-                            _ptr(self.step_index, C.c_uint64), _ptr(self.acc, C.c_double),
-                            _ptr(self.kappa, C.c_double), _ptr(led, C.c_double),
-                            int(trace_n), int(trace_len), int(trace_stride), _ptr(tr, C.c_int32))
+        rc = lib().orc_step_rx(C.byref(self.grid), _ptr(self.nh, C.c_double), _ptr(self.x, C.c_double),
+                               _ptr(self.T, C.c_double), len(self.src_ndot),
+                               _ptr(self.src_ijk, C.c_int32), _ptr(self.src_ndot, C.c_double),
+                               _ptr(self.src_sed, C.c_double), self.src_flags, float(dt),
+                               int(packets), int(w.n_sub), int(seed), int(w.solve_id),
+                               _ptr(self.step_index, C.c_uint64), _ptr(self.acc, C.c_double),
+                               _ptr(self.kappa, C.c_double), _ptr(led, C.c_double),
+                               int(trace_n), int(trace_len), int(trace_stride), _ptr(tr, C.c_int32),
+                               C.byref(self._reemit) if self._reemit is not None else None,
+                               _ptr(self.rc, C.c_double))
         if rc != 0:
             raise ValueError("oracle step rejected: fewer packets than sources in a sub-step")
         self.trace = tr

@@ -88,18 +88,18 @@ void orc_philox4x64_10(const uint64_t ctr_in[4], const uint64_t key_in[2], uint6
 
 /* Isotropic integer direction (Sec. 2: emission direction from the source's
  * angular PDF, isotropic here).  Each attempt draws one Philox block keyed by
- * (seed, solve id) at counter (packet id, sub-step index, attempt, 0); the top
+ * (seed, solve id) at counter (packet id, sub-step index, attempt, stream); the top
  * 21 bits of the first three words give components in [-2^20, 2^20).  The
  * vector is kept if 2^36 <= |c|^2 <= 2^40 (a spherical shell: uniform
  * direction).  After 64 rejections the diagonal (2^19, 2^19, 2^19) is used.
  * A corner (octant) source folds the direction into the positive octant.
  * Returns the number of attempts made. */
-int orc_direction(uint64_t seed, uint64_t solve_id, uint64_t g, uint64_t step_index,
-                  int octant, int32_t c[3])
+int orc_direction_ex(uint64_t seed, uint64_t solve_id, uint64_t g, uint64_t step_index,
+                     int octant, uint64_t stream, int32_t c[3])
 {
     const uint64_t key[2] = {seed, solve_id};
     for (int attempt = 0; attempt < 64; ++attempt) {
-        uint64_t ctr[4] = {g, step_index, (uint64_t)attempt, 0};
+        uint64_t ctr[4] = {g, step_index, (uint64_t)attempt, stream};
         uint64_t r[4];
         orc_philox4x64_10(ctr, key, r);
         int64_t v[3], q = 0;
@@ -115,6 +115,14 @@ int orc_direction(uint64_t seed, uint64_t solve_id, uint64_t g, uint64_t step_in
     }
     c[0] = c[1] = c[2] = 1 << 19;
     return 64;
+}
+
+/* Source packets use stream word 0 with their packet id as g; a diffuse
+ * (recombination) packet uses stream word 1 with its cell's natural index. */
+int orc_direction(uint64_t seed, uint64_t solve_id, uint64_t g, uint64_t step_index,
+                  int octant, int32_t c[3])
+{
+    return orc_direction_ex(seed, solve_id, g, step_index, octant, 0, c);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -221,7 +229,9 @@ static void nsum(double *s, double *cmp, double v)
 /* ledger layout (doubles) */
 enum {
     L_EMIT = 0, L_ABS = 2, L_ESC = 4, L_TRUNC = 6,   /* (sum, compensation) pairs */
-    L_CROSS = 8, L_NESC = 9, L_NTRUNC = 10, L_PACKETS = 11, L_SIZE = 16
+    L_CROSS = 8, L_NESC = 9, L_NTRUNC = 10, L_PACKETS = 11,
+    L_DEMIT = 12,                                    /* diffuse photons emitted (pair, in L_EMIT too) */
+    L_DPACKETS = 14, L_SIZE = 16
 };
 
 /* Source of packet g when P packets are shared equally by S sources: the first
@@ -234,6 +244,103 @@ static int64_t source_of(int64_t g, int64_t P, int64_t S, int64_t *n_s)
     else s = rem + (g - rem * (q + 1)) / q;
     *n_s = q + (s < rem ? 1 : 0);
     return s;
+}
+
+/* Heat per absorbed photon of bin j by species s [erg]. */
+static void heat_table(const orc_grid *G, double heat_ev[3][ORC_MAX_BINS])
+{
+    for (int s = 0; s < 3; ++s)
+        for (int j = 0; j < G->n_bins; ++j)
+            heat_ev[s][j] = (G->e_ev[j] - ORC_ETH_EV[s]) * ORC_EV;
+}
+
+/*
+ * Follow one packet of w photons per unit of sed, starting at o (half-cell
+ * units) in direction c, until it is extinguished or leaves the box; deposits
+ * go to acc, the packet's end to the ledger (its emission is the caller's).
+ * rec, when not NULL, receives the crossed cells and the end (words 0-6).
+ */
+static void march_packet(const orc_grid *G, const double *kappa, const double heat_ev[3][ORC_MAX_BINS],
+                         double w, const double *sed, const int32_t o[3], const int32_t c[3],
+                         double *acc, double *ledger, int32_t trace_len, int32_t *rec)
+{
+    const int64_t ncell = (int64_t)G->n[0] * G->n[1] * G->n[2];
+    const int nb = G->n_bins;
+    const int pure_h = !(G->y_he > 0.0);
+    double f[ORC_MAX_BINS], T[ORC_MAX_BINS];
+    for (int j = 0; j < nb; ++j) { f[j] = 1.0; T[j] = 0.0; }
+    const double len_scale =
+        sqrt((double)((int64_t)c[0] * c[0] + (int64_t)c[1] * c[1] + (int64_t)c[2] * c[2]))
+        * (0.5 * G->cell_cm);
+
+    orc_ray r;
+    ray_start(&r, o, c);
+    double s_prev = 0.0;
+    int64_t count = 0;
+    int fate = 0, face = 0;
+    int64_t last = -1;
+
+    for (;;) {
+        int64_t num, den;
+        int mask = ray_exit_axes(&r, &num, &den);
+        const double s_new = (double)num / (double)den;
+        const double l = (s_new - s_prev) * len_scale;     /* chord in this cell [cm] */
+        const int64_t cell = cell_index(r.k, G->n);
+        const double kap[3] = {kappa[cell], pure_h ? 0.0 : kappa[ncell + cell],
+                               pure_h ? 0.0 : kappa[2 * ncell + cell]};
+
+        /* Eq. (1) per bin and the split among absorbers */
+        double dep[3] = {0.0, 0.0, 0.0}, heat = 0.0, absorbed = 0.0;
+        for (int j = 0; j < nb; ++j) {
+            if (!(sed[j] > 0.0)) continue;
+            double part[3];
+            for (int s = 0; s < 3; ++s) part[s] = kap[s] * G->sigma[s][j];
+            const double ksum = (part[0] + part[1]) + part[2];
+            const double tau = l * ksum;
+            const double d = f[j] * (-expm1(-tau));
+            f[j] = f[j] - d;
+            T[j] = T[j] + tau;
+            const double nabs = sed[j] * d;
+            absorbed += nabs;
+            if (ksum > 0.0) {
+                for (int s = 0; s < 3; ++s) {
+                    const double share = part[s] / ksum;
+                    dep[s] += nabs * share;
+                    heat += nabs * share * heat_ev[s][j];
+                }
+            }
+        }
+        for (int s = 0; s < 3; ++s) acc[s * ncell + cell] += w * dep[s];
+        acc[3 * ncell + cell] += w * heat;
+        nsum(&ledger[L_ABS], &ledger[L_ABS + 1], w * absorbed);
+        ledger[L_CROSS] += 1.0;
+        if (rec && count < trace_len) rec[8 + count] = (int32_t)cell;
+        ++count;
+        last = cell;
+
+        /* extinguished: every populated bin has accumulated tau >= tau_kill */
+        double tmin = INFINITY;
+        for (int j = 0; j < nb; ++j)
+            if (sed[j] > 0.0 && T[j] < tmin) tmin = T[j];
+        if (tmin >= G->tau_kill) { fate = ORC_FATE_TRUNC; break; }
+
+        face = ray_step(&r, mask, G->n);
+        if (face) { fate = ORC_FATE_ESCAPE; break; }
+        s_prev = s_new;
+    }
+    double left = 0.0;
+    for (int j = 0; j < nb; ++j) left += sed[j] * f[j];
+    if (fate == ORC_FATE_TRUNC) {
+        nsum(&ledger[L_TRUNC], &ledger[L_TRUNC + 1], w * left);
+        ledger[L_NTRUNC] += 1.0;
+    } else {
+        nsum(&ledger[L_ESC], &ledger[L_ESC + 1], w * left);
+        ledger[L_NESC] += 1.0;
+    }
+    if (rec) {
+        rec[0] = (int32_t)count; rec[1] = fate; rec[2] = face; rec[3] = (int32_t)last;
+        rec[4] = c[0]; rec[5] = c[1]; rec[6] = c[2];
+    }
 }
 
 /*
@@ -252,14 +359,10 @@ void orc_march(const orc_grid *G, const double *kappa,
                int64_t g_begin, int64_t g_end, double *acc, double *ledger,
                int32_t trace_n, int32_t trace_len, int32_t trace_stride, int32_t *trace)
 {
-    const int64_t ncell = (int64_t)G->n[0] * G->n[1] * G->n[2];
     const int nb = G->n_bins;
-    const int pure_h = !(G->y_he > 0.0);
     const int octant = (src_flags & ORC_SRC_OCTANT) != 0;
     double heat_ev[3][ORC_MAX_BINS];
-    for (int s = 0; s < 3; ++s)
-        for (int j = 0; j < nb; ++j)
-            heat_ev[s][j] = (G->e_ev[j] - ORC_ETH_EV[s]) * ORC_EV;
+    heat_table(G, heat_ev);
 
     for (int64_t g = g_begin; g < g_end; ++g) {
         /* --- emission --- */
@@ -278,83 +381,11 @@ void orc_march(const orc_grid *G, const double *kappa,
         nsum(&ledger[L_EMIT], &ledger[L_EMIT + 1], w * emitted);
         ledger[L_PACKETS] += 1.0;
 
-        double f[ORC_MAX_BINS], T[ORC_MAX_BINS];
-        for (int j = 0; j < nb; ++j) { f[j] = 1.0; T[j] = 0.0; }
-        const double len_scale =
-            sqrt((double)((int64_t)c[0] * c[0] + (int64_t)c[1] * c[1] + (int64_t)c[2] * c[2]))
-            * (0.5 * G->cell_cm);
-
-        orc_ray r;
-        ray_start(&r, o, c);
-        double s_prev = 0.0;
-        int64_t count = 0;
-        int fate = 0, face = 0;
-        int64_t last = -1;
         const int64_t stride = trace_stride > 0 ? trace_stride : 1;
         int32_t *rec = (trace && g % stride == 0 && g / stride < trace_n)
                      ? trace + (g / stride) * (8 + trace_len) : NULL;
-
-        for (;;) {
-            int64_t num, den;
-            int mask = ray_exit_axes(&r, &num, &den);
-            const double s_new = (double)num / (double)den;
-            const double l = (s_new - s_prev) * len_scale;     /* chord in this cell [cm] */
-            const int64_t cell = cell_index(r.k, G->n);
-            const double kap[3] = {kappa[cell], pure_h ? 0.0 : kappa[ncell + cell],
-                                   pure_h ? 0.0 : kappa[2 * ncell + cell]};
-
-            /* Eq. (1) per bin and the split among absorbers */
-            double dep[3] = {0.0, 0.0, 0.0}, heat = 0.0, absorbed = 0.0;
-            for (int j = 0; j < nb; ++j) {
-                if (!(sed[j] > 0.0)) continue;
-                double part[3];
-                for (int s = 0; s < 3; ++s) part[s] = kap[s] * G->sigma[s][j];
-                const double ksum = (part[0] + part[1]) + part[2];
-                const double tau = l * ksum;
-                const double d = f[j] * (-expm1(-tau));
-                f[j] = f[j] - d;
-                T[j] = T[j] + tau;
-                const double nabs = sed[j] * d;
-                absorbed += nabs;
-                if (ksum > 0.0) {
-                    for (int s = 0; s < 3; ++s) {
-                        const double share = part[s] / ksum;
-                        dep[s] += nabs * share;
-                        heat += nabs * share * heat_ev[s][j];
-                    }
-                }
-            }
-            for (int s = 0; s < 3; ++s) acc[s * ncell + cell] += w * dep[s];
-            acc[3 * ncell + cell] += w * heat;
-            nsum(&ledger[L_ABS], &ledger[L_ABS + 1], w * absorbed);
-            ledger[L_CROSS] += 1.0;
-            if (rec && count < trace_len) rec[8 + count] = (int32_t)cell;
-            ++count;
-            last = cell;
-
-            /* extinguished: every populated bin has accumulated tau >= tau_kill */
-            double tmin = INFINITY;
-            for (int j = 0; j < nb; ++j)
-                if (sed[j] > 0.0 && T[j] < tmin) tmin = T[j];
-            if (tmin >= G->tau_kill) { fate = ORC_FATE_TRUNC; break; }
-
-            face = ray_step(&r, mask, G->n);
-            if (face) { fate = ORC_FATE_ESCAPE; break; }
-            s_prev = s_new;
-        }
-        double left = 0.0;
-        for (int j = 0; j < nb; ++j) left += sed[j] * f[j];
-        if (fate == ORC_FATE_TRUNC) {
-            nsum(&ledger[L_TRUNC], &ledger[L_TRUNC + 1], w * left);
-            ledger[L_NTRUNC] += 1.0;
-        } else {
-            nsum(&ledger[L_ESC], &ledger[L_ESC + 1], w * left);
-            ledger[L_NESC] += 1.0;
-        }
-        if (rec) {
-            rec[0] = (int32_t)count; rec[1] = fate; rec[2] = face; rec[3] = (int32_t)last;
-            rec[4] = c[0]; rec[5] = c[1]; rec[6] = c[2]; rec[7] = (int32_t)src;
-        }
+        march_packet(G, kappa, heat_ev, w, sed, o, c, acc, ledger, trace_len, rec);
+        if (rec) rec[7] = (int32_t)src;
     }
 }
 
@@ -371,10 +402,52 @@ typedef struct {
     double b_hi, b_hei, b_heii;        /* collisional ionisation [cm^3/s] */
 } orc_rates;
 
+void orc_rates_at(double T, orc_rates *r);
+
 static double hg97_hydrogenic(double T, double t_th)
 {
     const double lam = 2.0 * t_th / T;
     return 2.753e-14 * pow(lam, 1.5) / pow(1.0 + pow(lam / 2.740, 0.407), 2.242);
+}
+
+/* Case A of the same fits: every recombination counted, ground state included. */
+static double hg97_hydrogenic_a(double T, double t_th)
+{
+    const double lam = 2.0 * t_th / T;
+    return 1.269e-13 * pow(lam, 1.503) / pow(1.0 + pow(lam / 0.522, 0.470), 1.923);
+}
+
+static double heii_dielectronic(double T)
+{
+    return 1.9e-3 * pow(T, -1.5) * exp(-470000.0 / T) * (1.0 + 0.3 * exp(-94000.0 / T));
+}
+
+/* Rates with case-A recombination (used when recombination photons are
+ * followed as packets instead of being absorbed on the spot). */
+void orc_rates_case_a(double T, orc_rates *r)
+{
+    orc_rates_at(T, r);
+    r->a_hii = hg97_hydrogenic_a(T, 157807.0);
+    r->a_heiii = 2.0 * hg97_hydrogenic_a(T, 631515.0);
+    r->a_heii = 3.0e-14 * pow(2.0 * 285335.0 / T, 0.654) + heii_dielectronic(T);
+}
+
+/* Share of each ion's recombinations that go directly to the ground state and
+ * so emit an ionising photon: (alpha_A - alpha_B) / alpha_A of the radiative
+ * rates (HeII: over the total with the dielectronic part), at least 0.
+ * p = HII, HeII, HeIII. */
+void orc_ground_fraction(double T, double p[3])
+{
+    const double ah_a = hg97_hydrogenic_a(T, 157807.0), ah_b = hg97_hydrogenic(T, 157807.0);
+    const double ahe_a = hg97_hydrogenic_a(T, 631515.0), ahe_b = hg97_hydrogenic(T, 631515.0);
+    const double r_a = 3.0e-14 * pow(2.0 * 285335.0 / T, 0.654);
+    const double r_b = 1.26e-14 * pow(2.0 * 285335.0 / T, 0.750);
+    p[0] = (ah_a - ah_b) / ah_a;
+    p[1] = (r_a - r_b) / (r_a + heii_dielectronic(T));
+    p[2] = (ahe_a - ahe_b) / ahe_a;
+    /* the HeII power laws cross below ~70 K, outside the fits' range: no
+       ground-state share there */
+    for (int i = 0; i < 3; ++i) p[i] = p[i] > 0.0 ? p[i] : 0.0;
 }
 
 void orc_rates_at(double T, orc_rates *r)
@@ -494,6 +567,33 @@ static void advance_fractions(double xo[5], const double x[5], const orc_rates *
                      gam[2] + R->b_heii * ne, R->a_heiii * ne, h);
 }
 
+/* Time integral over h of x_HII along the two-level solution (rates I, R)
+ * that took it from x0 to xh: h x_eq + (x0 - xh) / (I + R). */
+double orc_hii_time(double x0, double xh, double I, double R, double h)
+{
+    const double lam = I + R;
+    if (!(lam > 0.0)) return h * x0;
+    const double v = h * (I / lam) + (x0 - xh) / lam;
+    return v > 0.0 ? v : 0.0;
+}
+
+/* Time integrals over h of x_HeII and x_HeIII along the chain's solution
+ * from x0 to xh (x = HeI, HeII, HeIII): h x_eq + z, where z is the zero-sum
+ * solution of M z = xh - x0 (M the generator of solve_he), i.e.
+ * z_HeII = (R3 d0 + I1 d2) / det, z_HeIII = (I2 d0 - (I1 + R2) d2) / det. */
+void orc_he_ion_time(const double x0[3], const double xh[3], double I1, double R2, double I2,
+                     double R3, double h, double out[2])
+{
+    const double det = I1 * I2 + I1 * R3 + R2 * R3;
+    if (!(det > 0.0)) { out[0] = h * x0[1]; out[1] = h * x0[2]; return; }
+    const double d0 = xh[0] - x0[0], d2 = xh[2] - x0[2];
+    const double z1 = (R3 * d0 + I1 * d2) / det;
+    const double z2 = (I2 * d0 - (I1 + R2) * d2) / det;
+    const double v1 = h * (I1 * R3 / det) + z1, v2 = h * (I1 * I2 / det) + z2;
+    out[0] = v1 > 0.0 ? v1 : 0.0;
+    out[1] = v2 > 0.0 ? v2 : 0.0;
+}
+
 static void renormalise(double *a, int n)
 {
     double s = 0.0;
@@ -514,8 +614,9 @@ static void renormalise(double *a, int n)
  * fixed != NULL replaces the temperature-dependent rates, no_cool drops
  * every cooling and Compton term (both used only by closed-form tests).
  */
-void orc_update_cell_ex(const orc_grid *G, double dt, double nh, double x[5], double *T,
-                        const double acc[4], const orc_rates *fixed, int no_cool)
+void orc_update_cell_rx(const orc_grid *G, double dt, double nh, double x[5], double *T,
+                        const double acc[4], const orc_rates *fixed, int no_cool, int case_a,
+                        double rc[3])
 {
     const int he = G->y_he > 0.0;
     const double nhe = he ? G->y_he * nh : 0.0;
@@ -532,14 +633,31 @@ void orc_update_cell_ex(const orc_grid *G, double dt, double nh, double x[5], do
     const double h = dt / G->n_chem;
 
     orc_rates R;
-    if (fixed) R = *fixed; else orc_rates_at(*T, &R);
+    if (fixed) R = *fixed; else if (case_a) orc_rates_case_a(*T, &R); else orc_rates_at(*T, &R);
     for (int m = 0; m < G->n_chem; ++m) {
-        if (m > 0 && !fixed && !iso) orc_rates_at(*T, &R);   /* T moved: new rates */
+        if (m > 0 && !fixed && !iso) {                        /* T moved: new rates */
+            if (case_a) orc_rates_case_a(*T, &R); else orc_rates_at(*T, &R);
+        }
         const double ne0 = electrons(nh, nhe, x);
         double xp[5], xn[5];
         advance_fractions(xp, x, &R, gam, ne0, h, he);
         const double ne_bar = 0.5 * (ne0 + electrons(nh, nhe, xp));
         advance_fractions(xn, x, &R, gam, ne_bar, h, he);
+        if (rc) {
+            /* recombinations per atom over h (Sec. 2: N_rec is recorded by the
+             * network): rate coefficient times the time integral of the ion
+             * fraction along the corrector's solution */
+            const double rh = R.a_hii * ne_bar;
+            rc[0] += rh * orc_hii_time(x[1], xn[1], gam[0] + R.b_hi * ne_bar, rh, h);
+            if (he) {
+                const double r2 = R.a_heii * ne_bar, r3 = R.a_heiii * ne_bar;
+                double tm[2];
+                orc_he_ion_time(&x[2], &xn[2], gam[1] + R.b_hei * ne_bar, r2, gam[2] + R.b_heii * ne_bar,
+                            r3, h, tm);
+                rc[1] += r2 * tm[0];
+                rc[2] += r3 * tm[1];
+            }
+        }
         renormalise(&xn[0], 2);
         if (he) renormalise(&xn[2], 3);
         if (!iso) {
@@ -555,6 +673,12 @@ void orc_update_cell_ex(const orc_grid *G, double dt, double nh, double x[5], do
         }
         for (int i = 0; i < 5; ++i) x[i] = xn[i];
     }
+}
+
+void orc_update_cell_ex(const orc_grid *G, double dt, double nh, double x[5], double *T,
+                        const double acc[4], const orc_rates *fixed, int no_cool)
+{
+    orc_update_cell_rx(G, dt, nh, x, T, acc, fixed, no_cool, 0, NULL);
 }
 
 void orc_update_cell(const orc_grid *G, double dt, double nh, double x[5], double *T,
@@ -591,21 +715,147 @@ void orc_absorbers(const orc_grid *G, const double *nh, const double *x, double 
     }
 }
 
+/* Update with case-A rates and recombination counters rc [3][ncell]
+ * (recombinations per atom of HII, HeII, HeIII since the cell last emitted). */
+void orc_update_cells_rx(const orc_grid *G, double dt, const double *nh, double *x, double *T,
+                         const double *acc, double *rc)
+{
+    const int64_t ncell = (int64_t)G->n[0] * G->n[1] * G->n[2];
+    for (int64_t c = 0; c < ncell; ++c) {
+        double xc[5], a[4], r[3];
+        for (int f = 0; f < 5; ++f) xc[f] = x[f * ncell + c];
+        for (int f = 0; f < 4; ++f) a[f] = acc[f * ncell + c];
+        for (int f = 0; f < 3; ++f) r[f] = rc[f * ncell + c];
+        orc_update_cell_rx(G, dt, nh[c], xc, &T[c], a, NULL, 0, 1, r);
+        for (int f = 0; f < 5; ++f) x[f * ncell + c] = xc[f];
+        for (int f = 0; f < 3; ++f) rc[f * ncell + c] = r[f];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Recombination re-emission (Sec. 2; Sec. 3: pCRASH2 emits when a packet    */
+/* crosses a cell whose recombination count has reached f_rec N_a).          */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double f_rec;              /* threshold, recombinations per atom */
+    int32_t n_t;               /* temperature nodes of the spectrum table (>= 2) */
+    double log10_t0, dlog10_t; /* node m sits at log10 T = log10_t0 + m dlog10_t */
+    const double *milne;       /* [3][n_t][n_bins] photon fraction per bin of the
+                                  ground-state recombination continuum (Milne
+                                  spectrum) of HII, HeII, HeIII */
+} orc_reemit;
+
+/* Spectrum of ion `ion` at T: linear in log10 T between the table's nodes,
+ * clamped to the end nodes. */
+static void milne_at(const orc_reemit *E, int nb, int ion, double T, double *out)
+{
+    double u = (log10(T) - E->log10_t0) / E->dlog10_t;
+    const double top = (double)(E->n_t - 1);
+    if (!(u > 0.0)) u = 0.0;
+    if (u > top) u = top;
+    int m = (int)floor(u);
+    if (m > E->n_t - 2) m = E->n_t - 2;
+    const double f = u - (double)m;
+    const double *a = E->milne + ((size_t)ion * E->n_t + m) * nb, *b = a + nb;
+    for (int j = 0; j < nb; ++j) out[j] = (1.0 - f) * a[j] + f * b[j];
+}
+
+/*
+ * One sub-step's recombination emission, after the source packets have been
+ * marched (their deposits in acc, the crossing test) and before the cell
+ * update.  A cell crossed by a source packet in this sub-step (some photons
+ * deposited in it) emits one diffuse packet holding, for every ion whose
+ * counter is positive and at least f_rec, counter x atoms x ground-state share
+ * photons with that ion's Milne spectrum at the cell's temperature; those
+ * counters restart from zero.  The packet leaves the cell centre in an
+ * isotropic direction (stream word 1, g = the cell's natural index) and is
+ * marched like a source packet.  Returns the number of diffuse packets.
+ */
+int64_t orc_reemit_substep(const orc_grid *G, const orc_reemit *E, const double *nh, const double *T,
+                           const double *kappa, double *rc, uint64_t seed, uint64_t solve_id,
+                           uint64_t step_index, double *acc, double *ledger)
+{
+    const int64_t ncell = (int64_t)G->n[0] * G->n[1] * G->n[2];
+    const int nb = G->n_bins;
+    const int ions = G->y_he > 0.0 ? 3 : 1;
+    const double y = G->y_he > 0.0 ? G->y_he : 0.0;
+    const double V = G->cell_cm * G->cell_cm * G->cell_cm;
+    int64_t *list = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ncell > 0 ? ncell : 1));
+    double *wl = (double *)malloc(sizeof(double) * (size_t)(ncell > 0 ? ncell : 1));
+    double *sl = (double *)malloc(sizeof(double) * (size_t)(ncell > 0 ? ncell : 1) * nb);
+    int64_t ne = 0;
+    /* first every emitter, from the source packets' deposits alone */
+    for (int64_t c = 0; c < ncell; ++c) {
+        if (!(acc[c] > 0.0 || acc[ncell + c] > 0.0 || acc[2 * ncell + c] > 0.0)) continue;
+        double p[3], ph[3] = {0.0, 0.0, 0.0};
+        int any = 0;
+        orc_ground_fraction(T[c], p);
+        const double atoms[3] = {nh[c] * V, (y * nh[c]) * V, (y * nh[c]) * V};
+        for (int a = 0; a < ions; ++a) {
+            const double r = rc[a * ncell + c];
+            if (r > 0.0 && r >= E->f_rec) {
+                ph[a] = (r * atoms[a]) * p[a];
+                rc[a * ncell + c] = 0.0;
+                any = 1;
+            }
+        }
+        const double w = (ph[0] + ph[1]) + ph[2];
+        if (!any || !(w > 0.0)) continue;         /* no ionising photon among them: no packet */
+        double *sed = sl + ne * nb;
+        for (int j = 0; j < nb; ++j) sed[j] = 0.0;
+        for (int a = 0; a < ions; ++a) {
+            if (!(ph[a] > 0.0)) continue;
+            double m[ORC_MAX_BINS];
+            milne_at(E, nb, a, T[c], m);
+            for (int j = 0; j < nb; ++j) sed[j] += ph[a] * m[j];
+        }
+        for (int j = 0; j < nb; ++j) sed[j] = sed[j] / w;
+        list[ne] = c;
+        wl[ne] = w;
+        ++ne;
+    }
+    /* then their packets */
+    double heat_ev[3][ORC_MAX_BINS];
+    heat_table(G, heat_ev);
+    for (int64_t e = 0; e < ne; ++e) {
+        const int64_t c = list[e];
+        const int64_t k0 = c % G->n[0], k1 = (c / G->n[0]) % G->n[1], k2 = c / ((int64_t)G->n[0] * G->n[1]);
+        const int32_t o[3] = {(int32_t)(2 * k0 + 1), (int32_t)(2 * k1 + 1), (int32_t)(2 * k2 + 1)};
+        int32_t dir[3];
+        orc_direction_ex(seed, solve_id, (uint64_t)c, step_index, 0, 1, dir);
+        const double *sed = sl + e * nb;
+        double carried = 0.0;
+        for (int j = 0; j < nb; ++j) carried += sed[j];
+        nsum(&ledger[L_EMIT], &ledger[L_EMIT + 1], wl[e] * carried);
+        nsum(&ledger[L_DEMIT], &ledger[L_DEMIT + 1], wl[e] * carried);
+        ledger[L_PACKETS] += 1.0;
+        ledger[L_DPACKETS] += 1.0;
+        march_packet(G, kappa, heat_ev, wl[e], sed, o, dir, acc, ledger, 0, NULL);
+    }
+    free(list);
+    free(wl);
+    free(sl);
+    return ne;
+}
+
 /*
  * One call = n_sub frozen sub-steps of dt / n_sub, the packets shared as
  * evenly as possible (the first P mod n_sub sub-steps get one more).  Each
  * sub-step: absorbers, zeroed accumulators, march of every packet in id order,
- * cell update.  *step_index is the Philox sub-step counter, advanced once per
- * sub-step.  acc holds the last sub-step's deposits on return; ledger
- * accumulates over all sub-steps; trace (if given) records the last sub-step.
+ * [with E: recombination emission and the march of its packets,] cell update
+ * (with E: case-A rates and the counters rc [3][ncell]).  *step_index is the
+ * Philox sub-step counter, advanced once per sub-step.  acc holds the last
+ * sub-step's deposits on return; ledger accumulates over all sub-steps; trace
+ * (if given) records the last sub-step's source packets.
  * Returns 0, or -1 if some sub-step has fewer packets than sources.
  */
-int orc_step(const orc_grid *G, const double *nh, double *x, double *T,
-             int32_t n_src, const int32_t *src_ijk, const double *src_ndot,
-             const double *src_sed, uint32_t src_flags,
-             double dt, int64_t P, int32_t n_sub, uint64_t seed, uint64_t solve_id,
-             uint64_t *step_index, double *acc, double *kappa, double *ledger,
-             int32_t trace_n, int32_t trace_len, int32_t trace_stride, int32_t *trace)
+int orc_step_rx(const orc_grid *G, const double *nh, double *x, double *T,
+                int32_t n_src, const int32_t *src_ijk, const double *src_ndot,
+                const double *src_sed, uint32_t src_flags,
+                double dt, int64_t P, int32_t n_sub, uint64_t seed, uint64_t solve_id,
+                uint64_t *step_index, double *acc, double *kappa, double *ledger,
+                int32_t trace_n, int32_t trace_len, int32_t trace_stride, int32_t *trace,
+                const orc_reemit *E, double *rc)
 {
     const int64_t ncell = (int64_t)G->n[0] * G->n[1] * G->n[2];
     if (n_src > 0 && P / n_sub < n_src) return -1;
@@ -618,8 +868,25 @@ int orc_step(const orc_grid *G, const double *nh, double *x, double *T,
             orc_march(G, kappa, n_src, src_ijk, src_ndot, src_sed, src_flags, dts, Pi,
                       seed, solve_id, *step_index, 0, Pi, acc, ledger, trace_n, trace_len,
                       trace_stride, trace);
-        orc_update_cells(G, dts, nh, x, T, acc, ncell, NULL);
+        if (E) {
+            orc_reemit_substep(G, E, nh, T, kappa, rc, seed, solve_id, *step_index, acc, ledger);
+            orc_update_cells_rx(G, dts, nh, x, T, acc, rc);
+        } else {
+            orc_update_cells(G, dts, nh, x, T, acc, ncell, NULL);
+        }
         *step_index += 1;
     }
     return 0;
+}
+
+int orc_step(const orc_grid *G, const double *nh, double *x, double *T,
+             int32_t n_src, const int32_t *src_ijk, const double *src_ndot,
+             const double *src_sed, uint32_t src_flags,
+             double dt, int64_t P, int32_t n_sub, uint64_t seed, uint64_t solve_id,
+             uint64_t *step_index, double *acc, double *kappa, double *ledger,
+             int32_t trace_n, int32_t trace_len, int32_t trace_stride, int32_t *trace)
+{
+    return orc_step_rx(G, nh, x, T, n_src, src_ijk, src_ndot, src_sed, src_flags, dt, P, n_sub, seed,
+                       solve_id, step_index, acc, kappa, ledger, trace_n, trace_len, trace_stride, trace,
+                       NULL, NULL);
 }

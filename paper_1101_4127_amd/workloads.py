@@ -141,6 +141,77 @@ def blackbody_table(t_bb: float = 1.0e5, edges_ev=None) -> BinTable:
 # ----------------------------------------------------------------------------
 # Gas fields
 # ----------------------------------------------------------------------------
+@dataclasses.dataclass
+class RecombEmission:
+    """Inputs of recombination re-emission: the threshold and the per-bin
+    spectra of the ground-state recombination photons of HII, HeII and HeIII
+    on a grid of temperatures (node m at log10 T = log10_t0 + m dlog10_t)."""
+    f_rec: float
+    log10_t0: float
+    dlog10_t: float
+    milne: np.ndarray         # (3, n_t, nb) photon fraction per bin; rows sum to 1
+
+    @property
+    def n_t(self) -> int:
+        return int(self.milne.shape[1])
+
+
+def milne_table(bins: BinTable, log10_t0: float = 1.0, log10_t1: float = 9.0,
+                per_decade: int = 16) -> np.ndarray:
+    """Photon fractions per bin of the recombination continuum to the ground
+    state of HI, HeI and HeII (from HII, HeII, HeIII) at each temperature node.
+
+    Milne relation (detailed balance with photo-ionisation): the photon-number
+    spectrum above the threshold E0 is dN/dE ~ E^2 sigma(E) exp(-(E - E0)/kT),
+    sigma the Verner fit of the recombined species.  Fractions are taken over
+    the bins' covered range [E0, last edge] (adaptive quadrature in
+    x = (E - E0)/kT, float64); fractions below 1e-12 are set to zero and the
+    rest renormalised.  A table without edges (one bin) sends every photon to
+    that bin."""
+    from scipy.integrate import quad
+
+    nt = int(round((log10_t1 - log10_t0) * per_decade)) + 1
+    nb = bins.n_bins
+    out = np.zeros((3, nt, nb))
+    if bins.edges_ev is None:
+        if nb != 1:
+            raise ValueError("a multi-bin table needs bin edges")
+        out[:] = 1.0
+        return out
+    edges = np.asarray(bins.edges_ev, np.float64)
+    top = float(edges[-1])
+    for a in range(3):
+        e0 = E_TH_EV[a]
+        for m in range(nt):
+            kt = K_B * 10.0 ** (log10_t0 + m / per_decade) / EV_ERG
+
+            def f(x):
+                e = e0 + kt * x
+                return e * e * float(verner_sigma(a, e)) * math.exp(-x)
+
+            part = np.zeros(nb)
+            for j in range(nb):
+                lo, hi = max(float(edges[j]), e0), min(float(edges[j + 1]), top)
+                if hi <= lo:
+                    continue
+                xlo, xhi = (lo - e0) / kt, min((hi - e0) / kt, 800.0)
+                if xhi <= xlo:
+                    continue
+                part[j] = quad(f, xlo, xhi, epsabs=0.0, epsrel=1e-12, limit=400)[0]
+            tot = part.sum()
+            if tot > 0.0:
+                part = part / tot
+                part[part < 1e-12] = 0.0          # photons that cannot matter: no bin kept alive for them
+                out[a, m] = part / part.sum()
+    return out
+
+
+def with_recombination(w: "Workload", f_rec: float = 0.1) -> "Workload":
+    """The same workload with recombination photons re-emitted as packets."""
+    t0, per = 1.0, 16
+    return w.with_(recomb=RecombEmission(float(f_rec), t0, 1.0 / per, milne_table(w.bins, t0, 9.0, per)))
+
+
 def lognormal_field(n: int, sigma_ln: float, mean: float, seed: int) -> np.ndarray:
     """Seeded lognormal density, natural order (i fastest), float64 values
     that are exactly float32-representable.
@@ -210,6 +281,7 @@ class Workload:
     flags: int = 0
     seed: int = 1
     solve_id: int = 0
+    recomb: Optional[RecombEmission] = None   # recombination re-emission (None: off)
 
     @property
     def ncell(self) -> int:
@@ -262,6 +334,30 @@ def thermal_test2(n: int = 32, packets: int = 100000, steps: int = 5, n_sub: int
         src_sed=bins.sed[None, :].copy(), src_flags=SRC_CORNER_OCTANT,
         dt_s=10.0 * MYR_S, packets=packets, steps=steps, n_sub=n_sub, n_chem=8,
         flags=(FP64_MARCH if fp64 else 0), seed=1)
+
+
+def stromgren_reemit(n: int = 32, packets: int = 100000, steps: int = 10, n_sub: int = 10,
+                     f_rec: Optional[float] = 0.1, fp64: bool = True, box_kpc: float = 17.3) -> Workload:
+    """Test 0's gas (uniform pure H, n_H = 1e-3, isothermal 1e4 K, initially
+    neutral) around one 5e48 ph/s source with a 1e5 K black-body spectrum in 8
+    bins, with recombination photons re-emitted at threshold f_rec (Sec. 4.1
+    uses 10 %).  The source sits at the centre cell of the box (not a corner),
+    so diffuse photons are not lost through symmetry planes; the box (17.3 kpc
+    on 32 cells) puts the case-B Stroemgren radius near 10 cells.  50 Myr steps,
+    10 steps = 500 Myr (Test 0's simulated time, about four recombination
+    times).  f_rec None: case-B rates and no re-emission."""
+    box = box_kpc * KPC_CM
+    ncell = n ** 3
+    x, t = _neutral_state(ncell, 1.0e4)
+    bins = blackbody_table(1.0e5)
+    w = Workload(
+        name=f"stromgren_reemit_{n}^3", n=(n, n, n), cell_cm=box / n, y_he=0.0, bins=bins,
+        redshift=-1.0, n_h=np.full(ncell, 1.0e-3), x=x, temp=t,
+        src_ijk=np.full((1, 3), n // 2, np.int32), src_ndot=np.array([5.0e48]),
+        src_sed=bins.sed[None, :].copy(), src_flags=0,
+        dt_s=50.0 * MYR_S, packets=packets, steps=steps, n_sub=n_sub, n_chem=8,
+        flags=ISOTHERMAL | (FP64_MARCH if fp64 else 0), seed=1)
+    return w if f_rec is None else with_recombination(w, f_rec)
 
 
 def blackbody_photon_rate(luminosity_erg_s: float, t_bb: float, lo_ev: float = 13.6,

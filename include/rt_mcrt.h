@@ -62,6 +62,17 @@ extern "C" {
                                deposits gathered per tile in on-chip memory,
                                packets handed between tiles pass by pass).
                                Both give the same packet histories. */
+#define RT_RECOMB 0x10u     /* recombination re-emission (Sec. 2; Sec. 3, pCRASH2):
+                               case-A recombination in the cell update, which
+                               also counts each cell's recombinations per atom
+                               of HII, HeII and HeIII; in every sub-step, after
+                               the source packets, each cell they deposited in
+                               whose counters have reached the threshold emits
+                               one packet of ground-state recombination photons
+                               (Milne spectrum), marched before the update.
+                               Needs rt_set_recombination before rt_step; not
+                               with RT_DIRECT_MARCH.  The workspace then holds
+                               one packet record per cell at least. */
 
 /* rt_add_sources src_flags */
 #define RT_SRC_CORNER_OCTANT 0x1u /* source at the lowest corner of its cell,
@@ -80,7 +91,13 @@ extern "C" {
 #define RT_F_DHEI 0x100u   /* ... by HeI */
 #define RT_F_DHEII 0x200u  /* ... by HeII */
 #define RT_F_Q 0x400u      /* photo-heating energy [erg] of the last sub-step */
-#define RT_F_ALL 0x7ffu
+#define RT_F_RHII 0x800u   /* RT_RECOMB: HII recombinations per H atom since the
+                              cell last emitted (0 without RT_RECOMB) */
+#define RT_F_RHEII 0x1000u /* ... HeII recombinations per He atom */
+#define RT_F_RHEIII 0x2000u /* ... HeIII recombinations per He atom */
+#define RT_F_ALL 0x3fffu
+
+#define RT_MAX_MILNE_T 512  /* temperature nodes of a recombination spectrum table */
 
 /* trace record: RT_TRACE_HDR int32 words then trace_len cell indices */
 #define RT_TRACE_HDR 8
@@ -156,6 +173,9 @@ typedef struct {
     double kernel_ms;   /* RT_TIME_MARCH: summed time of the march kernel's own
                            launches (tiled march: one per pass), else 0 */
     int64_t kernel_launches; /* launches timed in kernel_ms */
+    double diffuse_emitted; /* RT_RECOMB: recombination photons emitted (part of
+                               emitted), else 0 */
+    int64_t diffuse_packets; /* RT_RECOMB: recombination packets (part of packets) */
 } rt_step_stats;
 
 /* Fill *d with defaults: 1 bin, tau_kill 30, n_sub 1, n_chem 8, redshift -1,
@@ -196,6 +216,30 @@ int32_t rt_add_sources(rt_solve_t h, int32_t n, const int32_t *h_ijk, const doub
  * a solve without sources runs the cell update only.  Stream-ordered and
  * asynchronous; if stats is not NULL the call synchronises and fills it. */
 int32_t rt_step(rt_solve_t h, double dt_s, int64_t n_packets, uint64_t seed, rt_step_stats *stats);
+
+/* Recombination re-emission inputs of a solve created with RT_RECOMB (Sec. 2:
+ * a cell emits once its recombinations reach f_rec N_a; Sec. 3: on a crossing).
+ *   f_rec        threshold in recombinations per atom (>= 0; a counter must
+ *                also be positive to emit)
+ *   n_t, log10_t0, dlog10_t
+ *                temperature nodes of the spectrum table: node k at
+ *                log10 T = log10_t0 + k dlog10_t, 2 <= n_t <= RT_MAX_MILNE_T;
+ *                the spectrum at T is linear in log10 T between nodes, clamped
+ *                to the end nodes
+ *   h_milne      host [3][n_t][n_bins]: photon fraction per bin of the ground-
+ *                state recombination continuum of HII, HeII, HeIII (each row
+ *                >= 0, summing to 1; zero in bins below the ion's threshold)
+ *   d_counters   device [species][ncell] initial counters in natural order
+ *                (species 1 for pure hydrogen, else 3), float64 or float32 per
+ *                counters_fp64; NULL: all zero
+ * Each photon packet from a cell carries, for every ion whose counter is
+ * positive and >= f_rec, counter x atoms x (alpha_A - alpha_B)/alpha_A photons
+ * with that ion's spectrum at the cell temperature; those counters restart at
+ * zero.  Its direction is isotropic (Philox stream word 1, counter word 0 the
+ * cell's natural index) from the cell centre.  Returns RT_ESTATE for a solve
+ * created without RT_RECOMB.  Synchronous. */
+int32_t rt_set_recombination(rt_solve_t h, double f_rec, int32_t n_t, double log10_t0, double dlog10_t,
+                             const double *h_milne, const void *d_counters, int32_t counters_fp64);
 
 /* Synchronise the handle's stream and return the ledger of the last rt_step. */
 int32_t rt_read_stats(rt_solve_t h, rt_step_stats *stats);

@@ -297,8 +297,11 @@ static void march_packet(const orc_grid *G, const double *kappa, const double he
             for (int s = 0; s < 3; ++s) part[s] = kap[s] * G->sigma[s][j];
             const double ksum = (part[0] + part[1]) + part[2];
             const double tau = l * ksum;
+            /* Eq. (1): absorbed f (1 - e^-tau), transmitted f e^-tau; each
+               from its own function (f - d would leave an opaque cell's
+               transmitted remainder without a correct digit) */
             const double d = f[j] * (-expm1(-tau));
-            f[j] = f[j] - d;
+            f[j] = f[j] * exp(-tau);
             T[j] = T[j] + tau;
             const double nabs = sed[j] * d;
             absorbed += nabs;

@@ -37,6 +37,8 @@ struct Plan {
     size_t real;
     size_t off_state, off_kappa, off_acc, off_src, off_ndot, off_sedsum, off_sed, off_tab, off_slots,
         off_ledger, off_queue, off_trace, off_stage, total;
+    bool recomb;            // recombination photons re-emitted as packets
+    size_t off_rc, off_milne;
     // tiled march
     uint32_t capacity, cmax, max_chunks, n_tiles, scan_blocks, passes, park_passes, park_lanes;
     size_t rec_bytes;
@@ -63,7 +65,9 @@ int32_t validate_desc(const rt_grid_desc *d) {
     if (!isfinite(d->redshift)) return RT_EINVAL;
     if (!(isfinite(d->tau_kill) && d->tau_kill > 0.0)) return RT_EINVAL;
     if (d->n_sub < 1 || d->n_chem < 1) return RT_EINVAL;
-    if (d->flags & ~(RT_ISOTHERMAL | RT_FP64 | RT_TIME_MARCH | RT_DIRECT_MARCH)) return RT_EINVAL;
+    if (d->flags & ~(RT_ISOTHERMAL | RT_FP64 | RT_TIME_MARCH | RT_DIRECT_MARCH | RT_RECOMB)) return RT_EINVAL;
+    // recombination packets are marched by the tiled march only
+    if ((d->flags & RT_RECOMB) && (d->flags & RT_DIRECT_MARCH)) return RT_EINVAL;
     if (d->brick_log2 < -1 || d->brick_log2 > 3) return RT_EINVAL;
     // the tiled march's tiles are the bricks of side 8
     if (!(d->flags & RT_DIRECT_MARCH) && d->brick_log2 != -1 && d->brick_log2 != 3) return RT_EINVAL;
@@ -120,13 +124,21 @@ int32_t make_plan(const rt_grid_desc *d, int64_t max_sources, Plan *p) {
     p->off_trace = o;
     o = align_up(o + (size_t)d->trace_packets * (RT_TRACE_HDR + (size_t)d->trace_len) * sizeof(int32_t));
     p->off_stage = o; o = align_up(o + (size_t)p->ncell * sizeof(double));
+    p->recomb = (d->flags & RT_RECOMB) != 0;
+    p->off_rc = p->off_milne = 0;
+    if (p->recomb) {
+        p->off_rc = o; o = align_up(o + (size_t)p->species * np * sizeof(double));
+        p->off_milne = o; o = align_up(o + 3 * (size_t)RT_MAX_MILNE_T * p->mb * sizeof(double));
+    }
     p->capacity = p->cmax = p->max_chunks = p->n_tiles = p->scan_blocks = p->passes = 0;
     p->park_passes = p->park_lanes = 0;
     p->rec_bytes = 0;
     p->off_rec = p->off_idx0 = p->off_idx1 = p->off_side = p->off_cnt = p->off_off = p->off_cbase = p->off_bsum =
         p->off_ch0 = p->off_ch1 = p->off_ctrl = 0;
     if (p->tiled) {
-        const uint64_t cap = (uint64_t)(d->inflight > 0 ? d->inflight : kDefaultInflight);
+        uint64_t cap = (uint64_t)(d->inflight > 0 ? d->inflight : kDefaultInflight);
+        // a sub-step's recombination packets (at most one per cell) form one batch
+        if (p->recomb && cap < (uint64_t)p->ncell) cap = (uint64_t)p->ncell;
         const uint64_t nt = (uint64_t)g.nb[0] * g.nb[1] * g.nb[2];
         p->capacity = (uint32_t)cap;
         p->cmax = (uint32_t)(d->run_len > 0 ? d->run_len : kDefaultRun);
@@ -209,6 +221,10 @@ struct rt_solve {
     int timed;
     std::vector<hipEvent_t> kev;
     int ktimed;
+    // recombination re-emission (RT_RECOMB), set by rt_set_recombination
+    bool recomb_set;
+    double f_rec, log10_t0, dlog10_t;
+    int32_t n_t;
 };
 
 namespace {
@@ -279,8 +295,26 @@ rtk::CellLaunch cell_launch(rt_solve_t h, double dt) {
     c.n_chem = h->d.n_chem;
     c.queue = reinterpret_cast<unsigned long long *>(h->ws + p.off_queue);
     c.ledger = reinterpret_cast<rtk::StepLedger *>(h->ws + p.off_ledger);
+    c.rc = p.recomb ? reinterpret_cast<double *>(h->ws + p.off_rc) : nullptr;
     c.stream = h->stream;
     return c;
+}
+
+rtk::RecombParams recomb_params(rt_solve_t h) {
+    const Plan &p = h->plan;
+    rtk::RecombParams r;
+    r.rc = reinterpret_cast<double *>(h->ws + p.off_rc);
+    r.milne = reinterpret_cast<const double *>(h->ws + p.off_milne);
+    r.state = h->ws + p.off_state;
+    r.n_t = h->n_t;
+    r.acc_stride = p.acc_stride;
+    r.log10_t0 = h->log10_t0;
+    r.dlog10_t = h->dlog10_t;
+    r.f_rec = h->f_rec;
+    r.volume = h->d.cell_cm * h->d.cell_cm * h->d.cell_cm;
+    r.y_he = h->d.y_he;
+    r.ledger = reinterpret_cast<rtk::StepLedger *>(h->ws + p.off_ledger);
+    return r;
 }
 
 }  // namespace
@@ -352,6 +386,9 @@ int32_t rt_init_grid(const rt_grid_desc *d, void *d_ws, size_t ws_bytes, int64_t
     h->dead = false;
     h->timed = 0;
     h->ktimed = 0;
+    h->recomb_set = false;
+    h->f_rec = h->log10_t0 = h->dlog10_t = 0.0;
+    h->n_t = 0;
     if (d->flags & RT_TIME_MARCH) {
         h->ev.resize(2 * kMaxTimedSubsteps);
         h->kev.resize(p.tiled ? 2 * kMaxTimedKernels : 0);
@@ -376,6 +413,7 @@ int32_t rt_init_grid(const rt_grid_desc *d, void *d_ws, size_t ws_bytes, int64_t
         hipStreamSynchronize(h->stream) != hipSuccess ||
         rtk::launch_import(c, d_nh, d_x, d_temp, fields_fp64, p.ncell) != hipSuccess ||
         rtk::launch_ledger_zero(c.ledger, h->stream) != hipSuccess ||
+        (p.recomb && rtk::launch_import_counters(c, nullptr, 1, p.ncell) != hipSuccess) ||
         (p.tiled && rtk::launch_tiled_reset(tiled_launch(h, tiled_base(h))) != hipSuccess)) {
         for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
         for (hipEvent_t e : h->kev) (void)hipEventDestroy(e);
@@ -456,6 +494,8 @@ int32_t rt_read_stats(rt_solve_t h, rt_step_stats *stats) {
     stats->substeps = (int64_t)l.substeps;
     stats->nonfinite = l.nonfinite;
     stats->errors = l.errors;
+    stats->diffuse_emitted = l.d_emit;
+    stats->diffuse_packets = (int64_t)l.d_packets;
     stats->march_ms = 0.0;
     for (int i = 0; i < h->timed; ++i) {
         float ms = 0.0f;
@@ -489,6 +529,7 @@ int32_t rt_step(rt_solve_t h, double dt_s, int64_t n_packets, uint64_t seed, rt_
     const int32_t nsub = h->d.n_sub;
     const int64_t base = n_packets / nsub, extra = n_packets % nsub;
     if (h->n_src > 0 && base < h->n_src) return RT_EINVAL;
+    if (h->plan.recomb && !h->recomb_set) return RT_ESTATE;
     if (base + 1 > ((int64_t)1 << 31)) return RT_EOVERFLOW;
     const Plan &p = h->plan;
     const double dts = dt_s / nsub;
@@ -553,6 +594,7 @@ int32_t rt_step(rt_solve_t h, double dt_s, int64_t n_packets, uint64_t seed, rt_
                     t.nbatch = (uint32_t)(Pi - g0 < (int64_t)p.capacity ? Pi - g0 : p.capacity);
                     if (rtk::launch_tiled_batch(t) != hipSuccess) return fail(h);
                 }
+                if (p.recomb && rtk::launch_tiled_reemit(t, recomb_params(h)) != hipSuccess) return fail(h);
             } else if (rtk::launch_march(m) != hipSuccess) {
                 return fail(h);
             }
@@ -584,7 +626,7 @@ int32_t rt_fetch_fields(rt_solve_t h, uint32_t mask, void *dst, int32_t dst_is_d
     } else {
         void *stage = h->ws + p.off_stage;
         char *out = reinterpret_cast<char *>(dst);
-        for (int f = 0; f < 11; ++f) {
+        for (int f = 0; f < 14; ++f) {
             if (!(mask & (1u << f))) continue;
             if (rtk::launch_export(c, 1u << f, stage, as_fp64, p.ncell) != hipSuccess ||
                 hipMemcpyAsync(out, stage, (size_t)p.ncell * esz, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
@@ -594,6 +636,44 @@ int32_t rt_fetch_fields(rt_solve_t h, uint32_t mask, void *dst, int32_t dst_is_d
         }
     }
     if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(h);
+    return RT_OK;
+}
+
+int32_t rt_set_recombination(rt_solve_t h, double f_rec, int32_t n_t, double log10_t0, double dlog10_t,
+                             const double *h_milne, const void *d_counters, int32_t counters_fp64) {
+    if (!valid(h)) return RT_EINVAL;
+    if (h->dead) return RT_ESTATE;
+    const Plan &p = h->plan;
+    if (!p.recomb) return RT_ESTATE;
+    if (!(isfinite(f_rec) && f_rec >= 0.0) || n_t < 2 || n_t > RT_MAX_MILNE_T || !isfinite(log10_t0) ||
+        !(isfinite(dlog10_t) && dlog10_t > 0.0) || !h_milne || (counters_fp64 != 0 && counters_fp64 != 1))
+        return RT_EINVAL;
+    const int nb = h->d.n_bins, mb = p.mb;
+    std::vector<double> tab(3 * (size_t)n_t * mb, 0.0);
+    for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < n_t; ++k) {
+            double sum = 0.0;
+            for (int j = 0; j < nb; ++j) {
+                const double v = h_milne[((size_t)a * n_t + k) * nb + j];
+                if (!finite_nonneg(v)) return RT_EINVAL;
+                // no photons of an ion in a bin that is not above its threshold
+                if (v > 0.0 && h->d.e_bin_ev[j] < kThresholdEv[a] && nb > 1) return RT_EINVAL;
+                tab[((size_t)a * n_t + k) * mb + j] = v;
+                sum += v;
+            }
+            if (!(fabs(sum - 1.0) <= 1.0e-9)) return RT_EINVAL;
+        }
+    rtk::CellLaunch c = cell_launch(h, 0.0);
+    if (hipMemcpyAsync(h->ws + p.off_milne, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice,
+                       h->stream) != hipSuccess ||
+        rtk::launch_import_counters(c, d_counters, counters_fp64, p.ncell) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+        return fail(h);
+    h->f_rec = f_rec;
+    h->n_t = n_t;
+    h->log10_t0 = log10_t0;
+    h->dlog10_t = dlog10_t;
+    h->recomb_set = true;
     return RT_OK;
 }
 
@@ -823,7 +903,8 @@ int32_t rt_step_many(rt_batch_t b, const rt_solve_t *solves, int32_t n, const do
         for (int k = 0; k < i; ++k)
             if (solves[k] == h) return RT_EINVAL;
         const Plan &p = h->plan;
-        if (h->device != b->device || p.species != 1 || p.mb != 1 || h->d.trace_packets > 0) return RT_EINVAL;
+        if (h->device != b->device || p.species != 1 || p.mb != 1 || h->d.trace_packets > 0 || p.recomb)
+            return RT_EINVAL;
         if ((fp64 >= 0 && p.fp64 != fp64) || (thermal >= 0 && p.thermal != thermal)) return RT_EINVAL;
         fp64 = p.fp64;
         thermal = p.thermal;

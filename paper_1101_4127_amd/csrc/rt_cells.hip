@@ -9,6 +9,7 @@
 
 #include "rt_device.h"
 #include "rt_internal.h"
+#include "rt_recomb.h"
 
 namespace rtk {
 
@@ -61,7 +62,8 @@ __global__ void __launch_bounds__(kCellBlock) k_prep(GridGeom G, const R *__rest
 // ---------------------------------------------------------------------------
 // Rates (cgs).  Recombination: case B of Hui & Gnedin (1997) for HII and
 // HeIII (the hydrogenic form scaled by Z = 2), their HeII fit plus dielectronic
-// recombination; collisional ionisation and cooling after Cen (1992);
+// recombination (case A of the same fits when recombination photons are
+// followed as packets); collisional ionisation and cooling after Cen (1992);
 // bremsstrahlung with a temperature-dependent Gaunt factor; Compton exchange
 // with the CMB.
 // ---------------------------------------------------------------------------
@@ -70,19 +72,20 @@ struct Rates {
     double col_hi, col_hei, col_heii;      // cm^3 / s
 };
 
-__device__ double hydrogenic_caseb(double T, double t_ion) {
-    const double lam = 2.0 * t_ion / T;
-    return 2.753e-14 * pow(lam, 1.5) / pow(1.0 + pow(lam / 2.740, 0.407), 2.242);
-}
-
-__device__ Rates rates_at(double T) {
+__device__ Rates rates_at(double T, bool case_a = false) {
     Rates r;
     const double damp = 1.0 / (1.0 + sqrt(T * 1.0e-5));
     const double rt = sqrt(T);
-    r.rec_hii = hydrogenic_caseb(T, 157807.0);
-    r.rec_heiii = 2.0 * hydrogenic_caseb(T, 631515.0);
-    const double diel = 1.9e-3 * pow(T, -1.5) * exp(-470000.0 / T) * (1.0 + 0.3 * exp(-94000.0 / T));
-    r.rec_heii = 1.26e-14 * pow(570670.0 / T, 0.750) + diel;
+    if (case_a) {
+        r.rec_hii = hydrogenic_casea(T, 157807.0);
+        r.rec_heiii = 2.0 * hydrogenic_casea(T, 631515.0);
+        r.rec_heii = heii_rad_casea(T) + heii_dielectronic(T);
+    } else {
+        r.rec_hii = hydrogenic_caseb(T, 157807.0);
+        r.rec_heiii = 2.0 * hydrogenic_caseb(T, 631515.0);
+        const double diel = 1.9e-3 * pow(T, -1.5) * exp(-470000.0 / T) * (1.0 + 0.3 * exp(-94000.0 / T));
+        r.rec_heii = 1.26e-14 * pow(570670.0 / T, 0.750) + diel;
+    }
     r.col_hi = 5.85e-11 * rt * exp(-157809.1 / T) * damp;
     r.col_hei = 2.38e-11 * rt * exp(-285335.4 / T) * damp;
     r.col_heii = 5.68e-12 * rt * exp(-631515.0 / T) * damp;
@@ -182,11 +185,15 @@ struct UpdateConst {
 };
 
 // The update of slot s (padding slots outside the grid are left alone); bad is
-// set when a result is not finite.
+// set when a result is not finite.  rc non-null: case-A rates, and the
+// recombinations per atom of each ion over the sub-step are added to its
+// counters (rate times the time integral of the ion fraction along the
+// corrector's solution).
 template <typename R, int S, bool TH>
 __device__ __forceinline__ void update_slot(const GridGeom &G, R *__restrict__ st, const double *__restrict__ acc,
                                             int acc_stride, double y_he, double dt, int n_chem,
-                                            const UpdateConst &u, uint32_t s, unsigned int &bad) {
+                                            const UpdateConst &u, uint32_t s, unsigned int &bad,
+                                            double *__restrict__ rc = nullptr) {
     constexpr bool he = (S == 3);
     const uint32_t np = G.ncell_pad;
     const double V = u.V, kb = u.kb, tcmb = u.tcmb, ccomp = u.ccomp, h = u.h;
@@ -210,14 +217,30 @@ __device__ __forceinline__ void update_slot(const GridGeom &G, R *__restrict__ s
         for (int q = 0; q < 3; ++q)
             gam[q] = (dep[q] > 0.0 && absorbers[q] > 0.0) ? dep[q] / (absorbers[q] * V * dt) : 0.0;
         const double heat = qheat / (V * dt);
-        Rates r = rates_at(T);
+        const bool count = rc != nullptr;
+        double n_rec[3] = {0.0, 0.0, 0.0};
+        if (count)
+            for (int q = 0; q < S; ++q) n_rec[q] = rc[(size_t)q * np + s];
+        Rates r = rates_at(T, count);
         for (int m = 0; m < n_chem; ++m) {
-            if (TH && m > 0) r = rates_at(T);
+            if (TH && m > 0) r = rates_at(T, count);
             const double ne0 = nh * x.hii + nhe * (x.heii + 2.0 * x.heiii);
             Frac xp, xn;
             evolve(xp, x, r, gam, ne0, h, he);
             const double ne_bar = 0.5 * (ne0 + (nh * xp.hii + nhe * (xp.heii + 2.0 * xp.heiii)));
             evolve(xn, x, r, gam, ne_bar, h, he);
+            if (count) {
+                const double rh = r.rec_hii * ne_bar;
+                n_rec[0] += rh * hii_time(x.hii, xn.hii, gam[0] + r.col_hi * ne_bar, rh, h);
+                if (he) {
+                    const double r2 = r.rec_heii * ne_bar, r3 = r.rec_heiii * ne_bar;
+                    double t2, t3;
+                    he_ion_time(x.hei, x.heii, x.heiii, xn.hei, xn.heii, xn.heiii, gam[1] + r.col_hei * ne_bar, r2,
+                                gam[2] + r.col_heii * ne_bar, r3, h, t2, t3);
+                    n_rec[1] += r2 * t2;
+                    n_rec[2] += r3 * t3;
+                }
+            }
             // clamp and renormalise each element's fractions
             xn.hi = fmax(xn.hi, 0.0); xn.hii = fmax(xn.hii, 0.0);
             const double sh = xn.hi + xn.hii;
@@ -245,19 +268,25 @@ __device__ __forceinline__ void update_slot(const GridGeom &G, R *__restrict__ s
             if (!isfinite(vals[q])) bad = 1;
             st[(size_t)(q + 1) * np + s] = (R)vals[q];
         }
+        if (count)
+            for (int q = 0; q < S; ++q) {
+                if (!isfinite(n_rec[q])) bad = 1;
+                rc[(size_t)q * np + s] = n_rec[q];
+            }
     }
 }
 
 template <typename R, int S, bool TH>
 __global__ void __launch_bounds__(kCellBlock) k_update(GridGeom G, R *__restrict__ st, const double *__restrict__ acc,
                                                        int acc_stride, double y_he, double cell_cm, double dt,
-                                                       double redshift, int n_chem, StepLedger *ledger) {
+                                                       double redshift, int n_chem, StepLedger *ledger,
+                                                       double *__restrict__ rc) {
     const uint32_t np = G.ncell_pad;
     const uint32_t stride = gridDim.x * blockDim.x;
     const UpdateConst u(cell_cm, dt, redshift, n_chem);
     unsigned int bad = 0;
     for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < np; s += stride)
-        update_slot<R, S, TH>(G, st, acc, acc_stride, y_he, dt, n_chem, u, s, bad);
+        update_slot<R, S, TH>(G, st, acc, acc_stride, y_he, dt, n_chem, u, s, bad, rc);
     if (bad) atomicOr(&ledger->nonfinite, 1u);
 }
 
@@ -286,11 +315,26 @@ __global__ void __launch_bounds__(kCellBlock) k_import(GridGeom G, R *__restrict
     }
 }
 
+// Recombination counters from natural order (src null: all zero).
+template <typename In>
+__global__ void __launch_bounds__(kCellBlock) k_import_rc(GridGeom G, double *__restrict__ rc,
+                                                          const In *__restrict__ src, int species, uint32_t ncell) {
+    const uint32_t np = G.ncell_pad;
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += gridDim.x * blockDim.x) {
+        const int i = (int)(c % (uint32_t)G.n[0]);
+        const int j = (int)((c / (uint32_t)G.n[0]) % (uint32_t)G.n[1]);
+        const int k = (int)(c / ((uint32_t)G.n[0] * (uint32_t)G.n[1]));
+        const uint32_t s = cell_slot(G, i, j, k);
+        for (int q = 0; q < species; ++q) rc[(size_t)q * np + s] = src ? (double)src[(size_t)q * ncell + c] : 0.0;
+    }
+}
+
 template <typename R, typename Out>
 __global__ void __launch_bounds__(kCellBlock) k_export(GridGeom G, const R *__restrict__ st,
                                                        const double *__restrict__ acc, int acc_stride,
                                                        int species, int thermal, uint32_t mask,
-                                                       Out *__restrict__ dst, uint32_t ncell) {
+                                                       Out *__restrict__ dst, uint32_t ncell,
+                                                       const double *__restrict__ rc) {
     const uint32_t np = G.ncell_pad;
     for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += gridDim.x * blockDim.x) {
         const int i = (int)(c % (uint32_t)G.n[0]);
@@ -298,11 +342,13 @@ __global__ void __launch_bounds__(kCellBlock) k_export(GridGeom G, const R *__re
         const int k = (int)(c / ((uint32_t)G.n[0] * (uint32_t)G.n[1]));
         const uint32_t s = cell_slot(G, i, j, k);
         int out = 0;
-        for (int f = 0; f < 11; ++f) {
+        for (int f = 0; f < 14; ++f) {
             if (!(mask & (1u << f))) continue;
             double v;
             if (f < 7) {
                 v = (double)st[(size_t)f * np + s];
+            } else if (f >= 11) {
+                v = (rc && f - 11 < species) ? rc[(size_t)(f - 11) * np + s] : 0.0;
             } else {
                 const double *a = acc + (size_t)s * acc_stride;
                 if (species == 3) v = (f < 10 || thermal) ? a[f - 7] : 0.0;
@@ -324,6 +370,8 @@ __device__ __forceinline__ void zero_ledger(StepLedger *l) {
     z.substeps = 0ull;
     z.nonfinite = 0u;
     z.errors = 0u;
+    z.d_emit = 0.0;
+    z.d_packets = 0ull;
     *l = z;
 }
 
@@ -540,7 +588,7 @@ hipError_t launch_prep(const CellLaunch &c) {
 template <typename R, int S, bool TH>
 static void upd(const CellLaunch &c, int nb) {
     hipLaunchKernelGGL((k_update<R, S, TH>), dim3(nb), dim3(kCellBlock), 0, c.stream, c.geo, (R *)c.state,
-                       c.acc, c.acc_stride, c.y_he, c.cell_cm, c.dt, c.redshift, c.n_chem, c.ledger);
+                       c.acc, c.acc_stride, c.y_he, c.cell_cm, c.dt, c.redshift, c.n_chem, c.ledger, c.rc);
 }
 
 hipError_t launch_update(const CellLaunch &c) {
@@ -594,21 +642,32 @@ hipError_t launch_export(const CellLaunch &c, uint32_t mask, void *dst, int as_f
         if (as_fp64)
             hipLaunchKernelGGL((k_export<double, double>), dim3(nb), dim3(kCellBlock), 0, c.stream, c.geo,
                                (const double *)c.state, c.acc, c.acc_stride, c.species, c.thermal, mask,
-                               (double *)dst, (uint32_t)ncell);
+                               (double *)dst, (uint32_t)ncell, c.rc);
         else
             hipLaunchKernelGGL((k_export<double, float>), dim3(nb), dim3(kCellBlock), 0, c.stream, c.geo,
                                (const double *)c.state, c.acc, c.acc_stride, c.species, c.thermal, mask,
-                               (float *)dst, (uint32_t)ncell);
+                               (float *)dst, (uint32_t)ncell, c.rc);
     } else {
         if (as_fp64)
             hipLaunchKernelGGL((k_export<float, double>), dim3(nb), dim3(kCellBlock), 0, c.stream, c.geo,
                                (const float *)c.state, c.acc, c.acc_stride, c.species, c.thermal, mask,
-                               (double *)dst, (uint32_t)ncell);
+                               (double *)dst, (uint32_t)ncell, c.rc);
         else
             hipLaunchKernelGGL((k_export<float, float>), dim3(nb), dim3(kCellBlock), 0, c.stream, c.geo,
                                (const float *)c.state, c.acc, c.acc_stride, c.species, c.thermal, mask,
-                               (float *)dst, (uint32_t)ncell);
+                               (float *)dst, (uint32_t)ncell, c.rc);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_import_counters(const CellLaunch &c, const void *src, int src_fp64, int64_t ncell) {
+    const int nb = cell_blocks((uint64_t)ncell);
+    if (src_fp64 || !src)
+        hipLaunchKernelGGL((k_import_rc<double>), dim3(nb), dim3(kCellBlock), 0, c.stream, c.geo, c.rc,
+                           (const double *)src, c.species, (uint32_t)ncell);
+    else
+        hipLaunchKernelGGL((k_import_rc<float>), dim3(nb), dim3(kCellBlock), 0, c.stream, c.geo, c.rc,
+                           (const float *)src, c.species, (uint32_t)ncell);
     return hipGetLastError();
 }
 

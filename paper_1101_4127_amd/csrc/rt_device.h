@@ -39,10 +39,13 @@ __device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_
 // the top 21 bits of Philox words 0..2 shifted to [-2^20, 2^20); the first
 // attempt whose squared length lies in [2^36, 2^40] is used (uniform on the
 // sphere); 64 failed attempts give the diagonal 2^19 (1,1,1).
+// Source packets draw from stream word 0 (g = packet id), recombination
+// packets from stream word 1 (g = natural index of the emitting cell).
 __device__ __forceinline__ void sample_direction(uint64_t seed, uint64_t solve_id, uint64_t g,
-                                                 uint64_t step, bool octant, int32_t c[3]) {
+                                                 uint64_t step, bool octant, int32_t c[3],
+                                                 uint64_t stream = 0ull) {
     for (uint32_t attempt = 0; attempt < 64u; ++attempt) {
-        const U64x4 r = philox4x64_10(g, step, attempt, 0ull, seed, solve_id);
+        const U64x4 r = philox4x64_10(g, step, attempt, stream, seed, solve_id);
         const int32_t x = (int32_t)(r.v[0] >> 43) - (1 << 20);
         const int32_t y = (int32_t)(r.v[1] >> 43) - (1 << 20);
         const int32_t z = (int32_t)(r.v[2] >> 43) - (1 << 20);

@@ -30,6 +30,8 @@ struct StepLedger {
     unsigned long long substeps;
     unsigned int nonfinite;
     unsigned int errors;         // an internal consistency check of the march failed
+    double d_emit;               // recombination photons emitted (also in s[0])
+    unsigned long long d_packets; // recombination packets (also in c[1])
 };
 
 struct SourceRec {
@@ -86,6 +88,8 @@ struct CellLaunch {
     int32_t n_chem;
     unsigned long long *queue;
     StepLedger *ledger;
+    double *rc;          // [species][ncell_pad] recombination counters; non-null: case-A
+                         // rates and counting (recombination re-emission on)
     hipStream_t stream;
 };
 
@@ -110,7 +114,8 @@ struct TCtrl {
     uint32_t total[2];      // packets in list 0 / 1
     uint32_t claim;         // next run of the current pass
     uint32_t err;           // a bounds check failed
-    uint32_t pad[2];
+    uint32_t ndiff;         // recombination packets of the current sub-step
+    uint32_t pad;
 };
 
 struct TiledLaunch {
@@ -134,7 +139,24 @@ struct TiledLaunch {
     int *ev_used;         // pairs recorded so far (host counter)
 };
 
+// Inputs of the recombination emission of one sub-step.
+struct RecombParams {
+    double *rc;            // [species][ncell_pad] recombinations per atom since the last emission
+    const double *milne;   // [3][n_t][mb] photon fraction per bin of each ion's ground-state continuum
+    const void *state;     // the frozen state ([7][ncell_pad], march precision)
+    int32_t n_t;
+    int32_t acc_stride;
+    double log10_t0, dlog10_t;
+    double f_rec;
+    double volume;         // cell volume [cm^3]
+    double y_he;
+    StepLedger *ledger;
+};
+
 size_t tiled_record_bytes(int fp64, int species, int mb);
+// Recombination emission of the sub-step and the march of its packets (after
+// the sub-step's source batches, before the cell update).
+hipError_t launch_tiled_reemit(const TiledLaunch &t, const RecombParams &r);
 hipError_t launch_tiled_reset(const TiledLaunch &t);
 hipError_t launch_tiled_slots_zero(const TiledLaunch &t);
 hipError_t launch_tiled_batch(const TiledLaunch &t);
@@ -200,6 +222,8 @@ hipError_t launch_update(const CellLaunch &c);
 hipError_t launch_import(const CellLaunch &c, const void *nh, const void *x, const void *t,
                          int fields_fp64, int64_t ncell);
 hipError_t launch_export(const CellLaunch &c, uint32_t mask, void *dst, int as_fp64, int64_t ncell);
+// Counters c.rc ([species][ncell_pad]) from natural order [species][ncell]; src null: zero.
+hipError_t launch_import_counters(const CellLaunch &c, const void *src, int src_fp64, int64_t ncell);
 hipError_t launch_ledger_zero(StepLedger *l, hipStream_t s);
 hipError_t launch_ledger_reduce(const LedgerSlot *slots, int nslots, StepLedger *l, hipStream_t s);
 hipError_t launch_trace_rays(const GridGeom &g, int m, const int32_t *o, const int32_t *c,

@@ -34,6 +34,7 @@
 #include "rt_cross.h"
 #include "rt_device.h"
 #include "rt_internal.h"
+#include "rt_recomb.h"
 
 namespace rtk {
 
@@ -347,6 +348,160 @@ __global__ void __launch_bounds__(kTBlock) k_tscatter_emit(const TParams p) {
         const uint32_t tile = tile_of_cell(p.geo, sr.o[0] >> 1, sr.o[1] >> 1, sr.o[2] >> 1);
         const uint32_t pos = p.off[tile] + p.side[i];
         if (tile < p.n_tiles && pos < p.capacity) p.idx0[pos] = i;
+        else atomicOr(&p.ctrl->err, 1u);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Recombination emission of one sub-step (Sec. 2; Sec. 3: a cell emits when a
+// packet crosses it and its count of recombinations has reached f_rec N_a),
+// after the sub-step's source packets have been marched and before the cell
+// update.  One lane per slot.  A cell the source packets deposited in emits
+// when some ion's counter is positive and at least f_rec: those counters give
+// counter x atoms x ground-state share photons with the ion's Milne spectrum
+// at the cell temperature, and restart from zero.  The packet (isotropic,
+// Philox stream word 1 keyed by the cell's natural index, from the cell
+// centre) takes the next free record, one atomic per wavefront; its tile
+// counts it as for emitted source packets.
+// ---------------------------------------------------------------------------
+template <typename R, int S, int MB>
+__global__ void __launch_bounds__(kTBlock) k_remit(const TParams p, const RecombParams rp) {
+    using RL = TRec<R, S, MB>;
+    constexpr int ND = RL::ND;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
+    const uint32_t gw = (blockIdx.x * kTBlock + threadIdx.x) >> 6;
+    const uint32_t nw = gridDim.x * kTWaves;
+    const uint32_t np = p.geo.ncell_pad;
+    const R *st = reinterpret_cast<const R *>(rp.state);
+    uint4 *recs = reinterpret_cast<uint4 *>(p.rec);
+    double l_emit = 0.0;
+    uint32_t n_pk = 0;
+    for (uint32_t base = gw * 64u; base < np; base += nw * 64u) {
+        const uint32_t s = base + lane;
+        bool emit = false;
+        double ww = 0.0;
+        R F[MB];
+#pragma unroll
+        for (int j = 0; j < MB; ++j) F[j] = R(0);
+        int k0 = 0, k1 = 0, k2 = 0;
+        if (s < np && slot_cell(p.geo, s, k0, k1, k2)) {
+            const double *a = p.acc + (size_t)s * rp.acc_stride;
+            const bool crossed = a[0] > 0.0 || (S == 3 && (a[1] > 0.0 || a[2] > 0.0));
+            if (crossed) {
+                const double T = (double)st[6 * (size_t)np + s];
+                const double nh = (double)st[s];
+                double pg[3];
+                ground_fraction(T, pg);
+                const double atoms[3] = {nh * rp.volume, (rp.y_he * nh) * rp.volume, (rp.y_he * nh) * rp.volume};
+                double ph[3] = {0.0, 0.0, 0.0};
+                bool any = false;
+#pragma unroll
+                for (int q = 0; q < S; ++q) {
+                    double *cp = rp.rc + (size_t)q * np + s;
+                    const double r = *cp;
+                    if (r > 0.0 && r >= rp.f_rec) {
+                        ph[q] = (r * atoms[q]) * pg[q];
+                        *cp = 0.0;
+                        any = true;
+                    }
+                }
+                const double w = (ph[0] + ph[1]) + ph[2];
+                if (any && w > 0.0) {
+                    double sed[MB];
+#pragma unroll
+                    for (int j = 0; j < MB; ++j) sed[j] = 0.0;
+#pragma unroll
+                    for (int q = 0; q < S; ++q) {
+                        if (!(ph[q] > 0.0)) continue;
+                        double m[MB];
+                        milne_at<MB>(rp, q, T, m);
+#pragma unroll
+                        for (int j = 0; j < MB; ++j) sed[j] += ph[q] * m[j];
+                    }
+#pragma unroll
+                    for (int j = 0; j < MB; ++j) F[j] = (R)(sed[j] / w);
+                    ww = w;
+                    emit = true;
+                }
+            }
+        }
+        const uint64_t em = __ballot(emit);
+        if (em == 0ull) continue;                       // wavefront-uniform
+        uint32_t b0 = 0;
+        if (lane == 0) b0 = atomicAdd(&p.ctrl->ndiff, (uint32_t)__popcll(em));
+        b0 = (uint32_t)__shfl((int)b0, 0);
+        const uint32_t idx = b0 + (uint32_t)__popcll(em & lt_mask);
+        const bool act = emit && idx < p.capacity;
+        if (emit && !act) atomicOr(&p.ctrl->err, 128u);
+        uint32_t tile = 0;
+        if (act) {
+            const uint32_t cell = (uint32_t)k0 + (uint32_t)p.geo.n[0] * ((uint32_t)k1 + (uint32_t)p.geo.n[1] * (uint32_t)k2);
+            int32_t c[3];
+            sample_direction(p.seed, p.solve_id, cell, p.step, false, c, 1ull);
+            uint32_t active = 0u;
+            double carried = 0.0;
+#pragma unroll
+            for (int j = 0; j < MB; ++j) {
+                if (F[j] > R(0)) active |= 1u << j;
+                carried += (double)F[j];
+            }
+            R D[ND];
+#pragma unroll
+            for (int j = 0; j < ND; ++j) D[j] = (!RL::F64 || ((active >> j) & 1u)) ? R(0) : R(INFINITY);
+            const uint32_t a0 = pack_dir(c[0]), a1 = pack_dir(c[1]), a2 = pack_dir(c[2]);
+            const int64_t qq = (int64_t)c[0] * c[0] + (int64_t)c[1] * c[1] + (int64_t)c[2] * c[2];
+            const double Ld = sqrt((double)qq) * p.half_dl;
+            const R len = RL::F64 ? (R)Ld : (R)(Ld * p.len_scale);
+            const uint32_t jw = active ? (uint32_t)__builtin_ctz(active) : 0u;
+            store_record<R, S, MB>(recs + (size_t)idx * RL::STRIDE, c[0], c[1], c[2], pack_cell(k0, k1, k2, 3u),
+                                   next_face(k0, 2 * k0 + 1, a0), jw, next_face(k1, 2 * k1 + 1, a1),
+                                   next_face(k2, 2 * k2 + 1, a2), active, ww, len, F, D);
+            l_emit += ww * carried;
+            n_pk += 1u;
+            tile = tile_of_cell(p.geo, k0, k1, k2);
+        }
+        // rank in the tile's list: one atomic per distinct tile of the wavefront
+        uint64_t pend = __ballot(act);
+        uint32_t rel = 0;
+        while (pend != 0ull) {
+            const int lead = __ffsll((unsigned long long)pend) - 1;
+            const uint32_t lt = (uint32_t)__shfl((int)tile, lead);
+            const uint64_t same = __ballot(act && tile == lt) & pend;
+            uint32_t b = 0;
+            if ((int)lane == lead) b = atomicAdd(p.cnt + lt, (uint32_t)__popcll(same));
+            b = (uint32_t)__shfl((int)b, lead);
+            if ((same >> lane) & 1ull) rel = b + (uint32_t)__popcll(same & lt_mask);
+            pend &= ~same;
+        }
+        if (act) p.side[idx] = rel;
+    }
+    // the diffuse totals of the step: one float64 atomic per wavefront
+    double de = l_emit, dc = 0.0;
+    wave_sum_pair(de, dc);
+    const unsigned long long dn = wave_sum_u64((unsigned long long)n_pk);
+    if (lane == 0 && dn != 0ull) {
+        atomicAdd(&rp.ledger->d_emit, de + dc);
+        atomicAdd(&rp.ledger->d_packets, dn);
+    }
+    double v[8] = {l_emit, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    unsigned long long cc[4] = {0ull, n_pk, 0ull, 0ull};
+    block_ledger_add(p.slots + blockIdx.x, v, cc);
+}
+
+// List positions of the recombination packets: offset of the cell's tile +
+// rank (records RS 16-byte units apart; the cell is word 3).
+template <int RS>
+__global__ void __launch_bounds__(kTBlock) k_tscatter_diffuse(const TParams p) {
+    const uint32_t stride = gridDim.x * kTBlock;
+    const uint32_t n = min(p.ctrl->ndiff, p.capacity);
+    const uint4 *recs = reinterpret_cast<const uint4 *>(p.rec);
+    for (uint32_t i = blockIdx.x * kTBlock + threadIdx.x; i < n; i += stride) {
+        const uint32_t kw = recs[(size_t)i * RS].w;
+        const int k0 = (int)(kw & 1023u), k1 = (int)((kw >> 10) & 1023u), k2 = (int)((kw >> 20) & 1023u);
+        const uint32_t tile = tile_of_cell(p.geo, k0, k1, k2);
+        const uint32_t pos = tile < p.n_tiles ? p.off[tile] + p.side[i] : 0xffffffffu;
+        if (pos < p.capacity) p.idx0[pos] = i;
         else atomicOr(&p.ctrl->err, 1u);
     }
 }
@@ -938,6 +1093,9 @@ void scan(const TParams &p, const TiledLaunch &t, int nxt) {
 }
 
 template <typename R, int S, bool TH, int MB, int NA, int NB>
+void run_passes(const TParams &p, const TiledLaunch &t);
+
+template <typename R, int S, bool TH, int MB, int NA, int NB>
 hipError_t run_batch(const TiledLaunch &t) {
     const TParams p = make_params(t);
     const hipStream_t st = t.m.stream;
@@ -945,6 +1103,32 @@ hipError_t run_batch(const TiledLaunch &t) {
     hipLaunchKernelGGL((k_temit<R, S, TH, MB>), grid, blk, 0, st, p);
     scan(p, t, 0);
     hipLaunchKernelGGL(k_tscatter_emit, dim3(8 * t.m.blocks), blk, 0, st, p);
+    run_passes<R, S, TH, MB, NA, NB>(p, t);
+    return hipGetLastError();
+}
+
+// The recombination packets of the sub-step, as a batch of their own (not
+// traced; record ids from 0).
+template <typename R, int S, bool TH, int MB, int NA, int NB>
+hipError_t run_reemit(const TiledLaunch &t, const RecombParams &rp) {
+    TParams p = make_params(t);
+    p.trace_n = 0;
+    p.g0 = 0u;
+    p.nbatch = 0u;
+    const hipStream_t st = t.m.stream;
+    const dim3 grid(t.m.blocks), blk(kTBlock);
+    hipLaunchKernelGGL(k_tzero_u32, dim3(1), dim3(64), 0, st, &t.ctrl->ndiff, 1u);
+    hipLaunchKernelGGL((k_remit<R, S, MB>), grid, blk, 0, st, p, rp);
+    scan(p, t, 0);
+    hipLaunchKernelGGL((k_tscatter_diffuse<TRec<R, S, MB>::STRIDE>), dim3(8 * t.m.blocks), blk, 0, st, p);
+    run_passes<R, S, TH, MB, NA, NB>(p, t);
+    return hipGetLastError();
+}
+
+template <typename R, int S, bool TH, int MB, int NA, int NB>
+void run_passes(const TParams &p, const TiledLaunch &t) {
+    const hipStream_t st = t.m.stream;
+    const dim3 grid(t.m.blocks), blk(kTBlock);
     int cur = 0;
     TParams pp = p;
     for (uint32_t pass = 0; pass < t.passes; ++pass) {
@@ -963,7 +1147,6 @@ hipError_t run_batch(const TiledLaunch &t) {
         cur ^= 1;
     }
     hipLaunchKernelGGL(k_tcheck, dim3(1), dim3(64), 0, st, t.ctrl, cur, t.ledger);
-    return hipGetLastError();
 }
 
 template <typename R, int S, bool TH, int MB>
@@ -972,25 +1155,33 @@ hipError_t occ(int *n) {
         n, reinterpret_cast<const void *>(&k_tmarch<R, S, TH, MB, 0, 0>), kTBlock, 0);
 }
 
+template <typename R, int S, bool TH, int MB, int NA, int NB>
+hipError_t run(const TiledLaunch &t, const RecombParams *rp) {
+    return rp ? run_reemit<R, S, TH, MB, NA, NB>(t, *rp) : run_batch<R, S, TH, MB, NA, NB>(t);
+}
+
 template <typename R, int S, bool TH>
-hipError_t pick_mb(const TiledLaunch *t, int mb, int *o) {
+hipError_t pick_mb(const TiledLaunch *t, const RecombParams *rp, int mb, int *o) {
     switch (mb) {
-    case 1: return t ? run_batch<R, S, TH, 1, 0, 0>(*t) : occ<R, S, TH, 1>(o);
+    case 1: return t ? run<R, S, TH, 1, 0, 0>(*t, rp) : occ<R, S, TH, 1>(o);
     case 8:
         if (!t) return occ<R, S, TH, 8>(o);
-        if (S == 3 && t->m.layout == 1) return run_batch<R, S, TH, 8, 3, 2>(*t);
-        return run_batch<R, S, TH, 8, 0, 0>(*t);
+        if (S == 3 && t->m.layout == 1) return run<R, S, TH, 8, 3, 2>(*t, rp);
+        return run<R, S, TH, 8, 0, 0>(*t, rp);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t dispatch(const TiledLaunch *t, int species, int thermal, int fp64, int mb, int *o) {
+hipError_t dispatch(const TiledLaunch *t, const RecombParams *rp, int species, int thermal, int fp64, int mb,
+                    int *o) {
     if (fp64) {
-        if (species == 1) return thermal ? pick_mb<double, 1, true>(t, mb, o) : pick_mb<double, 1, false>(t, mb, o);
-        return thermal ? pick_mb<double, 3, true>(t, mb, o) : pick_mb<double, 3, false>(t, mb, o);
+        if (species == 1)
+            return thermal ? pick_mb<double, 1, true>(t, rp, mb, o) : pick_mb<double, 1, false>(t, rp, mb, o);
+        return thermal ? pick_mb<double, 3, true>(t, rp, mb, o) : pick_mb<double, 3, false>(t, rp, mb, o);
     }
-    if (species == 1) return thermal ? pick_mb<float, 1, true>(t, mb, o) : pick_mb<float, 1, false>(t, mb, o);
-    return thermal ? pick_mb<float, 3, true>(t, mb, o) : pick_mb<float, 3, false>(t, mb, o);
+    if (species == 1)
+        return thermal ? pick_mb<float, 1, true>(t, rp, mb, o) : pick_mb<float, 1, false>(t, rp, mb, o);
+    return thermal ? pick_mb<float, 3, true>(t, rp, mb, o) : pick_mb<float, 3, false>(t, rp, mb, o);
 }
 
 template <typename R, int S, int MB> constexpr size_t rec_bytes() { return 16u * TRec<R, S, MB>::STRIDE; }
@@ -1020,11 +1211,15 @@ hipError_t launch_tiled_slots_zero(const TiledLaunch &t) {
 }
 
 hipError_t launch_tiled_batch(const TiledLaunch &t) {
-    return dispatch(&t, t.m.species, t.m.thermal, t.m.fp64, t.m.mb, nullptr);
+    return dispatch(&t, nullptr, t.m.species, t.m.thermal, t.m.fp64, t.m.mb, nullptr);
+}
+
+hipError_t launch_tiled_reemit(const TiledLaunch &t, const RecombParams &r) {
+    return dispatch(&t, &r, t.m.species, t.m.thermal, t.m.fp64, t.m.mb, nullptr);
 }
 
 hipError_t tiled_occupancy(int species, int thermal, int fp64, int mb, int *blocks_per_cu) {
-    return dispatch(nullptr, species, thermal, fp64, mb, blocks_per_cu);
+    return dispatch(nullptr, nullptr, species, thermal, fp64, mb, blocks_per_cu);
 }
 
 }  // namespace rtk

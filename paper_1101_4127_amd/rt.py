@@ -18,16 +18,19 @@ LIB_PATH = os.path.join(PKG, "librt_mcrt.so")
 
 RT_MAX_BINS = 16
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_ESTATE, RT_EOVERFLOW, RT_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
-RT_ISOTHERMAL, RT_FP64, RT_TIME_MARCH, RT_DIRECT_MARCH = 0x1, 0x2, 0x4, 0x8
+RT_ISOTHERMAL, RT_FP64, RT_TIME_MARCH, RT_DIRECT_MARCH, RT_RECOMB = 0x1, 0x2, 0x4, 0x8, 0x10
 RT_SRC_CORNER_OCTANT = 0x1
 RT_TRACE_HDR = 8
 RT_FATE_TRUNC, RT_FATE_ESCAPE = 1, 2
 RT_MAX_BATCH = 64
 RT_BATCH_GRAPH = 0x1
 
-FIELDS = ("nh", "x_hi", "x_hii", "x_hei", "x_heii", "x_heiii", "temp", "d_hi", "d_hei", "d_heii", "q")
+FIELDS = ("nh", "x_hi", "x_hii", "x_hei", "x_heii", "x_heiii", "temp", "d_hi", "d_hei", "d_heii", "q",
+          "r_hii", "r_heii", "r_heiii")
 F = {name: 1 << i for i, name in enumerate(FIELDS)}
 RT_F_ALL = (1 << len(FIELDS)) - 1
+RT_F_STATE = (1 << 11) - 1          # every field but the recombination counters
+RT_MAX_MILNE_T = 512
 
 
 class GridDesc(C.Structure):
@@ -51,6 +54,7 @@ class StepStats(C.Structure):
         ("n_escaped", C.c_int64), ("n_truncated", C.c_int64), ("substeps", C.c_int64),
         ("nonfinite", C.c_uint32), ("errors", C.c_uint32), ("march_ms", C.c_double),
         ("kernel_ms", C.c_double), ("kernel_launches", C.c_int64),
+        ("diffuse_emitted", C.c_double), ("diffuse_packets", C.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -71,6 +75,7 @@ SIGNATURES = {
     "rt_fetch_trace": (_I32, [_VP, _VP, _I64]),
     "rt_trace_rays": (_I32, [_VP, _I32, _VP, _VP, _I32, _VP, _VP, _VP]),
     "rt_get_step_index": (_I32, [_VP, C.POINTER(_U64)]),
+    "rt_set_recombination": (_I32, [_VP, _D, _I32, _D, _D, _VP, _VP, _I32]),
     "rt_release": (_I32, [_VP]),
     "rt_batch_workspace_bytes": (_I32, [_I32, C.POINTER(C.c_size_t)]),
     "rt_batch_init": (_I32, [_I32, _VP, C.c_size_t, _VP, _U32, C.POINTER(_VP)]),
@@ -210,6 +215,23 @@ def rt_get_step_index(h) -> int:
     return int(v.value)
 
 
+def rt_set_recombination(h, f_rec: float, log10_t0: float, dlog10_t: float, milne, counters=None):
+    """Threshold, spectrum table [3][n_t][n_bins] (host) and optional initial
+    counters (device tensor [species][ncell], float64 or float32)."""
+    tab = np.ascontiguousarray(milne, dtype=np.float64)
+    if tab.ndim != 3 or tab.shape[0] != 3:
+        raise ValueError("milne table must be [3][n_t][n_bins]")
+    fp64 = 1
+    cp = None
+    if counters is not None:
+        import torch
+        fp64 = 1 if counters.dtype == torch.float64 else 0
+        cp = _ptr(counters)
+    _check("rt_set_recombination", lib().rt_set_recombination(
+        h, float(f_rec), int(tab.shape[1]), float(log10_t0), float(dlog10_t),
+        tab.ctypes.data_as(C.c_void_p), cp, fp64))
+
+
 def rt_release(h):
     _check("rt_release", lib().rt_release(h))
 
@@ -271,7 +293,8 @@ def desc_from_workload(work, *, fp64: Optional[bool] = None, brick_log2: int = -
     d.n_chem = int(work.n_chem)
     f64 = bool(work.flags & 0x2) if fp64 is None else bool(fp64)
     d.flags = ((RT_ISOTHERMAL if work.flags & 0x1 else 0) | (RT_FP64 if f64 else 0)
-               | (RT_TIME_MARCH if time_march else 0) | (RT_DIRECT_MARCH if direct else 0))
+               | (RT_TIME_MARCH if time_march else 0) | (RT_DIRECT_MARCH if direct else 0)
+               | (RT_RECOMB if getattr(work, "recomb", None) is not None else 0))
     d.solve_id = int(work.solve_id)
     d.brick_log2 = int(brick_log2)
     d.wave_chunk = int(wave_chunk)
@@ -289,7 +312,9 @@ def desc_from_workload(work, *, fp64: Optional[bool] = None, brick_log2: int = -
 class Solve:
     """One solve on the current GPU: workspace and fields in torch device memory."""
 
-    def __init__(self, work, *, device: str = "cuda", stream=None, **tiles):
+    def __init__(self, work, *, device: str = "cuda", stream=None, counters=None, **tiles):
+        """counters: optional initial recombination counters [species][ncell]
+        (numpy, float64) of a workload with recombination re-emission."""
         import torch
         self.work = work
         if not tiles.get("inflight"):
@@ -308,6 +333,14 @@ class Solve:
         self.h = rt_init_grid(self.desc, self.workspace, len(work.src_ndot), nh, x, t, stream)
         if len(work.src_ndot):
             rt_add_sources(self.h, work.src_ijk, work.src_ndot, work.src_sed, work.src_flags)
+        self.recomb = getattr(work, "recomb", None) is not None
+        if self.recomb:
+            r = work.recomb
+            rc = None
+            if counters is not None:
+                rc = torch.as_tensor(np.asarray(counters, np.float64), device=device).contiguous()
+            rt_set_recombination(self.h, r.f_rec, r.log10_t0, r.dlog10_t, r.milne, rc)
+            del rc
         # the import is stream-ordered: wait for it before the inputs are freed
         (stream if stream is not None else torch.cuda.current_stream()).synchronize()
         del nh, x, t
@@ -318,7 +351,11 @@ class Solve:
         return rt_step(self.h, w.dt_s if dt is None else dt, w.packets if packets is None else packets,
                        w.seed if seed is None else seed, stats)
 
-    def fetch(self, mask: int = RT_F_ALL) -> np.ndarray:
+    def fetch(self, mask: Optional[int] = None) -> np.ndarray:
+        """Fields in FIELDS order (default: all, the recombination counters
+        only for a solve with re-emission)."""
+        if mask is None:
+            mask = RT_F_ALL if self.recomb else RT_F_STATE
         return rt_fetch_fields(self.h, mask, self.ncell)
 
     def trace(self, count: Optional[int] = None) -> np.ndarray:

@@ -87,13 +87,21 @@ def test_workspace_bytes_scales_and_validates(L):
     # invalid descriptions
     for field, bad in (("n_bins", 0), ("n_bins", 9), ("n_bins", 17), ("tau_kill", 0.0), ("n_sub", 0), ("n_chem", 0),
                        ("cell_cm", -1.0), ("brick_log2", 4), ("wave_chunk", 100), ("refill_min", 65),
-                       ("flags", 0x10), ("trace_stride", -1), ("brick_log2", 2), ("run_len", 10),
+                       ("flags", 0x20), ("flags", rt.RT_RECOMB | rt.RT_DIRECT_MARCH), ("trace_stride", -1), ("brick_log2", 2), ("run_len", 10),
                        ("run_len", 2049), ("park_lanes", -1), ("park_lanes", 65), ("inflight", -1), ("inflight", 1 << 31)):
         e = rt.rt_desc_defaults()
         setattr(e, field, bad)
         with pytest.raises(rt.RTError) as ex:
             rt.rt_workspace_bytes(e, 1)
         assert ex.value.status == rt.RT_EINVAL, field
+    # re-emission: counters, the spectrum table and a record per cell at least
+    e = rt.rt_desc_defaults()
+    e.n[0] = e.n[1] = e.n[2] = 64
+    e.cell_cm = 1e21
+    e.inflight = 1000
+    plain = rt.rt_workspace_bytes(e, 1)
+    e.flags = rt.RT_RECOMB
+    assert rt.rt_workspace_bytes(e, 1) >= plain + 64 ** 3 * (8 + 32)
     e = rt.rt_desc_defaults()
     e.n[1] = 1025
     with pytest.raises(rt.RTError):

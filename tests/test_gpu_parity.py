@@ -267,7 +267,7 @@ def test_checkpoint_resume(gpu):
     h = rt.rt_init_grid(desc, ws, len(w2.src_ndot), f(w2.n_h), f(np.asarray(w2.x).reshape(5, -1)), f(w2.temp))
     rt.rt_add_sources(h, w2.src_ijk, w2.src_ndot, w2.src_sed, 0)
     rt.rt_step(h, w2.dt_s, w2.packets, 8)
-    fc = rt.rt_fetch_fields(h, rt.RT_F_ALL, w2.ncell)
+    fc = rt.rt_fetch_fields(h, rt.RT_F_STATE, w2.ncell)
     tc = rt.rt_fetch_trace(h, 1000, 64)
     rt.rt_release(h)
     assert PT.traces_equal(ta, tc)

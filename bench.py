@@ -230,6 +230,44 @@ def serving_leg(count: int, accuracy_requests: int = 32):
     return out
 
 
+def reemit_leg(n: int, packets: int):
+    """Recombination re-emission at scale: one step of an established H II
+    region whose counters put about half of its cells over the threshold,
+    with re-emission (float32 march) and, for the cost, the same step
+    without it.  Each is timed on a fresh solve after a warm-up solve."""
+    import torch
+    from paper_1101_4127_amd import rt
+    from paper_1101_4127_amd import workloads as W
+    w, counters = W.hii_region_reemit(n=n, packets=packets)
+    res = {}
+    for tag, wk, rc in (("reemit", w, counters), ("plain", w.with_(recomb=None), None)):
+        for timed in (False, True):
+            s = rt.Solve(wk, time_march=True, counters=rc)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = s.step(seed=7)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            s.release()
+        res[tag] = dict(ms_per_step=1e3 * wall, crossings=st["crossings"], packets=st["packets"],
+                        diffuse_packets=st["diffuse_packets"], march_ms=st["march_ms"],
+                        kernel_ms=st["kernel_ms"],
+                        residual=abs(st["emitted"] - st["absorbed"] - st["escaped"] - st["truncated"])
+                        / st["emitted"])
+    r, p = res["reemit"], res["plain"]
+    log(f"re-emission: {r['ms_per_step']:.1f} ms/step ({r['diffuse_packets']} recombination packets, "
+        f"{r['crossings']:.4g} crossings) vs {p['ms_per_step']:.1f} ms without")
+    return {"workload": w.name, "grid": list(w.n), "source_packets": packets, "f_rec": w.recomb.f_rec,
+            "form": "float32 march, float64 accumulators and cell update; case-A rates",
+            "ms_per_step": r["ms_per_step"], "crossings_per_s": r["crossings"] / (r["ms_per_step"] * 1e-3),
+            "recombination_packets": r["diffuse_packets"],
+            "crossings_of_recombination_packets": r["crossings"] - p["crossings"],
+            "march_ms": r["march_ms"], "march_kernel_ms": r["kernel_ms"],
+            "conservation_residual": r["residual"],
+            "without_reemission": {"ms_per_step": p["ms_per_step"], "march_ms": p["march_ms"],
+                                   "crossings_per_s": p["crossings"] / (p["ms_per_step"] * 1e-3)}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,6 +284,9 @@ def main():
     ap.add_argument("--refill", type=int, default=0)
     ap.add_argument("--bpcu", type=int, default=0)
     ap.add_argument("--serving-requests", type=int, default=512, help="0 skips the serving workload")
+    ap.add_argument("--reemit-grid", type=int, default=256,
+                    help="cells per axis of the re-emission workload (0 skips it)")
+    ap.add_argument("--reemit-packets", type=int, default=10_000_000)
     ap.add_argument("--autotune", action="store_true",
                     help="choose the march's launch parameters by measurement first (tiled march)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -322,6 +363,8 @@ def main():
                              "speedup_of_fp32_form": value / v64, "conservation_residual": f64["resid"]}
     if args.serving_requests > 0:
         out["serving"] = serving_leg(args.serving_requests)
+    if args.reemit_grid > 0:
+        out["reemission"] = reemit_leg(args.reemit_grid, args.reemit_packets)
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(work, args.cpu_seconds)

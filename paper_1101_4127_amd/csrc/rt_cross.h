@@ -183,18 +183,10 @@ __device__ __forceinline__ void cross_cell(R l, const KV &kap, TT tab, R (&F)[MB
         R d;
         if constexpr (F64) {
             // absorbed share 1 - e^-tau and transmitted share e^-tau, each
-            // with a few ulp of relative error at every tau: below ln 2 the
-            // absorbed one from expm1, above it the transmitted one from exp
-            // (either share is then >= 1/2, so the other is 1 minus it without
-            // loss; an opaque cell's remainder keeps its digits)
+            // with a few ulp of relative error at every tau (an opaque cell's
+            // remainder keeps its digits)
             double em, tr;
-            if (tau < 0.69314718055994531) {
-                em = -expm1(-tau);
-                tr = 1.0 - em;
-            } else {
-                tr = exp(-tau);
-                em = 1.0 - tr;
-            }
+            attenuation(tau, em, tr);
             d = F[j] * em;
             F[j] = F[j] * tr;
             D[j] = D[j] + tau;

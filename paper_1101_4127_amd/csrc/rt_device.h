@@ -128,6 +128,41 @@ __device__ __forceinline__ void attenuation(float t, float &em, float &tr) {
     tr = lo ? 1.0f - small : e;
 }
 
+// Float64 form of the same pair, em = 1 - e^-t and tr = e^-t, both from one
+// range reduction (Cody & Waite: -t = k ln2 + r, |r| <= ln2 / 2, ln2 split in
+// two parts so k ln2 is exact) and one Taylor polynomial p = e^r - 1 to r^13
+// (truncation below 2e-17 relative): tr = 2^k (1 + p) and
+// em = (1 - 2^k) - 2^k p, both within a few ulp at every t >= 0, where
+// computing either as 1 minus the other would lose the small one's digits.
+__device__ __forceinline__ void attenuation(double t, double &em, double &tr) {
+    if (!(t < 745.0)) {                       // e^-t below the smallest double
+        em = 1.0;
+        tr = 0.0;
+        return;
+    }
+    const double x = -t;
+    const double k = rint(x * 1.4426950408889634);
+    const double r = fma(-k, 1.9082149292705877e-10, fma(-k, 0.69314718036912382, x));
+    double p = 1.0 / 6227020800.0;                                   // 1/13!
+    p = fma(p, r, 1.0 / 479001600.0);
+    p = fma(p, r, 1.0 / 39916800.0);
+    p = fma(p, r, 1.0 / 3628800.0);
+    p = fma(p, r, 1.0 / 362880.0);
+    p = fma(p, r, 1.0 / 40320.0);
+    p = fma(p, r, 1.0 / 5040.0);
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = p * r;                                                       // e^r - 1
+    const int ki = (int)k;
+    const double s = ldexp(1.0, ki);                                 // 2^k, k <= 0
+    tr = fma(s, p, s);
+    em = fma(-s, p, 1.0 - s);
+}
+
 // Error-free sum a + b = s + e (Knuth's TwoSum).
 __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
     s = a + b;

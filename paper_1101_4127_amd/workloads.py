@@ -360,6 +360,37 @@ def stromgren_reemit(n: int = 32, packets: int = 100000, steps: int = 10, n_sub:
     return w if f_rec is None else with_recombination(w, f_rec)
 
 
+def hii_region_reemit(n: int = 256, packets: int = 10_000_000, f_rec: float = 0.1, seed: int = 21,
+                      fp64: bool = False):
+    """An established H II region with recombination radiation, for measuring
+    re-emission at scale: Test 0's gas (uniform pure H, n_H = 1e-3, isothermal
+    1e4 K) around one central 5e48 ph/s source with a 1e5 K black body in 8
+    bins; the box (18 kpc) puts the case-B Stroemgren radius at 0.3 n cells.
+    Cells inside that radius start ionised (x_HI = 1e-3) with recombination
+    counters drawn uniformly in [0, 2 f_rec) (seeded), so about half of them
+    emit in the first sub-step; outside, the gas is neutral with zero counters.
+    Returns (workload, counters [1][ncell])."""
+    box = 18.0 * KPC_CM
+    ncell = n ** 3
+    x, t = _neutral_state(ncell, 1.0e4)
+    c = (np.arange(n) + 0.5 - n / 2.0)
+    r2 = (c[:, None, None] ** 2 + c[None, :, None] ** 2 + c[None, None, :] ** 2).transpose(2, 1, 0).ravel()
+    inside = r2 < (0.3 * n) ** 2
+    x[X_HI, inside] = float(np.float32(1.0e-3))
+    x[X_HII, inside] = float(np.float32(1.0 - 1.0e-3))
+    rng = np.random.default_rng(seed)
+    counters = np.zeros((1, ncell))
+    counters[0, inside] = rng.random(int(inside.sum())) * (2.0 * f_rec)
+    bins = blackbody_table(1.0e5)
+    w = Workload(
+        name=f"hii_region_reemit_{n}^3", n=(n, n, n), cell_cm=box / n, y_he=0.0, bins=bins,
+        redshift=-1.0, n_h=np.full(ncell, 1.0e-3), x=x, temp=t,
+        src_ijk=np.full((1, 3), n // 2, np.int32), src_ndot=np.array([5.0e48]),
+        src_sed=bins.sed[None, :].copy(), src_flags=0, dt_s=MYR_S, packets=packets, steps=2, n_sub=1,
+        n_chem=8, flags=ISOTHERMAL | (FP64_MARCH if fp64 else 0), seed=1)
+    return with_recombination(w, f_rec), counters
+
+
 def blackbody_photon_rate(luminosity_erg_s: float, t_bb: float, lo_ev: float = 13.6,
                           hi_ev: float = 200.0) -> float:
     """Photons/s in [lo_ev, hi_ev] of a black body of total luminosity L."""

@@ -19,7 +19,8 @@ SRC = os.path.join(HERE, "rt_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 MAX_BINS = 16
-FATE_TRUNC, FATE_ESCAPE = 1, 2
+FATE_TRUNC, FATE_ESCAPE, FATE_PATH = 1, 2, 3
+PERIODIC = 0x2
 TRACE_HDR = 8
 
 _lock = threading.Lock()
@@ -40,7 +41,8 @@ class Grid(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("cell_cm", C.c_double), ("y_he", C.c_double),
                 ("n_bins", C.c_int32), ("e_ev", C.c_double * MAX_BINS),
                 ("sigma", (C.c_double * MAX_BINS) * 3), ("redshift", C.c_double),
-                ("tau_kill", C.c_double), ("n_chem", C.c_int32), ("flags", C.c_uint32)]
+                ("tau_kill", C.c_double), ("n_chem", C.c_int32), ("flags", C.c_uint32),
+                ("path_cells", C.c_int32)]
 
 
 class Reemit(C.Structure):
@@ -154,7 +156,8 @@ def make_grid(work, flags: Optional[int] = None, n_chem: Optional[int] = None) -
     g.redshift = float(work.redshift)
     g.tau_kill = float(work.tau_kill)
     g.n_chem = int(work.n_chem if n_chem is None else n_chem)
-    g.flags = int(work.flags if flags is None else flags) & 1
+    g.flags = (int(work.flags if flags is None else flags) & 1) | (PERIODIC if work.periodic else 0)
+    g.path_cells = int(work.path_cells or max(work.n))
     return g
 
 

@@ -20,8 +20,10 @@
  *   5. per bin, Eq. (1): the absorbed photons are the transmitted ones times
  *      1 - exp(-tau); they are shared among the species in proportion to
  *      their part of tau (Sec. 2) and added to per-cell accumulators;
- *   6. the packet ends when it leaves the box (no periodic boundaries) or is
- *      extinguished (Sec. 2), here: every populated bin has tau >= tau_kill;
+ *   6. the packet ends when it leaves the box or is extinguished (Sec. 2),
+ *      here: every populated bin has tau >= tau_kill; with periodic boundaries
+ *      it re-enters through the opposite face instead of leaving and ends
+ *      after a set number of cell faces along one axis;
  *   7. after all packets, every cell's ionisation fractions and temperature
  *      are advanced from the accumulated photons (Sec. 2's network, applied
  *      once per cell per sub-step instead of once per crossing).
@@ -41,9 +43,9 @@ static const double ORC_ETH_EV[3] = {13.598434, 24.587387, 54.417760};
 static const double ORC_EV = 1.602176634e-12;
 static const double ORC_KB = 1.380649e-16;
 
-enum { ORC_ISOTHERMAL = 1 };
+enum { ORC_ISOTHERMAL = 1, ORC_PERIODIC = 2 };
 enum { ORC_SRC_OCTANT = 1 };
-enum { ORC_FATE_TRUNC = 1, ORC_FATE_ESCAPE = 2 };
+enum { ORC_FATE_TRUNC = 1, ORC_FATE_ESCAPE = 2, ORC_FATE_PATH = 3 };
 
 typedef struct {
     int32_t n[3];
@@ -56,6 +58,8 @@ typedef struct {
     double tau_kill;
     int32_t n_chem;
     uint32_t flags;
+    int32_t path_cells;                /* periodic: a packet ends once it has crossed more
+                                          than this many cell faces along one axis */
 } orc_grid;
 
 /* ------------------------------------------------------------------------ */
@@ -267,6 +271,7 @@ static void march_packet(const orc_grid *G, const double *kappa, const double he
     const int64_t ncell = (int64_t)G->n[0] * G->n[1] * G->n[2];
     const int nb = G->n_bins;
     const int pure_h = !(G->y_he > 0.0);
+    const int periodic = (G->flags & ORC_PERIODIC) != 0;
     double f[ORC_MAX_BINS], T[ORC_MAX_BINS];
     for (int j = 0; j < nb; ++j) { f[j] = 1.0; T[j] = 0.0; }
     const double len_scale =
@@ -328,7 +333,22 @@ static void march_packet(const orc_grid *G, const double *kappa, const double he
         if (tmin >= G->tau_kill) { fate = ORC_FATE_TRUNC; break; }
 
         face = ray_step(&r, mask, G->n);
-        if (face) { fate = ORC_FATE_ESCAPE; break; }
+        if (periodic) {
+            /* Sec. 2: with periodic boundaries a packet leaving through a face
+               comes back through the opposite one; it ends (its photons counted
+               as escaped) once it has crossed more than path_cells faces along
+               some axis */
+            for (int a = 0; a < 3; ++a) {
+                if (r.k[a] < 0) r.k[a] += G->n[a];
+                else if (r.k[a] >= G->n[a]) r.k[a] -= G->n[a];
+            }
+            face = 0;
+            const int64_t dmax = 2 * (int64_t)G->path_cells + 2;
+            if (r.dist[0] > dmax || r.dist[1] > dmax || r.dist[2] > dmax) { fate = ORC_FATE_PATH; break; }
+        } else if (face) {
+            fate = ORC_FATE_ESCAPE;
+            break;
+        }
         s_prev = s_new;
     }
     double left = 0.0;

@@ -282,6 +282,8 @@ class Workload:
     seed: int = 1
     solve_id: int = 0
     recomb: Optional[RecombEmission] = None   # recombination re-emission (None: off)
+    periodic: bool = False      # periodic boundaries (packets re-enter through the opposite face)
+    path_cells: int = 0         # periodic: faces a packet may cross along one axis (0: the longest side)
 
     @property
     def ncell(self) -> int:

@@ -73,6 +73,12 @@ extern "C" {
                                Needs rt_set_recombination before rt_step; not
                                with RT_DIRECT_MARCH.  The workspace then holds
                                one packet record per cell at least. */
+#define RT_PERIODIC 0x20u   /* periodic boundaries (Sec. 2): a packet leaving
+                               through a face re-enters through the opposite
+                               one; it ends when extinguished or once it has
+                               crossed more than path_cells cell faces along
+                               one axis (its photons then count as escaped).
+                               Tiled march only. */
 
 /* rt_add_sources src_flags */
 #define RT_SRC_CORNER_OCTANT 0x1u /* source at the lowest corner of its cell,
@@ -98,11 +104,13 @@ extern "C" {
 #define RT_F_ALL 0x3fffu
 
 #define RT_MAX_MILNE_T 512  /* temperature nodes of a recombination spectrum table */
+#define RT_MAX_PATH_CELLS 2046 /* largest rt_grid_desc.path_cells */
 
 /* trace record: RT_TRACE_HDR int32 words then trace_len cell indices */
 #define RT_TRACE_HDR 8
 #define RT_FATE_TRUNC 1     /* extinguished: every populated bin reached tau_kill */
 #define RT_FATE_ESCAPE 2    /* left the grid (non-periodic boundaries) */
+#define RT_FATE_PATH 3      /* periodic: reached the path limit */
 
 typedef struct rt_solve *rt_solve_t;
 
@@ -152,6 +160,9 @@ typedef struct {
                                      workspace holds one record each); a sub-step
                                      with more packets runs in batches of this
                                      size.  0 = default (2^24) */
+    int32_t path_cells;           /* RT_PERIODIC: cell faces a packet may cross along
+                                     one axis, 1..RT_MAX_PATH_CELLS; 0 = the longest
+                                     side of the grid */
 } rt_grid_desc;
 
 /* Photon ledger and counters of the most recent rt_step (all its sub-steps). */

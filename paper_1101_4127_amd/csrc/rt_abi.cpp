@@ -41,6 +41,7 @@ struct Plan {
     size_t off_rc, off_milne;
     // tiled march
     uint32_t capacity, cmax, max_chunks, n_tiles, scan_blocks, passes, park_passes, park_lanes;
+    uint32_t periodic, dmax;
     size_t rec_bytes;
     size_t off_rec, off_idx0, off_idx1, off_side, off_cnt, off_off, off_cbase, off_bsum, off_ch0, off_ch1,
         off_ctrl;
@@ -65,7 +66,11 @@ int32_t validate_desc(const rt_grid_desc *d) {
     if (!isfinite(d->redshift)) return RT_EINVAL;
     if (!(isfinite(d->tau_kill) && d->tau_kill > 0.0)) return RT_EINVAL;
     if (d->n_sub < 1 || d->n_chem < 1) return RT_EINVAL;
-    if (d->flags & ~(RT_ISOTHERMAL | RT_FP64 | RT_TIME_MARCH | RT_DIRECT_MARCH | RT_RECOMB)) return RT_EINVAL;
+    if (d->flags & ~(RT_ISOTHERMAL | RT_FP64 | RT_TIME_MARCH | RT_DIRECT_MARCH | RT_RECOMB | RT_PERIODIC))
+        return RT_EINVAL;
+    // periodic boundaries are marched by the tiled march only
+    if ((d->flags & RT_PERIODIC) && (d->flags & RT_DIRECT_MARCH)) return RT_EINVAL;
+    if (d->path_cells < 0 || d->path_cells > RT_MAX_PATH_CELLS) return RT_EINVAL;
     // recombination packets are marched by the tiled march only
     if ((d->flags & RT_RECOMB) && (d->flags & RT_DIRECT_MARCH)) return RT_EINVAL;
     if (d->brick_log2 < -1 || d->brick_log2 > 3) return RT_EINVAL;
@@ -150,7 +155,21 @@ int32_t make_plan(const rt_grid_desc *d, int64_t max_sources, Plan *p) {
         // a packet visits at most tx + ty + tz - 2 tiles.  Parking is allowed in
         // that many passes and the same number follow without it, so a packet
         // parked in the last parking pass still reaches the end of its path.
-        const uint32_t visits = (uint32_t)(g.nb[0] + g.nb[1] + g.nb[2] - 2);
+        uint32_t visits = (uint32_t)(g.nb[0] + g.nb[1] + g.nb[2] - 2);
+        p->periodic = (d->flags & RT_PERIODIC) ? 1u : 0u;
+        p->dmax = 0;
+        if (p->periodic) {
+            // at most path_cells faces along an axis: a path of L cells spans at most
+            // (L / n + 2) periods of that axis's nb tiles
+            int lmax = d->path_cells;
+            if (lmax == 0) lmax = d->n[0] > d->n[1] ? (d->n[0] > d->n[2] ? d->n[0] : d->n[2])
+                                                   : (d->n[1] > d->n[2] ? d->n[1] : d->n[2]);
+            if (lmax > RT_MAX_PATH_CELLS) lmax = RT_MAX_PATH_CELLS;
+            p->dmax = 2u * (uint32_t)lmax + 2u;
+            visits = 0;
+            for (int a = 0; a < 3; ++a) visits += (uint32_t)((lmax / d->n[a] + 2) * g.nb[a] + 1);
+            visits -= 2u;
+        }
         p->park_lanes = (uint32_t)d->park_lanes;
         p->park_passes = p->park_lanes ? visits : 0u;
         p->passes = visits + p->park_passes;
@@ -262,6 +281,8 @@ rtk::TiledLaunch tiled_launch(rt_solve_t h, const rtk::MarchLaunch &m) {
     t.passes = p.passes;
     t.park_passes = p.park_passes;
     t.park_lanes = p.park_lanes;
+    t.periodic = p.periodic;
+    t.dmax = p.dmax;
     t.rec = h->ws + p.off_rec;
     t.idx[0] = reinterpret_cast<uint32_t *>(h->ws + p.off_idx0);
     t.idx[1] = reinterpret_cast<uint32_t *>(h->ws + p.off_idx1);

@@ -128,6 +128,8 @@ struct TiledLaunch {
     uint32_t passes;        // passes launched per batch
     uint32_t park_passes;   // passes (from the first) in which packets may be parked
     uint32_t park_lanes;    // park when at most this many lanes still march (0: never)
+    uint32_t periodic;      // periodic boundaries
+    uint32_t dmax;          // periodic: a packet ends once a next-face distance exceeds this
     void *rec;
     uint32_t *idx[2], *side, *cnt, *off, *cbase, *bsum;
     TChunk *chunks[2];

@@ -67,6 +67,8 @@ struct TParams {
     uint32_t refill_min;
     uint32_t park;                        // park at most this many marching lanes (0: never)
     uint32_t g0, nbatch, capacity, cmax, max_chunks, n_tiles;
+    uint32_t periodic;                    // periodic boundaries: neighbour tiles wrap
+    uint32_t dmax;                        // periodic: largest next-face distance (half cells)
     void *rec;
     uint32_t *idx0, *idx1, *side, *cnt, *off, *cbase, *bsum;
     TChunk *ch0, *ch1;
@@ -149,6 +151,26 @@ __device__ __forceinline__ int64_t code_offset(const GridGeom &G, uint32_t code)
     const int dx = (int)(code % 3u) - 1, dy = (int)((code / 3u) % 3u) - 1, dz = (int)(code / 9u) - 1;
     return (int64_t)dx + (int64_t)G.nb[0] * ((int64_t)dy + (int64_t)G.nb[1] * (int64_t)dz);
 }
+
+// Tile reached from `tile` by neighbour code `code`; with periodic boundaries
+// the tile coordinates wrap.  Out of the grid (non-periodic): a negative or
+// too large id, which the callers flag.
+__device__ __forceinline__ int64_t neighbour_tile(const GridGeom &G, uint32_t tile, uint32_t code, bool periodic) {
+    if (!periodic) return (int64_t)tile + code_offset(G, code);
+    const int nx = G.nb[0], ny = G.nb[1], nz = G.nb[2];
+    int x = (int)(tile % (uint32_t)nx) + (int)(code % 3u) - 1;
+    int y = (int)((tile / (uint32_t)nx) % (uint32_t)ny) + (int)((code / 3u) % 3u) - 1;
+    int z = (int)(tile / ((uint32_t)nx * (uint32_t)ny)) + (int)(code / 9u) - 1;
+    x = x < 0 ? x + nx : (x >= nx ? x - nx : x);
+    y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+    z = z < 0 ? z + nz : (z >= nz ? z - nz : z);
+    return (int64_t)x + (int64_t)nx * ((int64_t)y + (int64_t)ny * (int64_t)z);
+}
+
+// Periodic boundaries: a step of one cell that left [0, n) comes back through
+// the opposite face; the tile offset of that step as a neighbour code digit.
+__device__ __forceinline__ int wrap_cell(int k, int n) { return k < 0 ? k + n : (k >= n ? k - n : k); }
+__device__ __forceinline__ int wrap_step(int v) { return v > 1 ? -1 : (v < -1 ? 1 : v); }
 
 __device__ __forceinline__ void wave_sum_pair(double &s, double &c) {
 #pragma unroll
@@ -623,7 +645,7 @@ __global__ void __launch_bounds__(kTBlock) k_tscatter(const TParams p, int cur) 
         if (ch.start > p.capacity || ch.len > p.capacity - ch.start) continue;   // flagged by the march
         if (threadIdx.x < kCodes) {
             // bases of codes this run did not use are never read
-            const int64_t y = (int64_t)ch.tile + code_offset(p.geo, threadIdx.x);
+            const int64_t y = neighbour_tile(p.geo, ch.tile, threadIdx.x, p.periodic != 0u);
             s_dst[threadIdx.x] = (y >= 0 && y < (int64_t)p.n_tiles)
                                      ? p.off[y] + p.cbase[(size_t)c * kCodes + threadIdx.x] : 0xffffffffu;
         }
@@ -650,7 +672,7 @@ template <typename R, int MB> struct TOcc { static constexpr int value = 2; };
 template <> struct TOcc<float, 1> { static constexpr int value = 4; };
 template <> struct TOcc<float, 8> { static constexpr int value = 4; };
 
-template <typename R, int S, bool TH, int MB, int NA, int NB>
+template <typename R, int S, bool TH, int MB, int NA, int NB, bool PER>
 __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const TParams p, int cur) {
     constexpr bool F64 = std::is_same<R, double>::value;
     constexpr uint32_t ACC = (S == 1) ? (TH ? 2u : 1u) : 4u;
@@ -745,11 +767,18 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
             if (trigger && npend != 0u && pend) {
                 bool ex = kill;
                 if constexpr (!F64) ex = kill && dtest.ext.full(tab, active, (float)p.tau_kill, D);
-                const bool o0 = (uint32_t)k0 >= (uint32_t)p.geo.n[0];
-                const bool o1 = (uint32_t)k1 >= (uint32_t)p.geo.n[1];
-                const bool o2 = (uint32_t)k2 >= (uint32_t)p.geo.n[2];
-                const bool out = o0 | o1 | o2;
-                const int dx = (k0 >> kTileLog2) - tx, dy = (k1 >> kTileLog2) - ty, dz = (k2 >> kTileLog2) - tz;
+                // (periodic: the cell has been wrapped at the crossing; "out" is
+                // the end of the packet's path)
+                const bool o0 = !PER && (uint32_t)k0 >= (uint32_t)p.geo.n[0];
+                const bool o1 = !PER && (uint32_t)k1 >= (uint32_t)p.geo.n[1];
+                const bool o2 = !PER && (uint32_t)k2 >= (uint32_t)p.geo.n[2];
+                const bool out = PER ? (d0 > p.dmax || d1 > p.dmax || d2 > p.dmax) : (o0 | o1 | o2);
+                int dx = (k0 >> kTileLog2) - tx, dy = (k1 >> kTileLog2) - ty, dz = (k2 >> kTileLog2) - tz;
+                if constexpr (PER) {
+                    dx = wrap_step(dx);
+                    dy = wrap_step(dy);
+                    dz = wrap_step(dz);
+                }
                 const bool leave = !out && (dx | dy | dz) != 0;
                 const uint32_t fate = ex ? 1u : (out ? 2u : (leave ? 3u : 0u));
                 if (fate != 0u) {                  // fate 0: a new witness bin, the packet marches on
@@ -780,7 +809,8 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                                 : ((o0 ? 1 : 0) | (o1 ? 2 : 0) | (o2 ? 4 : 0)
                                    | (k0 >= p.geo.n[0] ? 8 : 0) | (k1 >= p.geo.n[1] ? 16 : 0)
                                    | (k2 >= p.geo.n[2] ? 32 : 0));
-                            rec[0] = (int32_t)count; rec[1] = (int32_t)fate; rec[2] = face; rec[3] = hlast;
+                            rec[0] = (int32_t)count; rec[1] = (PER && fate == 2u) ? 3 : (int32_t)fate;
+                            rec[2] = face; rec[3] = hlast;
                             rec[4] = unpack_dir(a0);
                             rec[5] = unpack_dir(a1);
                             rec[6] = unpack_dir(a2);
@@ -912,11 +942,25 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                 if (m0) { k0 += (a0 & kNeg) ? -1 : 1; d0 += 2u; }
                 if (m1) { k1 += (a1 & kNeg) ? -1 : 1; d1 += 2u; }
                 if (m2) { k2 += (a2 & kNeg) ? -1 : 1; d2 += 2u; }
-                const bool o0 = (uint32_t)k0 >= (uint32_t)p.geo.n[0];
-                const bool o1 = (uint32_t)k1 >= (uint32_t)p.geo.n[1];
-                const bool o2 = (uint32_t)k2 >= (uint32_t)p.geo.n[2];
-                const bool out = o0 | o1 | o2;
-                const int dx = (k0 >> kTileLog2) - tx, dy = (k1 >> kTileLog2) - ty, dz = (k2 >> kTileLog2) - tz;
+                bool out;
+                int dx, dy, dz;
+                if constexpr (PER) {
+                    // Sec. 2, periodic boundaries: back in through the opposite
+                    // face; the path ends past dmax half cells along an axis
+                    k0 = wrap_cell(k0, p.geo.n[0]);
+                    k1 = wrap_cell(k1, p.geo.n[1]);
+                    k2 = wrap_cell(k2, p.geo.n[2]);
+                    out = d0 > p.dmax || d1 > p.dmax || d2 > p.dmax;
+                    dx = wrap_step((k0 >> kTileLog2) - tx);
+                    dy = wrap_step((k1 >> kTileLog2) - ty);
+                    dz = wrap_step((k2 >> kTileLog2) - tz);
+                } else {
+                    out = (uint32_t)k0 >= (uint32_t)p.geo.n[0] || (uint32_t)k1 >= (uint32_t)p.geo.n[1]
+                        || (uint32_t)k2 >= (uint32_t)p.geo.n[2];
+                    dx = (k0 >> kTileLog2) - tx;
+                    dy = (k1 >> kTileLog2) - ty;
+                    dz = (k2 >> kTileLog2) - tz;
+                }
                 const bool leave = !out && (dx | dy | dz) != 0;
                 // next cell's absorbers, read before this cell's arithmetic (the
                 // masked index stays inside the tile; unused when the packet leaves)
@@ -1001,7 +1045,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
         if (threadIdx.x < kCodes) {
             const uint32_t n = s_cnt[threadIdx.x];
             if (n != 0u) {
-                const int64_t y = (int64_t)tile + code_offset(p.geo, threadIdx.x);
+                const int64_t y = neighbour_tile(p.geo, tile, threadIdx.x, PER);
                 if (y >= 0 && y < (int64_t)p.n_tiles) p.cbase[(size_t)c * kCodes + threadIdx.x] = atomicAdd(p.cnt + y, n);
                 else atomicOr(&p.ctrl->err, 32u);
             }
@@ -1071,6 +1115,8 @@ TParams make_params(const TiledLaunch &t) {
     p.cmax = t.cmax;
     p.max_chunks = t.max_chunks;
     p.n_tiles = t.n_tiles;
+    p.periodic = t.periodic;
+    p.dmax = t.dmax;
     p.rec = t.rec;
     p.idx0 = t.idx[0];
     p.idx1 = t.idx[1];
@@ -1135,7 +1181,10 @@ void run_passes(const TParams &p, const TiledLaunch &t) {
         pp.park = pass < t.park_passes ? t.park_lanes : 0u;
         const bool timed = t.ev && *t.ev_used < t.ev_cap;
         if (timed) (void)hipEventRecord(t.ev[2 * *t.ev_used], st);
-        hipLaunchKernelGGL((k_tmarch<R, S, TH, MB, NA, NB>), grid, blk, 0, st, pp, cur);
+        if (p.periodic)
+            hipLaunchKernelGGL((k_tmarch<R, S, TH, MB, NA, NB, true>), grid, blk, 0, st, pp, cur);
+        else
+            hipLaunchKernelGGL((k_tmarch<R, S, TH, MB, NA, NB, false>), grid, blk, 0, st, pp, cur);
         if (timed) {
             (void)hipEventRecord(t.ev[2 * *t.ev_used + 1], st);
             ++*t.ev_used;
@@ -1152,7 +1201,7 @@ void run_passes(const TParams &p, const TiledLaunch &t) {
 template <typename R, int S, bool TH, int MB>
 hipError_t occ(int *n) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        n, reinterpret_cast<const void *>(&k_tmarch<R, S, TH, MB, 0, 0>), kTBlock, 0);
+        n, reinterpret_cast<const void *>(&k_tmarch<R, S, TH, MB, 0, 0, false>), kTBlock, 0);
 }
 
 template <typename R, int S, bool TH, int MB, int NA, int NB>

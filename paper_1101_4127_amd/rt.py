@@ -18,10 +18,11 @@ LIB_PATH = os.path.join(PKG, "librt_mcrt.so")
 
 RT_MAX_BINS = 16
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_ESTATE, RT_EOVERFLOW, RT_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
-RT_ISOTHERMAL, RT_FP64, RT_TIME_MARCH, RT_DIRECT_MARCH, RT_RECOMB = 0x1, 0x2, 0x4, 0x8, 0x10
+RT_ISOTHERMAL, RT_FP64, RT_TIME_MARCH, RT_DIRECT_MARCH, RT_RECOMB, RT_PERIODIC = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
+RT_MAX_PATH_CELLS = 2046
 RT_SRC_CORNER_OCTANT = 0x1
 RT_TRACE_HDR = 8
-RT_FATE_TRUNC, RT_FATE_ESCAPE = 1, 2
+RT_FATE_TRUNC, RT_FATE_ESCAPE, RT_FATE_PATH = 1, 2, 3
 RT_MAX_BATCH = 64
 RT_BATCH_GRAPH = 0x1
 
@@ -43,7 +44,7 @@ class GridDesc(C.Structure):
         ("brick_log2", C.c_int32), ("wave_chunk", C.c_int32), ("refill_min", C.c_int32),
         ("blocks_per_cu", C.c_int32), ("trace_packets", C.c_int32), ("trace_len", C.c_int32),
         ("trace_stride", C.c_int32), ("run_len", C.c_int32), ("park_lanes", C.c_int32),
-        ("inflight", C.c_int64),
+        ("inflight", C.c_int64), ("path_cells", C.c_int32),
     ]
 
 
@@ -294,7 +295,8 @@ def desc_from_workload(work, *, fp64: Optional[bool] = None, brick_log2: int = -
     f64 = bool(work.flags & 0x2) if fp64 is None else bool(fp64)
     d.flags = ((RT_ISOTHERMAL if work.flags & 0x1 else 0) | (RT_FP64 if f64 else 0)
                | (RT_TIME_MARCH if time_march else 0) | (RT_DIRECT_MARCH if direct else 0)
-               | (RT_RECOMB if getattr(work, "recomb", None) is not None else 0))
+               | (RT_RECOMB if getattr(work, "recomb", None) is not None else 0)
+               | (RT_PERIODIC if getattr(work, "periodic", False) else 0))
     d.solve_id = int(work.solve_id)
     d.brick_log2 = int(brick_log2)
     d.wave_chunk = int(wave_chunk)
@@ -306,6 +308,7 @@ def desc_from_workload(work, *, fp64: Optional[bool] = None, brick_log2: int = -
     d.run_len = int(run_len)
     d.park_lanes = int(park_lanes)
     d.inflight = int(inflight)
+    d.path_cells = int(getattr(work, "path_cells", 0) or 0)
     return d
 
 

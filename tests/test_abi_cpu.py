@@ -46,12 +46,13 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "{HEADER}"
 int main(void) {{
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(rt_grid_desc), offsetof(rt_grid_desc, solve_id),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(rt_grid_desc), offsetof(rt_grid_desc, solve_id),
          offsetof(rt_grid_desc, trace_stride), offsetof(rt_grid_desc, run_len),
          offsetof(rt_grid_desc, inflight), sizeof(rt_step_stats),
          offsetof(rt_step_stats, crossings), offsetof(rt_step_stats, nonfinite),
          offsetof(rt_step_stats, errors), offsetof(rt_step_stats, march_ms),
-         offsetof(rt_step_stats, kernel_launches));
+         offsetof(rt_step_stats, kernel_launches), offsetof(rt_grid_desc, path_cells),
+         offsetof(rt_step_stats, diffuse_packets));
   return 0;
 }}""")
     exe = tmp_path / "layout"
@@ -61,7 +62,8 @@ int main(void) {{
                     rt.GridDesc.run_len.offset, rt.GridDesc.inflight.offset,
                     C.sizeof(rt.StepStats), rt.StepStats.crossings.offset, rt.StepStats.nonfinite.offset,
                     rt.StepStats.errors.offset, rt.StepStats.march_ms.offset,
-                    rt.StepStats.kernel_launches.offset]
+                    rt.StepStats.kernel_launches.offset, rt.GridDesc.path_cells.offset,
+                    rt.StepStats.diffuse_packets.offset]
 
 
 def test_defaults_and_strerror(L):
@@ -87,7 +89,8 @@ def test_workspace_bytes_scales_and_validates(L):
     # invalid descriptions
     for field, bad in (("n_bins", 0), ("n_bins", 9), ("n_bins", 17), ("tau_kill", 0.0), ("n_sub", 0), ("n_chem", 0),
                        ("cell_cm", -1.0), ("brick_log2", 4), ("wave_chunk", 100), ("refill_min", 65),
-                       ("flags", 0x20), ("flags", rt.RT_RECOMB | rt.RT_DIRECT_MARCH), ("trace_stride", -1), ("brick_log2", 2), ("run_len", 10),
+                       ("flags", 0x40), ("flags", rt.RT_RECOMB | rt.RT_DIRECT_MARCH),
+                       ("flags", rt.RT_PERIODIC | rt.RT_DIRECT_MARCH), ("path_cells", -1), ("path_cells", 2047), ("trace_stride", -1), ("brick_log2", 2), ("run_len", 10),
                        ("run_len", 2049), ("park_lanes", -1), ("park_lanes", 65), ("inflight", -1), ("inflight", 1 << 31)):
         e = rt.rt_desc_defaults()
         setattr(e, field, bad)

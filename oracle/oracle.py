@@ -50,6 +50,10 @@ class Reemit(C.Structure):
                 ("dlog10_t", C.c_double), ("milne", C.POINTER(C.c_double))]
 
 
+class Background(C.Structure):
+    _fields_ = [("ndot", C.c_double), ("sed", C.POINTER(C.c_double)), ("packets", C.c_int64)]
+
+
 class Rates(C.Structure):
     _fields_ = [("a_hii", C.c_double), ("a_heii", C.c_double), ("a_heiii", C.c_double),
                 ("b_hi", C.c_double), ("b_hei", C.c_double), ("b_heii", C.c_double)]
@@ -87,7 +91,7 @@ def lib():
                                    C.c_double, C.c_int64, C.c_int32, C.c_uint64, C.c_uint64,
                                    u64p, dp, dp, dp, C.c_int32, C.c_int32, C.c_int32, ip]
             L.orc_step.restype = C.c_int
-            L.orc_step_rx.argtypes = L.orc_step.argtypes + [_P(Reemit), dp]
+            L.orc_step_rx.argtypes = L.orc_step.argtypes + [_P(Reemit), dp, _P(Background)]
             L.orc_step_rx.restype = C.c_int
             L.orc_rates_case_a.argtypes = [C.c_double, _P(Rates)]
             L.orc_ground_fraction.argtypes = [C.c_double, dp]
@@ -269,6 +273,11 @@ class OracleSolve:
             self._milne = _c64(r.milne).copy()
             self._reemit = Reemit(float(r.f_rec), int(r.n_t), float(r.log10_t0), float(r.dlog10_t),
                                   _ptr(self._milne, C.c_double))
+        self._bg = None
+        if getattr(work, "background", None) is not None:
+            b = work.background
+            self._bg_sed = _c64(b.sed).copy()
+            self._bg = Background(float(b.ndot), _ptr(self._bg_sed, C.c_double), int(b.packets))
 
     def step(self, dt: Optional[float] = None, packets: Optional[int] = None,
              seed: Optional[int] = None, trace_n: int = 0, trace_len: int = 0,
@@ -288,7 +297,8 @@ class OracleSolve:
                                _ptr(self.kappa, C.c_double), _ptr(led, C.c_double),
                                int(trace_n), int(trace_len), int(trace_stride), _ptr(tr, C.c_int32),
                                C.byref(self._reemit) if self._reemit is not None else None,
-                               _ptr(self.rc, C.c_double))
+                               _ptr(self.rc, C.c_double),
+                               C.byref(self._bg) if self._bg is not None else None)
         if rc != 0:
             raise ValueError("oracle step rejected: fewer packets than sources in a sub-step")
         self.trace = tr

@@ -786,8 +786,8 @@ static void milne_at(const orc_reemit *E, int nb, int ion, double T, double *out
 /*
  * One sub-step's recombination emission, after the source packets have been
  * marched (their deposits in acc, the crossing test) and before the cell
- * update.  A cell crossed by a source packet in this sub-step (some photons
- * deposited in it) emits one diffuse packet holding, for every ion whose
+ * update.  A cell crossed by a source or background packet in this sub-step
+ * (some photons deposited in it) emits one diffuse packet holding, for every ion whose
  * counter is positive and at least f_rec, counter x atoms x ground-state share
  * photons with that ion's Milne spectrum at the cell's temperature; those
  * counters restart from zero.  The packet leaves the cell centre in an
@@ -861,11 +861,82 @@ int64_t orc_reemit_substep(const orc_grid *G, const orc_reemit *E, const double 
     return ne;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Background field (Sec. 2: packets from diffuse fields such as the UV      */
+/* background): photons entering the box through its faces.                  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double ndot;               /* photons per second entering through the whole boundary */
+    const double *sed;         /* [n_bins] photon fraction per bin */
+    int64_t packets;           /* packets per step (shared over the sub-steps like source packets) */
+} orc_background;
+
+/*
+ * Background packet b of a sub-step.  Its boundary cell face is uniform over
+ * all 2 (n1 n2 + n0 n2 + n0 n1) faces of boundary cells: Philox block at
+ * counter (b, sub-step, 0, 2), word 0 scaled to that count by a 64x64 -> high
+ * 64 multiply; faces in the order x-, x+, y-, y+, z-, z+, cells x fastest.
+ * It starts at the centre of that face, its direction is the isotropic one of
+ * stream word 3 turned inward along the face normal, and, the field being
+ * isotropic, its weight carries the cosine to the normal:
+ * w = (ndot dt / P) 2 |c_n| / |c| (2 cos theta averages 1 over the hemisphere).
+ */
+static double background_packet(const orc_grid *G, const orc_background *B, double dt, int64_t P,
+                                uint64_t seed, uint64_t solve_id, uint64_t step_index, uint64_t b,
+                                int32_t o[3], int32_t c[3])
+{
+    const int64_t n0 = G->n[0], n1 = G->n[1], n2 = G->n[2];
+    const uint64_t faces[6] = {(uint64_t)(n1 * n2), (uint64_t)(n1 * n2), (uint64_t)(n0 * n2),
+                               (uint64_t)(n0 * n2), (uint64_t)(n0 * n1), (uint64_t)(n0 * n1)};
+    const uint64_t total = 2 * (faces[0] + faces[2] + faces[4]);
+    const uint64_t key[2] = {seed, solve_id};
+    const uint64_t ctr[4] = {b, step_index, 0, 2};
+    uint64_t r[4], hi, lo;
+    orc_philox4x64_10(ctr, key, r);
+    mul128(r[0], total, &hi, &lo);
+    uint64_t idx = hi;
+    int f = 0;
+    while (idx >= faces[f]) { idx -= faces[f]; ++f; }
+    const int axis = f / 2, plus = f % 2;
+    const int u = axis == 0 ? 1 : 0, v = axis == 2 ? 1 : 2;       /* the face's two in-plane axes */
+    const int64_t a = (int64_t)(idx % (uint64_t)G->n[u]), bb = (int64_t)(idx / (uint64_t)G->n[u]);
+    o[axis] = plus ? 2 * G->n[axis] : 0;
+    o[u] = (int32_t)(2 * a + 1);
+    o[v] = (int32_t)(2 * bb + 1);
+    orc_direction_ex(seed, solve_id, b, step_index, 0, 3, c);
+    const int32_t cn = c[axis] < 0 ? -c[axis] : c[axis];
+    c[axis] = plus ? -cn : cn;
+    const double q = (double)((int64_t)c[0] * c[0] + (int64_t)c[1] * c[1] + (int64_t)c[2] * c[2]);
+    double w = B->ndot * dt;
+    w = w / (double)P;
+    return w * (2.0 * (double)cn) / sqrt(q);
+}
+
+/* March background packets [0, P) of one sub-step. */
+void orc_march_background(const orc_grid *G, const double *kappa, const orc_background *B, double dt,
+                          int64_t P, uint64_t seed, uint64_t solve_id, uint64_t step_index,
+                          double *acc, double *ledger)
+{
+    const int nb = G->n_bins;
+    double heat_ev[3][ORC_MAX_BINS];
+    heat_table(G, heat_ev);
+    double carried = 0.0;
+    for (int j = 0; j < nb; ++j) carried += B->sed[j];
+    for (int64_t b = 0; b < P; ++b) {
+        int32_t o[3], c[3];
+        const double w = background_packet(G, B, dt, P, seed, solve_id, step_index, (uint64_t)b, o, c);
+        nsum(&ledger[L_EMIT], &ledger[L_EMIT + 1], w * carried);
+        ledger[L_PACKETS] += 1.0;
+        march_packet(G, kappa, heat_ev, w, B->sed, o, c, acc, ledger, 0, NULL);
+    }
+}
+
 /*
  * One call = n_sub frozen sub-steps of dt / n_sub, the packets shared as
  * evenly as possible (the first P mod n_sub sub-steps get one more).  Each
  * sub-step: absorbers, zeroed accumulators, march of every packet in id order,
- * [with E: recombination emission and the march of its packets,] cell update
+ * [with B: the background packets of the sub-step,] [with E: recombination
+ * emission, decided from all deposits so far, and the march of its packets,] cell update
  * (with E: case-A rates and the counters rc [3][ncell]).  *step_index is the
  * Philox sub-step counter, advanced once per sub-step.  acc holds the last
  * sub-step's deposits on return; ledger accumulates over all sub-steps; trace
@@ -878,7 +949,7 @@ int orc_step_rx(const orc_grid *G, const double *nh, double *x, double *T,
                 double dt, int64_t P, int32_t n_sub, uint64_t seed, uint64_t solve_id,
                 uint64_t *step_index, double *acc, double *kappa, double *ledger,
                 int32_t trace_n, int32_t trace_len, int32_t trace_stride, int32_t *trace,
-                const orc_reemit *E, double *rc)
+                const orc_reemit *E, double *rc, const orc_background *B)
 {
     const int64_t ncell = (int64_t)G->n[0] * G->n[1] * G->n[2];
     if (n_src > 0 && P / n_sub < n_src) return -1;
@@ -891,6 +962,11 @@ int orc_step_rx(const orc_grid *G, const double *nh, double *x, double *T,
             orc_march(G, kappa, n_src, src_ijk, src_ndot, src_sed, src_flags, dts, Pi,
                       seed, solve_id, *step_index, 0, Pi, acc, ledger, trace_n, trace_len,
                       trace_stride, trace);
+        if (B && B->packets > 0) {
+            const int64_t Pb = B->packets / n_sub + (i < B->packets % n_sub ? 1 : 0);
+            if (Pb > 0)
+                orc_march_background(G, kappa, B, dts, Pb, seed, solve_id, *step_index, acc, ledger);
+        }
         if (E) {
             orc_reemit_substep(G, E, nh, T, kappa, rc, seed, solve_id, *step_index, acc, ledger);
             orc_update_cells_rx(G, dts, nh, x, T, acc, rc);
@@ -911,5 +987,5 @@ int orc_step(const orc_grid *G, const double *nh, double *x, double *T,
 {
     return orc_step_rx(G, nh, x, T, n_src, src_ijk, src_ndot, src_sed, src_flags, dt, P, n_sub, seed,
                        solve_id, step_index, acc, kappa, ledger, trace_n, trace_len, trace_stride, trace,
-                       NULL, NULL);
+                       NULL, NULL, NULL);
 }

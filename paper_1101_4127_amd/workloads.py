@@ -258,6 +258,24 @@ SRC_CORNER_OCTANT = 0x1
 
 
 @dataclasses.dataclass
+class Background:
+    """An isotropic background field entering the box through its faces:
+    photons per second through the whole boundary, their spectrum over the
+    bins, and packets per step."""
+    ndot: float
+    sed: np.ndarray
+    packets: int
+
+
+def background_rate(j_photons: float, n: Sequence[int], cell_cm: float) -> float:
+    """Photons per second entering a box through all six faces from an
+    isotropic intensity j_photons [photons s^-1 cm^-2 sr^-1]: the inward flux
+    through a surface is pi j, times the boundary area."""
+    area = 2.0 * (n[1] * n[2] + n[0] * n[2] + n[0] * n[1]) * cell_cm * cell_cm
+    return math.pi * j_photons * area
+
+
+@dataclasses.dataclass
 class Workload:
     name: str
     n: tuple                    # cells per axis
@@ -284,6 +302,7 @@ class Workload:
     recomb: Optional[RecombEmission] = None   # recombination re-emission (None: off)
     periodic: bool = False      # periodic boundaries (packets re-enter through the opposite face)
     path_cells: int = 0         # periodic: faces a packet may cross along one axis (0: the longest side)
+    background: Optional[Background] = None   # background field through the faces (None: none)
 
     @property
     def ncell(self) -> int:

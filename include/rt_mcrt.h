@@ -252,6 +252,21 @@ int32_t rt_step(rt_solve_t h, double dt_s, int64_t n_packets, uint64_t seed, rt_
 int32_t rt_set_recombination(rt_solve_t h, double f_rec, int32_t n_t, double log10_t0, double dlog10_t,
                              const double *h_milne, const void *d_counters, int32_t counters_fp64);
 
+/* Background field of a solve (Sec. 2: packets from diffuse fields such as the
+ * UV background), an isotropic intensity entering the box through its faces.
+ *   ndot              photons per second through the whole boundary (for an
+ *                     intensity J in photons/s/cm^2/sr: pi J times the area)
+ *   h_sed             host [n_bins] photon fraction per bin (>= 0, sum > 0)
+ *   packets_per_step  background packets per rt_step, shared over the
+ *                     sub-steps like source packets; 0 switches the field off
+ * In each sub-step, after the source packets, packet g starts at the centre of
+ * a boundary cell face chosen uniformly over the boundary (Philox counter
+ * (g, sub-step, 0, 2)), moves in the isotropic direction of stream word 3
+ * turned inward, and carries (ndot dt_sub / P) 2 cos(theta) photons per unit
+ * of the spectrum.  Tiled march only (else RT_ESTATE); solves with a
+ * background do not enter rt_step_many.  Synchronous. */
+int32_t rt_set_background(rt_solve_t h, double ndot, const double *h_sed, int64_t packets_per_step);
+
 /* Synchronise the handle's stream and return the ledger of the last rt_step. */
 int32_t rt_read_stats(rt_solve_t h, rt_step_stats *stats);
 

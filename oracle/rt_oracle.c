@@ -904,7 +904,8 @@ static double background_packet(const orc_grid *G, const orc_background *B, doub
     o[u] = (int32_t)(2 * a + 1);
     o[v] = (int32_t)(2 * bb + 1);
     orc_direction_ex(seed, solve_id, b, step_index, 0, 3, c);
-    const int32_t cn = c[axis] < 0 ? -c[axis] : c[axis];
+    int32_t cn = c[axis] < 0 ? -c[axis] : c[axis];
+    if (cn == 0) cn = 1;                        /* never along the face itself */
     c[axis] = plus ? -cn : cn;
     const double q = (double)((int64_t)c[0] * c[0] + (int64_t)c[1] * c[1] + (int64_t)c[2] * c[2]);
     double w = B->ndot * dt;

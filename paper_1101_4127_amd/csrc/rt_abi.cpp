@@ -39,6 +39,7 @@ struct Plan {
         off_ledger, off_queue, off_trace, off_stage, total;
     bool recomb;            // recombination photons re-emitted as packets
     size_t off_rc, off_milne;
+    size_t off_bg;          // background spectrum row
     // tiled march
     uint32_t capacity, cmax, max_chunks, n_tiles, scan_blocks, passes, park_passes, park_lanes;
     uint32_t periodic, dmax;
@@ -129,6 +130,7 @@ int32_t make_plan(const rt_grid_desc *d, int64_t max_sources, Plan *p) {
     p->off_trace = o;
     o = align_up(o + (size_t)d->trace_packets * (RT_TRACE_HDR + (size_t)d->trace_len) * sizeof(int32_t));
     p->off_stage = o; o = align_up(o + (size_t)p->ncell * sizeof(double));
+    p->off_bg = o; o = align_up(o + (size_t)p->mb * p->real);
     p->recomb = (d->flags & RT_RECOMB) != 0;
     p->off_rc = p->off_milne = 0;
     if (p->recomb) {
@@ -244,6 +246,10 @@ struct rt_solve {
     bool recomb_set;
     double f_rec, log10_t0, dlog10_t;
     int32_t n_t;
+    // background field (rt_set_background)
+    double bg_ndot, bg_carried;
+    int64_t bg_packets;
+    uint32_t bg_active;
 };
 
 namespace {
@@ -410,6 +416,9 @@ int32_t rt_init_grid(const rt_grid_desc *d, void *d_ws, size_t ws_bytes, int64_t
     h->recomb_set = false;
     h->f_rec = h->log10_t0 = h->dlog10_t = 0.0;
     h->n_t = 0;
+    h->bg_ndot = h->bg_carried = 0.0;
+    h->bg_packets = 0;
+    h->bg_active = 0u;
     if (d->flags & RT_TIME_MARCH) {
         h->ev.resize(2 * kMaxTimedSubsteps);
         h->kev.resize(p.tiled ? 2 * kMaxTimedKernels : 0);
@@ -596,7 +605,9 @@ int32_t rt_step(rt_solve_t h, double dt_s, int64_t n_packets, uint64_t seed, rt_
     for (int32_t i = 0; i < nsub; ++i) {
         const int64_t Pi = base + (i < extra ? 1 : 0);
         if (rtk::launch_prep(c) != hipSuccess) return fail(h);
-        const bool march = h->n_src > 0 && Pi > 0;
+        const bool sources = h->n_src > 0 && Pi > 0;
+        const int64_t Pb = h->bg_packets / nsub + (i < h->bg_packets % nsub ? 1 : 0);
+        const bool march = sources || Pb > 0;
         if (march) {
             m.packets = (uint32_t)Pi;
             m.step_index = h->step_index;
@@ -610,10 +621,25 @@ int32_t rt_step(rt_solve_t h, double dt_s, int64_t n_packets, uint64_t seed, rt_
                     t.ev_used = &h->ktimed;
                 }
                 if (rtk::launch_tiled_slots_zero(t) != hipSuccess) return fail(h);
-                for (int64_t g0 = 0; g0 < Pi; g0 += p.capacity) {
+                for (int64_t g0 = 0; sources && g0 < Pi; g0 += p.capacity) {
                     t.g0 = (uint32_t)g0;
                     t.nbatch = (uint32_t)(Pi - g0 < (int64_t)p.capacity ? Pi - g0 : p.capacity);
                     if (rtk::launch_tiled_batch(t) != hipSuccess) return fail(h);
+                }
+                if (Pb > 0) {
+                    rtk::BackgroundParams bp;
+                    bp.ndot = h->bg_ndot;
+                    bp.carried = h->bg_carried;
+                    bp.sed = h->ws + p.off_bg;
+                    bp.active = h->bg_active;
+                    bp.packets = (uint32_t)Pb;
+                    bp.pad = 0;
+                    for (int64_t g0 = 0; g0 < Pb; g0 += p.capacity) {
+                        bp.g0 = (uint32_t)g0;
+                        t.g0 = 0;
+                        t.nbatch = (uint32_t)(Pb - g0 < (int64_t)p.capacity ? Pb - g0 : p.capacity);
+                        if (rtk::launch_tiled_background(t, bp) != hipSuccess) return fail(h);
+                    }
                 }
                 if (p.recomb && rtk::launch_tiled_reemit(t, recomb_params(h)) != hipSuccess) return fail(h);
             } else if (rtk::launch_march(m) != hipSuccess) {
@@ -695,6 +721,45 @@ int32_t rt_set_recombination(rt_solve_t h, double f_rec, int32_t n_t, double log
     h->log10_t0 = log10_t0;
     h->dlog10_t = dlog10_t;
     h->recomb_set = true;
+    return RT_OK;
+}
+
+int32_t rt_set_background(rt_solve_t h, double ndot, const double *h_sed, int64_t packets_per_step) {
+    if (!valid(h)) return RT_EINVAL;
+    if (h->dead) return RT_ESTATE;
+    const Plan &p = h->plan;
+    if (!p.tiled) return RT_ESTATE;
+    if (!finite_nonneg(ndot) || packets_per_step < 0) return RT_EINVAL;
+    if (packets_per_step / h->d.n_sub + 1 > ((int64_t)1 << 31)) return RT_EOVERFLOW;
+    if (packets_per_step == 0) {
+        h->bg_packets = 0;
+        return RT_OK;
+    }
+    if (!h_sed) return RT_EINVAL;
+    const int nb = h->d.n_bins, mb = p.mb;
+    std::vector<double> sd(mb, 0.0);
+    std::vector<float> sf(mb, 0.0f);
+    double carried = 0.0, sum = 0.0;
+    uint32_t active = 0u;
+    for (int j = 0; j < nb; ++j) {
+        const double v = h_sed[j];
+        if (!finite_nonneg(v)) return RT_EINVAL;
+        sd[j] = v;
+        sf[j] = (float)v;
+        sum += v;
+        carried += v;                       // as for source rows: the float64 spectrum's sum
+        if (v > 0.0) active |= 1u << j;
+    }
+    if (!(sum > 0.0)) return RT_EINVAL;
+    const void *src = p.fp64 ? (const void *)sd.data() : (const void *)sf.data();
+    if (hipMemcpyAsync(h->ws + p.off_bg, src, (size_t)mb * p.real, hipMemcpyHostToDevice, h->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+        return fail(h);
+    h->bg_ndot = ndot;
+    h->bg_carried = carried;
+    h->bg_active = active;
+    h->bg_packets = packets_per_step;
     return RT_OK;
 }
 
@@ -924,7 +989,8 @@ int32_t rt_step_many(rt_batch_t b, const rt_solve_t *solves, int32_t n, const do
         for (int k = 0; k < i; ++k)
             if (solves[k] == h) return RT_EINVAL;
         const Plan &p = h->plan;
-        if (h->device != b->device || p.species != 1 || p.mb != 1 || h->d.trace_packets > 0 || p.recomb)
+        if (h->device != b->device || p.species != 1 || p.mb != 1 || h->d.trace_packets > 0 || p.recomb ||
+            h->bg_packets > 0)
             return RT_EINVAL;
         if ((fp64 >= 0 && p.fp64 != fp64) || (thermal >= 0 && p.thermal != thermal)) return RT_EINVAL;
         fp64 = p.fp64;

@@ -155,7 +155,20 @@ struct RecombParams {
     StepLedger *ledger;
 };
 
+// Background packets of one batch of a sub-step (packet ids g0.. of the
+// sub-step's `packets`; TiledLaunch.nbatch of them).
+struct BackgroundParams {
+    double ndot;           // photons / s entering through the boundary
+    double carried;        // sum of the spectrum row as stored
+    const void *sed;       // [mb] photon fraction per bin, march precision
+    uint32_t active;       // bins with photons
+    uint32_t g0;           // first packet id of the batch
+    uint32_t packets;      // background packets of the sub-step
+    uint32_t pad;
+};
+
 size_t tiled_record_bytes(int fp64, int species, int mb);
+hipError_t launch_tiled_background(const TiledLaunch &t, const BackgroundParams &b);
 // Recombination emission of the sub-step and the march of its packets (after
 // the sub-step's source batches, before the cell update).
 hipError_t launch_tiled_reemit(const TiledLaunch &t, const RecombParams &r);

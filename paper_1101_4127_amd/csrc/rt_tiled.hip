@@ -511,6 +511,101 @@ __global__ void __launch_bounds__(kTBlock) k_remit(const TParams p, const Recomb
     block_ledger_add(p.slots + blockIdx.x, v, cc);
 }
 
+// ---------------------------------------------------------------------------
+// Background field (Sec. 2: packets from diffuse fields such as the UV
+// background), an isotropic intensity entering through the box faces.
+// Packet g of a sub-step starts at the centre of a boundary cell face chosen
+// uniformly over all 2 (n1 n2 + n0 n2 + n0 n1) of them (Philox counter
+// (g, sub-step, 0, 2), word 0 scaled by a high multiply; faces x-, x+, y-, y+,
+// z-, z+, cells x fastest), takes the isotropic direction of stream word 3
+// turned inward, and carries w = (ndot dt / P) 2 |c_n| / |c| photons per unit
+// of the spectrum (2 cos theta averages 1 over the hemisphere).
+// ---------------------------------------------------------------------------
+template <typename R, int S, int MB>
+__global__ void __launch_bounds__(kTBlock) k_bgemit(const TParams p, const BackgroundParams bp) {
+    using RL = TRec<R, S, MB>;
+    constexpr int ND = RL::ND;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
+    const uint32_t gw = (blockIdx.x * kTBlock + threadIdx.x) >> 6;
+    const uint32_t nw = gridDim.x * kTWaves;
+    const R *sed = reinterpret_cast<const R *>(bp.sed);
+    uint4 *recs = reinterpret_cast<uint4 *>(p.rec);
+    const int n0 = p.geo.n[0], n1 = p.geo.n[1], n2 = p.geo.n[2];
+    const uint64_t fx = (uint64_t)n1 * n2, fy = (uint64_t)n0 * n2, fz = (uint64_t)n0 * n1;
+    const uint64_t total = 2ull * (fx + fy + fz);
+    double l_emit = 0.0;
+    uint32_t n_pk = 0;
+    for (uint32_t base = gw * 64u; base < p.nbatch; base += nw * 64u) {
+        const uint32_t i = base + lane;
+        const bool act = i < p.nbatch;
+        uint32_t tile = 0;
+        if (act) {
+            const uint64_t g = (uint64_t)bp.g0 + i;
+            const U64x4 r = philox4x64_10(g, p.step, 0ull, 2ull, p.seed, p.solve_id);
+            uint64_t idx = __umul64hi(r.v[0], total);
+            int axis, plus;
+            if (idx < 2ull * fx) { axis = 0; plus = idx >= fx; idx -= plus ? fx : 0ull; }
+            else if ((idx -= 2ull * fx) < 2ull * fy) { axis = 1; plus = idx >= fy; idx -= plus ? fy : 0ull; }
+            else { idx -= 2ull * fy; axis = 2; plus = idx >= fz; idx -= plus ? fz : 0ull; }
+            const int u = axis == 0 ? 1 : 0, v = axis == 2 ? 1 : 2;
+            const uint64_t nu = (uint64_t)p.geo.n[u];
+            const int ia = (int)(idx % nu), ib = (int)(idx / nu);
+            int32_t o[3], kk[3], c[3];
+            o[axis] = plus ? 2 * p.geo.n[axis] : 0;
+            kk[axis] = plus ? p.geo.n[axis] - 1 : 0;
+            o[u] = 2 * ia + 1;
+            kk[u] = ia;
+            o[v] = 2 * ib + 1;
+            kk[v] = ib;
+            sample_direction(p.seed, p.solve_id, g, p.step, false, c, 3ull);
+            int32_t cn = c[axis] < 0 ? -c[axis] : c[axis];
+            if (cn == 0) cn = 1;                               // never along the face itself
+            c[axis] = plus ? -cn : cn;
+            const int64_t qq = (int64_t)c[0] * c[0] + (int64_t)c[1] * c[1] + (int64_t)c[2] * c[2];
+            double ww = bp.ndot * p.dt;
+            ww = ww / (double)bp.packets;
+            ww = ww * (2.0 * (double)cn) / sqrt((double)qq);
+            l_emit += ww * bp.carried;
+            n_pk += 1u;
+            const uint32_t active = bp.active;
+            R F[MB], D[ND];
+#pragma unroll
+            for (int j = 0; j < MB; ++j) F[j] = sed[j];
+#pragma unroll
+            for (int j = 0; j < ND; ++j) D[j] = (!RL::F64 || ((active >> j) & 1u)) ? R(0) : R(INFINITY);
+            const uint32_t a0 = pack_dir(c[0]), a1 = pack_dir(c[1]), a2 = pack_dir(c[2]);
+            const double Ld = sqrt((double)qq) * p.half_dl;
+            const R len = RL::F64 ? (R)Ld : (R)(Ld * p.len_scale);
+            const uint32_t jw = active ? (uint32_t)__builtin_ctz(active) : 0u;
+            store_record<R, S, MB>(recs + (size_t)i * RL::STRIDE, c[0], c[1], c[2],
+                                   pack_cell(kk[0], kk[1], kk[2], 3u), next_face(kk[0], o[0], a0), jw,
+                                   next_face(kk[1], o[1], a1), next_face(kk[2], o[2], a2), active, ww, len, F, D);
+            tile = tile_of_cell(p.geo, kk[0], kk[1], kk[2]);
+        }
+        uint64_t pend = __ballot(act);
+        uint32_t rel = 0;
+        while (pend != 0ull) {
+            const int lead = __ffsll((unsigned long long)pend) - 1;
+            const uint32_t lt = (uint32_t)__shfl((int)tile, lead);
+            const uint64_t same = __ballot(act && tile == lt) & pend;
+            uint32_t b = 0;
+            if ((int)lane == lead) b = atomicAdd(p.cnt + lt, (uint32_t)__popcll(same));
+            b = (uint32_t)__shfl((int)b, lead);
+            if ((same >> lane) & 1ull) rel = b + (uint32_t)__popcll(same & lt_mask);
+            pend &= ~same;
+        }
+        if (act) p.side[i] = rel;
+    }
+    double v[8] = {l_emit, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    unsigned long long cc[4] = {0ull, n_pk, 0ull, 0ull};
+    block_ledger_add(p.slots + blockIdx.x, v, cc);
+}
+
+__global__ void k_tset_u32(uint32_t *p, uint32_t v) {
+    if (threadIdx.x == 0) *p = v;
+}
+
 // List positions of the recombination packets: offset of the cell's tile +
 // rank (records RS 16-byte units apart; the cell is word 3).
 template <int RS>
@@ -1171,6 +1266,21 @@ hipError_t run_reemit(const TiledLaunch &t, const RecombParams &rp) {
     return hipGetLastError();
 }
 
+// A batch of background packets: records 0..nbatch-1 (not traced).
+template <typename R, int S, bool TH, int MB, int NA, int NB>
+hipError_t run_background(const TiledLaunch &t, const BackgroundParams &bp) {
+    TParams p = make_params(t);
+    p.trace_n = 0;
+    const hipStream_t st = t.m.stream;
+    const dim3 grid(t.m.blocks), blk(kTBlock);
+    hipLaunchKernelGGL((k_bgemit<R, S, MB>), grid, blk, 0, st, p, bp);
+    scan(p, t, 0);
+    hipLaunchKernelGGL(k_tset_u32, dim3(1), dim3(64), 0, st, &t.ctrl->ndiff, t.nbatch);
+    hipLaunchKernelGGL((k_tscatter_diffuse<TRec<R, S, MB>::STRIDE>), dim3(8 * t.m.blocks), blk, 0, st, p);
+    run_passes<R, S, TH, MB, NA, NB>(p, t);
+    return hipGetLastError();
+}
+
 template <typename R, int S, bool TH, int MB, int NA, int NB>
 void run_passes(const TParams &p, const TiledLaunch &t) {
     const hipStream_t st = t.m.stream;
@@ -1204,33 +1314,41 @@ hipError_t occ(int *n) {
         n, reinterpret_cast<const void *>(&k_tmarch<R, S, TH, MB, 0, 0, false>), kTBlock, 0);
 }
 
+// What a launch runs after its packets are drawn: source packets (neither
+// pointer), recombination packets (rp) or background packets (bp).
+struct Extra {
+    const RecombParams *rp;
+    const BackgroundParams *bp;
+};
+
 template <typename R, int S, bool TH, int MB, int NA, int NB>
-hipError_t run(const TiledLaunch &t, const RecombParams *rp) {
-    return rp ? run_reemit<R, S, TH, MB, NA, NB>(t, *rp) : run_batch<R, S, TH, MB, NA, NB>(t);
+hipError_t run(const TiledLaunch &t, Extra x) {
+    if (x.rp) return run_reemit<R, S, TH, MB, NA, NB>(t, *x.rp);
+    if (x.bp) return run_background<R, S, TH, MB, NA, NB>(t, *x.bp);
+    return run_batch<R, S, TH, MB, NA, NB>(t);
 }
 
 template <typename R, int S, bool TH>
-hipError_t pick_mb(const TiledLaunch *t, const RecombParams *rp, int mb, int *o) {
+hipError_t pick_mb(const TiledLaunch *t, Extra x, int mb, int *o) {
     switch (mb) {
-    case 1: return t ? run<R, S, TH, 1, 0, 0>(*t, rp) : occ<R, S, TH, 1>(o);
+    case 1: return t ? run<R, S, TH, 1, 0, 0>(*t, x) : occ<R, S, TH, 1>(o);
     case 8:
         if (!t) return occ<R, S, TH, 8>(o);
-        if (S == 3 && t->m.layout == 1) return run<R, S, TH, 8, 3, 2>(*t, rp);
-        return run<R, S, TH, 8, 0, 0>(*t, rp);
+        if (S == 3 && t->m.layout == 1) return run<R, S, TH, 8, 3, 2>(*t, x);
+        return run<R, S, TH, 8, 0, 0>(*t, x);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t dispatch(const TiledLaunch *t, const RecombParams *rp, int species, int thermal, int fp64, int mb,
-                    int *o) {
+hipError_t dispatch(const TiledLaunch *t, Extra x, int species, int thermal, int fp64, int mb, int *o) {
     if (fp64) {
         if (species == 1)
-            return thermal ? pick_mb<double, 1, true>(t, rp, mb, o) : pick_mb<double, 1, false>(t, rp, mb, o);
-        return thermal ? pick_mb<double, 3, true>(t, rp, mb, o) : pick_mb<double, 3, false>(t, rp, mb, o);
+            return thermal ? pick_mb<double, 1, true>(t, x, mb, o) : pick_mb<double, 1, false>(t, x, mb, o);
+        return thermal ? pick_mb<double, 3, true>(t, x, mb, o) : pick_mb<double, 3, false>(t, x, mb, o);
     }
     if (species == 1)
-        return thermal ? pick_mb<float, 1, true>(t, rp, mb, o) : pick_mb<float, 1, false>(t, rp, mb, o);
-    return thermal ? pick_mb<float, 3, true>(t, rp, mb, o) : pick_mb<float, 3, false>(t, rp, mb, o);
+        return thermal ? pick_mb<float, 1, true>(t, x, mb, o) : pick_mb<float, 1, false>(t, x, mb, o);
+    return thermal ? pick_mb<float, 3, true>(t, x, mb, o) : pick_mb<float, 3, false>(t, x, mb, o);
 }
 
 template <typename R, int S, int MB> constexpr size_t rec_bytes() { return 16u * TRec<R, S, MB>::STRIDE; }
@@ -1260,15 +1378,19 @@ hipError_t launch_tiled_slots_zero(const TiledLaunch &t) {
 }
 
 hipError_t launch_tiled_batch(const TiledLaunch &t) {
-    return dispatch(&t, nullptr, t.m.species, t.m.thermal, t.m.fp64, t.m.mb, nullptr);
+    return dispatch(&t, Extra{nullptr, nullptr}, t.m.species, t.m.thermal, t.m.fp64, t.m.mb, nullptr);
 }
 
 hipError_t launch_tiled_reemit(const TiledLaunch &t, const RecombParams &r) {
-    return dispatch(&t, &r, t.m.species, t.m.thermal, t.m.fp64, t.m.mb, nullptr);
+    return dispatch(&t, Extra{&r, nullptr}, t.m.species, t.m.thermal, t.m.fp64, t.m.mb, nullptr);
+}
+
+hipError_t launch_tiled_background(const TiledLaunch &t, const BackgroundParams &b) {
+    return dispatch(&t, Extra{nullptr, &b}, t.m.species, t.m.thermal, t.m.fp64, t.m.mb, nullptr);
 }
 
 hipError_t tiled_occupancy(int species, int thermal, int fp64, int mb, int *blocks_per_cu) {
-    return dispatch(nullptr, nullptr, species, thermal, fp64, mb, blocks_per_cu);
+    return dispatch(nullptr, Extra{nullptr, nullptr}, species, thermal, fp64, mb, blocks_per_cu);
 }
 
 }  // namespace rtk

@@ -77,6 +77,7 @@ SIGNATURES = {
     "rt_trace_rays": (_I32, [_VP, _I32, _VP, _VP, _I32, _VP, _VP, _VP]),
     "rt_get_step_index": (_I32, [_VP, C.POINTER(_U64)]),
     "rt_set_recombination": (_I32, [_VP, _D, _I32, _D, _D, _VP, _VP, _I32]),
+    "rt_set_background": (_I32, [_VP, _D, _VP, _I64]),
     "rt_release": (_I32, [_VP]),
     "rt_batch_workspace_bytes": (_I32, [_I32, C.POINTER(C.c_size_t)]),
     "rt_batch_init": (_I32, [_I32, _VP, C.c_size_t, _VP, _U32, C.POINTER(_VP)]),
@@ -233,6 +234,13 @@ def rt_set_recombination(h, f_rec: float, log10_t0: float, dlog10_t: float, miln
         tab.ctypes.data_as(C.c_void_p), cp, fp64))
 
 
+def rt_set_background(h, ndot: float, sed, packets_per_step: int):
+    """Background field through the box faces: photons/s, spectrum, packets per step."""
+    row = np.ascontiguousarray(sed, dtype=np.float64)
+    _check("rt_set_background", lib().rt_set_background(h, float(ndot), row.ctypes.data_as(C.c_void_p),
+                                                         int(packets_per_step)))
+
+
 def rt_release(h):
     _check("rt_release", lib().rt_release(h))
 
@@ -336,6 +344,9 @@ class Solve:
         self.h = rt_init_grid(self.desc, self.workspace, len(work.src_ndot), nh, x, t, stream)
         if len(work.src_ndot):
             rt_add_sources(self.h, work.src_ijk, work.src_ndot, work.src_sed, work.src_flags)
+        bg = getattr(work, "background", None)
+        if bg is not None:
+            rt_set_background(self.h, bg.ndot, bg.sed, bg.packets)
         self.recomb = getattr(work, "recomb", None) is not None
         if self.recomb:
             r = work.recomb

@@ -268,6 +268,47 @@ def reemit_leg(n: int, packets: int):
                                    "crossings_per_s": p["crossings"] / (p["ms_per_step"] * 1e-3)}}
 
 
+def periodic_leg(steps: int, packets):
+    """The benchmark workload with periodic boundaries (a packet may cross 256
+    cell faces along an axis) and a background field entering through the
+    faces (a quarter of the sources' photon rate, a quarter as many packets,
+    the sources' spectrum), float32 march; one warm-up step."""
+    import numpy as np
+    import torch
+    from paper_1101_4127_amd import rt
+    from paper_1101_4127_amd import workloads as W
+    w = W.lognormal_256(packets=packets or 100_000_000)
+    bg = W.Background(0.25 * float(np.sum(w.src_ndot)), w.bins.sed.copy(), w.packets // 4)
+    w = w.with_(periodic=True, path_cells=256, background=bg)
+    s = rt.Solve(w, time_march=True, inflight=w.packets)
+    s.step(seed=500)
+    torch.cuda.synchronize()
+    cross = 0
+    kernel_ms = march_ms = 0.0
+    launches = 0
+    resid = 0.0
+    t0 = time.perf_counter()
+    for i in range(steps):
+        st = s.step(seed=501 + i)
+        cross += st["crossings"]
+        kernel_ms += st["kernel_ms"]
+        march_ms += st["march_ms"]
+        launches += st["kernel_launches"]
+        resid = max(resid, abs(st["emitted"] - st["absorbed"] - st["escaped"] - st["truncated"]) / st["emitted"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    s.release()
+    log(f"periodic + background: {1e3 * wall / steps:.1f} ms/step, {cross / wall:.4g} crossings/s, "
+        f"{launches // steps} march launches per step")
+    return {"workload": w.name + "_periodic_background", "grid": list(w.n), "source_packets": w.packets,
+            "background_packets": bg.packets, "path_cells": 256, "steps": steps,
+            "form": "float32 march, float64 accumulators and cell update",
+            "ms_per_step": 1e3 * wall / steps, "crossings_per_s": cross / wall,
+            "crossings_per_step": cross / steps, "march_ms_per_step": march_ms / steps,
+            "march_kernel_ms_per_step": kernel_ms / steps, "march_launches_per_step": launches / steps,
+            "conservation_residual": resid}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -287,6 +328,8 @@ def main():
     ap.add_argument("--reemit-grid", type=int, default=256,
                     help="cells per axis of the re-emission workload (0 skips it)")
     ap.add_argument("--reemit-packets", type=int, default=10_000_000)
+    ap.add_argument("--periodic-steps", type=int, default=1,
+                    help="timed steps of the periodic-boundary + background variant (0 skips it)")
     ap.add_argument("--autotune", action="store_true",
                     help="choose the march's launch parameters by measurement first (tiled march)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -365,6 +408,8 @@ def main():
         out["serving"] = serving_leg(args.serving_requests)
     if args.reemit_grid > 0:
         out["reemission"] = reemit_leg(args.reemit_grid, args.reemit_packets)
+    if args.periodic_steps > 0:
+        out["periodic_background"] = periodic_leg(args.periodic_steps, args.packets)
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(work, args.cpu_seconds)

@@ -97,6 +97,7 @@ def lib():
             L.orc_ground_fraction.argtypes = [C.c_double, dp]
             L.orc_update_cell_rx.argtypes = [gp, C.c_double, C.c_double, dp, dp, dp,
                                              _P(Rates), C.c_int, C.c_int, dp]
+            L.orc_milne_at.argtypes = [_P(Reemit), C.c_int, C.c_int, C.c_double, dp]
             L.orc_hii_time.argtypes = [C.c_double] * 5
             L.orc_hii_time.restype = C.c_double
             L.orc_he_ion_time.argtypes = [dp, dp] + [C.c_double] * 5 + [dp]
@@ -182,6 +183,16 @@ def ground_fraction(T: float) -> np.ndarray:
     p = np.zeros(3)
     lib().orc_ground_fraction(float(T), _ptr(p, C.c_double))
     return p
+
+
+def milne_at(recomb, nb: int, ion: int, T: float) -> np.ndarray:
+    """The spectrum the oracle gives recombination photons of ion at T."""
+    tab = _c64(recomb.milne).copy()
+    e = Reemit(float(recomb.f_rec), int(recomb.n_t), float(recomb.log10_t0), float(recomb.dlog10_t),
+               _ptr(tab, C.c_double))
+    out = np.zeros(nb)
+    lib().orc_milne_at(C.byref(e), int(nb), int(ion), float(T), _ptr(out, C.c_double))
+    return out
 
 
 def hii_time(x0: float, xh: float, I: float, R: float, h: float) -> float:

@@ -770,7 +770,7 @@ typedef struct {
 
 /* Spectrum of ion `ion` at T: linear in log10 T between the table's nodes,
  * clamped to the end nodes. */
-static void milne_at(const orc_reemit *E, int nb, int ion, double T, double *out)
+void orc_milne_at(const orc_reemit *E, int nb, int ion, double T, double *out)
 {
     double u = (log10(T) - E->log10_t0) / E->dlog10_t;
     const double top = (double)(E->n_t - 1);
@@ -829,7 +829,7 @@ int64_t orc_reemit_substep(const orc_grid *G, const orc_reemit *E, const double 
         for (int a = 0; a < ions; ++a) {
             if (!(ph[a] > 0.0)) continue;
             double m[ORC_MAX_BINS];
-            milne_at(E, nb, a, T[c], m);
+            orc_milne_at(E, nb, a, T[c], m);
             for (int j = 0; j < nb; ++j) sed[j] += ph[a] * m[j];
         }
         for (int j = 0; j < nb; ++j) sed[j] = sed[j] / w;

@@ -114,6 +114,19 @@ def test_pure_recombination_counts_the_ions_lost():
     assert rc[2] == pytest.approx(x0[4] - x[4], rel=1e-10)
 
 
+def test_counting_update_recombines_at_the_case_a_rate():
+    """Pure H, no photons, 3000 K (no collisional ionisation): with
+    recombinations counted the update follows dx/dt = -alpha_A n_H x^2, whose
+    solution is x0 / (1 + alpha_A n_H x0 t), and the counter is x0 - x."""
+    g = one_cell(y_he=0.0, n_chem=64)
+    a = O.rates_case_a(3000.0).a_hii
+    nh, t, x0 = 1.0e-2, 3.0e13, 0.9
+    x, _, rc = O.update_cell_rx(g, t, nh, [1 - x0, x0, 1, 0, 0], 3000.0, [0, 0, 0, 0], [0, 0, 0])
+    assert x[1] < 0.8 * x0
+    assert x[1] == pytest.approx(x0 / (1.0 + a * nh * x0 * t), rel=2e-3)
+    assert rc[0] == pytest.approx(x0 - x[1], rel=1e-9)
+
+
 def test_counters_add_to_their_start_values():
     g = one_cell(y_he=0.1)
     args = (g, 1.0e13, 1.0e-2, [0.2, 0.8, 0.1, 0.5, 0.4], 3000.0, [0, 0, 0, 0])
@@ -158,6 +171,24 @@ def test_milne_quadrature_against_closed_form(monkeypatch):
             part = np.array(part) / sum(part)
             part[part < 1e-12] = 0.0
             assert np.allclose(m[a, k], part / part.sum(), rtol=1e-8, atol=1e-13)
+
+
+def test_spectrum_interpolation():
+    """Linear in log10 T between the table's nodes: a node's row at a node
+    temperature, the mean of two rows halfway (in log T) between them, the end
+    rows beyond the table."""
+    w = W.with_recombination(W.small_mixed(n=8, n_src=1, packets=10), 0.1)
+    r, nb = w.recomb, w.bins.n_bins
+    for ion in range(3):
+        for k in (0, 17, 48, 100, r.n_t - 1):
+            t = 10.0 ** (r.log10_t0 + k * r.dlog10_t)
+            assert np.allclose(O.milne_at(r, nb, ion, t), r.milne[ion, k], rtol=1e-12, atol=1e-15)
+        for k in (3, 47, 64):
+            t = 10.0 ** (r.log10_t0 + (k + 0.5) * r.dlog10_t)
+            want = 0.5 * (r.milne[ion, k] + r.milne[ion, k + 1])
+            assert np.allclose(O.milne_at(r, nb, ion, t), want, rtol=1e-9, atol=1e-15)
+        assert np.array_equal(O.milne_at(r, nb, ion, 1.0), r.milne[ion, 0])
+        assert np.array_equal(O.milne_at(r, nb, ion, 1.0e12), r.milne[ion, -1])
 
 
 def test_diffuse_direction_stream():
@@ -212,9 +243,17 @@ def test_emitters_are_crossed_cells_over_threshold(y_he):
     assert want_n > 0
     assert led["diffuse_packets"] == want_n
     assert led["diffuse_emitted"] == pytest.approx(want_ph, rel=1e-12)
-    # counters that did not emit only grew
-    kept = ~crossed
-    assert np.all(s.rc[:ions, kept] >= rc0[:ions, kept])
+    # counters after the step: emitting ions restart from zero, the others keep
+    # theirs; both then add the cell update's recombinations (one sub-step, so
+    # the update saw the initial state and the step's final deposits)
+    g = O.make_grid(w)
+    for c in range(0, w.ncell, 5):
+        _, _, inc = O.update_cell_rx(g, w.dt_s, w.n_h[c], w.x[:, c], w.temp[c], s.acc[:, c], [0, 0, 0])
+        hit = crossed[c] and np.any((rc0[:ions, c] > 0) & (rc0[:ions, c] >= 0.05))
+        for a in range(ions):
+            reset = hit and rc0[a, c] > 0 and rc0[a, c] >= 0.05
+            want = inc[a] + (0.0 if reset else rc0[a, c])
+            assert s.rc[a, c] == pytest.approx(want, rel=1e-12, abs=1e-300), (c, a)
 
 
 def test_ledger_closes_with_diffuse_photons():

@@ -37,7 +37,7 @@ HBM_PEAK_GBS = 8000.0
 BYTES_F32 = 3 * 4 + 4 * 8
 BYTES_F64 = 3 * 8 + 4 * 8
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "march_traffic.json")
-KERNELS = {False: "k_tmarch<float, 3, true, 8, 3, 2>", True: "k_march<float, 3, true, 8, 3, 2>"}
+KERNELS = {False: "k_tmarch<float, 3, true, 8, 3, 2, false>", True: "k_march<float, 3, true, 8, 3, 2>"}
 
 
 def log(*a):

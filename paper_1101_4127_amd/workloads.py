@@ -405,7 +405,7 @@ def hii_region_reemit(n: int = 256, packets: int = 10_000_000, f_rec: float = 0.
     bins = blackbody_table(1.0e5)
     w = Workload(
         name=f"hii_region_reemit_{n}^3", n=(n, n, n), cell_cm=box / n, y_he=0.0, bins=bins,
-        redshift=-1.0, n_h=np.full(ncell, 1.0e-3), x=x, temp=t,
+        redshift=-1.0, n_h=np.full(ncell, float(np.float32(1.0e-3))), x=x, temp=t,
         src_ijk=np.full((1, 3), n // 2, np.int32), src_ndot=np.array([5.0e48]),
         src_sed=bins.sed[None, :].copy(), src_flags=0, dt_s=MYR_S, packets=packets, steps=2, n_sub=1,
         n_chem=8, flags=ISOTHERMAL | (FP64_MARCH if fp64 else 0), seed=1)

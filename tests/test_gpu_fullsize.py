@@ -157,3 +157,40 @@ def test_fullsize_512_fp32():
     del o
     check_sampled_updates(work, fields, 1e-5)
 
+
+
+def test_fullsize_reemission_256(gpu):
+    """The re-emission measurement case (256^3 H II region, 1e7 source packets,
+    about half of the ionised cells over the threshold), float32 march, as
+    bench.py runs it: every ionised cell is crossed by the source's packets, so
+    the recombination packets are exactly the cells whose input counter is
+    >= f_rec; conservation; and for a sample of cells the update (fractions and
+    counters: reset for emitting cells), driven by the GPU's deposits, against
+    the oracle's update of the same cell."""
+    from paper_1101_4127_amd import rt
+    w, rc0 = W.hii_region_reemit()
+    s = rt.Solve(w, counters=rc0)
+    st = s.step(seed=7)
+    f = s.fetch()
+    s.release()
+    want = int(np.count_nonzero((rc0[0] > 0) & (rc0[0] >= w.recomb.f_rec)))
+    assert st["diffuse_packets"] == want > 100000
+    assert abs(st["emitted"] - st["absorbed"] - st["escaped"] - st["truncated"]) <= 1e-6 * st["emitted"]
+    assert np.all(f[11] >= 0.0) and np.all(np.isfinite(f[11]))
+    g = O.make_grid(w)
+    rng = np.random.default_rng(1)
+    inside = np.nonzero(rc0[0] > 0)[0]
+    cells = np.concatenate([rng.choice(inside, 1500, replace=False), rng.choice(w.ncell, 500, replace=False)])
+    worst_x = worst_r = 0.0
+    for c in cells:
+        acc = np.array([f[7, c], f[8, c], f[9, c], f[10, c]])
+        x, _, inc = O.update_cell_rx(g, w.dt_s, w.n_h[c], w.x[:, c], w.temp[c], acc, [0, 0, 0])
+        emitted = acc[0] > 0 and rc0[0, c] > 0 and rc0[0, c] >= w.recomb.f_rec
+        r_want = inc[0] + (0.0 if emitted else rc0[0, c])
+        worst_x = max(worst_x, abs(f[2, c] - x[1]) / max(x[1], 1e-8))
+        # counters relative to max(|b|, 1e-6 f_rec): in neutral cells the
+        # increment is h x_eq - (x_h - x_0)/lambda with lambda h ~ 1e-10, so its
+        # few digits differ between two libm's exp; no threshold sees them
+        worst_r = max(worst_r, abs(f[11, c] - r_want) / max(abs(r_want), 1e-6 * w.recomb.f_rec))
+    assert worst_x <= 1e-6, worst_x            # float32 storage of a float64 update
+    assert worst_r <= 1e-9, worst_r

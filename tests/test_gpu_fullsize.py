@@ -194,3 +194,26 @@ def test_fullsize_reemission_256(gpu):
         worst_r = max(worst_r, abs(f[11, c] - r_want) / max(abs(r_want), 1e-6 * w.recomb.f_rec))
     assert worst_x <= 1e-6, worst_x            # float32 storage of a float64 update
     assert worst_r <= 1e-9, worst_r
+
+
+def test_fullsize_periodic_background_fp64(gpu, work):
+    """The benchmark workload with periodic boundaries (256 faces) and a
+    background field (2.5e7 packets, a quarter of the sources' rate), as
+    bench.py's periodic leg runs it, in the float64 form: sampled source packet
+    histories bit-exact against the oracle marching each alone (paths up to 256
+    cells per axis, wrapping), conservation, every packet ending once, sampled
+    cell updates driven by the GPU's deposits (source and background) at 1e-9."""
+    bg = W.Background(0.25 * float(np.sum(work.src_ndot)), work.bins.sed.copy(), work.packets // 4)
+    w = work.with_(periodic=True, path_cells=256, background=bg)
+    st, fields, tr = run_gpu(w, fp64=True)
+    assert st["errors"] == 0 and st["nonfinite"] == 0
+    assert st["packets"] == w.packets + bg.packets
+    assert st["n_escaped"] + st["n_truncated"] == st["packets"]
+    assert abs(st["emitted"] - st["absorbed"] - st["escaped"] - st["truncated"]) <= 1e-12 * st["emitted"]
+    o = O.OracleSolve(w)
+    o.absorbers()
+    ids = np.arange(0, w.packets, STRIDE)
+    otr = oracle_traces(o, w, ids)
+    assert {1, 3} <= set(np.unique(otr[:, 1]).tolist())          # extinguished and path-limited
+    PT.compare_traces(w, o.kappa, tr, otr, exact=True)
+    check_sampled_updates(w, fields, 1e-9, o=O.OracleSolve(w))

@@ -201,3 +201,21 @@ def test_rejections():
         rt.rt_set_recombination(s0.h, r.f_rec, r.log10_t0, r.dlog10_t, r.milne)
     assert ex.value.status == rt.RT_ESTATE
     s0.release()
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_one_bin_pure_hydrogen_fp64(periodic):
+    """The one-bin instances (13.6 eV, every recombination photon in that bin):
+    Test 0's corner source on 16^3 with re-emission, also with periodic
+    boundaries."""
+    w = W.stromgren_c1(n=16, packets=20000, steps=2, n_sub=4, fp64=True)
+    w = W.with_recombination(w.with_(periodic=periodic, path_cells=24 if periodic else 0), 0.002)
+    o, stats, fields = run_both(w, fp64=True, steps=2)
+    total = 0
+    for g, r in stats:
+        assert g["diffuse_packets"] == r["diffuse_packets"] and g["crossings"] == r["crossings"]
+        assert PT.ledger_close(g, r, 1e-12) <= 1e-12
+        total += g["diffuse_packets"]
+    assert total > 0
+    PT.compare_state(o, fields, w, frac_tol=1e-9, temp_tol=1e-9, dep_tol=1e-9)
+    check_counters(o, fields, 1, 1e-9)

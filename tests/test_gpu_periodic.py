@@ -29,7 +29,7 @@ def periodic_case(*, n=20, fp64=True, path_cells=0, tau_kill=30.0, packets=4000,
 
 
 @pytest.mark.parametrize("n,path_cells,tau_kill,thin", [(20, 0, 30.0, 0.1), (20, 7, 30.0, 0.1), (12, 50, 6.0, 0.02),
-                                                        (6, 13, 30.0, 0.02), (9, 30, 30.0, 0.02)])
+                                                        (6, 13, 30.0, 0.02), (9, 30, 30.0, 0.02), (6, 1, 30.0, 0.02)])
 def test_fp64_bitexact_traces_deposits_state(n, path_cells, tau_kill, thin):
     """Ragged grids (20, 9: partial tiles; 12: two tiles per axis; 6: one tile,
     so wraps stay in the tile), short and long path limits, packets ending both
@@ -44,6 +44,22 @@ def test_fp64_bitexact_traces_deposits_state(n, path_cells, tau_kill, thin):
     PT.compare_traces(w, o.kappa, tr, o.trace, exact=True)
     if r["n_escaped"] > 50:
         assert np.any(tr[:, 1] == 3)                      # traced packets that end at the path limit
+    assert PT.ledger_close(g, r, 1e-12) <= 1e-12
+    PT.compare_state(o, fields, w, frac_tol=1e-9, temp_tol=1e-9, dep_tol=1e-9)
+
+
+def test_longest_path():
+    """path_cells at its maximum (2046) in a nearly transparent 6^3 box: packets
+    wrap ~340 times along an axis (up to ~5700 crossings) before the limit;
+    their recorded first 256 cells, fates and the deposits match the oracle."""
+    from paper_1101_4127_amd import rt
+    w = periodic_case(n=6, path_cells=rt.RT_MAX_PATH_CELLS, tau_kill=1.0e4, thin=0.0005, packets=400)
+    o, stats, fields, tr = PT.run_both(w, fp64=True, trace_n=100, trace_len=256, stride=4)
+    g, r = stats[0]
+    assert g["crossings"] == r["crossings"] > 1000000
+    assert g["n_escaped"] == r["n_escaped"] == w.packets
+    PT.compare_traces(w, o.kappa, tr, o.trace, exact=True)
+    assert np.all(tr[:, 1] == 3) and tr[:, 0].max() > 5000
     assert PT.ledger_close(g, r, 1e-12) <= 1e-12
     PT.compare_state(o, fields, w, frac_tol=1e-9, temp_tol=1e-9, dep_tol=1e-9)
 

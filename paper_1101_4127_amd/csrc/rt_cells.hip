@@ -72,32 +72,53 @@ struct Rates {
     double col_hi, col_hei, col_heii;      // cm^3 / s
 };
 
-__device__ Rates rates_at(double T, bool case_a = false) {
+// Factors of T that the rates and the cooling of one chemistry sub-step share
+// (evaluated once; each rate multiplies them in the order its formula is
+// written, so the results are those of the formulas evaluated separately).
+struct TFac {
+    double damp, rt, e_hi, e_hei, e_heii;   // 1/(1+sqrt(T/1e5)), sqrt(T), exp(-T_X/T)
+    double p15, e470, e94;                  // T^-1.5, exp(-470000/T), 1 + 0.3 exp(-94000/T)
+};
+
+__device__ __forceinline__ TFac tfac(double T) {
+    TFac f;
+    f.damp = 1.0 / (1.0 + sqrt(T * 1.0e-5));
+    f.rt = sqrt(T);
+    f.e_hi = exp(-157809.1 / T);
+    f.e_hei = exp(-285335.4 / T);
+    f.e_heii = exp(-631515.0 / T);
+    f.p15 = pow(T, -1.5);
+    f.e470 = exp(-470000.0 / T);
+    f.e94 = 1.0 + 0.3 * exp(-94000.0 / T);
+    return f;
+}
+
+__device__ Rates rates_at(double T, const TFac &f, bool case_a = false) {
     Rates r;
-    const double damp = 1.0 / (1.0 + sqrt(T * 1.0e-5));
-    const double rt = sqrt(T);
+    const double damp = f.damp;
+    const double rt = f.rt;
+    const double diel = 1.9e-3 * f.p15 * f.e470 * f.e94;
     if (case_a) {
         r.rec_hii = hydrogenic_casea(T, 157807.0);
         r.rec_heiii = 2.0 * hydrogenic_casea(T, 631515.0);
-        r.rec_heii = heii_rad_casea(T) + heii_dielectronic(T);
+        r.rec_heii = heii_rad_casea(T) + diel;
     } else {
         r.rec_hii = hydrogenic_caseb(T, 157807.0);
         r.rec_heiii = 2.0 * hydrogenic_caseb(T, 631515.0);
-        const double diel = 1.9e-3 * pow(T, -1.5) * exp(-470000.0 / T) * (1.0 + 0.3 * exp(-94000.0 / T));
         r.rec_heii = 1.26e-14 * pow(570670.0 / T, 0.750) + diel;
     }
-    r.col_hi = 5.85e-11 * rt * exp(-157809.1 / T) * damp;
-    r.col_hei = 2.38e-11 * rt * exp(-285335.4 / T) * damp;
-    r.col_heii = 5.68e-12 * rt * exp(-631515.0 / T) * damp;
+    r.col_hi = 5.85e-11 * rt * f.e_hi * damp;
+    r.col_hei = 2.38e-11 * rt * f.e_hei * damp;
+    r.col_heii = 5.68e-12 * rt * f.e_heii * damp;
     return r;
 }
 
 // Cooling [erg cm^-3 s^-1] without the Compton term.
-__device__ double cooling_rate(double T, double ne, double n_hi, double n_hii, double n_hei,
+__device__ double cooling_rate(double T, const TFac &f, double ne, double n_hi, double n_hii, double n_hei,
                                double n_heii, double n_heiii) {
-    const double damp = 1.0 / (1.0 + sqrt(T * 1.0e-5));
-    const double rt = sqrt(T);
-    const double e_hi = exp(-157809.1 / T), e_hei = exp(-285335.4 / T), e_heii = exp(-631515.0 / T);
+    const double damp = f.damp;
+    const double rt = f.rt;
+    const double e_hi = f.e_hi, e_hei = f.e_hei, e_heii = f.e_heii;
     const double t3 = pow(T * 1.0e-3, -0.2);
     const double t6 = 1.0 / (1.0 + pow(T * 1.0e-6, 0.7));
     const double lg = log10(T);
@@ -107,7 +128,7 @@ __device__ double cooling_rate(double T, double ne, double n_hi, double n_hii, d
     double per_ne_heii = 5.54e-17 * pow(T, -0.397) * exp(-473638.0 / T) * damp
                        + 4.95e-22 * rt * e_heii * damp
                        + 1.55e-26 * pow(T, 0.3647)                 // recombination
-                       + 1.24e-13 * pow(T, -1.5) * exp(-470000.0 / T) * (1.0 + 0.3 * exp(-94000.0 / T));
+                       + 1.24e-13 * f.p15 * f.e470 * f.e94;
     double lam = ne * (per_ne_hi * n_hi + per_ne_heii * n_heii
                        + 9.38e-22 * rt * e_hei * damp * n_hei
                        + 8.70e-27 * rt * t3 * t6 * n_hii
@@ -221,9 +242,13 @@ __device__ __forceinline__ void update_slot(const GridGeom &G, R *__restrict__ s
         double n_rec[3] = {0.0, 0.0, 0.0};
         if (count)
             for (int q = 0; q < S; ++q) n_rec[q] = rc[(size_t)q * np + s];
-        Rates r = rates_at(T, count);
+        TFac tf = tfac(T);
+        Rates r = rates_at(T, tf, count);
         for (int m = 0; m < n_chem; ++m) {
-            if (TH && m > 0) r = rates_at(T, count);
+            if (TH && m > 0) {
+                tf = tfac(T);
+                r = rates_at(T, tf, count);
+            }
             const double ne0 = nh * x.hii + nhe * (x.heii + 2.0 * x.heiii);
             Frac xp, xn;
             evolve(xp, x, r, gam, ne0, h, he);
@@ -254,7 +279,7 @@ __device__ __forceinline__ void update_slot(const GridGeom &G, R *__restrict__ s
                 const double ntot0 = nh * (1.0 + x.hii) + nhe * (1.0 + x.heii + 2.0 * x.heiii);
                 const double ntot1 = nh * (1.0 + xn.hii) + nhe * (1.0 + xn.heii + 2.0 * xn.heiii);
                 const double ne1 = nh * xn.hii + nhe * (xn.heii + 2.0 * xn.heiii);
-                const double lam = cooling_rate(T, ne1, nh * xn.hi, nh * xn.hii, nhe * xn.hei,
+                const double lam = cooling_rate(T, tf, ne1, nh * xn.hi, nh * xn.hii, nhe * xn.hei,
                                                 nhe * xn.heii, nhe * xn.heiii);
                 const double cne = ccomp * ne1;
                 double tn = (1.5 * kb * ntot0 * T + h * (heat + cne * tcmb))
@@ -277,7 +302,7 @@ __device__ __forceinline__ void update_slot(const GridGeom &G, R *__restrict__ s
 }
 
 template <typename R, int S, bool TH>
-__global__ void __launch_bounds__(kCellBlock) k_update(GridGeom G, R *__restrict__ st, const double *__restrict__ acc,
+__global__ void __launch_bounds__(kCellBlock, (TH ? 3 : 4)) k_update(GridGeom G, R *__restrict__ st, const double *__restrict__ acc,
                                                        int acc_stride, double y_he, double cell_cm, double dt,
                                                        double redshift, int n_chem, StepLedger *ledger,
                                                        double *__restrict__ rc) {

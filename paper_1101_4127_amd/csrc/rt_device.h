@@ -60,6 +60,75 @@ __device__ __forceinline__ void sample_direction(uint64_t seed, uint64_t solve_i
     c[0] = c[1] = c[2] = 1 << 19;
 }
 
+// Lane number of the t-th set bit (t < popcount) of a wavefront-wide mask.
+__device__ __forceinline__ uint32_t nth_set_bit(uint64_t m, uint32_t t) {
+    uint32_t lo = 0, hi = 63;                  // the answer b: popc(m & ((2 << b) - 1)) > t
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        const uint64_t below = mid == 63u ? m : (m & ((2ull << mid) - 1ull));
+        if ((uint32_t)__popcll(below) > t) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+// The directions of sample_direction for a wavefront's packets, with the
+// attempts shared out among all its lanes: each round, the packets still
+// without a direction take every lane, a packet's further attempts going to
+// its lanes in increasing order (so the first accepted attempt is found, as
+// in the one-lane loop).  The wavefront then waits about three rounds of draws
+// instead of its slowest packet's seven or so.  Every lane of the wavefront
+// must call it (uniform control flow); lanes with `want` false only help.
+__device__ __forceinline__ void sample_direction_wave(uint64_t seed, uint64_t solve_id, uint64_t g,
+                                                      uint64_t step, bool octant, bool want, int32_t c[3],
+                                                      uint64_t stream = 0ull) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t lt = lane == 0u ? 0ull : (~0ull >> (64u - lane));
+    bool done = !want;
+    uint32_t next = 0;                          // next attempt of this lane's own packet
+    int32_t cx = 1 << 19, cy = 1 << 19, cz = 1 << 19;
+    for (;;) {
+        const uint64_t open = __ballot(!done);
+        if (open == 0ull) break;
+        const uint32_t k = (uint32_t)__popcll(open);
+        const uint32_t rank = (uint32_t)__popcll(open & lt);
+        const uint32_t t = lane % k, o = lane / k;
+        const uint32_t src = nth_set_bit(open, t);
+        const uint64_t gt = (uint64_t)__shfl((long long)g, (int)src);
+        const uint32_t at = (uint32_t)__shfl((int)next, (int)src) + o;
+        bool ok = false;
+        int32_t x = 0, y = 0, z = 0;
+        if (at < 64u) {
+            const U64x4 r = philox4x64_10(gt, step, at, stream, seed, solve_id);
+            x = (int32_t)(r.v[0] >> 43) - (1 << 20);
+            y = (int32_t)(r.v[1] >> 43) - (1 << 20);
+            z = (int32_t)(r.v[2] >> 43) - (1 << 20);
+            const int64_t q = (int64_t)x * x + (int64_t)y * y + (int64_t)z * z;
+            ok = q >= (1ll << 36) && q <= (1ll << 40);
+        }
+        const uint64_t acc = __ballot(ok);
+        uint64_t pat = 0ull;                    // lanes 0, k, 2k, ... (wavefront-uniform)
+        for (uint32_t j = 0; j < 64u; j += k) pat |= 1ull << j;
+        const uint64_t mine = done ? 0ull : (pat << rank);
+        const uint64_t hit = mine & acc;
+        const uint32_t first = hit ? (uint32_t)__builtin_ctzll(hit) : lane;
+        const int32_t sx = __shfl(x, (int)first), sy = __shfl(y, (int)first), sz = __shfl(z, (int)first);
+        if (!done) {
+            if (hit) {
+                cx = sx;
+                cy = sy;
+                cz = sz;
+                done = true;
+            } else {
+                next += (uint32_t)__popcll(mine);
+                if (next >= 64u) done = true;   // no attempt accepted: the diagonal
+            }
+        }
+    }
+    c[0] = octant ? abs(cx) : cx;
+    c[1] = octant ? abs(cy) : cy;
+    c[2] = octant ? abs(cz) : cz;
+}
+
 // ---------------------------------------------------------------------------
 // Brick layout: the grid is cut into bricks of 2^b cells per side, stored
 // brick after brick (x fastest); inside a brick cells follow the Morton

@@ -77,29 +77,37 @@ struct TParams {
 };
 
 // Record of a packet between passes (16-byte units), holding everything the
-// march needs to resume it without touching the source tables.  Words:
-//   0-2  c[3], the integer direction
-//   3    the cell it is in (or about to enter) | axis of the last face crossed
+// march needs to resume it without touching the source tables.  The words a
+// crossing changes come first:
+//   0    the cell it is in (or about to enter) | axis of the last face crossed
 //        (3: none yet) << 30
-//   4    next-face distances d0 | d1 << 16 (half cells), with the witness
+//   1    next-face distances d0 | d1 << 16 (half cells), with the witness
 //        bin of the float32 extinction test in bits 12-15
-//   5    d2 | bins the source populates << 16
-//   6-7  packet weight (photons per unit of the SED), float64
-//   8    length scale |c| dx / 2 of the chord (float32 form, in 1e18 cm);
-//        float64 form: words 8-9, float64 in cm
-// float32 form: then the column densities N_s and the photons per bin F_j;
-// float64 form: F_j and the optical depths T_j.
+//   2    d2 | bins the source populates << 16
+//   3..  float32 form: the column densities N_s, then the photons per bin F_j;
+//        float64 form: F_j, then the optical depths T_j (two words each)
+// then, from word MOV, what stays fixed: c[3], the integer direction; the
+// packet weight (photons per unit of the SED, float64, two words); the length
+// scale |c| dx / 2 of the chord (float32 form: one word, in 1e18 cm; float64
+// form: two words, in cm).
+// A write-back between passes rewrites whole 64-byte pieces from word 0 (the
+// fixed words that share them included): HBM takes a partly written piece
+// only as a read-modify-write, which made the float32 emission half again
+// slower.
 template <typename R, int S, int MB>
 struct TRec {
     static constexpr bool F64 = std::is_same<R, double>::value;
     static constexpr int ND = DepthState<R, S, MB>::N;
-    static constexpr int HDR = F64 ? 10 : 9;
-    static constexpr int BYTES = 4 * HDR + (int)sizeof(R) * (MB + ND);
-    static constexpr int UNITS = (BYTES + 15) / 16;
+    static constexpr int MOV = 3 + (F64 ? 4 * MB : ND + MB);
+    static constexpr int NWORD = MOV + (F64 ? 7 : 6);
+    static constexpr int UNITS = (NWORD + 3) / 4;
     static constexpr int WORDS = 4 * UNITS;
-    // records sit on a power-of-two stride (whole 128-byte lines from 128 bytes
-    // up), so a record read or written back never straddles a line boundary
-    static constexpr int STRIDE = UNITS <= 2 ? 2 : (UNITS <= 4 ? 4 : (UNITS <= 8 ? 8 : 16));
+    static constexpr int WHOLE = ((UNITS + 3) / 4) * 4;     // units of the whole 64-byte pieces it touches
+    // records sit on a power-of-two stride of at least 64 bytes, so a record
+    // read or written back never straddles a 128-byte line it does not fill
+    static constexpr int STRIDE = UNITS <= 4 ? 4 : (UNITS <= 8 ? 8 : 16);
+    static constexpr int BACK = ((MOV + 15) / 16) * 4 < STRIDE ? ((MOV + 15) / 16) * 4 : STRIDE;
+    static_assert(UNITS <= 16 && 4 * BACK >= MOV && WHOLE <= STRIDE, "record layout");
 };
 
 // Longest run of a tile's list one block marches (its record ids are staged in LDS).
@@ -225,67 +233,72 @@ __device__ void block_ledger_add(LedgerSlot *slot, double (&v)[8], unsigned long
     }
 }
 
+// The first NU units of a record (layout above); words past its end are zero.
+template <typename R, int S, int MB, int NU>
+__device__ __forceinline__ void put_record(uint4 *dst, int32_t c0, int32_t c1, int32_t c2, uint32_t kw,
+                                           uint32_t d0, uint32_t jw, uint32_t d1, uint32_t d2, uint32_t active,
+                                           double w, R len, const R (&F)[MB],
+                                           const R (&D)[DepthState<R, S, MB>::N]) {
+    using RL = TRec<R, S, MB>;
+    constexpr int NW = 4 * NU;
+    constexpr int M = RL::MOV;
+    uint32_t x[NW];
+    // indices are compile-time constants once unrolled: words past NW drop out
+    auto put = [&x](int i, uint32_t v) {
+        if (i < NW) x[i] = v;
+    };
+#pragma unroll
+    for (int i = 0; i < NW; ++i) x[i] = 0u;
+    put(0, kw);
+    put(1, d0 | (jw << 12) | (d1 << 16));
+    put(2, d2 | (active << 16));
+    if constexpr (RL::F64) {
+#pragma unroll
+        for (int j = 0; j < MB; ++j) {
+            put(3 + 2 * j, (uint32_t)__double2loint(F[j]));
+            put(4 + 2 * j, (uint32_t)__double2hiint(F[j]));
+            put(3 + 2 * MB + 2 * j, (uint32_t)__double2loint(D[j]));
+            put(4 + 2 * MB + 2 * j, (uint32_t)__double2hiint(D[j]));
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < RL::ND; ++j) put(3 + j, __float_as_uint(D[j]));
+#pragma unroll
+        for (int j = 0; j < MB; ++j) put(3 + RL::ND + j, __float_as_uint(F[j]));
+    }
+    put(M, (uint32_t)c0);
+    put(M + 1, (uint32_t)c1);
+    put(M + 2, (uint32_t)c2);
+    put(M + 3, (uint32_t)__double2loint(w));
+    put(M + 4, (uint32_t)__double2hiint(w));
+    if constexpr (RL::F64) {
+        put(M + 5, (uint32_t)__double2loint((double)len));
+        put(M + 6, (uint32_t)__double2hiint((double)len));
+    } else {
+        put(M + 5, __float_as_uint((float)len));
+    }
+#pragma unroll
+    for (int u = 0; u < NU; ++u) dst[u] = make_uint4(x[4 * u], x[4 * u + 1], x[4 * u + 2], x[4 * u + 3]);
+}
+
+// A new packet's record, padded with zeros to whole 64-byte pieces.
 template <typename R, int S, int MB>
 __device__ __forceinline__ void store_record(uint4 *dst, int32_t c0, int32_t c1, int32_t c2, uint32_t kw,
                                              uint32_t d0, uint32_t jw, uint32_t d1, uint32_t d2, uint32_t active,
-                                             double w,
-                                             R len, const R (&F)[MB],
+                                             double w, R len, const R (&F)[MB],
                                              const R (&D)[DepthState<R, S, MB>::N]) {
-    using RL = TRec<R, S, MB>;
-    uint32_t x[RL::WORDS];
-#pragma unroll
-    for (int i = 0; i < RL::WORDS; ++i) x[i] = 0u;
-    x[0] = (uint32_t)c0; x[1] = (uint32_t)c1; x[2] = (uint32_t)c2; x[3] = kw;
-    x[4] = d0 | (jw << 12) | (d1 << 16);
-    x[5] = d2 | (active << 16);
-    x[6] = (uint32_t)__double2loint(w);
-    x[7] = (uint32_t)__double2hiint(w);
-    if constexpr (RL::F64) {
-        x[8] = (uint32_t)__double2loint(len);
-        x[9] = (uint32_t)__double2hiint(len);
-#pragma unroll
-        for (int j = 0; j < MB; ++j) {
-            x[RL::HDR + 2 * j] = (uint32_t)__double2loint(F[j]);
-            x[RL::HDR + 1 + 2 * j] = (uint32_t)__double2hiint(F[j]);
-            x[RL::HDR + 2 * MB + 2 * j] = (uint32_t)__double2loint(D[j]);
-            x[RL::HDR + 2 * MB + 1 + 2 * j] = (uint32_t)__double2hiint(D[j]);
-        }
-    } else {
-        x[8] = __float_as_uint(len);
-#pragma unroll
-        for (int j = 0; j < RL::ND; ++j) x[RL::HDR + j] = __float_as_uint(D[j]);
-#pragma unroll
-        for (int j = 0; j < MB; ++j) x[RL::HDR + RL::ND + j] = __float_as_uint(F[j]);
-    }
-#pragma unroll
-    for (int u = 0; u < RL::UNITS; ++u) dst[u] = make_uint4(x[4 * u], x[4 * u + 1], x[4 * u + 2], x[4 * u + 3]);
+    put_record<R, S, MB, TRec<R, S, MB>::WHOLE>(dst, c0, c1, c2, kw, d0, jw, d1, d2, active, w, len, F, D);
 }
 
-// Write back what a crossing changes (cell, face distances, witness, depth
-// state, photons); direction, weight, chord scale and SED mask stay.
+// Write-back between passes: the 64-byte pieces that hold what a crossing
+// changes (cell, face distances, witness, depth state, photons), written
+// whole with the fixed words that fall in them.
 template <typename R, int S, int MB>
-__device__ __forceinline__ void store_moving(uint4 *dst, uint32_t kw, uint32_t d0, uint32_t jw, uint32_t d1,
-                                             uint32_t d2, uint32_t active, const R (&F)[MB],
+__device__ __forceinline__ void store_moving(uint4 *dst, int32_t c0, int32_t c1, int32_t c2, uint32_t kw,
+                                             uint32_t d0, uint32_t jw, uint32_t d1, uint32_t d2, uint32_t active,
+                                             double w, R len, const R (&F)[MB],
                                              const R (&D)[DepthState<R, S, MB>::N]) {
-    using RL = TRec<R, S, MB>;
-    uint32_t *w = reinterpret_cast<uint32_t *>(dst);
-    w[3] = kw;
-    w[4] = d0 | (jw << 12) | (d1 << 16);
-    w[5] = d2 | (active << 16);
-    if constexpr (RL::F64) {
-#pragma unroll
-        for (int j = 0; j < MB; ++j) {
-            w[RL::HDR + 2 * j] = (uint32_t)__double2loint(F[j]);
-            w[RL::HDR + 1 + 2 * j] = (uint32_t)__double2hiint(F[j]);
-            w[RL::HDR + 2 * MB + 2 * j] = (uint32_t)__double2loint(D[j]);
-            w[RL::HDR + 2 * MB + 1 + 2 * j] = (uint32_t)__double2hiint(D[j]);
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < RL::ND; ++j) w[RL::HDR + j] = __float_as_uint(D[j]);
-#pragma unroll
-        for (int j = 0; j < MB; ++j) w[RL::HDR + RL::ND + j] = __float_as_uint(F[j]);
-    }
+    put_record<R, S, MB, TRec<R, S, MB>::BACK>(dst, c0, c1, c2, kw, d0, jw, d1, d2, active, w, len, F, D);
 }
 
 // ---------------------------------------------------------------------------
@@ -309,17 +322,17 @@ __global__ void __launch_bounds__(kTBlock) k_temit(const TParams p) {
         const uint32_t i = base + lane;
         const bool act = i < p.nbatch;
         uint32_t tile = 0;
+        const uint32_t g = p.g0 + i;
+        uint32_t ns = 1u, sidx = 0u;
+        if (act) sidx = source_of(g, p.q, p.r, ns);
+        const SourceRec sr = p.src[sidx];
+        const bool oct = (sr.flags & kSrcOctant) != 0u;
+        int32_t c[3];
+        sample_direction_wave(p.seed, p.solve_id, g, p.step, oct, act, c);
         if (act) {
-            const uint32_t g = p.g0 + i;
-            uint32_t ns;
-            const uint32_t sidx = source_of(g, p.q, p.r, ns);
-            const SourceRec sr = p.src[sidx];
-            const bool oct = (sr.flags & kSrcOctant) != 0u;
             const double ww = packet_weight(p, sidx, ns, oct);
             l_emit += ww * p.src_sedsum[sidx];
             n_pk += 1u;
-            int32_t c[3];
-            sample_direction(p.seed, p.solve_id, g, p.step, oct, c);
             const int k0 = sr.o[0] >> 1, k1 = sr.o[1] >> 1, k2 = sr.o[2] >> 1;
             const uint32_t active = sr.flags >> kSrcMaskShift;
             R F[MB], D[ND];
@@ -457,10 +470,10 @@ __global__ void __launch_bounds__(kTBlock) k_remit(const TParams p, const Recomb
         const bool act = emit && idx < p.capacity;
         if (emit && !act) atomicOr(&p.ctrl->err, 128u);
         uint32_t tile = 0;
+        const uint32_t cell = (uint32_t)k0 + (uint32_t)p.geo.n[0] * ((uint32_t)k1 + (uint32_t)p.geo.n[1] * (uint32_t)k2);
+        int32_t c[3];
+        sample_direction_wave(p.seed, p.solve_id, cell, p.step, false, act, c, 1ull);
         if (act) {
-            const uint32_t cell = (uint32_t)k0 + (uint32_t)p.geo.n[0] * ((uint32_t)k1 + (uint32_t)p.geo.n[1] * (uint32_t)k2);
-            int32_t c[3];
-            sample_direction(p.seed, p.solve_id, cell, p.step, false, c, 1ull);
             uint32_t active = 0u;
             double carried = 0.0;
 #pragma unroll
@@ -540,8 +553,10 @@ __global__ void __launch_bounds__(kTBlock) k_bgemit(const TParams p, const Backg
         const uint32_t i = base + lane;
         const bool act = i < p.nbatch;
         uint32_t tile = 0;
+        const uint64_t g = (uint64_t)bp.g0 + i;
+        int32_t c[3];
+        sample_direction_wave(p.seed, p.solve_id, g, p.step, false, act, c, 3ull);
         if (act) {
-            const uint64_t g = (uint64_t)bp.g0 + i;
             const U64x4 r = philox4x64_10(g, p.step, 0ull, 2ull, p.seed, p.solve_id);
             uint64_t idx = __umul64hi(r.v[0], total);
             int axis, plus;
@@ -551,14 +566,13 @@ __global__ void __launch_bounds__(kTBlock) k_bgemit(const TParams p, const Backg
             const int u = axis == 0 ? 1 : 0, v = axis == 2 ? 1 : 2;
             const uint64_t nu = (uint64_t)p.geo.n[u];
             const int ia = (int)(idx % nu), ib = (int)(idx / nu);
-            int32_t o[3], kk[3], c[3];
+            int32_t o[3], kk[3];
             o[axis] = plus ? 2 * p.geo.n[axis] : 0;
             kk[axis] = plus ? p.geo.n[axis] - 1 : 0;
             o[u] = 2 * ia + 1;
             kk[u] = ia;
             o[v] = 2 * ib + 1;
             kk[v] = ib;
-            sample_direction(p.seed, p.solve_id, g, p.step, false, c, 3ull);
             int32_t cn = c[axis] < 0 ? -c[axis] : c[axis];
             if (cn == 0) cn = 1;                               // never along the face itself
             c[axis] = plus ? -cn : cn;
@@ -614,7 +628,7 @@ __global__ void __launch_bounds__(kTBlock) k_tscatter_diffuse(const TParams p) {
     const uint32_t n = min(p.ctrl->ndiff, p.capacity);
     const uint4 *recs = reinterpret_cast<const uint4 *>(p.rec);
     for (uint32_t i = blockIdx.x * kTBlock + threadIdx.x; i < n; i += stride) {
-        const uint32_t kw = recs[(size_t)i * RS].w;
+        const uint32_t kw = recs[(size_t)i * RS].x;       // word 0: the cell
         const int k0 = (int)(kw & 1023u), k1 = (int)((kw >> 10) & 1023u), k2 = (int)((kw >> 20) & 1023u);
         const uint32_t tile = tile_of_cell(p.geo, k0, k1, k2);
         const uint32_t pos = tile < p.n_tiles ? p.off[tile] + p.side[i] : 0xffffffffu;
@@ -886,8 +900,9 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                         // packets bound for the same tile
                         uint32_t jw = 0;
                         if constexpr (!F64) jw = dtest.ext.jw;
-                        store_moving<R, S, MB>(recs + (size_t)rid * RL::STRIDE, pack_cell(k0, k1, k2, lax),
-                                               d0, jw, d1, d2, active, F, D);
+                        store_moving<R, S, MB>(recs + (size_t)rid * RL::STRIDE, unpack_dir(a0), unpack_dir(a1),
+                                               unpack_dir(a2), pack_cell(k0, k1, k2, lax), d0, jw, d1, d2, active,
+                                               w, F64 ? L : Lf, F, D);
                         const uint32_t code = (uint32_t)((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1));
                         const uint32_t rank = atomicAdd(&s_cnt[code], 1u);
                         p.side[pos] = code | (rank << 5);
@@ -949,28 +964,28 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                                 const uint4 v = rp[u];
                                 wd[4 * u] = v.x; wd[4 * u + 1] = v.y; wd[4 * u + 2] = v.z; wd[4 * u + 3] = v.w;
                             }
-                            const int32_t c0 = (int32_t)wd[0], c1 = (int32_t)wd[1], c2 = (int32_t)wd[2];
-                            const uint32_t kw = wd[3];
-                            d0 = wd[4] & 0xfffu;
-                            const uint32_t jw = (wd[4] >> 12) & 0xfu;
-                            d1 = wd[4] >> 16;
-                            d2 = wd[5] & 0xffffu;
-                            active = wd[5] >> 16;
-                            w = __hiloint2double((int)wd[7], (int)wd[6]);
-                            if constexpr (F64) L = __hiloint2double((int)wd[9], (int)wd[8]);
-                            else Lf = __uint_as_float(wd[8]);
+                            constexpr int M = RL::MOV;
+                            const int32_t c0 = (int32_t)wd[M], c1 = (int32_t)wd[M + 1], c2 = (int32_t)wd[M + 2];
+                            const uint32_t kw = wd[0];
+                            d0 = wd[1] & 0xfffu;
+                            const uint32_t jw = (wd[1] >> 12) & 0xfu;
+                            d1 = wd[1] >> 16;
+                            d2 = wd[2] & 0xffffu;
+                            active = wd[2] >> 16;
+                            w = __hiloint2double((int)wd[M + 4], (int)wd[M + 3]);
+                            if constexpr (F64) L = __hiloint2double((int)wd[M + 6], (int)wd[M + 5]);
+                            else Lf = __uint_as_float(wd[M + 5]);
                             if constexpr (F64) {
 #pragma unroll
                                 for (int j = 0; j < MB; ++j) {
-                                    F[j] = __hiloint2double((int)wd[RL::HDR + 1 + 2 * j], (int)wd[RL::HDR + 2 * j]);
-                                    D[j] = __hiloint2double((int)wd[RL::HDR + 2 * MB + 1 + 2 * j],
-                                                            (int)wd[RL::HDR + 2 * MB + 2 * j]);
+                                    F[j] = __hiloint2double((int)wd[4 + 2 * j], (int)wd[3 + 2 * j]);
+                                    D[j] = __hiloint2double((int)wd[4 + 2 * MB + 2 * j], (int)wd[3 + 2 * MB + 2 * j]);
                                 }
                             } else {
 #pragma unroll
-                                for (int j = 0; j < ND; ++j) D[j] = __uint_as_float(wd[RL::HDR + j]);
+                                for (int j = 0; j < ND; ++j) D[j] = __uint_as_float(wd[3 + j]);
 #pragma unroll
-                                for (int j = 0; j < MB; ++j) F[j] = __uint_as_float(wd[RL::HDR + ND + j]);
+                                for (int j = 0; j < MB; ++j) F[j] = __uint_as_float(wd[3 + ND + j]);
                             }
                             k0 = (int)(kw & 1023u);
                             k1 = (int)((kw >> 10) & 1023u);
@@ -1109,8 +1124,9 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                     if (alive && !pend) {
                         uint32_t jw = 0;
                         if constexpr (!F64) jw = dtest.ext.jw;
-                        store_moving<R, S, MB>(recs + (size_t)rid * RL::STRIDE, pack_cell(k0, k1, k2, lax), d0, jw,
-                                               d1, d2, active, F, D);
+                        store_moving<R, S, MB>(recs + (size_t)rid * RL::STRIDE, unpack_dir(a0), unpack_dir(a1),
+                                               unpack_dir(a2), pack_cell(k0, k1, k2, lax), d0, jw, d1, d2, active,
+                                               w, F64 ? L : Lf, F, D);
                         const uint32_t stay = 13u;                 // code of the tile itself
                         const uint32_t rank = atomicAdd(&s_cnt[stay], 1u);
                         p.side[pos] = stay | (rank << 5);

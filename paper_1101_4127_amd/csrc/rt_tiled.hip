@@ -539,7 +539,6 @@ __global__ void __launch_bounds__(kTBlock) k_bgemit(const TParams p, const Backg
     using RL = TRec<R, S, MB>;
     constexpr int ND = RL::ND;
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
     const uint32_t gw = (blockIdx.x * kTBlock + threadIdx.x) >> 6;
     const uint32_t nw = gridDim.x * kTWaves;
     const R *sed = reinterpret_cast<const R *>(bp.sed);
@@ -564,8 +563,8 @@ __global__ void __launch_bounds__(kTBlock) k_bgemit(const TParams p, const Backg
             else if ((idx -= 2ull * fx) < 2ull * fy) { axis = 1; plus = idx >= fy; idx -= plus ? fy : 0ull; }
             else { idx -= 2ull * fy; axis = 2; plus = idx >= fz; idx -= plus ? fz : 0ull; }
             const int u = axis == 0 ? 1 : 0, v = axis == 2 ? 1 : 2;
-            const uint64_t nu = (uint64_t)p.geo.n[u];
-            const int ia = (int)(idx % nu), ib = (int)(idx / nu);
+            const uint32_t nu = (uint32_t)p.geo.n[u], id = (uint32_t)idx;   // id < n_u n_v <= 2^20
+            const int ia = (int)(id % nu), ib = (int)(id / nu);
             int32_t o[3], kk[3];
             o[axis] = plus ? 2 * p.geo.n[axis] : 0;
             kk[axis] = plus ? p.geo.n[axis] - 1 : 0;
@@ -597,18 +596,11 @@ __global__ void __launch_bounds__(kTBlock) k_bgemit(const TParams p, const Backg
                                    next_face(kk[1], o[1], a1), next_face(kk[2], o[2], a2), active, ww, len, F, D);
             tile = tile_of_cell(p.geo, kk[0], kk[1], kk[2]);
         }
-        uint64_t pend = __ballot(act);
+        // rank in the tile's list: the packets of a wavefront start on boundary
+        // tiles drawn at random, nearly all different, so one atomic per lane
+        // (issued together) rather than one per distinct tile in turn
         uint32_t rel = 0;
-        while (pend != 0ull) {
-            const int lead = __ffsll((unsigned long long)pend) - 1;
-            const uint32_t lt = (uint32_t)__shfl((int)tile, lead);
-            const uint64_t same = __ballot(act && tile == lt) & pend;
-            uint32_t b = 0;
-            if ((int)lane == lead) b = atomicAdd(p.cnt + lt, (uint32_t)__popcll(same));
-            b = (uint32_t)__shfl((int)b, lead);
-            if ((same >> lane) & 1ull) rel = b + (uint32_t)__popcll(same & lt_mask);
-            pend &= ~same;
-        }
+        if (act) rel = atomicAdd(p.cnt + tile, 1u);
         if (act) p.side[i] = rel;
     }
     double v[8] = {l_emit, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};

@@ -74,26 +74,37 @@ struct Rates {
 
 // Factors of T that the rates and the cooling of one chemistry sub-step share
 // (evaluated once; each rate multiplies them in the order its formula is
-// written, so the results are those of the formulas evaluated separately).
+// written).  Powers of T: where the update counts recombinations (`exact`,
+// case-A rates) pow, as the formulas are written -- the counters' time
+// integral of x_HII cancels strongly in some cells, and pow keeps them equal
+// to the plain formulas' to the last bit; otherwise exp(a ln T) from one ln T,
+// within 5e-15 of pow at half the update's cost (pow is two float64
+// transcendentals in one).
 struct TFac {
     double damp, rt, e_hi, e_hei, e_heii;   // 1/(1+sqrt(T/1e5)), sqrt(T), exp(-T_X/T)
     double p15, e470, e94;                  // T^-1.5, exp(-470000/T), 1 + 0.3 exp(-94000/T)
+    double lt;                              // ln T (not formed when EXACT)
 };
 
+template <bool EXACT>
 __device__ __forceinline__ TFac tfac(double T) {
     TFac f;
+    f.lt = EXACT ? 0.0 : log(T);
     f.damp = 1.0 / (1.0 + sqrt(T * 1.0e-5));
     f.rt = sqrt(T);
     f.e_hi = exp(-157809.1 / T);
     f.e_hei = exp(-285335.4 / T);
     f.e_heii = exp(-631515.0 / T);
-    f.p15 = pow(T, -1.5);
+    f.p15 = EXACT ? pow(T, -1.5) : exp(-1.5 * f.lt);
     f.e470 = exp(-470000.0 / T);
     f.e94 = 1.0 + 0.3 * exp(-94000.0 / T);
     return f;
 }
 
-__device__ Rates rates_at(double T, const TFac &f, bool case_a = false) {
+// Case A with pow (recombination counting, EXACT) or case B from ln T.
+template <bool EXACT>
+__device__ Rates rates_at(double T, const TFac &f) {
+    constexpr bool case_a = EXACT;
     Rates r;
     const double damp = f.damp;
     const double rt = f.rt;
@@ -103,9 +114,11 @@ __device__ Rates rates_at(double T, const TFac &f, bool case_a = false) {
         r.rec_heiii = 2.0 * hydrogenic_casea(T, 631515.0);
         r.rec_heii = heii_rad_casea(T) + diel;
     } else {
-        r.rec_hii = hydrogenic_caseb(T, 157807.0);
-        r.rec_heiii = 2.0 * hydrogenic_caseb(T, 631515.0);
-        r.rec_heii = 1.26e-14 * pow(570670.0 / T, 0.750) + diel;
+        // lambda^1.5 / (1 + (lambda / 2.740)^0.407)^2.242 with ln lambda = ln 2 T_ion - ln T
+        const double lh = 12.662275226919286 - f.lt, lhe = 14.049024154019651 - f.lt;   // ln 2 x 157807, 631515
+        r.rec_hii = 2.753e-14 * exp(1.5 * lh - 2.242 * log1p(exp(0.407 * (lh - 1.007957920399979))));  // ln 2.740
+        r.rec_heiii = 2.0 * (2.753e-14 * exp(1.5 * lhe - 2.242 * log1p(exp(0.407 * (lhe - 1.007957920399979)))));
+        r.rec_heii = 1.26e-14 * exp(0.750 * (13.254566388120152 - f.lt)) + diel;                         // ln 570670
     }
     r.col_hi = 5.85e-11 * rt * f.e_hi * damp;
     r.col_hei = 2.38e-11 * rt * f.e_hei * damp;
@@ -114,20 +127,22 @@ __device__ Rates rates_at(double T, const TFac &f, bool case_a = false) {
 }
 
 // Cooling [erg cm^-3 s^-1] without the Compton term.
+template <bool EXACT>
 __device__ double cooling_rate(double T, const TFac &f, double ne, double n_hi, double n_hii, double n_hei,
                                double n_heii, double n_heiii) {
     const double damp = f.damp;
     const double rt = f.rt;
     const double e_hi = f.e_hi, e_hei = f.e_hei, e_heii = f.e_heii;
-    const double t3 = pow(T * 1.0e-3, -0.2);
-    const double t6 = 1.0 / (1.0 + pow(T * 1.0e-6, 0.7));
-    const double lg = log10(T);
+    constexpr bool ex = EXACT;
+    const double t3 = ex ? pow(T * 1.0e-3, -0.2) : exp(-0.2 * (f.lt - 6.907755278982137));          // ln 1e3
+    const double t6 = 1.0 / (1.0 + (ex ? pow(T * 1.0e-6, 0.7) : exp(0.7 * (f.lt - 13.815510557964274))));  // ln 1e6
+    const double lg = ex ? log10(T) : f.lt * 0.43429448190325176;                                      // 1 / ln 10
     const double gaunt = 1.1 + 0.34 * exp(-(5.5 - lg) * (5.5 - lg) / 3.0);
     double per_ne_hi = 7.50e-19 * exp(-118348.0 / T) * damp      // excitation
                      + 1.27e-21 * rt * e_hi * damp;              // ionisation
-    double per_ne_heii = 5.54e-17 * pow(T, -0.397) * exp(-473638.0 / T) * damp
+    double per_ne_heii = 5.54e-17 * (ex ? pow(T, -0.397) : exp(-0.397 * f.lt)) * exp(-473638.0 / T) * damp
                        + 4.95e-22 * rt * e_heii * damp
-                       + 1.55e-26 * pow(T, 0.3647)                 // recombination
+                       + 1.55e-26 * (ex ? pow(T, 0.3647) : exp(0.3647 * f.lt))                // recombination
                        + 1.24e-13 * f.p15 * f.e470 * f.e94;
     double lam = ne * (per_ne_hi * n_hi + per_ne_heii * n_heii
                        + 9.38e-22 * rt * e_hei * damp * n_hei
@@ -210,7 +225,8 @@ struct UpdateConst {
 // recombinations per atom of each ion over the sub-step are added to its
 // counters (rate times the time integral of the ion fraction along the
 // corrector's solution).
-template <typename R, int S, bool TH>
+// CNT: count the recombinations into rc (re-emission; case-A rates, pow).
+template <typename R, int S, bool TH, bool CNT>
 __device__ __forceinline__ void update_slot(const GridGeom &G, R *__restrict__ st, const double *__restrict__ acc,
                                             int acc_stride, double y_he, double dt, int n_chem,
                                             const UpdateConst &u, uint32_t s, unsigned int &bad,
@@ -238,16 +254,16 @@ __device__ __forceinline__ void update_slot(const GridGeom &G, R *__restrict__ s
         for (int q = 0; q < 3; ++q)
             gam[q] = (dep[q] > 0.0 && absorbers[q] > 0.0) ? dep[q] / (absorbers[q] * V * dt) : 0.0;
         const double heat = qheat / (V * dt);
-        const bool count = rc != nullptr;
+        constexpr bool count = CNT;
         double n_rec[3] = {0.0, 0.0, 0.0};
         if (count)
             for (int q = 0; q < S; ++q) n_rec[q] = rc[(size_t)q * np + s];
-        TFac tf = tfac(T);
-        Rates r = rates_at(T, tf, count);
+        TFac tf = tfac<CNT>(T);
+        Rates r = rates_at<CNT>(T, tf);
         for (int m = 0; m < n_chem; ++m) {
             if (TH && m > 0) {
-                tf = tfac(T);
-                r = rates_at(T, tf, count);
+                tf = tfac<CNT>(T);
+                r = rates_at<CNT>(T, tf);
             }
             const double ne0 = nh * x.hii + nhe * (x.heii + 2.0 * x.heiii);
             Frac xp, xn;
@@ -279,7 +295,7 @@ __device__ __forceinline__ void update_slot(const GridGeom &G, R *__restrict__ s
                 const double ntot0 = nh * (1.0 + x.hii) + nhe * (1.0 + x.heii + 2.0 * x.heiii);
                 const double ntot1 = nh * (1.0 + xn.hii) + nhe * (1.0 + xn.heii + 2.0 * xn.heiii);
                 const double ne1 = nh * xn.hii + nhe * (xn.heii + 2.0 * xn.heiii);
-                const double lam = cooling_rate(T, tf, ne1, nh * xn.hi, nh * xn.hii, nhe * xn.hei,
+                const double lam = cooling_rate<CNT>(T, tf, ne1, nh * xn.hi, nh * xn.hii, nhe * xn.hei,
                                                 nhe * xn.heii, nhe * xn.heiii);
                 const double cne = ccomp * ne1;
                 double tn = (1.5 * kb * ntot0 * T + h * (heat + cne * tcmb))
@@ -310,8 +326,13 @@ __global__ void __launch_bounds__(kCellBlock, (TH ? 3 : 4)) k_update(GridGeom G,
     const uint32_t stride = gridDim.x * blockDim.x;
     const UpdateConst u(cell_cm, dt, redshift, n_chem);
     unsigned int bad = 0;
-    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < np; s += stride)
-        update_slot<R, S, TH>(G, st, acc, acc_stride, y_he, dt, n_chem, u, s, bad, rc);
+    if (rc != nullptr) {
+        for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < np; s += stride)
+            update_slot<R, S, TH, true>(G, st, acc, acc_stride, y_he, dt, n_chem, u, s, bad, rc);
+    } else {
+        for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < np; s += stride)
+            update_slot<R, S, TH, false>(G, st, acc, acc_stride, y_he, dt, n_chem, u, s, bad);
+    }
     if (bad) atomicOr(&ledger->nonfinite, 1u);
 }
 
@@ -552,7 +573,7 @@ __global__ void __launch_bounds__(kCellBlock) k_bupdate(const BatchHead *hd, con
         if (round >= sv.n_sub) continue;
         const UpdateConst u(sv.cell_cm, sv.dt, sv.redshift, sv.n_chem);
         unsigned int bad = 0;
-        update_slot<R, 1, TH>(sv.geo, reinterpret_cast<R *>(sv.state), sv.acc, sv.acc_stride, sv.y_he, sv.dt,
+        update_slot<R, 1, TH, false>(sv.geo, reinterpret_cast<R *>(sv.state), sv.acc, sv.acc_stride, sv.y_he, sv.dt,
                               sv.n_chem, u, (uint32_t)(g - s_first[b]), bad);
         if (bad) atomicOr(&sv.ledger->nonfinite, 1u);
     }

@@ -81,6 +81,7 @@ def lib():
             L.orc_rates_at.argtypes = [C.c_double, _P(Rates)]
             L.orc_cooling.argtypes = [C.c_double] * 7
             L.orc_cooling.restype = C.c_double
+            L.orc_cooling_terms.argtypes = [C.c_double] * 7 + [dp]
             L.orc_compton_coeff.argtypes = [C.c_double]
             L.orc_compton_coeff.restype = C.c_double
             L.orc_update_cell_ex.argtypes = [gp, C.c_double, C.c_double, dp, dp, dp,
@@ -228,6 +229,18 @@ def update_cell_rx(grid: Grid, dt: float, nh: float, x, T: float, acc, rc,
 
 def cooling(T, ne, n_hi, n_hii, n_hei, n_heii, n_heiii) -> float:
     return lib().orc_cooling(*(float(v) for v in (T, ne, n_hi, n_hii, n_hei, n_heii, n_heiii)))
+
+
+COOLING_TERMS = ("exc_hi", "exc_heii", "ci_hi", "ci_hei", "ci_heii", "rec_hii", "rec_heii", "rec_heiii",
+                 "diel_heii", "brems")
+
+
+def cooling_terms(T, ne, n_hi, n_hii, n_hei, n_heii, n_heiii) -> dict:
+    """The cooling function's processes one by one (erg cm^-3 s^-1)."""
+    out = np.zeros(10)
+    lib().orc_cooling_terms(*(float(v) for v in (T, ne, n_hi, n_hii, n_hei, n_heii, n_heiii)),
+                            _ptr(out, C.c_double))
+    return dict(zip(COOLING_TERMS, out.tolist()))
 
 
 def compton_coeff(z: float) -> float:

@@ -485,31 +485,45 @@ void orc_rates_at(double T, orc_rates *r)
     r->b_heii = 5.68e-12 * sqrt(T) * exp(-631515.0 / T) * f5;
 }
 
-/* Radiative and collisional cooling [erg cm^-3 s^-1], Compton excluded. */
-double orc_cooling(double T, double ne, double n_hi, double n_hii,
-                   double n_hei, double n_heii, double n_heiii)
+/* The processes of the cooling function one by one [erg cm^-3 s^-1]:
+ *  0 collisional excitation of HI       1 collisional excitation of HeII
+ *  2 collisional ionisation of HI       3 ... of HeI       4 ... of HeII
+ *  5 recombination of HII               6 ... of HeII      7 ... of HeIII
+ *  8 dielectronic recombination of HeII 9 bremsstrahlung (free-free) */
+void orc_cooling_terms(double T, double ne, double n_hi, double n_hii,
+                       double n_hei, double n_heii, double n_heiii, double t[10])
 {
     const double f5 = 1.0 / (1.0 + sqrt(T / 1.0e5));
     const double sT = sqrt(T);
-    double lam = 0.0;
     /* collisional excitation */
-    lam += 7.50e-19 * exp(-118348.0 / T) * f5 * ne * n_hi;
-    lam += 5.54e-17 * pow(T, -0.397) * exp(-473638.0 / T) * f5 * ne * n_heii;
+    t[0] = 7.50e-19 * exp(-118348.0 / T) * f5 * ne * n_hi;
+    t[1] = 5.54e-17 * pow(T, -0.397) * exp(-473638.0 / T) * f5 * ne * n_heii;
     /* collisional ionisation */
-    lam += 1.27e-21 * sT * exp(-157809.1 / T) * f5 * ne * n_hi;
-    lam += 9.38e-22 * sT * exp(-285335.4 / T) * f5 * ne * n_hei;
-    lam += 4.95e-22 * sT * exp(-631515.0 / T) * f5 * ne * n_heii;
+    t[2] = 1.27e-21 * sT * exp(-157809.1 / T) * f5 * ne * n_hi;
+    t[3] = 9.38e-22 * sT * exp(-285335.4 / T) * f5 * ne * n_hei;
+    t[4] = 4.95e-22 * sT * exp(-631515.0 / T) * f5 * ne * n_heii;
     /* recombination */
     const double t3 = pow(T / 1.0e3, -0.2), t6 = 1.0 / (1.0 + pow(T / 1.0e6, 0.7));
-    lam += 8.70e-27 * sT * t3 * t6 * ne * n_hii;
-    lam += 1.55e-26 * pow(T, 0.3647) * ne * n_heii;
-    lam += 3.48e-26 * sT * t3 * t6 * ne * n_heiii;
+    t[5] = 8.70e-27 * sT * t3 * t6 * ne * n_hii;
+    t[6] = 1.55e-26 * pow(T, 0.3647) * ne * n_heii;
+    t[7] = 3.48e-26 * sT * t3 * t6 * ne * n_heiii;
     /* dielectronic recombination */
-    lam += 1.24e-13 * pow(T, -1.5) * exp(-470000.0 / T) * (1.0 + 0.3 * exp(-94000.0 / T)) * ne * n_heii;
+    t[8] = 1.24e-13 * pow(T, -1.5) * exp(-470000.0 / T) * (1.0 + 0.3 * exp(-94000.0 / T)) * ne * n_heii;
     /* bremsstrahlung */
     const double lt = log10(T);
     const double gff = 1.1 + 0.34 * exp(-(5.5 - lt) * (5.5 - lt) / 3.0);
-    lam += 1.42e-27 * gff * sT * (n_hii + n_heii + 4.0 * n_heiii) * ne;
+    t[9] = 1.42e-27 * gff * sT * (n_hii + n_heii + 4.0 * n_heiii) * ne;
+}
+
+/* Radiative and collisional cooling [erg cm^-3 s^-1], Compton excluded: the
+ * sum of the terms above in their order. */
+double orc_cooling(double T, double ne, double n_hi, double n_hii,
+                   double n_hei, double n_heii, double n_heiii)
+{
+    double t[10];
+    orc_cooling_terms(T, ne, n_hi, n_hii, n_hei, n_heii, n_heiii, t);
+    double lam = 0.0;
+    for (int i = 0; i < 10; ++i) lam += t[i];
     return lam;
 }
 

@@ -43,9 +43,9 @@ def test_path_limit_escape_is_the_closed_form(n, L, g):
     sigma = float(w.bins.sigma[0, 0])
     wgt = 1.0e48 * w.dt_s
     assert led["n_escaped"] == 1 and led["n_truncated"] == 0
-    assert led["escaped"] == pytest.approx(wgt * math.exp(-1.0e-6 * sigma * length), rel=1e-12)
+    assert led["escaped"] == pytest.approx(wgt * math.exp(-1.0e-6 * sigma * length), rel=1e-12, abs=0)
     assert s.trace[0][1] == O.FATE_PATH
-    assert led["emitted"] == pytest.approx(led["absorbed"] + led["escaped"], rel=1e-14)
+    assert led["emitted"] == pytest.approx(led["absorbed"] + led["escaped"], rel=1e-14, abs=0)
 
 
 def test_equals_the_unfolded_box():
@@ -68,7 +68,7 @@ def test_equals_the_unfolded_box():
     lb = sb.step()
     assert lb["n_escaped"] == 0 and lp["n_escaped"] == 0          # all extinguished inside the tiling
     assert lp["crossings"] == lb["crossings"] and lp["n_truncated"] == lb["n_truncated"] == P
-    assert lp["absorbed"] == pytest.approx(lb["absorbed"], rel=1e-13)
+    assert lp["absorbed"] == pytest.approx(lb["absorbed"], rel=1e-13, abs=0)
     folded = sb.acc[0].reshape(big_n[::-1]).reshape(5, n[2], 5, n[1], 5, n[0]).sum(axis=(0, 2, 4)).ravel()
     assert np.allclose(sp.acc[0], folded, rtol=1e-12, atol=0.0)
     assert np.count_nonzero(folded) > 0.5 * folded.size

@@ -51,13 +51,13 @@ def test_emission_budget_and_shares():
     assert list(counts) == [1001, 1000, 1000]
     assert led["packets"] == 3001
     # every source emits its full luminosity x dt
-    assert led["emitted"] == pytest.approx(w.src_ndot.sum() * w.dt_s, rel=1e-14)
+    assert led["emitted"] == pytest.approx(w.src_ndot.sum() * w.dt_s, rel=1e-14, abs=0)
 
 
 def test_octant_source_emits_one_eighth():
     w = uniform_case(src=((0, 0, 0),), octant=True, packets=2000)
     s, acc, led, tr = run_march(w)
-    assert led["emitted"] == pytest.approx(w.src_ndot[0] * w.dt_s / 8.0, rel=1e-14)
+    assert led["emitted"] == pytest.approx(w.src_ndot[0] * w.dt_s / 8.0, rel=1e-14, abs=0)
     assert np.all(tr[:, 4:7] >= 0)
 
 
@@ -75,8 +75,8 @@ def test_uniform_escape_closed_form(nh):
     for rec in tr:
         assert rec[1] == O.FATE_ESCAPE
         expect += wpk * math.exp(-nh * sig * exit_distance(w.n, o, rec[4:7], w.cell_cm))
-    assert led["escaped"] == pytest.approx(expect, rel=1e-12)
-    assert led["absorbed"] == pytest.approx(led["emitted"] - expect, rel=1e-12)
+    assert led["escaped"] == pytest.approx(expect, rel=1e-12, abs=0)
+    assert led["absorbed"] == pytest.approx(led["emitted"] - expect, rel=1e-12, abs=0)
 
 
 def test_single_cell_absorption_and_species_split():
@@ -93,11 +93,11 @@ def test_single_cell_absorption_and_species_split():
     tot = sum(wpk * -math.expm1(-ksum * exit_distance((1, 1, 1), (1, 1, 1), rec[4:7], w.cell_cm))
               for rec in tr)
     dsum = acc[:3, 0].sum()
-    assert dsum == pytest.approx(tot, rel=1e-12)
+    assert dsum == pytest.approx(tot, rel=1e-12, abs=0)
     for sp in range(3):
-        assert acc[sp, 0] / dsum == pytest.approx(kap[sp] * sig[sp] / ksum, rel=1e-12)
+        assert acc[sp, 0] / dsum == pytest.approx(kap[sp] * sig[sp] / ksum, rel=1e-12, abs=0)
     heat = sum(acc[sp, 0] * (80.0 - W.E_TH_EV[sp]) * W.EV_ERG for sp in range(3))
-    assert acc[3, 0] == pytest.approx(heat, rel=1e-12)
+    assert acc[3, 0] == pytest.approx(heat, rel=1e-12, abs=0)
 
 
 def test_truncation_cell_and_ledger():
@@ -122,7 +122,7 @@ def test_truncation_cell_and_ledger():
             trunc += wpk * math.exp(-tau[hit[0]])
         else:
             assert rec[1] == O.FATE_ESCAPE and rec[0] == cnt
-    assert led["truncated"] == pytest.approx(trunc, rel=1e-9)
+    assert led["truncated"] == pytest.approx(trunc, rel=1e-9, abs=0)
     assert 0 < led["n_truncated"] < w.packets
     assert np.mean(tr[tr[:, 1] == O.FATE_TRUNC, 0]) > 3
 
@@ -140,7 +140,7 @@ def test_photon_conservation(case):
     # the per-cell deposits add up to the absorbed ledger (last sub-step only
     # for the multi-sub-step case, so compare there with a fresh march)
     if w.n_sub == 1:
-        assert s.acc[:3].sum() == pytest.approx(led["absorbed"], rel=1e-12)
+        assert s.acc[:3].sum() == pytest.approx(led["absorbed"], rel=1e-12, abs=0)
 
 
 def test_optically_thin_inverse_square():

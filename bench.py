@@ -332,6 +332,8 @@ def main():
                     help="timed steps of the periodic-boundary + background variant (0 skips it)")
     ap.add_argument("--autotune", action="store_true",
                     help="choose the march's launch parameters by measurement first (tiled march)")
+    ap.add_argument("--ceilings", action="store_true",
+                    help="first measure the hardware ceilings (HBM copy/read, float64 atomics)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -350,6 +352,11 @@ def main():
                  blocks_per_cu=args.bpcu)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+    ceil = None
+    if args.ceilings:
+        from paper_1101_4127_amd import ceilings
+        ceil = ceilings.measure()
+        log("ceilings: " + ", ".join(f"{k} {v:.4g}" for k, v in ceil.items()))
     t0 = time.perf_counter()
     work = workload(args.workload, args.packets)
     log(f"workload {work.name}: {work.ncell} cells, {len(work.src_ndot)} sources, "
@@ -389,6 +396,8 @@ def main():
                      "whole_march_gcross_per_s": f32["crossings"] / (f32["march_ms"] * 1e-3) / 1e9},
         "conservation_residual": f32["resid"],
     }
+    if ceil is not None:
+        out["ceilings"] = ceil
     if tuned is not None:
         out["config"]["autotuned"] = tuned["config"]
         out["config"]["autotune_trials"] = len(tuned["trials"])

@@ -120,8 +120,13 @@ typedef struct {
     int32_t n[3];                 /* cells per axis, 1..RT_MAX_CELLS_PER_AXIS */
     double cell_cm;               /* proper cell size */
     double y_he;                  /* n_He / n_H ; 0 = pure hydrogen */
-    int32_t n_bins;               /* frequency bins, 1..RT_SUPPORTED_BINS (arrays
-                                     hold RT_MAX_BINS; larger counts -> RT_EINVAL) */
+    int32_t n_bins;               /* frequency bins: 1 or RT_SUPPORTED_BINS (arrays
+                                     hold RT_MAX_BINS; other counts -> RT_EINVAL).
+                                     H+He with 8 bins in the tiled march: the
+                                     table must be threshold-aligned (HeI and HeII
+                                     cross-sections 0 in bins 0-2, HeII 0 in bins
+                                     3-4), else RT_EINVAL; the per-packet march
+                                     takes any table */
     double e_bin_ev[RT_MAX_BINS]; /* photon energy of each bin (heat per absorption
                                      is E_j minus the species' threshold) */
     double sigma_cm2[3][RT_MAX_BINS]; /* HI, HeI, HeII cross-sections per bin;
@@ -194,7 +199,9 @@ typedef struct {
 int32_t rt_desc_defaults(rt_grid_desc *d);
 
 /* Workspace bytes a solve with this description and at most max_sources
- * sources needs.  Returns RT_EINVAL for an invalid description. */
+ * sources needs.  Returns RT_EINVAL for an invalid description (including a
+ * bin count other than 1 or 8, and an H+He table of 8 bins that the tiled
+ * march has no instance for). */
 int32_t rt_workspace_bytes(const rt_grid_desc *d, int64_t max_sources, size_t *bytes_out);
 
 /* Create a solve in the caller's device workspace and load its initial state.
@@ -310,7 +317,8 @@ int32_t rt_release(rt_solve_t h);
  * depend on which solves are in the batch).
  *
  * Solves of one call: pure hydrogen (y_he = 0), one bin, all float32 or all
- * float64, all thermal or all isothermal, no tracing, on the batch's device,
+ * float64, all thermal or all isothermal, no tracing, no periodic boundaries,
+ * no recombination re-emission or background field, on the batch's device,
  * each at most once.  They may use any march flags (the fused march is the
  * per-packet one); their own streams are ordered around the call with events,
  * so rt_fetch_fields and rt_read_stats on a solve see its result. */

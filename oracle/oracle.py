@@ -102,6 +102,9 @@ def lib():
             L.orc_hii_time.argtypes = [C.c_double] * 5
             L.orc_hii_time.restype = C.c_double
             L.orc_he_ion_time.argtypes = [dp, dp] + [C.c_double] * 5 + [dp]
+            L.orc_background_packet.argtypes = [gp, _P(Background), C.c_double, C.c_int64, C.c_uint64,
+                                                C.c_uint64, C.c_uint64, C.c_uint64, ip, ip]
+            L.orc_background_packet.restype = C.c_double
             L.orc_direction_ex.argtypes = [C.c_uint64] * 4 + [C.c_int, C.c_uint64, ip]
             L.orc_direction_ex.restype = C.c_int
             _lib = L
@@ -211,6 +214,19 @@ def direction_ex(seed: int, solve_id: int, g: int, step_index: int, octant: bool
     c = np.zeros(3, np.int32)
     att = lib().orc_direction_ex(seed, solve_id, g, step_index, int(octant), stream, _ptr(c, C.c_int32))
     return c, att
+
+
+def background_packet(grid: Grid, ndot: float, sed, dt: float, packets: int, seed: int, solve_id: int,
+                      step_index: int, b: int):
+    """Background packet b of a sub-step: (start point o, direction c, weight)."""
+    row = _c64(sed).copy()
+    bg = Background(float(ndot), _ptr(row, C.c_double), int(packets))
+    o = np.zeros(3, np.int32)
+    c = np.zeros(3, np.int32)
+    w = lib().orc_background_packet(C.byref(grid), C.byref(bg), float(dt), int(packets), int(seed),
+                                    int(solve_id), int(step_index), int(b), _ptr(o, C.c_int32),
+                                    _ptr(c, C.c_int32))
+    return o, c, float(w)
 
 
 def update_cell_rx(grid: Grid, dt: float, nh: float, x, T: float, acc, rc,

@@ -27,9 +27,9 @@
  *   7. after all packets, every cell's ionisation fractions and temperature
  *      are advanced from the accumulated photons (Sec. 2's network, applied
  *      once per cell per sub-step instead of once per crossing).
- * Parity of the physics rates (recombination, collisional, cooling) is
- * pinned only through closed forms and sanity bands; the rate formulas are a
- * stated reading (the paper lists the processes but gives no rates).
+ * The physics rates (recombination, collisional, cooling) are a stated
+ * reading (the paper lists the processes but gives no rates), pinned by the
+ * tests against physical identities, constants and published tables.
  */
 #include <math.h>
 #include <stdint.h>
@@ -925,6 +925,14 @@ static double background_packet(const orc_grid *G, const orc_background *B, doub
     double w = B->ndot * dt;
     w = w / (double)P;
     return w * (2.0 * (double)cn) / sqrt(q);
+}
+
+/* Background packet b of a sub-step (start point o in half cells, direction
+ * c); returns its weight. */
+double orc_background_packet(const orc_grid *G, const orc_background *B, double dt, int64_t P, uint64_t seed,
+                             uint64_t solve_id, uint64_t step_index, uint64_t b, int32_t o[3], int32_t c[3])
+{
+    return background_packet(G, B, dt, P, seed, solve_id, step_index, b, o, c);
 }
 
 /* March background packets [0, P) of one sub-step. */

@@ -18,6 +18,9 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "librt_mcrt.so")
 SOURCES = ("rt_march.hip", "rt_tiled.hip", "rt_cells.hip", "rt_abi.cpp")
+# microbenchmarks of the march's hardware ceilings, a library of their own
+CEIL_LIB = os.path.join(PKG, "librt_ceilings.so")
+CEIL_SOURCES = ("rt_ceilings.hip",)
 ARCH = "gfx950"
 
 FLAGS = [
@@ -45,19 +48,26 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link the shared library; returns its path."""
-    os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + f".tmp{os.getpid()}"
+def _link(objs, lib: str, verbose: bool):
+    tmp = lib + f".tmp{os.getpid()}"
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {lib}")
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source and link the shared libraries (the method's and the
+    ceilings microbenchmarks'); returns the method library's path."""
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = SOURCES + CEIL_SOURCES
+    with cf.ThreadPoolExecutor(max_workers=len(srcs)) as ex:
+        objs = list(ex.map(_compile, srcs))
+    _link(objs[:len(SOURCES)], LIB, verbose)
+    _link(objs[len(SOURCES):], CEIL_LIB, verbose)
     return LIB
 
 

@@ -56,7 +56,9 @@ int32_t validate_desc(const rt_grid_desc *d) {
         if (d->n[a] < 1 || d->n[a] > RT_MAX_CELLS_PER_AXIS) return RT_EINVAL;
     if (!(isfinite(d->cell_cm) && d->cell_cm > 0.0)) return RT_EINVAL;
     if (!finite_nonneg(d->y_he)) return RT_EINVAL;
-    if (d->n_bins < 1 || d->n_bins > kMaxSupportedBins) return RT_EINVAL;
+    // one bin or the full eight: the eight-wide instances are the only
+    // multi-bin ones run against the oracle (counts in between are refused)
+    if (d->n_bins != 1 && d->n_bins != kMaxSupportedBins) return RT_EINVAL;
     for (int j = 0; j < d->n_bins; ++j) {
         if (!finite_nonneg(d->e_bin_ev[j])) return RT_EINVAL;
         for (int s = 0; s < 3; ++s) {
@@ -92,8 +94,16 @@ int32_t validate_desc(const rt_grid_desc *d) {
 int32_t make_plan(const rt_grid_desc *d, int64_t max_sources, Plan *p) {
     const int32_t v = validate_desc(d);
     if (v != RT_OK) return v;
+    *p = Plan{};
     if (max_sources < 0 || max_sources > (int64_t)1 << 30) return RT_EINVAL;
     p->species = d->y_he > 0.0 ? 3 : 1;
+    // the tiled march has an instance for the threshold-aligned H+He table
+    // only (helium cross-sections zero in bins 0-2, HeII zero in bins 3-4);
+    // other H+He tables of several bins run in the per-packet march
+    if (p->species == 3 && d->n_bins > 1 && !(d->flags & RT_DIRECT_MARCH)) {
+        for (int j = 0; j < 5; ++j)
+            if (d->sigma_cm2[2][j] != 0.0 || (j < 3 && d->sigma_cm2[1][j] != 0.0)) return RT_EINVAL;
+    }
     p->thermal = (d->flags & RT_ISOTHERMAL) ? 0 : 1;
     p->fp64 = (d->flags & RT_FP64) ? 1 : 0;
     p->mb = bin_capacity(d->n_bins);
@@ -139,6 +149,7 @@ int32_t make_plan(const rt_grid_desc *d, int64_t max_sources, Plan *p) {
     }
     p->capacity = p->cmax = p->max_chunks = p->n_tiles = p->scan_blocks = p->passes = 0;
     p->park_passes = p->park_lanes = 0;
+    p->periodic = p->dmax = 0;
     p->rec_bytes = 0;
     p->off_rec = p->off_idx0 = p->off_idx1 = p->off_side = p->off_cnt = p->off_off = p->off_cbase = p->off_bsum =
         p->off_ch0 = p->off_ch1 = p->off_ctrl = 0;
@@ -365,7 +376,7 @@ int32_t rt_desc_defaults(rt_grid_desc *d) {
 
 int32_t rt_workspace_bytes(const rt_grid_desc *d, int64_t max_sources, size_t *bytes_out) {
     if (!bytes_out) return RT_EINVAL;
-    Plan p;
+    Plan p{};
     const int32_t r = make_plan(d, max_sources, &p);
     if (r != RT_OK) return r;
     *bytes_out = p.total;
@@ -377,7 +388,7 @@ int32_t rt_init_grid(const rt_grid_desc *d, void *d_ws, size_t ws_bytes, int64_t
                      void *hip_stream, rt_solve_t *out) {
     if (!out) return RT_EINVAL;
     *out = nullptr;
-    Plan p;
+    Plan p{};
     const int32_t r = make_plan(d, max_sources, &p);
     if (r != RT_OK) return r;
     if (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0) return RT_EINVAL;
@@ -990,7 +1001,7 @@ int32_t rt_step_many(rt_batch_t b, const rt_solve_t *solves, int32_t n, const do
             if (solves[k] == h) return RT_EINVAL;
         const Plan &p = h->plan;
         if (h->device != b->device || p.species != 1 || p.mb != 1 || h->d.trace_packets > 0 || p.recomb ||
-            h->bg_packets > 0)
+            h->bg_packets > 0 || p.periodic)
             return RT_EINVAL;
         if ((fp64 >= 0 && p.fp64 != fp64) || (thermal >= 0 && p.thermal != thermal)) return RT_EINVAL;
         fp64 = p.fp64;

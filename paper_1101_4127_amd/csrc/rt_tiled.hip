@@ -1316,10 +1316,17 @@ void run_passes(const TParams &p, const TiledLaunch &t) {
     hipLaunchKernelGGL(k_tcheck, dim3(1), dim3(64), 0, st, t.ctrl, cur, t.ledger);
 }
 
+// Bins of the first NA bins absorbed by hydrogen alone, of the next NB
+// without HeII: the threshold-aligned layout every H+He table of several bins
+// has in the tiled march (the host refuses others).
+template <int S, int MB> struct Layout { static constexpr int NA = 0, NB = 0; };
+template <> struct Layout<3, 8> { static constexpr int NA = 3, NB = 2; };
+
 template <typename R, int S, bool TH, int MB>
 hipError_t occ(int *n) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        n, reinterpret_cast<const void *>(&k_tmarch<R, S, TH, MB, 0, 0, false>), kTBlock, 0);
+        n, reinterpret_cast<const void *>(&k_tmarch<R, S, TH, MB, Layout<S, MB>::NA, Layout<S, MB>::NB, false>),
+        kTBlock, 0);
 }
 
 // What a launch runs after its packets are drawn: source packets (neither
@@ -1342,8 +1349,8 @@ hipError_t pick_mb(const TiledLaunch *t, Extra x, int mb, int *o) {
     case 1: return t ? run<R, S, TH, 1, 0, 0>(*t, x) : occ<R, S, TH, 1>(o);
     case 8:
         if (!t) return occ<R, S, TH, 8>(o);
-        if (S == 3 && t->m.layout == 1) return run<R, S, TH, 8, 3, 2>(*t, x);
-        return run<R, S, TH, 8, 0, 0>(*t, x);
+        if (S == 3 && t->m.layout != 1) return hipErrorInvalidValue;
+        return run<R, S, TH, 8, Layout<S, 8>::NA, Layout<S, 8>::NB>(*t, x);
     default: return hipErrorInvalidValue;
     }
 }

@@ -109,6 +109,31 @@ def test_workspace_bytes_scales_and_validates(L):
     e.n[1] = 1025
     with pytest.raises(rt.RTError):
         rt.rt_workspace_bytes(e, 1)
+    # bin counts: 1 or 8 only
+    for nb in range(2, 8):
+        e = rt.rt_desc_defaults()
+        e.n_bins = nb
+        for j in range(nb):
+            e.e_bin_ev[j] = 14.0 + j
+        with pytest.raises(rt.RTError) as ex:
+            rt.rt_workspace_bytes(e, 1)
+        assert ex.value.status == rt.RT_EINVAL, nb
+    # H+He with 8 bins: the tiled march takes the threshold-aligned table only
+    e = rt.rt_desc_defaults()
+    e.n_bins = 8
+    e.y_he = 0.08
+    for j in range(8):
+        e.e_bin_ev[j] = 60.0 + j
+        e.sigma_cm2[0][j] = 1e-19
+        e.sigma_cm2[1][j] = 1e-19 if j >= 3 else 0.0
+        e.sigma_cm2[2][j] = 1e-19 if j >= 5 else 0.0
+    assert rt.rt_workspace_bytes(e, 1) > 0
+    e.sigma_cm2[2][4] = 1e-19                     # HeII in bin 4: no tiled instance
+    with pytest.raises(rt.RTError) as ex:
+        rt.rt_workspace_bytes(e, 1)
+    assert ex.value.status == rt.RT_EINVAL
+    e.flags = rt.RT_DIRECT_MARCH                  # the per-packet march takes it
+    assert rt.rt_workspace_bytes(e, 1) > 0
     # a cross-section above zero below its threshold is rejected
     e = rt.rt_desc_defaults()
     e.e_bin_ev[0] = 20.0
@@ -178,3 +203,25 @@ def test_batch_arguments_are_checked_before_the_device(L):
     assert L.rt_step_many(None, None, 1, None, None, None, None) == rt.RT_EINVAL
     assert L.rt_batch_release(None) == rt.RT_EINVAL
 
+
+
+def test_ceilings_library_exports_its_header():
+    """The microbenchmark library (measured ceilings of the march) loads and
+    exports every function include/rt_ceilings.h declares; invalid arguments
+    are refused before any device call."""
+    from paper_1101_4127_amd import ceilings
+    if not os.path.exists(ceilings.LIB_PATH):
+        from paper_1101_4127_amd import build
+        build.build()
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "rt_ceilings.h")).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(rtc_[a-z0-9_]+)\s*\(", text)))
+    assert len(names) == 4 and set(names) == set(ceilings.SIGNATURES)
+    out = subprocess.run(["nm", "-D", "--defined-only", ceilings.LIB_PATH], capture_output=True, text=True).stdout
+    for n in names:
+        assert re.search(rf"\bT {n}\b", out), n
+    L = ceilings.lib()
+    r = C.c_double(0)
+    assert L.rtc_hbm_copy(None, None, 16, 1, None, C.byref(r)) == -1
+    assert L.rtc_hbm_copy(0x1000, 0x2000, 17, 1, None, C.byref(r)) == -1
+    assert L.rtc_global_atomic_f64(0x1000, 3, 1, None, C.byref(r)) == -1       # not a power of two
+    assert L.rtc_lds_atomic_f64(5, 0, 1, 0x1000, None, C.byref(r)) == -1       # acc > 4

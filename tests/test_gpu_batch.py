@@ -159,13 +159,14 @@ def test_fused_step_rejects_what_it_cannot_fuse():
     s64 = rt.Solve(reqs[0].work, fp64=True, direct=True, stream=b.stream)
     s32 = rt.Solve(reqs[1].work, fp64=False, direct=True, stream=b.stream)
     hhe = rt.Solve(W.small_mixed(n=8, n_src=2, packets=2000), fp64=True, direct=True, stream=b.stream)
-    for bad in ([s64, s32], [s64, s64], [hhe], [s64, s64, s64]):
+    per = rt.Solve(reqs[0].work.with_(periodic=True), fp64=True, stream=b.stream)
+    for bad in ([s64, s32], [s64, s64], [hhe], [s64, s64, s64], [per], [s64, per]):
         with pytest.raises(rt.RTError) as e:
             b.step(bad)
         assert e.value.status == rt.RT_EINVAL
     # nothing was enqueued: the solves still step alone
     assert s64.step()["packets"] == reqs[0].work.packets
-    for s in (s64, s32, hhe):
+    for s in (s64, s32, hhe, per):
         s.release()
     b.release()
 

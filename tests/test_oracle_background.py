@@ -3,6 +3,7 @@ such as the UV background), taken as an isotropic intensity entering the box
 through its faces: packets start at boundary cell faces chosen uniformly over
 the boundary area, with isotropic inward directions weighted by 2 cos(theta)."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -85,3 +86,62 @@ def test_periodic_background_absorbs_more_and_closes():
     for led in (lp, lo):
         assert abs(led["emitted"] - led["absorbed"] - led["escaped"] - led["truncated"]) <= 1e-13 * led["emitted"]
     assert lp["absorbed"] > 2.0 * lo["absorbed"]
+
+
+SCAN_C = r"""
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+int orc_direction_ex(uint64_t, uint64_t, uint64_t, uint64_t, int, uint64_t, int32_t *);
+int main(int argc, char **argv) {
+    const uint64_t seed = strtoull(argv[1], 0, 10), n = strtoull(argv[2], 0, 10);
+    int32_t c[3];
+    for (uint64_t b = 0; b < n; ++b) {
+        orc_direction_ex(seed, 0, b, 0, 0, 3, c);
+        for (int a = 0; a < 3; ++a)
+            if (c[a] == 0) printf("%llu %d\n", (unsigned long long)b, a);
+    }
+    return 0;
+}
+"""
+
+
+def test_zero_normal_component_is_taken_as_one(tmp_path):
+    """Reading of the face entry: a background packet whose isotropic
+    direction has no component along its face's normal (probability ~2^-21
+    per packet) would run along the face; it is sent inward with normal
+    component 1 and weighted 2 |c_n| / |c| as any other.  Packets with a zero
+    component are found by scanning the direction stream (a C loop over the
+    oracle's sampler)."""
+    import subprocess
+    src = tmp_path / "scan.c"
+    src.write_text(SCAN_C)
+    exe = tmp_path / "scan"
+    lib = O.build()
+    subprocess.check_call(["gcc", "-O2", "-o", str(exe), str(src), lib, f"-Wl,-rpath,{os.path.dirname(lib)}"])
+    seed = 7
+    hits = subprocess.check_output([str(exe), str(seed), str(1 << 24)], text=True).split("\n")
+    hits = [tuple(int(v) for v in h.split()) for h in hits if h.strip()]
+    assert len(hits) >= 5
+    g = O.Grid()
+    g.n[0], g.n[1], g.n[2] = 3, 4, 5
+    g.cell_cm = 1.0
+    g.n_bins = 1
+    ndot, dt, P = 1.0e50, 2.0, 1 << 24
+    checked = 0
+    for b, a in hits:
+        raw, _ = O.direction_ex(seed, 0, b, 0, False, 3)
+        o, c, w = O.background_packet(g, ndot, [1.0], dt, P, seed, 0, 0, b)
+        axis = [k for k in range(3) if o[k] in (0, 2 * g.n[k])]
+        assert len(axis) == 1
+        axis = axis[0]
+        assert all(c[k] == raw[k] for k in range(3) if k != axis)
+        inward = 1 if o[axis] == 0 else -1
+        if raw[axis] == 0:
+            assert c[axis] == inward
+            checked += 1
+        else:
+            assert c[axis] == inward * abs(raw[axis])
+        q = float(c[0]) ** 2 + float(c[1]) ** 2 + float(c[2]) ** 2
+        assert w == pytest.approx(ndot * dt / P * 2.0 * abs(c[axis]) / math.sqrt(q), rel=1e-14, abs=0)
+    assert checked >= 1

@@ -126,21 +126,14 @@ __device__ __forceinline__ float column_depth(float sH, float sHe1, float sHe2, 
 // not populate hold +inf), which ends the packet once it reaches tau_kill
 // (float32 form: see Extinction).
 //
-// Float32 form with several bins: a bin whose optical depth T_j reaches
-// tau_drop after this cell is dropped from the packet (its bit cleared in
-// `active`, its remaining photons added to `dropped` for the truncated
-// ledger).  The caller passes tau_drop = max(tau_kill, kDropDepth): the
-// extinction rule applied bin by bin, at a depth where a bin keeps at most
-// e^-30 (9.4e-14) of its share.  Bins outside `wbins` (wave-uniform; a
-// superset of the bins the wavefront's crossing lanes still carry, e.g. from
-// wave_bins) are skipped: every crossing lane holds exactly 0 photons in them,
-// so skipping changes nothing.
+// Bins outside `wbins` (wave-uniform; a superset of the bins the wavefront's
+// crossing lanes still carry, e.g. from wave_bins) are skipped: every crossing
+// lane holds exactly 0 photons in them, so skipping changes nothing.
 template <typename R, int S, bool TH, int MB, int NA = 0, int NB = 0, typename KV, typename TT>
 __device__ __forceinline__ void cross_cell(R l, const KV &kap, TT tab, R (&F)[MB],
                                            R (&D)[DepthState<R, S, MB>::N], R &absorbed, R &e0, R &e1,
-                                           R &e2, R &heat, R &tmin, uint32_t &active, float tau_drop,
-                                           R &dropped, uint32_t wbins = ~0u) {
-    constexpr bool DROP = !std::is_same<R, double>::value && MB > 1;
+                                           R &e2, R &heat, R &tmin, uint32_t wbins = ~0u) {
+    constexpr bool SKIP = !std::is_same<R, double>::value && MB > 1;
     constexpr bool F64 = std::is_same<R, double>::value;
     R kH, kHe1 = R(0), kHe2 = R(0);
     if constexpr (S == 1) kH = kap;
@@ -156,10 +149,9 @@ __device__ __forceinline__ void cross_cell(R l, const KV &kap, TT tab, R (&F)[MB
     R ab = R(0), g0 = R(0), g1 = R(0), g2 = R(0), h0 = R(0), h1 = R(0), h2 = R(0);
     R dH = R(0), qH = R(0);     // bins absorbed by hydrogen alone (j < NA): photons, heat
     R tm = R(INFINITY);
-    R drop = R(0);
 #pragma unroll
     for (int j = 0; j < MB; ++j) {
-        if constexpr (DROP) {
+        if constexpr (SKIP) {
             if (!((wbins >> j) & 1u)) continue;
         }
         struct { R x, y, z; } sg = {tab[j], tab[MB + j], tab[2 * MB + j]};
@@ -196,19 +188,6 @@ __device__ __forceinline__ void cross_cell(R l, const KV &kap, TT tab, R (&F)[MB
             attenuation(tau, em, tr);
             d = F[j] * em;
             F[j] = F[j] * tr;
-            if constexpr (DROP) {
-                // the same T_j as the extinction test forms (zero helium
-                // cross-sections add exact zeros)
-                float Tj;
-                if constexpr (S == 1) Tj = sg.x * D[0];
-                else if (j < NA) Tj = sg.x * D[0];
-                else if (j < NA + NB) Tj = __builtin_fmaf(sg.y, D[1], sg.x * D[0]);
-                else Tj = column_depth<S>(sg.x, sg.y, sg.z, D);
-                const bool gone = ((active >> j) & 1u) && Tj >= tau_drop;
-                drop += gone ? F[j] : R(0);
-                F[j] = gone ? R(0) : F[j];
-                active = gone ? (active & ~(1u << j)) : active;
-            }
         }
         ab += d;
         if (S == 3 && j < NA) {
@@ -252,7 +231,6 @@ __device__ __forceinline__ void cross_cell(R l, const KV &kap, TT tab, R (&F)[MB
     }
     absorbed = ab;
     tmin = tm;
-    dropped = drop;
     if (S == 1) {
         e0 = ab;
         e1 = e2 = R(0);
@@ -268,6 +246,35 @@ __device__ __forceinline__ void cross_cell(R l, const KV &kap, TT tab, R (&F)[MB
             heat = R(0);
         }
     }
+}
+
+// Float32 form with several bins, when a packet moves from one tile of 8^3
+// cells into the next: a bin whose optical depth T_j has reached tau_drop
+// leaves the packet (its bit cleared in `active`, its remaining photons
+// returned for the truncated ledger).  The caller passes
+// tau_drop = max(tau_kill, kDropDepth): a bin so dropped keeps at most e^-30
+// (9.4e-14) of its share.  Decided from the packet's own history at tile
+// boundaries, so every march organisation drops the same bins at the same
+// cells; T_j is formed as in the extinction test (zero helium cross-sections
+// of the layout's hydrogen-only bins add exact zeros).
+template <int S, int MB, int NA, int NB, typename TT>
+__device__ __forceinline__ float drop_exhausted(TT tab, uint32_t &active, float tau_drop,
+                                                const float (&N)[S == 1 ? 1 : 3], float (&F)[MB]) {
+    float drop = 0.0f;
+#pragma unroll
+    for (int j = 0; j < MB; ++j) {
+        const float sH = tab[j];
+        float Tj;
+        if constexpr (S == 1) Tj = sH * N[0];
+        else if (j < NA) Tj = sH * N[0];
+        else if (j < NA + NB) Tj = __builtin_fmaf(tab[MB + j], N[1], sH * N[0]);
+        else Tj = column_depth<S>(sH, tab[MB + j], tab[2 * MB + j], N);
+        const bool gone = ((active >> j) & 1u) && Tj >= tau_drop;
+        drop += gone ? F[j] : 0.0f;
+        F[j] = gone ? 0.0f : F[j];
+        active = gone ? (active & ~(1u << j)) : active;
+    }
+    return drop;
 }
 
 // Extinction test of the float32 form: a packet ends once every bin the

@@ -239,11 +239,13 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
                 snew = (double)num / (double)den;
                 l = (snew - sprev) * L;
             } else {
-                // exact: num/den - pnum/pden = (num pden - pnum den) / (den pden), both products < 2^32
-                const uint32_t diff = num * pden - pnum * den;
+                // exact: num/den - pnum/pden = (num pden - pnum den) / (den pden),
+                // num < 2^12, pden < 2^21, both products < 2^32
+                const uint32_t diff = __umul24(num, pden) - __umul24(pnum, den);
                 l = Lf * (float)diff * __builtin_amdgcn_rcpf((float)den * (float)pden);
             }
             const int here = k0 + p.geo.n[0] * (k1 + p.geo.n[1] * k2);
+            const int here_k0 = k0, here_k1 = k1, here_k2 = k2;
             if (m0) { k0 += (a0 & kNeg) ? -1 : 1; d0 += 2u; }
             if (m1) { k1 += (a1 & kNeg) ? -1 : 1; d1 += 2u; }
             if (m2) { k2 += (a2 & kNeg) ? -1 : 1; d2 += 2u; }
@@ -257,10 +259,8 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
             const KV knext = kappa[nslot];
 
             // ---- Eq. (1) per bin and the split among absorbers ----
-            R absorbed, e0, e1, e2, hs, tmin, dropped;
-            cross_cell<R, S, TH, MB, NA, NB>(l, kap, tab, F, D, absorbed, e0, e1, e2, hs, tmin, active,
-                                             fmaxf((float)p.tau_kill, kDropDepth), dropped);
-            if constexpr (!F64) dropf += dropped;
+            R absorbed, e0, e1, e2, hs, tmin;
+            cross_cell<R, S, TH, MB, NA, NB>(l, kap, tab, F, D, absorbed, e0, e1, e2, hs, tmin);
 
             // ---- deposit: float64 accumulators, hardware atomics at L2 ----
             double *cell = p.acc + (size_t)slot * ACC;
@@ -292,6 +292,13 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
 
             // ---- termination: extinguished (checked first) or out of the grid ----
             const uint32_t fate = dtest.extinguished(tab, active, p.tau_kill, tmin, D) ? 1u : (out ? 2u : 0u);
+            if constexpr (!F64 && MB > 1) {
+                // float32 form: bins exhausted when the packet moves into the next
+                // tile of 8^3 cells leave it (as in the tiled march)
+                const bool next_tile = ((here_k0 ^ k0) | (here_k1 ^ k1) | (here_k2 ^ k2)) >> 3 != 0;
+                if (fate == 0 && next_tile)
+                    dropf += drop_exhausted<S, MB, NA, NB>(tab, active, fmaxf((float)p.tau_kill, kDropDepth), D, F);
+            }
             if (fate == 0) {
                 slot = nslot;
                 kap = knext;
@@ -544,7 +551,7 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, 1>::value))
                 snew = (double)num / (double)den;
                 l = (snew - sprev) * L;
             } else {
-                const uint32_t diff = num * pden - pnum * den;
+                const uint32_t diff = __umul24(num, pden) - __umul24(pnum, den);
                 l = Lf * (float)diff * __builtin_amdgcn_rcpf((float)den * (float)pden);
             }
             if (m0) { k0 += (a0 & kNeg) ? -1 : 1; d0 += 2u; }
@@ -555,9 +562,8 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, 1>::value))
             const uint32_t nslot = out ? slot : cell_slot(geo, k0, k1, k2);
             const R knext = kappa[nslot];
 
-            R absorbed, e0, e1, e2, hs, tmin, dropped;
-            cross_cell<R, 1, TH, 1>(l, kap, tab, F, D, absorbed, e0, e1, e2, hs, tmin, active, (float)tau_kill,
-                                    dropped);
+            R absorbed, e0, e1, e2, hs, tmin;
+            cross_cell<R, 1, TH, 1>(l, kap, tab, F, D, absorbed, e0, e1, e2, hs, tmin);
 
             double *cell = acc + (size_t)slot * ACC;
             const double v = w * (double)absorbed;

@@ -773,7 +773,9 @@ template <typename R, int MB> struct TOcc { static constexpr int value = 2; };
 template <> struct TOcc<float, 1> { static constexpr int value = 4; };
 template <> struct TOcc<float, 8> { static constexpr int value = 4; };
 
-template <typename R, int S, bool TH, int MB, int NA, int NB, bool PER>
+// TR: packets are traced (their cells and fates recorded); the instance
+// without tracing carries no trace state.
+template <typename R, int S, bool TH, int MB, int NA, int NB, bool PER, bool TR>
 __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const TParams p, int cur) {
     constexpr bool F64 = std::is_same<R, double>::value;
     constexpr uint32_t ACC = (S == 1) ? (TH ? 2u : 1u) : 4u;
@@ -882,8 +884,13 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                 }
                 const bool leave = !out && (dx | dy | dz) != 0;
                 const uint32_t fate = ex ? 1u : (out ? 2u : (leave ? 3u : 0u));
+                if constexpr (!F64 && MB > 1) {
+                    // float32 form: bins exhausted at the tile boundary leave the packet
+                    if (fate == 3u)
+                        dropf += drop_exhausted<S, MB, NA, NB>(tab, active, fmaxf((float)p.tau_kill, kDropDepth), D, F);
+                }
                 if (fate != 0u) {                  // fate 0: a new witness bin, the packet marches on
-                    const bool traced = tix >= 0;
+                    const bool traced = TR && tix >= 0;
                     int32_t *rec = p.trace + (size_t)(traced ? tix : 0) * (RT_TRACE_HDR_DEV + p.trace_len);
                     st_abs = w * absd;
                     st_trunc = w * (double)dropf;
@@ -1003,8 +1010,11 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                                 }
                                 sprev = (ax == 3u) ? 0.0 : (double)pnum / (double)pden;
                                 if constexpr (!F64) dtest.ext.resume(jw < (uint32_t)MB ? jw : 0u, s_sigf);
-                                tix = trace_slot(p, p.g0 + ri);
-                                count = tix >= 0 ? (uint32_t)p.trace[(size_t)tix * (RT_TRACE_HDR_DEV + p.trace_len)] : 0u;
+                                if constexpr (TR) {
+                                    tix = trace_slot(p, p.g0 + ri);
+                                    count = tix >= 0 ? (uint32_t)p.trace[(size_t)tix * (RT_TRACE_HDR_DEV + p.trace_len)]
+                                                     : 0u;
+                                }
                                 absd = 0.0;
                                 dropf = 0.0f;
                                 loc = local_cell(k0, k1, k2);
@@ -1036,11 +1046,12 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                     snew = (double)num / (double)den;
                     l = (snew - sprev) * L;
                 } else {
-                    const uint32_t diff = num * pden - pnum * den;
+                    // exact: num < 2^12, pden < 2^21, both products < 2^32
+                    const uint32_t diff = __umul24(num, pden) - __umul24(pnum, den);
                     l = Lf * (float)diff * __builtin_amdgcn_rcpf((float)den * (float)pden);
                 }
                 int here = 0;                          // natural index, for traces only
-                if (p.trace_n > 0) here = k0 + p.geo.n[0] * (k1 + p.geo.n[1] * k2);
+                if constexpr (TR) here = k0 + p.geo.n[0] * (k1 + p.geo.n[1] * k2);
                 if (m0) { k0 += (a0 & kNeg) ? -1 : 1; d0 += 2u; }
                 if (m1) { k1 += (a1 & kNeg) ? -1 : 1; d1 += 2u; }
                 if (m2) { k2 += (a2 & kNeg) ? -1 : 1; d2 += 2u; }
@@ -1069,29 +1080,31 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                 const uint32_t nloc = local_cell(k0, k1, k2);
                 const KV knext = s_kap[nloc];
 
-                R absorbed, e0, e1, e2, hs, tmin, dropped;
-                cross_cell<R, S, TH, MB, NA, NB>(l, kap, tab, F, D, absorbed, e0, e1, e2, hs, tmin, active,
-                                                 fmaxf((float)p.tau_kill, kDropDepth), dropped, wbins);
-                if constexpr (!F64) dropf += dropped;
+                R absorbed, e0, e1, e2, hs, tmin;
+                cross_cell<R, S, TH, MB, NA, NB>(l, kap, tab, F, D, absorbed, e0, e1, e2, hs, tmin, wbins);
 
                 // ---- deposit into the tile's float64 accumulators in LDS ----
-                // (zero deposits are added too: an LDS add is cheaper than the branch)
-                double *cell = s_acc + loc * ACC;
+                // (zero deposits are added too: an LDS add is cheaper than the
+                // branch; one plane per accumulated value, so the adds of a
+                // wavefront spread over the banks)
+                double *cell = s_acc + loc;
                 if (S == 1) {
                     atomicAdd(cell, w * (double)absorbed);
-                    if (TH) atomicAdd(cell + 1, w * ((double)hs * kEvErg));
+                    if (TH) atomicAdd(cell + kTileCells, w * ((double)hs * kEvErg));
                 } else {
                     atomicAdd(cell, w * (double)e0);
-                    atomicAdd(cell + 1, w * (double)e1);
-                    atomicAdd(cell + 2, w * (double)e2);
-                    if (TH) atomicAdd(cell + 3, w * ((double)hs * kEvErg));
+                    atomicAdd(cell + kTileCells, w * (double)e1);
+                    atomicAdd(cell + 2 * kTileCells, w * (double)e2);
+                    if (TH) atomicAdd(cell + 3 * kTileCells, w * ((double)hs * kEvErg));
                 }
                 absd += (double)absorbed;
                 it_cross = 1;
-                const bool traced = tix >= 0;
-                int32_t *rec = p.trace + (size_t)(traced ? tix : 0) * (RT_TRACE_HDR_DEV + p.trace_len);
-                if (traced && count < (uint32_t)p.trace_len) rec[RT_TRACE_HDR_DEV + count] = here;
-                ++count;
+                if constexpr (TR) {
+                    const bool traced = tix >= 0;
+                    int32_t *rec = p.trace + (size_t)(traced ? tix : 0) * (RT_TRACE_HDR_DEV + p.trace_len);
+                    if (traced && count < (uint32_t)p.trace_len) rec[RT_TRACE_HDR_DEV + count] = here;
+                    ++count;
+                }
 
                 // the state moves on to the next cell; a packet that left the tile,
                 // the grid, or whose witness depth reached the cut is settled later
@@ -1099,7 +1112,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                 kap = knext;
                 lax = (uint32_t)ax;
                 if (F64) sprev = snew; else { pnum = num; pden = den; }
-                if (p.trace_n > 0) hlast = here;
+                if constexpr (TR) hlast = here;
                 if constexpr (F64) kill = tmin >= p.tau_kill;
                 else kill = Extinction<S, MB>::depth(dtest.ext.wH, dtest.ext.wHe1, dtest.ext.wHe2, D)
                             >= (float)p.tau_kill;
@@ -1122,7 +1135,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                         const uint32_t stay = 13u;                 // code of the tile itself
                         const uint32_t rank = atomicAdd(&s_cnt[stay], 1u);
                         p.side[pos] = stay | (rank << 5);
-                        if (tix >= 0) p.trace[(size_t)tix * (RT_TRACE_HDR_DEV + p.trace_len)] = (int32_t)count;
+                        if (TR && tix >= 0) p.trace[(size_t)tix * (RT_TRACE_HDR_DEV + p.trace_len)] = (int32_t)count;
                         pk_abs = w * absd;
                         pk_drop = w * (double)dropf;
                         alive = false;
@@ -1137,7 +1150,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
         // ---- the tile's deposits into the grid's accumulators ----
         double *ga = p.acc + ((size_t)tile << (3 * kTileLog2)) * ACC;
         for (int i = threadIdx.x; i < kTileCells * (int)ACC; i += kTBlock) {
-            const double v = s_acc[i];
+            const double v = s_acc[((uint32_t)i % ACC) * kTileCells + (uint32_t)i / ACC];
             if (v != 0.0) {
                 double *g = ga + local_to_morton((uint32_t)i / ACC) * ACC + (uint32_t)i % ACC;
                 if (ch.shared) unsafeAtomicAdd(g, v);
@@ -1299,10 +1312,14 @@ void run_passes(const TParams &p, const TiledLaunch &t) {
         pp.park = pass < t.park_passes ? t.park_lanes : 0u;
         const bool timed = t.ev && *t.ev_used < t.ev_cap;
         if (timed) (void)hipEventRecord(t.ev[2 * *t.ev_used], st);
-        if (p.periodic)
-            hipLaunchKernelGGL((k_tmarch<R, S, TH, MB, NA, NB, true>), grid, blk, 0, st, pp, cur);
-        else
-            hipLaunchKernelGGL((k_tmarch<R, S, TH, MB, NA, NB, false>), grid, blk, 0, st, pp, cur);
+        const bool tr = p.trace_n > 0;
+        if (p.periodic) {
+            if (tr) hipLaunchKernelGGL((k_tmarch<R, S, TH, MB, NA, NB, true, true>), grid, blk, 0, st, pp, cur);
+            else hipLaunchKernelGGL((k_tmarch<R, S, TH, MB, NA, NB, true, false>), grid, blk, 0, st, pp, cur);
+        } else {
+            if (tr) hipLaunchKernelGGL((k_tmarch<R, S, TH, MB, NA, NB, false, true>), grid, blk, 0, st, pp, cur);
+            else hipLaunchKernelGGL((k_tmarch<R, S, TH, MB, NA, NB, false, false>), grid, blk, 0, st, pp, cur);
+        }
         if (timed) {
             (void)hipEventRecord(t.ev[2 * *t.ev_used + 1], st);
             ++*t.ev_used;
@@ -1325,7 +1342,7 @@ template <> struct Layout<3, 8> { static constexpr int NA = 3, NB = 2; };
 template <typename R, int S, bool TH, int MB>
 hipError_t occ(int *n) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        n, reinterpret_cast<const void *>(&k_tmarch<R, S, TH, MB, Layout<S, MB>::NA, Layout<S, MB>::NB, false>),
+        n, reinterpret_cast<const void *>(&k_tmarch<R, S, TH, MB, Layout<S, MB>::NA, Layout<S, MB>::NB, false, false>),
         kTBlock, 0);
 }
 

@@ -47,6 +47,11 @@ extern "C" {
 #define RT_EOVERFLOW (-5)   /* a size exceeds what the library supports */
 #define RT_EINTERNAL (-6)   /* an internal consistency check of the march failed;
                                the handle only accepts rt_release */
+#define RT_ESCRATCH (-7)    /* rt_init_grid_static: the solve needs more than
+                               RT_STATIC_WORKSPACE_BYTES; nothing changed */
+
+/* Size of the library's static per-device workspace (rt_init_grid_static). */
+#define RT_STATIC_WORKSPACE_BYTES (64u << 20)
 
 /* rt_grid_desc.flags */
 #define RT_ISOTHERMAL 0x1u  /* temperature held fixed */
@@ -216,6 +221,23 @@ int32_t rt_workspace_bytes(const rt_grid_desc *d, int64_t max_sources, size_t *b
 int32_t rt_init_grid(const rt_grid_desc *d, void *d_ws, size_t ws_bytes, int64_t max_sources,
                      const void *d_nh, const void *d_x, const void *d_temp, int32_t fields_fp64,
                      void *hip_stream, rt_solve_t *out);
+
+/* rt_init_grid for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid allocation): the
+ * same solve, with its workspace in a static array of the library
+ * (RT_STATIC_WORKSPACE_BYTES on each device it runs on, held until the
+ * process ends) instead of a caller's buffer.  Arguments as rt_init_grid
+ * without d_ws / ws_bytes; the description may not ask for RT_TIME_MARCH.
+ * Allocates nothing: no hipMalloc, no host heap.
+ *   RT_ESCRATCH  the solve's workspace (rt_workspace_bytes) exceeds
+ *                RT_STATIC_WORKSPACE_BYTES; nothing changed
+ *   RT_ESTATE    a static solve on the current device has not been released
+ * One static solve per device at a time: it shares the device's array with
+ * every other call (the array keeps the last solve's contents; the call
+ * re-initialises all of it that a solve reads).  Calls that overlap on one
+ * device race.  rt_release frees the slot for the next static solve. */
+int32_t rt_init_grid_static(const rt_grid_desc *d, int64_t max_sources, const void *d_nh, const void *d_x,
+                            const void *d_temp, int32_t fields_fp64, void *hip_stream, rt_solve_t *out);
 
 /* Append n point sources (Sec. 2: position, luminosity L_s in photons/s, SED
  * over the bins by photon number).  Host arrays:

@@ -7,6 +7,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -203,13 +204,15 @@ int32_t make_plan(const rt_grid_desc *d, int64_t max_sources, Plan *p) {
     return RT_OK;
 }
 
-// Per-bin march table, [7][mb] in the march precision.  Rows 0-2: the
+// Per-bin march table, [7][mb] in the march precision, into t (returns the
+// number of values).  Rows 0-2: the
 // cross-sections of HI, HeI, HeII (float32 form: in units of 1e-18 cm^2,
 // lengths then in 1e18 cm, so optical depths stay far from the float32 range
 // limits).  Rows 3-5: heat factors in eV: pure hydrogen E_j - E_th,HI; H+He
 // sigma_s,j (E_j - E_th,s).  Row 6: E_j - E_th,HI.
-std::vector<double> march_table(const rt_grid_desc *d, const Plan &p) {
-    std::vector<double> t(7 * (size_t)p.mb, 0.0);
+int march_table(const rt_grid_desc *d, const Plan &p, double *t) {
+    const int n = 7 * p.mb;
+    for (int i = 0; i < n; ++i) t[i] = 0.0;
     const double scale = p.fp64 ? 1.0 : 1.0e18;
     for (int s = 0; s < 3; ++s)
         for (int j = 0; j < d->n_bins; ++j) {
@@ -219,7 +222,7 @@ std::vector<double> march_table(const rt_grid_desc *d, const Plan &p) {
             t[(size_t)(3 + s) * p.mb + j] = p.species == 1 ? de : sig * scale * de;
             if (s == 0) t[(size_t)6 * p.mb + j] = de;
         }
-    return t;
+    return n;
 }
 
 // 1 when the 8-bin H+He table has the threshold-aligned layout the tiled
@@ -238,6 +241,7 @@ int32_t bin_layout(const rt_grid_desc *d, const Plan &p) {
 
 struct rt_solve {
     uint64_t magic;
+    bool is_static;         // lives in the library's per-device static storage
     rt_grid_desc d;
     Plan plan;
     hipStream_t stream;
@@ -266,7 +270,18 @@ struct rt_solve {
 namespace {
 constexpr int kMaxTimedSubsteps = 1024;
 constexpr int kMaxTimedKernels = 16384;
-}
+
+// Workspace of rt_init_grid_static: a file-scope device array, one copy per
+// device the library runs on, held until the process ends.  Host code uses
+// the per-device address hipGetSymbolAddress returns, never the name.
+constexpr size_t kStaticBytes = (size_t)RT_STATIC_WORKSPACE_BYTES;
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxDevices];
+rt_solve g_static_solve[kMaxDevices];
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
 
 namespace {
 
@@ -355,6 +370,85 @@ rtk::RecombParams recomb_params(rt_solve_t h) {
     return r;
 }
 
+// Fill the handle h and load the initial state into the workspace ws (a plan
+// already validated and the arguments checked).  No device memory is
+// allocated; events are created only for RT_TIME_MARCH.
+int32_t init_solve(rt_solve *h, const rt_grid_desc *d, const Plan &p, char *ws, int64_t max_sources,
+                   const void *d_nh, const void *d_x, const void *d_temp, int32_t fields_fp64, void *hip_stream) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return RT_EDEVICE;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return RT_EDEVICE;
+    int bpcu = d->blocks_per_cu;
+    if (bpcu == 0) {
+        const hipError_t e = p.tiled ? rtk::tiled_occupancy(p.species, p.thermal, p.fp64, p.mb, &bpcu)
+                                     : rtk::march_occupancy(p.species, p.thermal, p.fp64, p.mb, &bpcu);
+        if (e != hipSuccess) return RT_EDEVICE;
+        if (bpcu < 1) bpcu = 1;
+    }
+    int blocks = cus * bpcu;
+    if (blocks > kMaxMarchBlocks) blocks = kMaxMarchBlocks;
+
+    h->magic = kMagic;
+    h->d = *d;
+    h->plan = p;
+    h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    h->device = dev;
+    h->ws = ws;
+    h->max_src = max_sources;
+    h->n_src = 0;
+    h->step_index = d->step_index0;
+    h->blocks = blocks;
+    h->chunk = d->wave_chunk > 0 ? d->wave_chunk : 256;
+    h->refill_min = d->refill_min > 0 ? d->refill_min : (p.tiled ? 16 : 8);
+    h->dead = false;
+    h->timed = 0;
+    h->ktimed = 0;
+    h->recomb_set = false;
+    h->f_rec = h->log10_t0 = h->dlog10_t = 0.0;
+    h->n_t = 0;
+    h->bg_ndot = h->bg_carried = 0.0;
+    h->bg_packets = 0;
+    h->bg_active = 0u;
+    h->ev.clear();
+    h->kev.clear();
+    auto destroy_events = [h] {
+        for (hipEvent_t e : h->ev) if (e) (void)hipEventDestroy(e);
+        for (hipEvent_t e : h->kev) if (e) (void)hipEventDestroy(e);
+        h->ev.clear();
+        h->kev.clear();
+    };
+    if (d->flags & RT_TIME_MARCH) {
+        h->ev.assign(2 * kMaxTimedSubsteps, nullptr);
+        h->kev.assign(p.tiled ? 2 * kMaxTimedKernels : 0, nullptr);
+        bool ok = true;
+        for (size_t i = 0; i < h->ev.size() && ok; ++i) ok = hipEventCreate(&h->ev[i]) == hipSuccess;
+        for (size_t i = 0; i < h->kev.size() && ok; ++i) ok = hipEventCreate(&h->kev[i]) == hipSuccess;
+        if (!ok) {
+            destroy_events();
+            return RT_EDEVICE;
+        }
+    }
+
+    rtk::CellLaunch c = cell_launch(h, 0.0);
+    // the per-bin march table in the march precision (at most 7 x 8 values)
+    double tab[7 * kMaxSupportedBins];
+    float tab_f[7 * kMaxSupportedBins];
+    const int ntab = march_table(d, p, tab);
+    for (int i = 0; i < ntab; ++i) tab_f[i] = (float)tab[i];
+    const void *tab_src = p.fp64 ? (const void *)tab : (const void *)tab_f;
+    if (hipMemcpyAsync(ws + p.off_tab, tab_src, (size_t)ntab * p.real, hipMemcpyHostToDevice, h->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess ||
+        rtk::launch_import(c, d_nh, d_x, d_temp, fields_fp64, p.ncell) != hipSuccess ||
+        rtk::launch_ledger_zero(c.ledger, h->stream) != hipSuccess ||
+        (p.recomb && rtk::launch_import_counters(c, nullptr, 1, p.ncell) != hipSuccess) ||
+        (p.tiled && rtk::launch_tiled_reset(tiled_launch(h, tiled_base(h))) != hipSuccess)) {
+        destroy_events();
+        return RT_EDEVICE;
+    }
+    return RT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -394,72 +488,48 @@ int32_t rt_init_grid(const rt_grid_desc *d, void *d_ws, size_t ws_bytes, int64_t
     if (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0) return RT_EINVAL;
     if (!d_nh || !d_x || !d_temp || (fields_fp64 != 0 && fields_fp64 != 1)) return RT_EINVAL;
     if (ws_bytes < p.total) return RT_ENOMEM;
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return RT_EDEVICE;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return RT_EDEVICE;
-    int bpcu = d->blocks_per_cu;
-    if (bpcu == 0) {
-        const hipError_t e = p.tiled ? rtk::tiled_occupancy(p.species, p.thermal, p.fp64, p.mb, &bpcu)
-                                     : rtk::march_occupancy(p.species, p.thermal, p.fp64, p.mb, &bpcu);
-        if (e != hipSuccess) return RT_EDEVICE;
-        if (bpcu < 1) bpcu = 1;
-    }
-    int blocks = cus * bpcu;
-    if (blocks > kMaxMarchBlocks) blocks = kMaxMarchBlocks;
-
     rt_solve *h = new (std::nothrow) rt_solve;
     if (!h) return RT_ENOMEM;
-    h->magic = kMagic;
-    h->d = *d;
-    h->plan = p;
-    h->stream = reinterpret_cast<hipStream_t>(hip_stream);
-    h->device = dev;
-    h->ws = reinterpret_cast<char *>(d_ws);
-    h->max_src = max_sources;
-    h->n_src = 0;
-    h->step_index = d->step_index0;
-    h->blocks = blocks;
-    h->chunk = d->wave_chunk > 0 ? d->wave_chunk : 256;
-    h->refill_min = d->refill_min > 0 ? d->refill_min : (p.tiled ? 16 : 8);
-    h->dead = false;
-    h->timed = 0;
-    h->ktimed = 0;
-    h->recomb_set = false;
-    h->f_rec = h->log10_t0 = h->dlog10_t = 0.0;
-    h->n_t = 0;
-    h->bg_ndot = h->bg_carried = 0.0;
-    h->bg_packets = 0;
-    h->bg_active = 0u;
-    if (d->flags & RT_TIME_MARCH) {
-        h->ev.resize(2 * kMaxTimedSubsteps);
-        h->kev.resize(p.tiled ? 2 * kMaxTimedKernels : 0);
-        bool ok = true;
-        for (size_t i = 0; i < h->ev.size() && ok; ++i) ok = hipEventCreate(&h->ev[i]) == hipSuccess;
-        for (size_t i = 0; i < h->kev.size() && ok; ++i) ok = hipEventCreate(&h->kev[i]) == hipSuccess;
-        if (!ok) {
-            // events are created in order; destroy the ones that exist
-            for (hipEvent_t e : h->ev) if (e) (void)hipEventDestroy(e);
-            for (hipEvent_t e : h->kev) if (e) (void)hipEventDestroy(e);
-            delete h;
-            return RT_EDEVICE;
-        }
-    }
-
-    rtk::CellLaunch c = cell_launch(h, 0.0);
-    const std::vector<double> tab = march_table(d, p);
-    std::vector<float> tab_f(tab.begin(), tab.end());
-    const void *tab_src = p.fp64 ? (const void *)tab.data() : (const void *)tab_f.data();
-    if (hipMemcpyAsync(h->ws + p.off_tab, tab_src, tab.size() * p.real, hipMemcpyHostToDevice, h->stream) !=
-            hipSuccess ||
-        hipStreamSynchronize(h->stream) != hipSuccess ||
-        rtk::launch_import(c, d_nh, d_x, d_temp, fields_fp64, p.ncell) != hipSuccess ||
-        rtk::launch_ledger_zero(c.ledger, h->stream) != hipSuccess ||
-        (p.recomb && rtk::launch_import_counters(c, nullptr, 1, p.ncell) != hipSuccess) ||
-        (p.tiled && rtk::launch_tiled_reset(tiled_launch(h, tiled_base(h))) != hipSuccess)) {
-        for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
-        for (hipEvent_t e : h->kev) (void)hipEventDestroy(e);
+    h->is_static = false;
+    const int32_t st = init_solve(h, d, p, reinterpret_cast<char *>(d_ws), max_sources, d_nh, d_x, d_temp,
+                                  fields_fp64, hip_stream);
+    if (st != RT_OK) {
         delete h;
-        return RT_EDEVICE;
+        return st;
+    }
+    *out = h;
+    return RT_OK;
+}
+
+int32_t rt_init_grid_static(const rt_grid_desc *d, int64_t max_sources, const void *d_nh, const void *d_x,
+                            const void *d_temp, int32_t fields_fp64, void *hip_stream, rt_solve_t *out) {
+    if (!out) return RT_EINVAL;
+    *out = nullptr;
+    Plan p{};
+    const int32_t r = make_plan(d, max_sources, &p);
+    if (r != RT_OK) return r;
+    if (!d_nh || !d_x || !d_temp || (fields_fp64 != 0 && fields_fp64 != 1)) return RT_EINVAL;
+    if (d->flags & RT_TIME_MARCH) return RT_EINVAL;         // its events would be allocated
+    if (p.total > kStaticBytes) return RT_ESCRATCH;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return RT_EDEVICE;
+    if (dev < 0 || dev >= kMaxDevices) return RT_EINVAL;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        // the array's device address on this device (the name itself is a
+        // host-side stand-in): once per device, with that device current
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return RT_EDEVICE;
+        g_static_ptr[dev] = ptr;
+    }
+    rt_solve *h = &g_static_solve[dev];
+    if (h->magic == kMagic) return RT_ESTATE;                // the last static solve was not released
+    h->is_static = true;
+    const int32_t st = init_solve(h, d, p, reinterpret_cast<char *>(g_static_ptr[dev]), max_sources, d_nh, d_x,
+                                  d_temp, fields_fp64, hip_stream);
+    if (st != RT_OK) {
+        h->magic = 0;
+        return st;
     }
     *out = h;
     return RT_OK;
@@ -810,8 +880,15 @@ int32_t rt_release(rt_solve_t h) {
     const bool ok = h->dead || hipStreamSynchronize(h->stream) == hipSuccess;
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : h->kev) (void)hipEventDestroy(e);
-    h->magic = 0;
-    delete h;
+    h->ev.clear();
+    h->kev.clear();
+    if (h->is_static) {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        h->magic = 0;                     // the device's static storage is free again
+    } else {
+        h->magic = 0;
+        delete h;
+    }
     return ok ? RT_OK : RT_EDEVICE;
 }
 
@@ -1109,6 +1186,7 @@ const char *rt_strerror(int32_t status) {
     case RT_ESTATE: return "call not valid in the handle's state";
     case RT_EOVERFLOW: return "size beyond what the library supports";
     case RT_EINTERNAL: return "internal consistency check of the march failed; the handle is unusable";
+    case RT_ESCRATCH: return "the solve needs more than the static workspace (RT_STATIC_WORKSPACE_BYTES)";
     default: return "unknown status";
     }
 }

@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(PKG, "librt_mcrt.so")
 
 RT_MAX_BINS = 16
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_ESTATE, RT_EOVERFLOW, RT_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+RT_ESCRATCH = -7
+RT_STATIC_WORKSPACE_BYTES = 64 << 20
 RT_ISOTHERMAL, RT_FP64, RT_TIME_MARCH, RT_DIRECT_MARCH, RT_RECOMB, RT_PERIODIC = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
 RT_MAX_PATH_CELLS = 2046
 RT_SRC_CORNER_OCTANT = 0x1
@@ -69,6 +71,7 @@ SIGNATURES = {
     "rt_workspace_bytes": (_I32, [C.POINTER(GridDesc), _I64, C.POINTER(C.c_size_t)]),
     "rt_init_grid": (_I32, [C.POINTER(GridDesc), _VP, C.c_size_t, _I64, _VP, _VP, _VP, _I32, _VP,
                             C.POINTER(_VP)]),
+    "rt_init_grid_static": (_I32, [C.POINTER(GridDesc), _I64, _VP, _VP, _VP, _I32, _VP, C.POINTER(_VP)]),
     "rt_add_sources": (_I32, [_VP, _I32, _VP, _VP, _VP, _U32]),
     "rt_step": (_I32, [_VP, _D, _I64, _U64, C.POINTER(StepStats)]),
     "rt_read_stats": (_I32, [_VP, C.POINTER(StepStats)]),
@@ -155,6 +158,21 @@ def rt_init_grid(desc: GridDesc, workspace, max_sources: int, nh, x, temp, strea
                             int(max_sources), _ptr(nh), _ptr(x), _ptr(temp), int(f64),
                             _stream_ptr(stream), C.byref(h))
     _check("rt_init_grid", st)
+    return h
+
+
+def rt_init_grid_static(desc: GridDesc, max_sources: int, nh, x, temp, stream=None):
+    """rt_init_grid with the library's static per-device workspace (allocates
+    nothing); the same field tensors as rt_init_grid."""
+    import torch
+    f64 = nh.dtype == torch.float64
+    for t in (nh, x, temp):
+        if not (t.is_cuda and t.is_contiguous() and t.dtype == nh.dtype):
+            raise ValueError("fields must be contiguous device tensors of one dtype")
+    h = C.c_void_p()
+    st = lib().rt_init_grid_static(C.byref(desc), int(max_sources), _ptr(nh), _ptr(x), _ptr(temp), int(f64),
+                                   _stream_ptr(stream), C.byref(h))
+    _check("rt_init_grid_static", st)
     return h
 
 

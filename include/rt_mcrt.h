@@ -110,6 +110,7 @@ extern "C" {
 
 #define RT_MAX_MILNE_T 512  /* temperature nodes of a recombination spectrum table */
 #define RT_MAX_PATH_CELLS 2046 /* largest rt_grid_desc.path_cells */
+#define RT_MAX_FINISH_PASS 65535 /* largest rt_grid_desc.finish_pass */
 
 /* trace record: RT_TRACE_HDR int32 words then trace_len cell indices */
 #define RT_TRACE_HDR 8
@@ -159,7 +160,7 @@ typedef struct {
     int32_t trace_stride;         /* spacing of traced packet ids; 0 = 1 */
     int32_t run_len;              /* tiled march: packets of one tile one block
                                      marches before it writes the tile's deposits
-                                     out; 0 = default (2048), else 64..2048 */
+                                     out; 0 = default (2048), else 64..65536 */
     int32_t park_lanes;           /* tiled march: once a run of a tile is used up,
                                      a wavefront with at most this many packets
                                      still marching writes them back; they resume
@@ -173,6 +174,14 @@ typedef struct {
     int32_t path_cells;           /* RT_PERIODIC: cell faces a packet may cross along
                                      one axis, 1..RT_MAX_PATH_CELLS; 0 = the longest
                                      side of the grid */
+    int32_t finish_pass;          /* tiled march: tile passes after which one
+                                     finishing pass marches every packet still in
+                                     flight to its end, reading the grid's
+                                     absorbers and adding to its accumulators
+                                     directly (float64 atomics); the histories do
+                                     not change.  0 = default (never), -1 = never,
+                                     else 1..RT_MAX_FINISH_PASS; not used while
+                                     tracing */
 } rt_grid_desc;
 
 /* Photon ledger and counters of the most recent rt_step (all its sub-steps). */
@@ -331,42 +340,53 @@ int32_t rt_release(rt_solve_t h);
  * per solve as rt_step (Sec. 2 march and cell update; Sec. 3.2 packet shares)
  * and the same packet ids, Philox counters and crossing arithmetic, so every
  * solve's result is the one rt_step gives alone, up to the order in which
- * float64 deposits are added.  Per sub-step the solves share three kernel
- * launches (absorbers, march, cell update; one packet id space over all
- * solves) plus a ledger reduction, instead of four per solve; with
- * RT_BATCH_GRAPH the whole call is captured once as a hipGraph and replayed
- * (the launches read the solves from a device table, so the graph does not
- * depend on which solves are in the batch).
+ * float64 deposits are added.  Per sub-step the solves share one tiled march
+ * over the concatenation of their tiles (each pass carries every live packet
+ * of every solve through one tile, a tile's deposits gathered on chip; the
+ * paper's subdomains, Sec. 3.2, here the 8^3 tiles of many grids), plus one
+ * launch each for the absorbers, the ledgers and the cell update; with
+ * RT_BATCH_GRAPH the whole call is captured once per (sub-step count, march
+ * passes) as a hipGraph and replayed (the launches read the solves from a
+ * device table, so the graph does not depend on which solves are in it).
  *
- * Solves of one call: pure hydrogen (y_he = 0), one bin, all float32 or all
- * float64, all thermal or all isothermal, no tracing, no periodic boundaries,
- * no recombination re-emission or background field, on the batch's device,
- * each at most once.  They may use any march flags (the fused march is the
- * per-packet one); their own streams are ordered around the call with events,
- * so rt_fetch_fields and rt_read_stats on a solve see its result. */
+ * A batch is created for one march instance, given by a shape description
+ * (rt_grid_desc: RT_FP64, RT_ISOTHERMAL, y_he > 0, n_bins; run_len,
+ * refill_min and blocks_per_cu tune its march).  Solves of a call must match
+ * it (precision, species, bins, thermal), keep their fields in bricks of 8^3
+ * (the tiled march, or the per-packet march with brick_log2 = 3), and have no
+ * tracing, periodic boundaries, recombination re-emission or background
+ * field; they sit on the batch's device, each at most once.  Their own streams
+ * are ordered around the call with events, so rt_fetch_fields and rt_read_stats
+ * on a solve see its result. */
 typedef struct rt_batch *rt_batch_t;
 
-#define RT_MAX_BATCH 64      /* solves per rt_step_many */
-#define RT_BATCH_GRAPH 0x1u  /* capture each call shape (sub-step count, precision,
-                                thermal) once as a hipGraph and replay it */
+#define RT_MAX_BATCH 256     /* solves per rt_step_many */
+#define RT_BATCH_GRAPH 0x1u  /* capture each call shape (sub-step count, march
+                                passes) once as a hipGraph and replay it */
 
 /* Device workspace bytes of a batch of at most max_solves (1..RT_MAX_BATCH)
- * solves: the solve table, per-(solve, block) ledger slots, a counter. */
-int32_t rt_batch_workspace_bytes(int32_t max_solves, size_t *bytes_out);
+ * solves of the given shape: the solve table, per-(solve, block) ledger
+ * slots, and the tiled march's records and lists for max_round_packets
+ * packets of one sub-step of all solves together and max_tiles tiles of 8^3
+ * cells of all solves together.  RT_EINVAL for an invalid shape or size. */
+int32_t rt_batch_workspace_bytes(int32_t max_solves, const rt_grid_desc *shape, int64_t max_round_packets,
+                                 int64_t max_tiles, size_t *bytes_out);
 
 /* Create a batch in the caller's device workspace (256-byte aligned, at least
- * rt_batch_workspace_bytes).  hip_stream: the stream the fused launches go to;
- * it must not be NULL with RT_BATCH_GRAPH (the legacy stream cannot be
- * captured).  Allocates pinned host memory for the table it stages. */
-int32_t rt_batch_init(int32_t max_solves, void *d_ws, size_t ws_bytes, void *hip_stream, uint32_t flags,
-                      rt_batch_t *out);
+ * rt_batch_workspace_bytes for the same arguments).  hip_stream: the stream
+ * the fused launches go to; it must not be NULL with RT_BATCH_GRAPH (the
+ * legacy stream cannot be captured).  Allocates pinned host memory for the
+ * table it stages. */
+int32_t rt_batch_init(int32_t max_solves, const rt_grid_desc *shape, int64_t max_round_packets, int64_t max_tiles,
+                      void *d_ws, size_t ws_bytes, void *hip_stream, uint32_t flags, rt_batch_t *out);
 
 /* Advance solves[0..n) by one step each: solve i by dt_s[i] with n_packets[i]
  * packets and Philox seed seeds[i], exactly as rt_step(solves[i], ...) would
  * (its n_sub sub-steps; the call runs max n_sub fused rounds).  Returns
  * RT_EINVAL (nothing enqueued) if a solve breaks the rules above or a step
- * argument would be rejected by rt_step.  Stream-ordered; if stats is not
- * NULL (n entries) the call synchronises and fills each solve's ledger. */
+ * argument would be rejected by rt_step, RT_ENOMEM if the solves' tiles or one
+ * round's packets exceed the batch's.  Stream-ordered; if stats is not NULL
+ * (n entries) the call synchronises and fills each solve's ledger. */
 int32_t rt_step_many(rt_batch_t b, const rt_solve_t *solves, int32_t n, const double *dt_s,
                      const int64_t *n_packets, const uint64_t *seeds, rt_step_stats *stats);
 

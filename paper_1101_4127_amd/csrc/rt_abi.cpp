@@ -29,6 +29,7 @@ int bin_capacity(int n_bins) { return n_bins <= 1 ? 1 : 8; }
 
 constexpr int64_t kDefaultInflight = (int64_t)1 << 24;   // packets in flight in the tiled march
 constexpr int kDefaultRun = 2048;                         // packets per tile run
+constexpr int kMaxRunLen = 1 << 16;                       // longest run a description may ask for
 
 struct Plan {
     int species, thermal, fp64, mb, acc_stride, bl;
@@ -43,6 +44,7 @@ struct Plan {
     size_t off_bg;          // background spectrum row
     // tiled march
     uint32_t capacity, cmax, max_chunks, n_tiles, scan_blocks, passes, park_passes, park_lanes;
+    uint32_t finish;        // tile passes before the finishing pass (0: none)
     uint32_t periodic, dmax;
     size_t rec_bytes;
     size_t off_rec, off_idx0, off_idx1, off_side, off_cnt, off_off, off_cbase, off_bsum, off_ch0, off_ch1,
@@ -75,12 +77,13 @@ int32_t validate_desc(const rt_grid_desc *d) {
     // periodic boundaries are marched by the tiled march only
     if ((d->flags & RT_PERIODIC) && (d->flags & RT_DIRECT_MARCH)) return RT_EINVAL;
     if (d->path_cells < 0 || d->path_cells > RT_MAX_PATH_CELLS) return RT_EINVAL;
+    if (d->finish_pass < -1 || d->finish_pass > RT_MAX_FINISH_PASS) return RT_EINVAL;
     // recombination packets are marched by the tiled march only
     if ((d->flags & RT_RECOMB) && (d->flags & RT_DIRECT_MARCH)) return RT_EINVAL;
     if (d->brick_log2 < -1 || d->brick_log2 > 3) return RT_EINVAL;
     // the tiled march's tiles are the bricks of side 8
     if (!(d->flags & RT_DIRECT_MARCH) && d->brick_log2 != -1 && d->brick_log2 != 3) return RT_EINVAL;
-    if (d->run_len < 0 || d->run_len > 2048 || (d->run_len > 0 && d->run_len < 64)) return RT_EINVAL;
+    if (d->run_len < 0 || d->run_len > kMaxRunLen || (d->run_len > 0 && d->run_len < 64)) return RT_EINVAL;
     if (d->inflight < 0 || d->inflight > ((int64_t)1 << 31) - 1) return RT_EINVAL;
     if (d->park_lanes < 0 || d->park_lanes > 64) return RT_EINVAL;
     if (d->wave_chunk < 0 || d->wave_chunk % 64 != 0 || d->wave_chunk > (1 << 20)) return RT_EINVAL;
@@ -150,6 +153,7 @@ int32_t make_plan(const rt_grid_desc *d, int64_t max_sources, Plan *p) {
     }
     p->capacity = p->cmax = p->max_chunks = p->n_tiles = p->scan_blocks = p->passes = 0;
     p->park_passes = p->park_lanes = 0;
+    p->finish = 0;
     p->periodic = p->dmax = 0;
     p->rec_bytes = 0;
     p->off_rec = p->off_idx0 = p->off_idx1 = p->off_side = p->off_cnt = p->off_off = p->off_cbase = p->off_bsum =
@@ -187,6 +191,7 @@ int32_t make_plan(const rt_grid_desc *d, int64_t max_sources, Plan *p) {
         p->park_lanes = (uint32_t)d->park_lanes;
         p->park_passes = p->park_lanes ? visits : 0u;
         p->passes = visits + p->park_passes;
+        p->finish = d->finish_pass > 0 ? (uint32_t)d->finish_pass : 0u;
         p->rec_bytes = rtk::tiled_record_bytes(p->fp64, p->species, p->mb);
         p->off_rec = o; o = align_up(o + cap * p->rec_bytes);
         p->off_idx0 = o; o = align_up(o + cap * sizeof(uint32_t));
@@ -313,6 +318,7 @@ rtk::TiledLaunch tiled_launch(rt_solve_t h, const rtk::MarchLaunch &m) {
     t.passes = p.passes;
     t.park_passes = p.park_passes;
     t.park_lanes = p.park_lanes;
+    t.finish = p.finish;
     t.periodic = p.periodic;
     t.dmax = p.dmax;
     t.rec = h->ws + p.off_rec;
@@ -902,25 +908,73 @@ namespace {
 constexpr uint64_t kBatchMagic = 0x52544d4342415443ull;
 constexpr int kMaxBatchBlocks = 2048;     // march blocks the ledger slots are sized for
 
-struct BatchLayout {
-    size_t off_head, off_table, off_slots, off_queue, total;
+// The march instance the solves of a batch share, from its shape description.
+struct BatchShape {
+    int fp64, species, mb, thermal, refill_min, cmax, bpcu;
+    uint32_t finish;
+    size_t rec_bytes;
 };
 
-BatchLayout batch_layout(int32_t max_solves) {
-    BatchLayout l;
+int32_t batch_shape(const rt_grid_desc *d, BatchShape *s) {
+    Plan p{};
+    const int32_t r = make_plan(d, 1, &p);
+    if (r != RT_OK) return r;
+    s->fp64 = p.fp64;
+    s->species = p.species;
+    s->mb = p.mb;
+    s->thermal = p.thermal;
+    s->refill_min = d->refill_min > 0 ? d->refill_min : 16;
+    s->cmax = d->run_len > 0 ? d->run_len : kDefaultRun;
+    s->bpcu = d->blocks_per_cu;
+    s->finish = d->finish_pass > 0 ? (uint32_t)d->finish_pass : 0u;
+    s->rec_bytes = rtk::batch_record_bytes(p.fp64, p.species, p.mb);
+    return RT_OK;
+}
+
+struct BatchLayout {
+    size_t off_head, off_table, off_slots, off_queue, off_rec, off_idx0, off_idx1, off_side, off_cnt, off_off,
+        off_tsolve, off_cbase, off_bsum, off_ch0, off_ch1, off_ctrl, off_first, total;
+    uint32_t capacity, max_tiles, max_chunks, scan_blocks;
+};
+
+int32_t batch_layout(int32_t max_solves, const BatchShape &sh, int64_t max_round_packets, int64_t max_tiles,
+                     BatchLayout *l) {
+    if (max_solves < 1 || max_solves > RT_MAX_BATCH || max_round_packets < 1 || max_tiles < 1) return RT_EINVAL;
+    if (max_round_packets > ((int64_t)1 << 31) - 1 || max_tiles > ((int64_t)1 << 26)) return RT_EOVERFLOW;
+    const uint64_t cap = (uint64_t)max_round_packets, nt = (uint64_t)max_tiles;
+    const uint64_t mc = nt + cap / (uint64_t)sh.cmax + 1;
+    if (mc >= (1ull << 31)) return RT_EOVERFLOW;
+    l->capacity = (uint32_t)cap;
+    l->max_tiles = (uint32_t)nt;
+    l->max_chunks = (uint32_t)mc;
+    l->scan_blocks = (uint32_t)((nt + 4095) / 4096);
     size_t o = 0;
     // the table follows the head directly, as in the staging memory it is copied from
-    l.off_head = o;
-    l.off_table = o + sizeof(rtk::BatchHead);
-    o = align_up(l.off_table + (size_t)max_solves * sizeof(rtk::BatchSolve));
-    l.off_slots = o; o = align_up(o + (size_t)max_solves * kMaxBatchBlocks * sizeof(rtk::LedgerSlot));
-    l.off_queue = o; o = align_up(o + sizeof(unsigned long long));
-    l.total = o;
-    return l;
+    l->off_head = o;
+    l->off_table = o + sizeof(rtk::BatchHead);
+    o = align_up(l->off_table + (size_t)max_solves * sizeof(rtk::BatchSolve));
+    l->off_slots = o; o = align_up(o + (size_t)rtk::kMaxBatch * kMaxBatchBlocks * sizeof(rtk::LedgerSlot));
+    l->off_queue = o; o = align_up(o + sizeof(unsigned long long));
+    l->off_rec = o; o = align_up(o + cap * sh.rec_bytes);
+    l->off_idx0 = o; o = align_up(o + cap * sizeof(uint32_t));
+    l->off_idx1 = o; o = align_up(o + cap * sizeof(uint32_t));
+    l->off_side = o; o = align_up(o + cap * sizeof(uint32_t));
+    l->off_cnt = o; o = align_up(o + nt * sizeof(uint32_t));
+    l->off_off = o; o = align_up(o + nt * sizeof(uint32_t));
+    l->off_tsolve = o; o = align_up(o + nt * sizeof(uint16_t));
+    l->off_cbase = o; o = align_up(o + mc * rtk::kCodes * sizeof(uint32_t));
+    l->off_bsum = o; o = align_up(o + 2 * (size_t)l->scan_blocks * sizeof(uint32_t));
+    l->off_ch0 = o; o = align_up(o + mc * sizeof(rtk::TChunk));
+    l->off_ch1 = o; o = align_up(o + mc * sizeof(rtk::TChunk));
+    l->off_ctrl = o; o = align_up(o + sizeof(rtk::TCtrl));
+    l->off_first = o; o = align_up(o + (rtk::kMaxBatch + 1) * sizeof(uint32_t));
+    l->total = o;
+    return RT_OK;
 }
 
 struct BatchGraph {
-    int rounds, fp64, thermal;
+    int rounds;
+    uint32_t passes;
     hipGraphExec_t exec;
 };
 
@@ -933,8 +987,9 @@ struct rt_batch {
     hipStream_t stream;
     int device, cus;
     char *ws;
+    BatchShape shape;
     BatchLayout lay;
-    int occ[2][2];                 // march blocks per CU by [fp64][thermal]
+    int blocks;                    // march blocks
     void *staging;                 // pinned: head then table
     hipEvent_t staged;             // the last table copy has been read
     bool staged_pending;
@@ -947,28 +1002,53 @@ namespace {
 
 bool batch_valid(rt_batch_t b) { return b && b->magic == kBatchMagic; }
 
-rtk::BatchLaunch batch_launch(rt_batch_t b, int fp64, int thermal) {
+rtk::BatchLaunch batch_launch(rt_batch_t b, uint32_t passes) {
     rtk::BatchLaunch l;
-    l.head = reinterpret_cast<const rtk::BatchHead *>(b->ws + b->lay.off_head);
-    l.table = reinterpret_cast<const rtk::BatchSolve *>(b->ws + b->lay.off_table);
-    l.slots = reinterpret_cast<rtk::LedgerSlot *>(b->ws + b->lay.off_slots);
-    l.queue = reinterpret_cast<unsigned long long *>(b->ws + b->lay.off_queue);
-    l.fp64 = fp64;
-    l.thermal = thermal;
-    int blocks = b->cus * b->occ[fp64][thermal];
-    if (blocks > kMaxBatchBlocks) blocks = kMaxBatchBlocks;
-    l.blocks = blocks < 1 ? 1 : blocks;
-    l.chunk = 256;
-    l.refill_min = 8;
+    memset(&l, 0, sizeof(l));
+    char *ws = b->ws;
+    const BatchLayout &y = b->lay;
+    l.head = reinterpret_cast<const rtk::BatchHead *>(ws + y.off_head);
+    l.table = reinterpret_cast<const rtk::BatchSolve *>(ws + y.off_table);
+    l.slots = reinterpret_cast<rtk::LedgerSlot *>(ws + y.off_slots);
+    l.queue = reinterpret_cast<unsigned long long *>(ws + y.off_queue);
+    l.fp64 = b->shape.fp64;
+    l.thermal = b->shape.thermal;
+    l.species = b->shape.species;
+    l.mb = b->shape.mb;
+    l.blocks = b->blocks;
+    l.refill_min = b->shape.refill_min;
     l.cell_blocks = b->cus * 8;
+    l.passes = passes;
+    l.finish = b->shape.finish;
+    rtk::BatchTiles &t = l.t;
+    t.rec = ws + y.off_rec;
+    t.idx[0] = reinterpret_cast<uint32_t *>(ws + y.off_idx0);
+    t.idx[1] = reinterpret_cast<uint32_t *>(ws + y.off_idx1);
+    t.side = reinterpret_cast<uint32_t *>(ws + y.off_side);
+    t.cnt = reinterpret_cast<uint32_t *>(ws + y.off_cnt);
+    t.off = reinterpret_cast<uint32_t *>(ws + y.off_off);
+    t.cbase = reinterpret_cast<uint32_t *>(ws + y.off_cbase);
+    t.bsum = reinterpret_cast<uint32_t *>(ws + y.off_bsum);
+    t.tsolve = reinterpret_cast<uint16_t *>(ws + y.off_tsolve);
+    t.first = reinterpret_cast<uint32_t *>(ws + y.off_first);
+    t.chunks[0] = reinterpret_cast<rtk::TChunk *>(ws + y.off_ch0);
+    t.chunks[1] = reinterpret_cast<rtk::TChunk *>(ws + y.off_ch1);
+    t.ctrl = reinterpret_cast<rtk::TCtrl *>(ws + y.off_ctrl);
+    t.capacity = y.capacity;
+    t.max_tiles = y.max_tiles;
+    t.max_chunks = y.max_chunks;
+    t.cmax = (uint32_t)b->shape.cmax;
+    t.scan_blocks = y.scan_blocks;
     l.stream = b->stream;
     return l;
 }
 
-// Every launch of one call: ledgers cleared, then per round absorbers, march,
-// ledger reduction and cell update of every solve that still has sub-steps.
+// Every launch of one call: ledgers cleared, each fused tile's solve, then per
+// round absorbers, the tiled march, ledger reduction and cell update of every
+// solve that still has sub-steps.
 hipError_t batch_enqueue(const rtk::BatchLaunch &l, int rounds) {
     hipError_t e = rtk::launch_batch_begin(l);
+    if (e == hipSuccess) e = rtk::launch_batch_tiles(l);
     for (int r = 0; r < rounds && e == hipSuccess; ++r) {
         e = rtk::launch_batch_prep(l, r);
         if (e == hipSuccess) e = rtk::launch_batch_march(l, r);
@@ -980,7 +1060,7 @@ hipError_t batch_enqueue(const rtk::BatchLaunch &l, int rounds) {
 
 hipError_t batch_graph(rt_batch_t b, const rtk::BatchLaunch &l, int rounds, hipGraphExec_t *out) {
     for (const BatchGraph &g : b->graphs)
-        if (g.rounds == rounds && g.fp64 == l.fp64 && g.thermal == l.thermal) {
+        if (g.rounds == rounds && g.passes == l.passes) {
             *out = g.exec;
             return hipSuccess;
         }
@@ -997,7 +1077,7 @@ hipError_t batch_graph(rt_batch_t b, const rtk::BatchLaunch &l, int rounds, hipG
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return e;
-    b->graphs.push_back(BatchGraph{rounds, l.fp64, l.thermal, exec});
+    b->graphs.push_back(BatchGraph{rounds, l.passes, exec});
     *out = exec;
     return hipSuccess;
 }
@@ -1016,20 +1096,32 @@ void batch_destroy(rt_batch_t b) {
 
 extern "C" {
 
-int32_t rt_batch_workspace_bytes(int32_t max_solves, size_t *bytes_out) {
-    if (!bytes_out || max_solves < 1 || max_solves > RT_MAX_BATCH) return RT_EINVAL;
-    *bytes_out = batch_layout(max_solves).total;
+int32_t rt_batch_workspace_bytes(int32_t max_solves, const rt_grid_desc *shape, int64_t max_round_packets,
+                                 int64_t max_tiles, size_t *bytes_out) {
+    if (!bytes_out || !shape) return RT_EINVAL;
+    BatchShape sh;
+    int32_t r = batch_shape(shape, &sh);
+    if (r != RT_OK) return r;
+    BatchLayout l;
+    r = batch_layout(max_solves, sh, max_round_packets, max_tiles, &l);
+    if (r != RT_OK) return r;
+    *bytes_out = l.total;
     return RT_OK;
 }
 
-int32_t rt_batch_init(int32_t max_solves, void *d_ws, size_t ws_bytes, void *hip_stream, uint32_t flags,
-                      rt_batch_t *out) {
+int32_t rt_batch_init(int32_t max_solves, const rt_grid_desc *shape, int64_t max_round_packets, int64_t max_tiles,
+                      void *d_ws, size_t ws_bytes, void *hip_stream, uint32_t flags, rt_batch_t *out) {
     if (!out) return RT_EINVAL;
     *out = nullptr;
-    if (max_solves < 1 || max_solves > RT_MAX_BATCH || (flags & ~RT_BATCH_GRAPH)) return RT_EINVAL;
+    if (!shape || (flags & ~RT_BATCH_GRAPH)) return RT_EINVAL;
     if ((flags & RT_BATCH_GRAPH) && !hip_stream) return RT_EINVAL;
     if (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0) return RT_EINVAL;
-    const BatchLayout lay = batch_layout(max_solves);
+    BatchShape sh;
+    int32_t r = batch_shape(shape, &sh);
+    if (r != RT_OK) return r;
+    BatchLayout lay;
+    r = batch_layout(max_solves, sh, max_round_packets, max_tiles, &lay);
+    if (r != RT_OK) return r;
     if (ws_bytes < lay.total) return RT_ENOMEM;
     rt_batch *b = new (std::nothrow) rt_batch;
     if (!b) return RT_ENOMEM;
@@ -1038,18 +1130,21 @@ int32_t rt_batch_init(int32_t max_solves, void *d_ws, size_t ws_bytes, void *hip
     b->flags = flags;
     b->stream = reinterpret_cast<hipStream_t>(hip_stream);
     b->ws = reinterpret_cast<char *>(d_ws);
+    b->shape = sh;
     b->lay = lay;
     b->staging = nullptr;
     b->staged = nullptr;
     b->done = nullptr;
     b->staged_pending = false;
+    int occ = 0;
     bool ok = hipGetDevice(&b->device) == hipSuccess &&
               hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->device) == hipSuccess;
-    for (int f = 0; f < 2 && ok; ++f)
-        for (int t = 0; t < 2 && ok; ++t) {
-            ok = rtk::batch_march_occupancy(f, t, &b->occ[f][t]) == hipSuccess;
-            if (ok && b->occ[f][t] < 1) b->occ[f][t] = 1;
-        }
+    if (ok && sh.bpcu == 0) ok = rtk::batch_march_occupancy(sh.fp64, sh.species, sh.thermal, sh.mb, &occ) == hipSuccess;
+    if (sh.bpcu > 0) occ = sh.bpcu;
+    if (occ < 1) occ = 1;
+    b->blocks = b->cus * occ;
+    if (b->blocks > kMaxBatchBlocks) b->blocks = kMaxBatchBlocks;
+    if (b->blocks < 1) b->blocks = 1;
     ok = ok && hipHostMalloc(&b->staging, sizeof(rtk::BatchHead) + (size_t)max_solves * sizeof(rtk::BatchSolve),
                              hipHostMallocDefault) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) == hipSuccess;
@@ -1069,7 +1164,10 @@ int32_t rt_step_many(rt_batch_t b, const rt_solve_t *solves, int32_t n, const do
                      const int64_t *n_packets, const uint64_t *seeds, rt_step_stats *stats) {
     if (!batch_valid(b) || !solves || !dt_s || !n_packets || !seeds) return RT_EINVAL;
     if (n < 1 || n > b->max_solves) return RT_EINVAL;
-    int fp64 = -1, thermal = -1, rounds = 0;
+    const BatchShape &sh = b->shape;
+    int rounds = 0;
+    uint64_t tiles = 0;
+    uint32_t passes = 1;
     for (int i = 0; i < n; ++i) {
         const rt_solve_t h = solves[i];
         if (!valid(h)) return RT_EINVAL;
@@ -1077,25 +1175,40 @@ int32_t rt_step_many(rt_batch_t b, const rt_solve_t *solves, int32_t n, const do
         for (int k = 0; k < i; ++k)
             if (solves[k] == h) return RT_EINVAL;
         const Plan &p = h->plan;
-        if (h->device != b->device || p.species != 1 || p.mb != 1 || h->d.trace_packets > 0 || p.recomb ||
-            h->bg_packets > 0 || p.periodic)
+        // the batch's march instance, cells in bricks of 8^3 (the tiles)
+        if (h->device != b->device || p.bl != 3 || p.species != sh.species || p.mb != sh.mb || p.fp64 != sh.fp64 ||
+            p.thermal != sh.thermal || h->d.trace_packets > 0 || p.recomb || h->bg_packets > 0 ||
+            (h->d.flags & RT_PERIODIC) || (p.species == 3 && p.mb > 1 && bin_layout(&h->d, p) != 1))
             return RT_EINVAL;
-        if ((fp64 >= 0 && p.fp64 != fp64) || (thermal >= 0 && p.thermal != thermal)) return RT_EINVAL;
-        fp64 = p.fp64;
-        thermal = p.thermal;
         if (!(isfinite(dt_s[i]) && dt_s[i] > 0.0) || n_packets[i] < 0) return RT_EINVAL;
         const int64_t base = n_packets[i] / h->d.n_sub;
         if (h->n_src > 0 && base < h->n_src) return RT_EINVAL;
         if (base + 1 > ((int64_t)1 << 31)) return RT_EOVERFLOW;
         if (h->d.n_sub > rounds) rounds = h->d.n_sub;
+        tiles += (uint64_t)p.geo.nb[0] * p.geo.nb[1] * p.geo.nb[2];
+        const uint32_t v = (uint32_t)(p.geo.nb[0] + p.geo.nb[1] + p.geo.nb[2] - 2);
+        if (v > passes) passes = v;
     }
-    const rtk::BatchLaunch l = batch_launch(b, fp64, thermal);
+    if (tiles > b->lay.max_tiles) return RT_ENOMEM;
+    // records: the packets of every round must fit those in flight
+    for (int r = 0; r < rounds; ++r) {
+        uint64_t tot = 0;
+        for (int i = 0; i < n; ++i) {
+            const rt_solve_t h = solves[i];
+            if (h->n_src == 0 || r >= h->d.n_sub) continue;
+            const int64_t base = n_packets[i] / h->d.n_sub, extra = n_packets[i] % h->d.n_sub;
+            tot += (uint64_t)(base + (r < extra ? 1 : 0));
+        }
+        if (tot > b->lay.capacity) return RT_ENOMEM;
+    }
+    const rtk::BatchLaunch l = batch_launch(b, passes);
 
     // the table: the previous copy out of the staging memory must have happened
     if (b->staged_pending && hipEventSynchronize(b->staged) != hipSuccess) return RT_EDEVICE;
     rtk::BatchHead *hd = reinterpret_cast<rtk::BatchHead *>(b->staging);
     rtk::BatchSolve *tb = reinterpret_cast<rtk::BatchSolve *>(hd + 1);
     uint64_t cells = 0;
+    uint32_t tile0 = 0;
     for (int i = 0; i < n; ++i) {
         const rt_solve_t h = solves[i];
         const Plan &p = h->plan;
@@ -1126,11 +1239,15 @@ int32_t rt_step_many(rt_batch_t b, const rt_solve_t *solves, int32_t n, const do
         t.n_chem = h->d.n_chem;
         t.acc_stride = p.acc_stride;
         t.cell0 = cells;
+        t.tile0 = tile0;
+        t.n_tiles = (uint32_t)p.geo.nb[0] * p.geo.nb[1] * p.geo.nb[2];
         cells += p.geo.ncell_pad;
+        tile0 += t.n_tiles;
     }
     memset(hd, 0, sizeof(*hd));
     hd->n = n;
     hd->cells = cells;
+    hd->tiles = tile0;
 
     // order: each solve's earlier work, the table copy, the fused launches
     for (int i = 0; i < n; ++i) {

@@ -533,7 +533,7 @@ __global__ void __launch_bounds__(64) k_bbegin(const BatchHead *hd, const BatchS
     if (threadIdx.x == 0 && (int)blockIdx.x < hd->n) zero_ledger(tb[blockIdx.x].ledger);
 }
 
-template <typename R>
+template <typename R, int S>
 __global__ void __launch_bounds__(kCellBlock) k_bprep(const BatchHead *hd, const BatchSolve *tb, int round,
                                                       unsigned long long *queue) {
     __shared__ uint64_t s_first[kMaxBatch];
@@ -547,7 +547,7 @@ __global__ void __launch_bounds__(kCellBlock) k_bprep(const BatchHead *hd, const
         const int b = batch_solve_of(s_first, n, g);
         const BatchSolve &sv = tb[b];
         if (round >= sv.n_sub) continue;
-        prep_slot<R, 1>(sv.geo.ncell_pad, reinterpret_cast<const R *>(sv.state), sv.kappa, sv.acc, sv.acc_stride,
+        prep_slot<R, S>(sv.geo.ncell_pad, reinterpret_cast<const R *>(sv.state), sv.kappa, sv.acc, sv.acc_stride,
                         sv.y_he, (uint32_t)(g - s_first[b]));
     }
 }
@@ -559,7 +559,7 @@ __global__ void __launch_bounds__(64) k_bledger(const BatchHead *hd, const Batch
     reduce_slots(slots + (size_t)b * nslots, nslots, tb[b].ledger);
 }
 
-template <typename R, bool TH>
+template <typename R, int S, bool TH>
 __global__ void __launch_bounds__(kCellBlock) k_bupdate(const BatchHead *hd, const BatchSolve *tb, int round) {
     __shared__ uint64_t s_first[kMaxBatch];
     const int n = hd->n;
@@ -573,7 +573,7 @@ __global__ void __launch_bounds__(kCellBlock) k_bupdate(const BatchHead *hd, con
         if (round >= sv.n_sub) continue;
         const UpdateConst u(sv.cell_cm, sv.dt, sv.redshift, sv.n_chem);
         unsigned int bad = 0;
-        update_slot<R, 1, TH, false>(sv.geo, reinterpret_cast<R *>(sv.state), sv.acc, sv.acc_stride, sv.y_he, sv.dt,
+        update_slot<R, S, TH, false>(sv.geo, reinterpret_cast<R *>(sv.state), sv.acc, sv.acc_stride, sv.y_he, sv.dt,
                               sv.n_chem, u, (uint32_t)(g - s_first[b]), bad);
         if (bad) atomicOr(&sv.ledger->nonfinite, 1u);
     }
@@ -587,11 +587,18 @@ hipError_t launch_batch_begin(const BatchLaunch &b) {
     return hipGetLastError();
 }
 
+template <typename R, int S>
+static void bprep(const BatchLaunch &b, int round) {
+    hipLaunchKernelGGL((k_bprep<R, S>), dim3(b.cell_blocks), dim3(kCellBlock), 0, b.stream, b.head, b.table, round,
+                       b.queue);
+}
+
 hipError_t launch_batch_prep(const BatchLaunch &b, int round) {
-    if (b.fp64) hipLaunchKernelGGL(k_bprep<double>, dim3(b.cell_blocks), dim3(kCellBlock), 0, b.stream, b.head,
-                                   b.table, round, b.queue);
-    else hipLaunchKernelGGL(k_bprep<float>, dim3(b.cell_blocks), dim3(kCellBlock), 0, b.stream, b.head, b.table,
-                            round, b.queue);
+    if (b.fp64) {
+        if (b.species == 1) bprep<double, 1>(b, round); else bprep<double, 3>(b, round);
+    } else {
+        if (b.species == 1) bprep<float, 1>(b, round); else bprep<float, 3>(b, round);
+    }
     return hipGetLastError();
 }
 
@@ -600,14 +607,18 @@ hipError_t launch_batch_ledger(const BatchLaunch &b, int round) {
     return hipGetLastError();
 }
 
-hipError_t launch_batch_update(const BatchLaunch &b, int round) {
+template <typename R, int S>
+static void bupdate(const BatchLaunch &b, int round) {
     const dim3 g(b.cell_blocks), t(kCellBlock);
+    if (b.thermal) hipLaunchKernelGGL((k_bupdate<R, S, true>), g, t, 0, b.stream, b.head, b.table, round);
+    else hipLaunchKernelGGL((k_bupdate<R, S, false>), g, t, 0, b.stream, b.head, b.table, round);
+}
+
+hipError_t launch_batch_update(const BatchLaunch &b, int round) {
     if (b.fp64) {
-        if (b.thermal) hipLaunchKernelGGL((k_bupdate<double, true>), g, t, 0, b.stream, b.head, b.table, round);
-        else hipLaunchKernelGGL((k_bupdate<double, false>), g, t, 0, b.stream, b.head, b.table, round);
+        if (b.species == 1) bupdate<double, 1>(b, round); else bupdate<double, 3>(b, round);
     } else {
-        if (b.thermal) hipLaunchKernelGGL((k_bupdate<float, true>), g, t, 0, b.stream, b.head, b.table, round);
-        else hipLaunchKernelGGL((k_bupdate<float, false>), g, t, 0, b.stream, b.head, b.table, round);
+        if (b.species == 1) bupdate<float, 1>(b, round); else bupdate<float, 3>(b, round);
     }
     return hipGetLastError();
 }

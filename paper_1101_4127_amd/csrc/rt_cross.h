@@ -257,12 +257,17 @@ __device__ __forceinline__ void cross_cell(R l, const KV &kap, TT tab, R (&F)[MB
 // boundaries, so every march organisation drops the same bins at the same
 // cells; T_j is formed as in the extinction test (zero helium cross-sections
 // of the layout's hydrogen-only bins add exact zeros).
+//
+// Bins outside `wbins` (wave-uniform superset of the bins the calling lanes
+// carry) are not looked at.
 template <int S, int MB, int NA, int NB, typename TT>
 __device__ __forceinline__ float drop_exhausted(TT tab, uint32_t &active, float tau_drop,
-                                                const float (&N)[S == 1 ? 1 : 3], float (&F)[MB]) {
+                                                const float (&N)[S == 1 ? 1 : 3], float (&F)[MB],
+                                                uint32_t wbins = ~0u) {
     float drop = 0.0f;
 #pragma unroll
     for (int j = 0; j < MB; ++j) {
+        if (!((wbins >> j) & 1u)) continue;
         const float sH = tab[j];
         float Tj;
         if constexpr (S == 1) Tj = sH * N[0];

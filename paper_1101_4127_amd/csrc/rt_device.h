@@ -78,6 +78,9 @@ __device__ __forceinline__ uint32_t nth_set_bit(uint64_t m, uint32_t t) {
 // in the one-lane loop).  The wavefront then waits about three rounds of draws
 // instead of its slowest packet's seven or so.  Every lane of the wavefront
 // must call it (uniform control flow); lanes with `want` false only help.
+// KEYED: the key (seed, solve id) and the sub-step differ between lanes (the
+// packets of several solves in one wavefront); else they are the same for all.
+template <bool KEYED = false>
 __device__ __forceinline__ void sample_direction_wave(uint64_t seed, uint64_t solve_id, uint64_t g,
                                                       uint64_t step, bool octant, bool want, int32_t c[3],
                                                       uint64_t stream = 0ull) {
@@ -97,8 +100,14 @@ __device__ __forceinline__ void sample_direction_wave(uint64_t seed, uint64_t so
         const uint32_t at = (uint32_t)__shfl((int)next, (int)src) + o;
         bool ok = false;
         int32_t x = 0, y = 0, z = 0;
+        uint64_t st = step, sd = seed, si = solve_id;
+        if constexpr (KEYED) {
+            st = (uint64_t)__shfl((long long)step, (int)src);
+            sd = (uint64_t)__shfl((long long)seed, (int)src);
+            si = (uint64_t)__shfl((long long)solve_id, (int)src);
+        }
         if (at < 64u) {
-            const U64x4 r = philox4x64_10(gt, step, at, stream, seed, solve_id);
+            const U64x4 r = philox4x64_10(gt, st, at, stream, sd, si);
             x = (int32_t)(r.v[0] >> 43) - (1 << 20);
             y = (int32_t)(r.v[1] >> 43) - (1 << 20);
             z = (int32_t)(r.v[2] >> 43) - (1 << 20);

@@ -128,6 +128,7 @@ struct TiledLaunch {
     uint32_t passes;        // passes launched per batch
     uint32_t park_passes;   // passes (from the first) in which packets may be parked
     uint32_t park_lanes;    // park when at most this many lanes still march (0: never)
+    uint32_t finish;        // tile passes before the finishing pass (0: none)
     uint32_t periodic;      // periodic boundaries
     uint32_t dmax;          // periodic: a packet ends once a next-face distance exceeds this
     void *rec;
@@ -179,12 +180,17 @@ hipError_t tiled_occupancy(int species, int thermal, int fp64, int mb, int *bloc
 hipError_t march_occupancy(int species, int thermal, int fp64, int mb, int *blocks_per_cu);
 
 // ---------------------------------------------------------------------------
-// Fused steps of many independent solves (pure hydrogen, one bin).  Every
-// kernel of a fused sub-step reads the solves from one device table, so the
-// launch shapes do not depend on the batch and one captured graph serves any
-// set of solves; round r of a call is every solve's sub-step r.
+// Fused steps of many independent solves.  The solves of one call share the
+// march instance (precision, species, bins, thermal) and their cell fields in
+// bricks of 8^3; every kernel of a fused sub-step reads the solves from one
+// device table, so the launch shapes do not depend on the batch and one
+// captured graph serves any set of solves; round r of a call is every
+// solve's sub-step r.  The march is the tiled one over the concatenation of
+// the solves' tiles: global tile id = the solve's first tile + its own tile
+// index; a run of a tile belongs to one solve, whose values (grid, absorbers,
+// accumulators, per-bin table) the block reads at the start of the run.
 // ---------------------------------------------------------------------------
-constexpr int kMaxBatch = 64;              // solves per fused call
+constexpr int kMaxBatch = 256;             // solves per fused call
 
 struct BatchSolve {
     GridGeom geo;
@@ -199,12 +205,15 @@ struct BatchSolve {
     StepLedger *ledger;
     int32_t n_sub, n_src, n_chem, acc_stride;
     uint64_t cell0;                        // first fused cell index of this solve
+    uint32_t tile0, n_tiles;               // first fused tile and tiles of this solve
 };
 
 struct BatchHead {
     int32_t n;                             // solves in the table
     int32_t pad;
     uint64_t cells;                        // fused cells: the solves' padded slot counts summed
+    uint32_t tiles;                        // fused tiles: the solves' tiles summed
+    uint32_t pad2;
 };
 
 // Packets of sub-step `round` of a solve (zero once its sub-steps are done).
@@ -214,23 +223,39 @@ __host__ __device__ inline uint32_t round_packets(const BatchSolve &s, int round
     return (uint32_t)(base + (round < extra ? 1 : 0));
 }
 
+// Lists, records and counters of the fused tiled march (in the batch's workspace).
+struct BatchTiles {
+    void *rec;
+    uint32_t *idx[2], *side, *cnt, *off, *cbase, *bsum;
+    uint16_t *tsolve;                      // solve of each fused tile
+    uint32_t *first;                       // [kMaxBatch + 1] first fused packet id per solve (this round)
+    TChunk *chunks[2];
+    TCtrl *ctrl;
+    uint32_t capacity, max_tiles, max_chunks, cmax, scan_blocks;
+};
+
 struct BatchLaunch {
     const BatchHead *head;
     const BatchSolve *table;
     LedgerSlot *slots;                     // [kMaxBatch][blocks] per-block partial ledgers
-    unsigned long long *queue;             // packet counter of the round
-    int32_t fp64, thermal;
-    int32_t blocks, chunk, refill_min;     // march grid and claim parameters
+    unsigned long long *queue;
+    int32_t fp64, thermal, species, mb;    // the march instance of the call
+    int32_t blocks, refill_min;            // march grid and refill threshold
     int32_t cell_blocks;                   // grid of the cell kernels
+    uint32_t passes;                       // march passes per sub-step
+    uint32_t finish;                       // tile passes before the finishing pass (0: none)
+    BatchTiles t;
     hipStream_t stream;
 };
 
 hipError_t launch_batch_begin(const BatchLaunch &b);
+hipError_t launch_batch_tiles(const BatchLaunch &b);
 hipError_t launch_batch_prep(const BatchLaunch &b, int round);
 hipError_t launch_batch_march(const BatchLaunch &b, int round);
 hipError_t launch_batch_ledger(const BatchLaunch &b, int round);
 hipError_t launch_batch_update(const BatchLaunch &b, int round);
-hipError_t batch_march_occupancy(int fp64, int thermal, int *blocks_per_cu);
+hipError_t batch_march_occupancy(int fp64, int species, int thermal, int mb, int *blocks_per_cu);
+size_t batch_record_bytes(int fp64, int species, int mb);
 
 hipError_t launch_prep(const CellLaunch &c);
 hipError_t launch_update(const CellLaunch &c);

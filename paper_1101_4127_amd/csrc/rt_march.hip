@@ -372,258 +372,6 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
 }
 
 // ---------------------------------------------------------------------------
-// Fused march of many pure-hydrogen, one-bin solves.  The packet ids of a
-// round are the concatenation of the solves' ids of that sub-step; a lane may
-// carry a packet of any solve, so it holds that solve's grid, absorbers,
-// accumulators and per-bin values itself.  Emission, traversal and the
-// crossing arithmetic are those of k_march (same ids, same Philox counters,
-// same directions and same arithmetic per crossing); the ledger gathers per
-// solve in LDS and goes out as one slot per (solve, block).
-// ---------------------------------------------------------------------------
-template <typename R, bool TH>
-__global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, 1>::value))
-    k_bmarch(const BatchHead *hd, const BatchSolve *tb, int round, unsigned long long *queue, LedgerSlot *slots,
-             uint32_t chunk, uint32_t refill_min) {
-    constexpr bool F64 = std::is_same<R, double>::value;
-    constexpr uint32_t ACC = TH ? 2u : 1u;
-    constexpr int ND = DepthState<R, 1, 1>::N;
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t wv = threadIdx.x >> 6;
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
-
-    __shared__ unsigned long long s_first[kMaxBatch + 1];   // first fused packet id of each solve
-    __shared__ double s_ls[kMaxBatch][4];                     // emitted, absorbed, escaped, truncated
-    __shared__ unsigned long long s_lc[kMaxBatch][4];         // crossings, packets, escaped, truncated
-    __shared__ int32_t sb_c[kWaves][3][64];
-    __shared__ uint32_t sb_g[kWaves][64], sb_src[kWaves][64], sb_b[kWaves][64];
-    __shared__ double sb_w[kWaves][64], sb_L[kWaves][64];
-
-    const int n = hd->n;
-    for (int i = threadIdx.x; i < kMaxBatch * 4; i += kMarchBlock) {
-        (&s_ls[0][0])[i] = 0.0;
-        (&s_lc[0][0])[i] = 0ull;
-    }
-    if (threadIdx.x == 0) {
-        unsigned long long a = 0;
-        for (int b = 0; b < n; ++b) {
-            s_first[b] = a;
-            a += round_packets(tb[b], round);
-        }
-        s_first[n] = a;
-    }
-    __syncthreads();
-    const unsigned long long total = s_first[n];
-
-    // ---- packet state ----
-    bool alive = false;
-    int k0 = 0, k1 = 0, k2 = 0;
-    uint32_t d0 = 1, d1 = 1, d2 = 1, a0 = 0, a1 = 0, a2 = 0, pnum = 0, pden = 1;
-    double sprev = 0.0, L = 0.0, w = 0.0, absd = 0.0, tau_kill = 0.0;
-    float Lf = 0.0f;
-    uint32_t slot = 0, count = 0, bi = 0, active = 0;
-    GridGeom geo{};
-    const R *kappa = nullptr;
-    double *acc = nullptr;
-    LaneTab1<R> tab{R(0), R(0)};
-    R kap = R(0), F[1] = {R(0)}, D[ND];
-#pragma unroll
-    for (int j = 0; j < ND; ++j) D[j] = R(0);
-    DepthTest<R, 1, 1> dtest;
-
-    uint32_t batch_cnt = 0, batch_used = 0;
-    unsigned long long pool_next = 0, pool_end = 0;
-    bool exhausted = false;
-
-    for (;;) {
-        uint64_t dead = __ballot(!alive);
-        uint32_t ndead = __popcll(dead);
-        if (ndead != 0 && (ndead >= refill_min || ndead == 64u)) {
-            while (ndead != 0) {
-                if (batch_used == batch_cnt) {
-                    if (pool_next == pool_end) {
-                        if (exhausted) break;
-                        unsigned long long base = 0;
-                        if (lane == 0) base = atomicAdd(queue, (unsigned long long)chunk);
-                        const uint32_t lo = uniform((uint32_t)base), hi = uniform((uint32_t)(base >> 32));
-                        const unsigned long long b = ((unsigned long long)hi << 32) | lo;
-                        if (b >= total) { exhausted = true; break; }
-                        pool_next = b;
-                        pool_end = min(b + chunk, total);
-                    }
-                    batch_cnt = (uint32_t)min(64ull, pool_end - pool_next);
-                    const unsigned long long id = pool_next + lane;
-                    pool_next += batch_cnt;
-                    batch_used = 0;
-                    if (lane < batch_cnt) {
-                        int lo = 0, hi = n - 1;            // the solve of fused id `id`
-                        while (lo < hi) {
-                            const int mid = (lo + hi + 1) >> 1;
-                            if (s_first[mid] <= id) lo = mid; else hi = mid - 1;
-                        }
-                        const BatchSolve &sv = tb[lo];
-                        const uint32_t P = (uint32_t)(s_first[lo + 1] - s_first[lo]);
-                        const uint32_t g = (uint32_t)(id - s_first[lo]);
-                        const uint32_t q = P / (uint32_t)sv.n_src, r = P % (uint32_t)sv.n_src;
-                        uint32_t sidx, ns;
-                        const uint32_t big = r * (q + 1u);
-                        if (g < big) { sidx = g / (q + 1u); ns = q + 1u; }
-                        else { sidx = r + (g - big) / q; ns = q; }
-                        const int32_t oct = (int32_t)(sv.src[sidx].flags & kSrcOctant);
-                        double ww = sv.src_ndot[sidx] * sv.dt;
-                        ww = ww / (double)ns;
-                        if (oct) ww = ww * 0.125;
-                        int32_t c[3];
-                        sample_direction(sv.seed, sv.solve_id, g, sv.step0 + (uint64_t)round, oct != 0, c);
-                        const int64_t qq = (int64_t)c[0] * c[0] + (int64_t)c[1] * c[1] + (int64_t)c[2] * c[2];
-                        sb_c[wv][0][lane] = c[0];
-                        sb_c[wv][1][lane] = c[1];
-                        sb_c[wv][2][lane] = c[2];
-                        sb_g[wv][lane] = g;
-                        sb_src[wv][lane] = sidx;
-                        sb_b[wv][lane] = (uint32_t)lo;
-                        sb_w[wv][lane] = ww;
-                        sb_L[wv][lane] = sqrt((double)qq) * sv.half_dl;
-                        atomicAdd(&s_ls[lo][0], ww * sv.src_sedsum[sidx]);
-                        atomicAdd(&s_lc[lo][1], 1ull);
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                }
-                const uint32_t take = min(ndead, batch_cnt - batch_used);
-                const uint32_t rank = __popcll(dead & lt_mask);
-                if (!alive && rank < take) {
-                    const uint32_t e = batch_used + rank;
-                    const int32_t c0 = sb_c[wv][0][e], c1 = sb_c[wv][1][e], c2 = sb_c[wv][2][e];
-                    const uint32_t srcid = sb_src[wv][e];
-                    bi = sb_b[wv][e];
-                    const BatchSolve &sv = tb[bi];
-                    geo = sv.geo;
-                    kappa = reinterpret_cast<const R *>(sv.kappa);
-                    acc = sv.acc;
-                    const R *tr = reinterpret_cast<const R *>(sv.tab);
-                    tab.sig = tr[0];
-                    tab.heat = tr[3];
-                    tau_kill = sv.tau_kill;
-                    w = sb_w[wv][e];
-                    const double Ld = sb_L[wv][e];
-                    const SourceRec sr = sv.src[srcid];
-                    if (F64) L = Ld; else Lf = (float)(Ld * 1.0e-18);
-                    k0 = sr.o[0] >> 1; k1 = sr.o[1] >> 1; k2 = sr.o[2] >> 1;
-                    a0 = pack_dir(c0);
-                    a1 = pack_dir(c1);
-                    a2 = pack_dir(c2);
-                    d0 = next_face(k0, sr.o[0], a0);
-                    d1 = next_face(k1, sr.o[1], a1);
-                    d2 = next_face(k2, sr.o[2], a2);
-                    active = sr.flags >> kSrcMaskShift;
-                    F[0] = reinterpret_cast<const R *>(sv.sed)[srcid];
-#pragma unroll
-                    for (int j = 0; j < ND; ++j)
-                        D[j] = (!DepthState<R, 1, 1>::F64 || ((active >> j) & 1u)) ? R(0) : R(INFINITY);
-                    dtest.start(tab, active, D);
-                    sprev = 0.0; pnum = 0; pden = 1;
-                    absd = 0.0;
-                    count = 0;
-                    slot = cell_slot(geo, k0, k1, k2);
-                    kap = kappa[slot];
-                    alive = true;
-                }
-                batch_used += take;
-                dead = __ballot(!alive);
-                ndead = __popcll(dead);
-                __builtin_amdgcn_wave_barrier();
-            }
-        }
-        if (__ballot(alive) == 0) {
-            if (exhausted && batch_used == batch_cnt && pool_next == pool_end) break;
-            continue;
-        }
-
-        if (alive) {
-            bool m0, m1, m2;
-            const int ax = exit_face(d0, d1, d2, a0, a1, a2, m0, m1, m2);
-            const uint32_t num = ax == 0 ? d0 : (ax == 1 ? d1 : d2);
-            const uint32_t den = (ax == 0 ? a0 : (ax == 1 ? a1 : a2)) & kMag;
-            R l;
-            double snew = 0.0;
-            if (F64) {
-                snew = (double)num / (double)den;
-                l = (snew - sprev) * L;
-            } else {
-                const uint32_t diff = __umul24(num, pden) - __umul24(pnum, den);
-                l = Lf * (float)diff * __builtin_amdgcn_rcpf((float)den * (float)pden);
-            }
-            if (m0) { k0 += (a0 & kNeg) ? -1 : 1; d0 += 2u; }
-            if (m1) { k1 += (a1 & kNeg) ? -1 : 1; d1 += 2u; }
-            if (m2) { k2 += (a2 & kNeg) ? -1 : 1; d2 += 2u; }
-            const bool out = (uint32_t)k0 >= (uint32_t)geo.n[0] || (uint32_t)k1 >= (uint32_t)geo.n[1]
-                             || (uint32_t)k2 >= (uint32_t)geo.n[2];
-            const uint32_t nslot = out ? slot : cell_slot(geo, k0, k1, k2);
-            const R knext = kappa[nslot];
-
-            R absorbed, e0, e1, e2, hs, tmin;
-            cross_cell<R, 1, TH, 1>(l, kap, tab, F, D, absorbed, e0, e1, e2, hs, tmin);
-
-            double *cell = acc + (size_t)slot * ACC;
-            const double v = w * (double)absorbed;
-            if (v != 0.0) unsafeAtomicAdd(cell, v);
-            if (TH) {
-                const double qh = w * ((double)hs * kEvErg);
-                if (qh != 0.0) unsafeAtomicAdd(cell + 1, qh);
-            }
-            absd += (double)absorbed;
-            ++count;
-
-            const uint32_t fate = dtest.extinguished(tab, active, tau_kill, tmin, D) ? 1u : (out ? 2u : 0u);
-            if (fate == 0) {
-                slot = nslot;
-                kap = knext;
-                if (F64) sprev = snew; else { pnum = num; pden = den; }
-            } else {
-                atomicAdd(&s_ls[bi][1], w * absd);
-                atomicAdd(&s_ls[bi][fate == 2u ? 2 : 3], w * (double)F[0]);
-                atomicAdd(&s_lc[bi][0], (unsigned long long)count);
-                atomicAdd(&s_lc[bi][fate == 2u ? 2 : 3], 1ull);
-                alive = false;
-            }
-        }
-    }
-
-    __syncthreads();
-    for (int b = threadIdx.x; b < n; b += kMarchBlock) {
-        LedgerSlot o;
-        for (int i = 0; i < 4; ++i) {
-            o.s[2 * i] = s_ls[b][i];
-            o.s[2 * i + 1] = 0.0;
-            o.c[i] = s_lc[b][i];
-        }
-        slots[(size_t)b * gridDim.x + blockIdx.x] = o;
-    }
-}
-
-hipError_t launch_batch_march(const BatchLaunch &b, int round) {
-    const dim3 g(b.blocks), t(kMarchBlock);
-    const uint32_t ch = (uint32_t)b.chunk, rm = (uint32_t)b.refill_min;
-    if (b.fp64) {
-        if (b.thermal) hipLaunchKernelGGL((k_bmarch<double, true>), g, t, 0, b.stream, b.head, b.table, round, b.queue, b.slots, ch, rm);
-        else hipLaunchKernelGGL((k_bmarch<double, false>), g, t, 0, b.stream, b.head, b.table, round, b.queue, b.slots, ch, rm);
-    } else {
-        if (b.thermal) hipLaunchKernelGGL((k_bmarch<float, true>), g, t, 0, b.stream, b.head, b.table, round, b.queue, b.slots, ch, rm);
-        else hipLaunchKernelGGL((k_bmarch<float, false>), g, t, 0, b.stream, b.head, b.table, round, b.queue, b.slots, ch, rm);
-    }
-    return hipGetLastError();
-}
-
-hipError_t batch_march_occupancy(int fp64, int thermal, int *blocks_per_cu) {
-    const void *k = fp64 ? (thermal ? reinterpret_cast<const void *>(&k_bmarch<double, true>)
-                                    : reinterpret_cast<const void *>(&k_bmarch<double, false>))
-                         : (thermal ? reinterpret_cast<const void *>(&k_bmarch<float, true>)
-                                    : reinterpret_cast<const void *>(&k_bmarch<float, false>));
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, kMarchBlock, 0);
-}
-
-// ---------------------------------------------------------------------------
 // host-side dispatch over (precision, species, thermal, bin capacity)
 // ---------------------------------------------------------------------------
 template <typename R, int S, bool TH, int MB, int NA, int NB>

@@ -29,6 +29,7 @@
 // visits at most tx + ty + tz - 2 tiles and that many passes empty every list.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <string.h>
 #include <type_traits>
 
 #include "rt_cross.h"
@@ -74,7 +75,62 @@ struct TParams {
     TChunk *ch0, *ch1;
     TCtrl *ctrl;
     StepLedger *ledger;
+    // fused steps of many solves (the kernels' B instances): the solve table,
+    // the round, each fused tile's solve, the first fused packet id of every
+    // solve in this round ([n + 1]), march blocks (ledger slots per solve)
+    const BatchHead *hd;
+    const BatchSolve *tb;
+    const uint16_t *tsolve;
+    const uint32_t *first;
+    int32_t round;
+    uint32_t nblocks;
 };
+
+// Values of the solve a run belongs to: the kernel's own in a single solve,
+// the table entry of the run's solve in a fused step.
+template <typename R>
+struct RunSolve {
+    GridGeom geo;
+    const void *kappa;
+    double *acc;
+    const void *tab;
+    double tau_kill;
+    uint32_t tile0, n_tiles;
+};
+
+template <typename R, bool B>
+__device__ __forceinline__ RunSolve<R> run_solve(const TParams &p, uint32_t sid) {
+    RunSolve<R> r;
+    if constexpr (B) {
+        const BatchSolve &sv = p.tb[sid];
+        r.geo = sv.geo;
+        r.kappa = sv.kappa;
+        r.acc = sv.acc;
+        r.tab = sv.tab;
+        r.tau_kill = sv.tau_kill;
+        r.tile0 = sv.tile0;
+        r.n_tiles = sv.n_tiles;
+    } else {
+        r.geo = p.geo;
+        r.kappa = p.kappa;
+        r.acc = p.acc;
+        r.tab = p.tab;
+        r.tau_kill = p.tau_kill;
+        r.tile0 = 0u;
+        r.n_tiles = p.n_tiles;
+    }
+    return r;
+}
+
+// The solve of fused packet id i: the last solve whose first id is <= i.
+__device__ __forceinline__ uint32_t solve_of_packet(const uint32_t *first, int n, uint32_t i) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    return (uint32_t)lo;
+}
 
 // Record of a packet between passes (16-byte units), holding everything the
 // march needs to resume it without touching the source tables.  The words a
@@ -110,7 +166,8 @@ struct TRec {
     static_assert(UNITS <= 16 && 4 * BACK >= MOV && WHOLE <= STRIDE, "record layout");
 };
 
-// Longest run of a tile's list one block marches (its record ids are staged in LDS).
+// Record ids of a run staged in LDS (the first kMaxRun of the run; a longer
+// run reads the rest of its list from memory).
 constexpr int kMaxRun = 2048;
 
 __device__ __forceinline__ uint32_t pack_cell(int k0, int k1, int k2, uint32_t axis) {
@@ -373,14 +430,148 @@ __global__ void __launch_bounds__(kTBlock) k_temit(const TParams p) {
     block_ledger_add(p.slots + blockIdx.x, v, c);
 }
 
+// Emission of one round of a fused step: packet i of the round belongs to the
+// solve whose range [first[s], first[s+1]) holds it and is that solve's
+// packet g = i - first[s] of its sub-step, drawn exactly as rt_step draws it
+// (equal share among the solve's sources, weight, Philox direction with the
+// solve's key and sub-step counter, SED).  Its fused tile is counted (one
+// atomic per distinct tile of the wavefront) and kept in list 1, free until
+// the first pass, for the scatter.  Emitted photons and packets go to the
+// (solve, block) ledger slot.
+template <typename R, int S, int MB>
+__global__ void __launch_bounds__(kTBlock) k_bemit(const TParams p) {
+    using RL = TRec<R, S, MB>;
+    constexpr int ND = RL::ND;
+    __shared__ uint32_t s_first[kMaxBatch + 1];
+    __shared__ double s_le[kMaxBatch];
+    __shared__ unsigned long long s_lp[kMaxBatch];
+    const int n = p.hd->n;
+    for (int i = threadIdx.x; i <= n; i += kTBlock) s_first[i] = p.first[i];
+    for (int i = threadIdx.x; i < kMaxBatch; i += kTBlock) {
+        s_le[i] = 0.0;
+        s_lp[i] = 0ull;
+    }
+    __syncthreads();
+    const uint32_t total = s_first[n];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
+    const uint32_t gw = (blockIdx.x * kTBlock + threadIdx.x) >> 6;
+    const uint32_t nw = gridDim.x * kTWaves;
+    uint4 *recs = reinterpret_cast<uint4 *>(p.rec);
+    for (uint32_t base = gw * 64u; base < total; base += nw * 64u) {
+        const uint32_t i = base + lane;
+        const bool act = i < total && i < p.capacity;
+        uint32_t tile = 0;
+        // the packet's solve and source, then its direction (the attempts of the
+        // wavefront's packets, of whatever solves, shared out among all lanes)
+        const uint32_t sid = act ? solve_of_packet(s_first, n, i) : 0u;
+        const BatchSolve &sv = p.tb[sid];
+        const uint32_t P = act ? s_first[sid + 1] - s_first[sid] : 1u;
+        const uint32_t g = act ? i - s_first[sid] : 0u;
+        uint32_t ns = 1u, sidx = 0u;
+        if (act) sidx = source_of(g, P / (uint32_t)sv.n_src, P % (uint32_t)sv.n_src, ns);
+        const SourceRec sr = act ? sv.src[sidx] : SourceRec{};
+        const bool oct = (sr.flags & kSrcOctant) != 0u;
+        int32_t c[3];
+        sample_direction_wave<true>(sv.seed, sv.solve_id, g, sv.step0 + (uint64_t)p.round, oct, act, c);
+        if (act) {
+            double ww = sv.src_ndot[sidx] * sv.dt;
+            ww = ww / (double)ns;
+            if (oct) ww = ww * 0.125;
+            atomicAdd(&s_le[sid], ww * sv.src_sedsum[sidx]);
+            atomicAdd(&s_lp[sid], 1ull);
+            const int k0 = sr.o[0] >> 1, k1 = sr.o[1] >> 1, k2 = sr.o[2] >> 1;
+            const uint32_t active = sr.flags >> kSrcMaskShift;
+            R F[MB], D[ND];
+            const R *sed = reinterpret_cast<const R *>(sv.sed) + (size_t)sidx * MB;
+#pragma unroll
+            for (int j = 0; j < MB; ++j) F[j] = sed[j];
+#pragma unroll
+            for (int j = 0; j < ND; ++j) D[j] = (!RL::F64 || ((active >> j) & 1u)) ? R(0) : R(INFINITY);
+            const uint32_t a0 = pack_dir(c[0]), a1 = pack_dir(c[1]), a2 = pack_dir(c[2]);
+            const int64_t qq = (int64_t)c[0] * c[0] + (int64_t)c[1] * c[1] + (int64_t)c[2] * c[2];
+            const double Ld = sqrt((double)qq) * sv.half_dl;
+            const R len = RL::F64 ? (R)Ld : (R)(Ld * 1.0e-18);
+            const uint32_t jw = active ? (uint32_t)__builtin_ctz(active) : 0u;
+            store_record<R, S, MB>(recs + (size_t)i * RL::STRIDE, c[0], c[1], c[2], pack_cell(k0, k1, k2, 3u),
+                                   next_face(k0, sr.o[0], a0), jw, next_face(k1, sr.o[1], a1),
+                                   next_face(k2, sr.o[2], a2), active, ww, len, F, D);
+            tile = sv.tile0 + tile_of_cell(sv.geo, k0, k1, k2);
+            p.idx1[i] = tile;
+        }
+        // rank in the tile's list: one atomic per distinct tile of the wavefront
+        uint64_t pend = __ballot(act);
+        uint32_t rel = 0;
+        while (pend != 0ull) {
+            const int lead = __ffsll((unsigned long long)pend) - 1;
+            const uint32_t lt = (uint32_t)__shfl((int)tile, lead);
+            const uint64_t same = __ballot(act && tile == lt) & pend;
+            uint32_t b = 0;
+            if ((int)lane == lead) b = atomicAdd(p.cnt + lt, (uint32_t)__popcll(same));
+            b = (uint32_t)__shfl((int)b, lead);
+            if ((same >> lane) & 1ull) rel = b + (uint32_t)__popcll(same & lt_mask);
+            pend &= ~same;
+        }
+        if (act) p.side[i] = rel;
+    }
+    __syncthreads();
+    for (int sid = threadIdx.x; sid < n; sid += kTBlock) {
+        if (s_lp[sid] == 0ull) continue;
+        LedgerSlot *slot = p.slots + (size_t)sid * p.nblocks + blockIdx.x;
+        double t, e;
+        two_sum(slot->s[0], s_le[sid], t, e);
+        slot->s[0] = t;
+        slot->s[1] += e;
+        slot->c[1] += s_lp[sid];
+    }
+}
+
+// First fused packet id of every solve in this round (round_packets summed in
+// table order); a round beyond the records is flagged.
+__global__ void k_bfirst(const TParams p) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int n = p.hd->n;
+    uint64_t a = 0;
+    for (int b = 0; b < n; ++b) {
+        const_cast<uint32_t *>(p.first)[b] = (uint32_t)a;
+        a += round_packets(p.tb[b], p.round);
+    }
+    if (a > p.capacity) {
+        p.ctrl->err |= 256u;
+        a = 0;
+        for (int b = 0; b < n; ++b) const_cast<uint32_t *>(p.first)[b] = 0u;
+    }
+    const_cast<uint32_t *>(p.first)[n] = (uint32_t)a;
+}
+
+// Solve of every fused tile (tiles of solve s: [tile0, tile0 + n_tiles)).
+__global__ void k_btiles(const TParams p) {
+    const int n = p.hd->n;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < p.n_tiles; t += gridDim.x * blockDim.x) {
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (p.tb[mid].tile0 <= t) lo = mid; else hi = mid - 1;
+        }
+        const_cast<uint16_t *>(p.tsolve)[t] = (uint16_t)lo;
+    }
+}
+
 // List positions of the emitted packets: offset of the source's tile + rank.
+template <bool B>
 __global__ void __launch_bounds__(kTBlock) k_tscatter_emit(const TParams p) {
     const uint32_t stride = gridDim.x * kTBlock;
-    for (uint32_t i = blockIdx.x * kTBlock + threadIdx.x; i < p.nbatch; i += stride) {
-        uint32_t ns;
-        const uint32_t sidx = source_of(p.g0 + i, p.q, p.r, ns);
-        const SourceRec sr = p.src[sidx];
-        const uint32_t tile = tile_of_cell(p.geo, sr.o[0] >> 1, sr.o[1] >> 1, sr.o[2] >> 1);
+    const uint32_t nb = B ? min(p.first[p.hd->n], p.capacity) : p.nbatch;
+    for (uint32_t i = blockIdx.x * kTBlock + threadIdx.x; i < nb; i += stride) {
+        uint32_t tile;
+        if constexpr (B) {
+            tile = p.idx1[i];
+        } else {
+            uint32_t ns;
+            const uint32_t sidx = source_of(p.g0 + i, p.q, p.r, ns);
+            const SourceRec sr = p.src[sidx];
+            tile = tile_of_cell(p.geo, sr.o[0] >> 1, sr.o[1] >> 1, sr.o[2] >> 1);
+        }
         const uint32_t pos = p.off[tile] + p.side[i];
         if (tile < p.n_tiles && pos < p.capacity) p.idx0[pos] = i;
         else atomicOr(&p.ctrl->err, 1u);
@@ -694,6 +885,9 @@ __global__ void __launch_bounds__(kScanBlock) k_tscan_b(const TParams p, uint32_
     }
 }
 
+// A run's `shared` word: bit 0 the tile has more than one run this pass, bits
+// 1 and up the solve of the tile (fused steps; 0 in a single solve).
+template <bool B>
 __global__ void __launch_bounds__(kScanBlock) k_tscan_c(const TParams p, int nxt) {
     const uint32_t t0 = blockIdx.x * kScanTiles + threadIdx.x * kScanPer;
     uint32_t n[kScanPer];
@@ -723,7 +917,7 @@ __global__ void __launch_bounds__(kScanBlock) k_tscan_c(const TParams p, int nxt
             c.tile = t;
             c.start = a + j * p.cmax;
             c.len = min(p.cmax, n[k] - j * p.cmax);
-            c.shared = nr > 1u ? 1u : 0u;
+            c.shared = (nr > 1u ? 1u : 0u) | (B ? ((uint32_t)p.tsolve[t] << 1) : 0u);
             out[b + j] = c;
         }
         a += n[k];
@@ -735,6 +929,7 @@ __global__ void __launch_bounds__(kScanBlock) k_tscan_c(const TParams p, int nxt
 // Record ids of the packets that moved on, into the next pass's lists.  The
 // run's 27 destination bases (neighbour's list offset + the run's reservation
 // in it) are formed once per run in LDS.
+template <bool B>
 __global__ void __launch_bounds__(kTBlock) k_tscatter(const TParams p, int cur) {
     const uint32_t nch = p.ctrl->n_chunks[cur];
     const TChunk *chs = cur ? p.ch1 : p.ch0;
@@ -746,9 +941,11 @@ __global__ void __launch_bounds__(kTBlock) k_tscatter(const TParams p, int cur) 
         if (ch.start > p.capacity || ch.len > p.capacity - ch.start) continue;   // flagged by the march
         if (threadIdx.x < kCodes) {
             // bases of codes this run did not use are never read
-            const int64_t y = neighbour_tile(p.geo, ch.tile, threadIdx.x, p.periodic != 0u);
-            s_dst[threadIdx.x] = (y >= 0 && y < (int64_t)p.n_tiles)
-                                     ? p.off[y] + p.cbase[(size_t)c * kCodes + threadIdx.x] : 0xffffffffu;
+            const RunSolve<float> rs = run_solve<float, B>(p, ch.shared >> 1);
+            const int64_t y = ch.tile >= rs.tile0
+                ? neighbour_tile(rs.geo, ch.tile - rs.tile0, threadIdx.x, p.periodic != 0u) : -1;
+            s_dst[threadIdx.x] = (y >= 0 && y < (int64_t)rs.n_tiles)
+                                     ? p.off[rs.tile0 + y] + p.cbase[(size_t)c * kCodes + threadIdx.x] : 0xffffffffu;
         }
         __syncthreads();
         for (uint32_t k = threadIdx.x; k < ch.len; k += kTBlock) {
@@ -774,9 +971,17 @@ template <> struct TOcc<float, 1> { static constexpr int value = 4; };
 template <> struct TOcc<float, 8> { static constexpr int value = 4; };
 
 // TR: packets are traced (their cells and fates recorded); the instance
-// without tracing carries no trace state.
-template <typename R, int S, bool TH, int MB, int NA, int NB, bool PER, bool TR>
+// without tracing carries no trace state.  B: a fused step of many solves
+// (each run's solve from the table; ledger per (solve, block) slot).
+// FIN: the finishing pass.  Every packet of the lists is marched to its end
+// (absorbed, escaped or extinguished) across as many tiles as it takes, with
+// the absorbers read from the grid and the deposits added to the grid's
+// accumulators by float64 atomics; a packet that enters another tile keeps
+// its lane (its exhausted bins are dropped there, as at a hand-over).  It
+// replaces the long tail of passes that carry few packets each.
+template <typename R, int S, bool TH, int MB, int NA, int NB, bool PER, bool TR, bool B, bool FIN>
 __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const TParams p, int cur) {
+    static_assert(!(FIN && TR), "the finishing pass does not trace");
     constexpr bool F64 = std::is_same<R, double>::value;
     constexpr uint32_t ACC = (S == 1) ? (TH ? 2u : 1u) : 4u;
     using KV = typename std::conditional<S == 1, R, typename Vec4<R>::T>::type;
@@ -792,15 +997,11 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
     __shared__ uint32_t s_list[kMaxRun];
     __shared__ uint32_t s_next, s_claim;
     __shared__ float s_sigf[3 * MB];          // float32 form: cross-sections, indexed per lane
-    const CTab<R> ctab = (CTab<R>)p.tab;
-    if (!F64 && threadIdx.x < 3 * MB) s_sigf[threadIdx.x] = (float)ctab[threadIdx.x];
-    const typename MarchTab<R, MB>::type tab = MarchTab<R, MB>::make(ctab);
 
     const uint32_t nch = p.ctrl->n_chunks[cur];
     const TChunk *chs = cur ? p.ch1 : p.ch0;
     const uint32_t *list = cur ? p.idx1 : p.idx0;
     uint4 *recs = reinterpret_cast<uint4 *>(p.rec);
-    const KV *kappa = reinterpret_cast<const KV *>(p.kappa);
 
     double l_abs = 0.0, l_esc = 0.0, l_trunc = 0.0;
     uint32_t n_cross = 0, n_esc = 0, n_trunc = 0;
@@ -812,21 +1013,31 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
         const uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_claim);   // block-uniform
         if (c >= nch) break;
         const TChunk ch = chs[c];
-        if (ch.tile >= p.n_tiles || ch.start > p.capacity || ch.len > p.capacity - ch.start
-            || ch.len > (uint32_t)kMaxRun) {
+        const uint32_t sid = ch.shared >> 1;        // the run's solve (fused steps)
+        const RunSolve<R> rs = run_solve<R, B>(p, sid);
+        if (ch.tile >= p.n_tiles || ch.tile < rs.tile0 || ch.tile - rs.tile0 >= rs.n_tiles
+            || ch.start > p.capacity || ch.len > p.capacity - ch.start || ch.len > p.cmax) {
             if (threadIdx.x == 0) atomicOr(&p.ctrl->err, 8u);
             continue;
         }
-        const uint32_t tile = ch.tile;
-        const int tx = (int)(tile % (uint32_t)p.geo.nb[0]);
-        const int ty = (int)((tile / (uint32_t)p.geo.nb[0]) % (uint32_t)p.geo.nb[1]);
-        const int tz = (int)(tile / ((uint32_t)p.geo.nb[0] * (uint32_t)p.geo.nb[1]));
+        const GridGeom geo = rs.geo;
+        const uint32_t tile = ch.tile - rs.tile0;   // the tile within its solve's grid
+        const int tx = (int)(tile % (uint32_t)geo.nb[0]);
+        const int ty = (int)((tile / (uint32_t)geo.nb[0]) % (uint32_t)geo.nb[1]);
+        const int tz = (int)(tile / ((uint32_t)geo.nb[0] * (uint32_t)geo.nb[1]));
+        const double tau_kill = rs.tau_kill;
+        const CTab<R> ctab = (CTab<R>)rs.tab;
+        if (!F64 && threadIdx.x < 3 * MB) s_sigf[threadIdx.x] = (float)ctab[threadIdx.x];
+        const typename MarchTab<R, MB>::type tab = MarchTab<R, MB>::make(ctab);
 
         // stage the tile's absorbers, clear its accumulators
-        const KV *kt = kappa + ((size_t)tile << (3 * kTileLog2));
-        for (int i = threadIdx.x; i < kTileCells; i += kTBlock) s_kap[i] = kt[local_to_morton(i)];
-        for (int i = threadIdx.x; i < kTileCells * (int)ACC; i += kTBlock) s_acc[i] = 0.0;
-        for (uint32_t i = threadIdx.x; i < ch.len; i += kTBlock) s_list[i] = list[ch.start + i];
+        const KV *kg = reinterpret_cast<const KV *>(rs.kappa);
+        if constexpr (!FIN) {
+            const KV *kt = kg + ((size_t)tile << (3 * kTileLog2));
+            for (int i = threadIdx.x; i < kTileCells; i += kTBlock) s_kap[i] = kt[local_to_morton(i)];
+            for (int i = threadIdx.x; i < kTileCells * (int)ACC; i += kTBlock) s_acc[i] = 0.0;
+        }
+        for (uint32_t i = threadIdx.x; i < ch.len && i < (uint32_t)kMaxRun; i += kTBlock) s_list[i] = list[ch.start + i];
         if (threadIdx.x < kCodes) s_cnt[threadIdx.x] = 0u;
         if (threadIdx.x == 0) s_next = 0u;
         __syncthreads();
@@ -846,6 +1057,8 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
         float dropf = 0.0f;                      // float32 form: photons of bins dropped in this segment
         uint32_t loc = 0, count = 0, active = 0;
         uint32_t wbins = 0;                      // wave-uniform: bins some crossing lane may carry
+        int ltx = tx, lty = ty, ltz = tz;        // finishing pass: the tile the lane's packet is in
+        uint32_t gcell = 0;                      // finishing pass: the grid slot of its cell
         DepthTest<R, S, MB> dtest;
         int32_t tix = -1;
         KV kap{};
@@ -869,12 +1082,12 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
             uint32_t st_nesc = 0, st_ntrunc = 0;
             if (trigger && npend != 0u && pend) {
                 bool ex = kill;
-                if constexpr (!F64) ex = kill && dtest.ext.full(tab, active, (float)p.tau_kill, D);
+                if constexpr (!F64) ex = kill && dtest.ext.full(tab, active, (float)tau_kill, D);
                 // (periodic: the cell has been wrapped at the crossing; "out" is
                 // the end of the packet's path)
-                const bool o0 = !PER && (uint32_t)k0 >= (uint32_t)p.geo.n[0];
-                const bool o1 = !PER && (uint32_t)k1 >= (uint32_t)p.geo.n[1];
-                const bool o2 = !PER && (uint32_t)k2 >= (uint32_t)p.geo.n[2];
+                const bool o0 = !PER && (uint32_t)k0 >= (uint32_t)geo.n[0];
+                const bool o1 = !PER && (uint32_t)k1 >= (uint32_t)geo.n[1];
+                const bool o2 = !PER && (uint32_t)k2 >= (uint32_t)geo.n[2];
                 const bool out = PER ? (d0 > p.dmax || d1 > p.dmax || d2 > p.dmax) : (o0 | o1 | o2);
                 int dx = (k0 >> kTileLog2) - tx, dy = (k1 >> kTileLog2) - ty, dz = (k2 >> kTileLog2) - tz;
                 if constexpr (PER) {
@@ -882,12 +1095,13 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                     dy = wrap_step(dy);
                     dz = wrap_step(dz);
                 }
-                const bool leave = !out && (dx | dy | dz) != 0;
+                const bool leave = !FIN && !out && (dx | dy | dz) != 0;
                 const uint32_t fate = ex ? 1u : (out ? 2u : (leave ? 3u : 0u));
                 if constexpr (!F64 && MB > 1) {
                     // float32 form: bins exhausted at the tile boundary leave the packet
                     if (fate == 3u)
-                        dropf += drop_exhausted<S, MB, NA, NB>(tab, active, fmaxf((float)p.tau_kill, kDropDepth), D, F);
+                        dropf += drop_exhausted<S, MB, NA, NB>(tab, active, fmaxf((float)tau_kill, kDropDepth), D, F,
+                                                               wbins);
                 }
                 if (fate != 0u) {                  // fate 0: a new witness bin, the packet marches on
                     const bool traced = TR && tix >= 0;
@@ -916,8 +1130,8 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                         if (traced) {
                             const int face = fate == 1u ? 0
                                 : ((o0 ? 1 : 0) | (o1 ? 2 : 0) | (o2 ? 4 : 0)
-                                   | (k0 >= p.geo.n[0] ? 8 : 0) | (k1 >= p.geo.n[1] ? 16 : 0)
-                                   | (k2 >= p.geo.n[2] ? 32 : 0));
+                                   | (k0 >= geo.n[0] ? 8 : 0) | (k1 >= geo.n[1] ? 16 : 0)
+                                   | (k2 >= geo.n[2] ? 32 : 0));
                             rec[0] = (int32_t)count; rec[1] = (PER && fate == 2u) ? 3 : (int32_t)fate;
                             rec[2] = face; rec[3] = hlast;
                             rec[4] = unpack_dir(a0);
@@ -950,7 +1164,8 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                     const uint32_t rank = (uint32_t)__popcll(dead & lt_mask);
                     if (!alive && rank < got) {
                         pos = ch.start + b0 + rank;
-                        const uint32_t ri = s_list[b0 + rank];
+                        const uint32_t li = b0 + rank;
+                        const uint32_t ri = li < (uint32_t)kMaxRun ? s_list[li] : list[ch.start + li];
                         if (ri >= p.capacity) {
                             atomicOr(&p.ctrl->err, 16u);
                             p.side[pos] = kSideDead;
@@ -992,8 +1207,8 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                             const uint32_t ax = kw >> 30;
                             lax = ax;
                             // a record that is not a packet of this tile is an internal error
-                            const bool bad = k0 >= p.geo.n[0] || k1 >= p.geo.n[1]
-                                || k2 >= p.geo.n[2] || (k0 >> kTileLog2) != tx || (k1 >> kTileLog2) != ty
+                            const bool bad = k0 >= geo.n[0] || k1 >= geo.n[1]
+                                || k2 >= geo.n[2] || (k0 >> kTileLog2) != tx || (k1 >> kTileLog2) != ty
                                 || (k2 >> kTileLog2) != tz || ((uint32_t)(c0 | c1 | c2) == 0u);
                             if (bad) {
                                 atomicOr(&p.ctrl->err, 16u);
@@ -1018,7 +1233,15 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                                 absd = 0.0;
                                 dropf = 0.0f;
                                 loc = local_cell(k0, k1, k2);
-                                kap = s_kap[loc];
+                                if constexpr (FIN) {
+                                    ltx = tx;
+                                    lty = ty;
+                                    ltz = tz;
+                                    gcell = (tile << (3 * kTileLog2)) | local_to_morton(loc);
+                                    kap = kg[gcell];
+                                } else {
+                                    kap = s_kap[loc];
+                                }
                                 alive = true;
                             }
                         }
@@ -1051,7 +1274,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                     l = Lf * (float)diff * __builtin_amdgcn_rcpf((float)den * (float)pden);
                 }
                 int here = 0;                          // natural index, for traces only
-                if constexpr (TR) here = k0 + p.geo.n[0] * (k1 + p.geo.n[1] * k2);
+                if constexpr (TR) here = k0 + geo.n[0] * (k1 + geo.n[1] * k2);
                 if (m0) { k0 += (a0 & kNeg) ? -1 : 1; d0 += 2u; }
                 if (m1) { k1 += (a1 & kNeg) ? -1 : 1; d1 += 2u; }
                 if (m2) { k2 += (a2 & kNeg) ? -1 : 1; d2 += 2u; }
@@ -1060,25 +1283,33 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                 if constexpr (PER) {
                     // Sec. 2, periodic boundaries: back in through the opposite
                     // face; the path ends past dmax half cells along an axis
-                    k0 = wrap_cell(k0, p.geo.n[0]);
-                    k1 = wrap_cell(k1, p.geo.n[1]);
-                    k2 = wrap_cell(k2, p.geo.n[2]);
+                    k0 = wrap_cell(k0, geo.n[0]);
+                    k1 = wrap_cell(k1, geo.n[1]);
+                    k2 = wrap_cell(k2, geo.n[2]);
                     out = d0 > p.dmax || d1 > p.dmax || d2 > p.dmax;
-                    dx = wrap_step((k0 >> kTileLog2) - tx);
-                    dy = wrap_step((k1 >> kTileLog2) - ty);
-                    dz = wrap_step((k2 >> kTileLog2) - tz);
+                    dx = wrap_step((k0 >> kTileLog2) - (FIN ? ltx : tx));
+                    dy = wrap_step((k1 >> kTileLog2) - (FIN ? lty : ty));
+                    dz = wrap_step((k2 >> kTileLog2) - (FIN ? ltz : tz));
                 } else {
-                    out = (uint32_t)k0 >= (uint32_t)p.geo.n[0] || (uint32_t)k1 >= (uint32_t)p.geo.n[1]
-                        || (uint32_t)k2 >= (uint32_t)p.geo.n[2];
-                    dx = (k0 >> kTileLog2) - tx;
-                    dy = (k1 >> kTileLog2) - ty;
-                    dz = (k2 >> kTileLog2) - tz;
+                    out = (uint32_t)k0 >= (uint32_t)geo.n[0] || (uint32_t)k1 >= (uint32_t)geo.n[1]
+                        || (uint32_t)k2 >= (uint32_t)geo.n[2];
+                    dx = (k0 >> kTileLog2) - (FIN ? ltx : tx);
+                    dy = (k1 >> kTileLog2) - (FIN ? lty : ty);
+                    dz = (k2 >> kTileLog2) - (FIN ? ltz : tz);
                 }
                 const bool leave = !out && (dx | dy | dz) != 0;
                 // next cell's absorbers, read before this cell's arithmetic (the
                 // masked index stays inside the tile; unused when the packet leaves)
                 const uint32_t nloc = local_cell(k0, k1, k2);
-                const KV knext = s_kap[nloc];
+                KV knext;
+                uint32_t ngc = gcell;
+                if constexpr (FIN) {
+                    // (a packet that left the grid reads its last cell again)
+                    if (!out) ngc = (tile_of_cell(geo, k0, k1, k2) << (3 * kTileLog2)) | local_to_morton(nloc);
+                    knext = kg[ngc];
+                } else {
+                    knext = s_kap[nloc];
+                }
 
                 R absorbed, e0, e1, e2, hs, tmin;
                 cross_cell<R, S, TH, MB, NA, NB>(l, kap, tab, F, D, absorbed, e0, e1, e2, hs, tmin, wbins);
@@ -1087,15 +1318,28 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                 // (zero deposits are added too: an LDS add is cheaper than the
                 // branch; one plane per accumulated value, so the adds of a
                 // wavefront spread over the banks)
-                double *cell = s_acc + loc;
-                if (S == 1) {
-                    atomicAdd(cell, w * (double)absorbed);
-                    if (TH) atomicAdd(cell + kTileCells, w * ((double)hs * kEvErg));
+                if constexpr (FIN) {
+                    double *g = rs.acc + (size_t)gcell * ACC;
+                    if (S == 1) {
+                        unsafeAtomicAdd(g, w * (double)absorbed);
+                        if (TH) unsafeAtomicAdd(g + 1, w * ((double)hs * kEvErg));
+                    } else {
+                        unsafeAtomicAdd(g, w * (double)e0);
+                        unsafeAtomicAdd(g + 1, w * (double)e1);
+                        unsafeAtomicAdd(g + 2, w * (double)e2);
+                        if (TH) unsafeAtomicAdd(g + 3, w * ((double)hs * kEvErg));
+                    }
                 } else {
-                    atomicAdd(cell, w * (double)e0);
-                    atomicAdd(cell + kTileCells, w * (double)e1);
-                    atomicAdd(cell + 2 * kTileCells, w * (double)e2);
-                    if (TH) atomicAdd(cell + 3 * kTileCells, w * ((double)hs * kEvErg));
+                    double *cell = s_acc + loc;
+                    if (S == 1) {
+                        atomicAdd(cell, w * (double)absorbed);
+                        if (TH) atomicAdd(cell + kTileCells, w * ((double)hs * kEvErg));
+                    } else {
+                        atomicAdd(cell, w * (double)e0);
+                        atomicAdd(cell + kTileCells, w * (double)e1);
+                        atomicAdd(cell + 2 * kTileCells, w * (double)e2);
+                        if (TH) atomicAdd(cell + 3 * kTileCells, w * ((double)hs * kEvErg));
+                    }
                 }
                 absd += (double)absorbed;
                 it_cross = 1;
@@ -1110,19 +1354,36 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                 // the grid, or whose witness depth reached the cut is settled later
                 loc = nloc;
                 kap = knext;
+                if constexpr (FIN) gcell = ngc;
                 lax = (uint32_t)ax;
                 if (F64) sprev = snew; else { pnum = num; pden = den; }
                 if constexpr (TR) hlast = here;
-                if constexpr (F64) kill = tmin >= p.tau_kill;
+                if constexpr (F64) kill = tmin >= tau_kill;
                 else kill = Extinction<S, MB>::depth(dtest.ext.wH, dtest.ext.wHe1, dtest.ext.wHe2, D)
-                            >= (float)p.tau_kill;
-                pend = kill || out || leave;
+                            >= (float)tau_kill;
+                if constexpr (FIN) {
+                    // into the next tile without a hand-over: the bins exhausted at
+                    // the boundary leave the packet there all the same (the order
+                    // against an extinction check at this crossing does not matter:
+                    // only bins past the cut are dropped)
+                    if (leave) {
+                        ltx = k0 >> kTileLog2;
+                        lty = k1 >> kTileLog2;
+                        ltz = k2 >> kTileLog2;
+                        if constexpr (!F64 && MB > 1)
+                            dropf += drop_exhausted<S, MB, NA, NB>(tab, active, fmaxf((float)tau_kill, kDropDepth), D,
+                                                                   F, wbins);
+                    }
+                    pend = kill || out;
+                } else {
+                    pend = kill || out || leave;
+                }
             }
             n_cross += it_cross;
 
             // ---- run used up and few lanes left: park them for the next pass ----
             // (every parked packet has crossed a cell in this pass, so it progresses)
-            if (exhausted && p.park != 0u) {
+            if (!FIN && exhausted && p.park != 0u) {
                 const uint64_t am = __ballot(alive && !pend);
                 if (am != 0ull && (uint32_t)__popcll(am) <= p.park) {
                     double pk_abs = 0.0, pk_drop = 0.0;
@@ -1148,29 +1409,42 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
         __syncthreads();
 
         // ---- the tile's deposits into the grid's accumulators ----
-        double *ga = p.acc + ((size_t)tile << (3 * kTileLog2)) * ACC;
-        for (int i = threadIdx.x; i < kTileCells * (int)ACC; i += kTBlock) {
-            const double v = s_acc[((uint32_t)i % ACC) * kTileCells + (uint32_t)i / ACC];
-            if (v != 0.0) {
-                double *g = ga + local_to_morton((uint32_t)i / ACC) * ACC + (uint32_t)i % ACC;
-                if (ch.shared) unsafeAtomicAdd(g, v);
-                else *g += v;
+        if constexpr (!FIN) {
+            double *ga = rs.acc + ((size_t)tile << (3 * kTileLog2)) * ACC;
+            for (int i = threadIdx.x; i < kTileCells * (int)ACC; i += kTBlock) {
+                const double v = s_acc[((uint32_t)i % ACC) * kTileCells + (uint32_t)i / ACC];
+                if (v != 0.0) {
+                    double *g = ga + local_to_morton((uint32_t)i / ACC) * ACC + (uint32_t)i % ACC;
+                    if (ch.shared & 1u) unsafeAtomicAdd(g, v);
+                    else *g += v;
+                }
             }
         }
         // ---- reserve the run's places in the neighbours' next lists ----
-        if (threadIdx.x < kCodes) {
+        if (!FIN && threadIdx.x < kCodes) {
             const uint32_t n = s_cnt[threadIdx.x];
             if (n != 0u) {
-                const int64_t y = neighbour_tile(p.geo, tile, threadIdx.x, PER);
-                if (y >= 0 && y < (int64_t)p.n_tiles) p.cbase[(size_t)c * kCodes + threadIdx.x] = atomicAdd(p.cnt + y, n);
+                const int64_t y = neighbour_tile(geo, tile, threadIdx.x, PER);
+                if (y >= 0 && y < (int64_t)rs.n_tiles)
+                    p.cbase[(size_t)c * kCodes + threadIdx.x] = atomicAdd(p.cnt + rs.tile0 + y, n);
                 else atomicOr(&p.ctrl->err, 32u);
             }
         }
+        if constexpr (B) {
+            // the run's ledger goes to its solve's slot of this block
+            double v[8] = {0.0, 0.0, l_abs, 0.0, l_esc, 0.0, l_trunc, 0.0};
+            unsigned long long cc[4] = {n_cross, 0ull, n_esc, n_trunc};
+            block_ledger_add(p.slots + (size_t)sid * p.nblocks + blockIdx.x, v, cc);
+            l_abs = l_esc = l_trunc = 0.0;
+            n_cross = n_esc = n_trunc = 0;
+        }
     }
 
-    double v[8] = {0.0, 0.0, l_abs, 0.0, l_esc, 0.0, l_trunc, 0.0};
-    unsigned long long cc[4] = {n_cross, 0ull, n_esc, n_trunc};
-    block_ledger_add(p.slots + blockIdx.x, v, cc);
+    if constexpr (!B) {
+        double v[8] = {0.0, 0.0, l_abs, 0.0, l_esc, 0.0, l_trunc, 0.0};
+        unsigned long long cc[4] = {n_cross, 0ull, n_esc, n_trunc};
+        block_ledger_add(p.slots + blockIdx.x, v, cc);
+    }
 }
 
 __global__ void k_tslots_zero(LedgerSlot *s, int n) {
@@ -1183,16 +1457,34 @@ __global__ void k_tslots_zero(LedgerSlot *s, int n) {
     }
 }
 
+// The ledger slots of the solves of this fused call ([solve][block]).
+__global__ void k_bslots_zero(const TParams p) {
+    const uint32_t n = (uint32_t)p.hd->n * p.nblocks;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        LedgerSlot &s = p.slots[i];
+        for (int k = 0; k < 8; ++k) s.s[k] = 0.0;
+        for (int k = 0; k < 4; ++k) s.c[k] = 0ull;
+    }
+}
+
 __global__ void k_tzero_u32(uint32_t *p, uint32_t n) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
 }
 
-// End of a batch: every list must be empty; errors go to the step ledger.
-__global__ void k_tcheck(TCtrl *ctrl, int cur, StepLedger *l) {
+// End of a batch: every list must be empty (unless a finishing pass marched
+// what was left); errors go to the step ledger
+// (fused steps: to every solve's).
+__global__ void k_tcheck(TCtrl *ctrl, int cur, StepLedger *l, const BatchHead *hd, const BatchSolve *tb) {
     if (threadIdx.x == 0) {
         uint32_t e = ctrl->err;
-        if (ctrl->total[cur] != 0u) e |= 64u;
-        if (e) l->errors |= e;
+        if (cur >= 0 && ctrl->total[cur] != 0u) e |= 64u;      // (cur < 0: a finishing pass ended the lists)
+        if (e) {
+            if (hd) {
+                for (int b = 0; b < hd->n; ++b) tb[b].ledger->errors |= e;
+            } else {
+                l->errors |= e;
+            }
+        }
     }
 }
 
@@ -1248,11 +1540,14 @@ TParams make_params(const TiledLaunch &t) {
     return p;
 }
 
-void scan(const TParams &p, const TiledLaunch &t, int nxt) {
-    hipLaunchKernelGGL(k_tscan_a, dim3(t.scan_blocks), dim3(kScanBlock), 0, t.m.stream, p);
-    hipLaunchKernelGGL(k_tscan_b, dim3(1), dim3(kScanBlock), 0, t.m.stream, p, t.scan_blocks, nxt);
-    hipLaunchKernelGGL(k_tscan_c, dim3(t.scan_blocks), dim3(kScanBlock), 0, t.m.stream, p, nxt);
+template <bool B = false>
+void scan_lists(const TParams &p, uint32_t scan_blocks, hipStream_t st, int nxt) {
+    hipLaunchKernelGGL(k_tscan_a, dim3(scan_blocks), dim3(kScanBlock), 0, st, p);
+    hipLaunchKernelGGL(k_tscan_b, dim3(1), dim3(kScanBlock), 0, st, p, scan_blocks, nxt);
+    hipLaunchKernelGGL(k_tscan_c<B>, dim3(scan_blocks), dim3(kScanBlock), 0, st, p, nxt);
 }
+
+void scan(const TParams &p, const TiledLaunch &t, int nxt) { scan_lists<false>(p, t.scan_blocks, t.m.stream, nxt); }
 
 template <typename R, int S, bool TH, int MB, int NA, int NB>
 void run_passes(const TParams &p, const TiledLaunch &t);
@@ -1264,7 +1559,7 @@ hipError_t run_batch(const TiledLaunch &t) {
     const dim3 grid(t.m.blocks), blk(kTBlock);
     hipLaunchKernelGGL((k_temit<R, S, TH, MB>), grid, blk, 0, st, p);
     scan(p, t, 0);
-    hipLaunchKernelGGL(k_tscatter_emit, dim3(8 * t.m.blocks), blk, 0, st, p);
+    hipLaunchKernelGGL(k_tscatter_emit<false>, dim3(8 * t.m.blocks), blk, 0, st, p);
     run_passes<R, S, TH, MB, NA, NB>(p, t);
     return hipGetLastError();
 }
@@ -1308,17 +1603,30 @@ void run_passes(const TParams &p, const TiledLaunch &t) {
     const dim3 grid(t.m.blocks), blk(kTBlock);
     int cur = 0;
     TParams pp = p;
+    const bool tr = p.trace_n > 0;
+    // the finishing pass (not while tracing): after `finish` tile passes
+    const uint32_t fin = (!tr && t.finish > 0u && t.finish < t.passes) ? t.finish : t.passes;
     for (uint32_t pass = 0; pass < t.passes; ++pass) {
         pp.park = pass < t.park_passes ? t.park_lanes : 0u;
         const bool timed = t.ev && *t.ev_used < t.ev_cap;
         if (timed) (void)hipEventRecord(t.ev[2 * *t.ev_used], st);
-        const bool tr = p.trace_n > 0;
+        if (pass == fin) {
+            pp.park = 0u;
+            if (p.periodic) hipLaunchKernelGGL((k_tmarch<R, S, TH, MB, NA, NB, true, false, false, true>), grid, blk, 0, st, pp, cur);
+            else hipLaunchKernelGGL((k_tmarch<R, S, TH, MB, NA, NB, false, false, false, true>), grid, blk, 0, st, pp, cur);
+            if (timed) {
+                (void)hipEventRecord(t.ev[2 * *t.ev_used + 1], st);
+                ++*t.ev_used;
+            }
+            cur = -1;
+            break;
+        }
         if (p.periodic) {
-            if (tr) hipLaunchKernelGGL((k_tmarch<R, S, TH, MB, NA, NB, true, true>), grid, blk, 0, st, pp, cur);
-            else hipLaunchKernelGGL((k_tmarch<R, S, TH, MB, NA, NB, true, false>), grid, blk, 0, st, pp, cur);
+            if (tr) hipLaunchKernelGGL((k_tmarch<R, S, TH, MB, NA, NB, true, true, false, false>), grid, blk, 0, st, pp, cur);
+            else hipLaunchKernelGGL((k_tmarch<R, S, TH, MB, NA, NB, true, false, false, false>), grid, blk, 0, st, pp, cur);
         } else {
-            if (tr) hipLaunchKernelGGL((k_tmarch<R, S, TH, MB, NA, NB, false, true>), grid, blk, 0, st, pp, cur);
-            else hipLaunchKernelGGL((k_tmarch<R, S, TH, MB, NA, NB, false, false>), grid, blk, 0, st, pp, cur);
+            if (tr) hipLaunchKernelGGL((k_tmarch<R, S, TH, MB, NA, NB, false, true, false, false>), grid, blk, 0, st, pp, cur);
+            else hipLaunchKernelGGL((k_tmarch<R, S, TH, MB, NA, NB, false, false, false, false>), grid, blk, 0, st, pp, cur);
         }
         if (timed) {
             (void)hipEventRecord(t.ev[2 * *t.ev_used + 1], st);
@@ -1327,10 +1635,11 @@ void run_passes(const TParams &p, const TiledLaunch &t) {
         scan(p, t, cur ^ 1);
         // each run's scatter waits on two dependent reads before its copies:
         // many more blocks than the march keep enough runs in flight
-        hipLaunchKernelGGL(k_tscatter, dim3(8 * t.m.blocks), blk, 0, st, p, cur);
+        hipLaunchKernelGGL(k_tscatter<false>, dim3(8 * t.m.blocks), blk, 0, st, p, cur);
         cur ^= 1;
     }
-    hipLaunchKernelGGL(k_tcheck, dim3(1), dim3(64), 0, st, t.ctrl, cur, t.ledger);
+    hipLaunchKernelGGL(k_tcheck, dim3(1), dim3(64), 0, st, t.ctrl, cur, t.ledger, (const BatchHead *)nullptr,
+                       (const BatchSolve *)nullptr);
 }
 
 // Bins of the first NA bins absorbed by hydrogen alone, of the next NB
@@ -1342,7 +1651,7 @@ template <> struct Layout<3, 8> { static constexpr int NA = 3, NB = 2; };
 template <typename R, int S, bool TH, int MB>
 hipError_t occ(int *n) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        n, reinterpret_cast<const void *>(&k_tmarch<R, S, TH, MB, Layout<S, MB>::NA, Layout<S, MB>::NB, false, false>),
+        n, reinterpret_cast<const void *>(&k_tmarch<R, S, TH, MB, Layout<S, MB>::NA, Layout<S, MB>::NB, false, false, false, false>),
         kTBlock, 0);
 }
 
@@ -1385,7 +1694,112 @@ hipError_t dispatch(const TiledLaunch *t, Extra x, int species, int thermal, int
 
 template <typename R, int S, int MB> constexpr size_t rec_bytes() { return 16u * TRec<R, S, MB>::STRIDE; }
 
+// ---------------------------------------------------------------------------
+// Fused steps of many solves: one round (every solve's sub-step `round`) of
+// the tiled march over the concatenation of the solves' tiles.
+// ---------------------------------------------------------------------------
+TParams make_bparams(const BatchLaunch &b, int round) {
+    TParams p;
+    memset(&p, 0, sizeof(p));
+    p.refill_min = (uint32_t)b.refill_min;
+    p.capacity = b.t.capacity;
+    p.cmax = b.t.cmax;
+    p.max_chunks = b.t.max_chunks;
+    p.n_tiles = b.t.max_tiles;
+    p.rec = b.t.rec;
+    p.idx0 = b.t.idx[0];
+    p.idx1 = b.t.idx[1];
+    p.side = b.t.side;
+    p.cnt = b.t.cnt;
+    p.off = b.t.off;
+    p.cbase = b.t.cbase;
+    p.bsum = b.t.bsum;
+    p.ch0 = b.t.chunks[0];
+    p.ch1 = b.t.chunks[1];
+    p.ctrl = b.t.ctrl;
+    p.slots = b.slots;
+    p.hd = b.head;
+    p.tb = b.table;
+    p.tsolve = b.t.tsolve;
+    p.first = b.t.first;
+    p.round = round;
+    p.nblocks = (uint32_t)b.blocks;
+    return p;
+}
+
+template <typename R, int S, bool TH, int MB, int NA, int NB>
+hipError_t run_bround(const BatchLaunch &b, int round) {
+    const TParams p = make_bparams(b, round);
+    const hipStream_t st = b.stream;
+    const dim3 grid(b.blocks), blk(kTBlock);
+    hipLaunchKernelGGL(k_bfirst, dim3(1), dim3(64), 0, st, p);
+    hipLaunchKernelGGL(k_bslots_zero, dim3(256), dim3(256), 0, st, p);
+    hipLaunchKernelGGL((k_bemit<R, S, MB>), grid, blk, 0, st, p);
+    scan_lists<true>(p, b.t.scan_blocks, st, 0);
+    hipLaunchKernelGGL(k_tscatter_emit<true>, dim3(8 * b.blocks), blk, 0, st, p);
+    int cur = 0;
+    const uint32_t fin = (b.finish > 0u && b.finish < b.passes) ? b.finish : b.passes;
+    for (uint32_t pass = 0; pass < b.passes; ++pass) {
+        if (pass == fin) {
+            hipLaunchKernelGGL((k_tmarch<R, S, TH, MB, NA, NB, false, false, true, true>), grid, blk, 0, st, p, cur);
+            cur = -1;
+            break;
+        }
+        hipLaunchKernelGGL((k_tmarch<R, S, TH, MB, NA, NB, false, false, true, false>), grid, blk, 0, st, p, cur);
+        scan_lists<true>(p, b.t.scan_blocks, st, cur ^ 1);
+        hipLaunchKernelGGL(k_tscatter<true>, dim3(8 * b.blocks), blk, 0, st, p, cur);
+        cur ^= 1;
+    }
+    hipLaunchKernelGGL(k_tcheck, dim3(1), dim3(64), 0, st, b.t.ctrl, cur, (StepLedger *)nullptr, b.head, b.table);
+    return hipGetLastError();
+}
+
+template <typename R, int S, bool TH>
+hipError_t bocc(int mb, int *o) {
+    if (mb == 1)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            o, reinterpret_cast<const void *>(&k_tmarch<R, S, TH, 1, 0, 0, false, false, true, false>), kTBlock, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        o, reinterpret_cast<const void *>(&k_tmarch<R, S, TH, 8, Layout<S, 8>::NA, Layout<S, 8>::NB, false, false, true, false>),
+        kTBlock, 0);
+}
+
+template <typename R, int S, bool TH>
+hipError_t bround(const BatchLaunch &b, int round) {
+    if (b.mb == 1) return run_bround<R, S, TH, 1, 0, 0>(b, round);
+    return run_bround<R, S, TH, 8, Layout<S, 8>::NA, Layout<S, 8>::NB>(b, round);
+}
+
 }  // namespace
+
+hipError_t launch_batch_tiles(const BatchLaunch &b) {
+    const TParams p = make_bparams(b, 0);
+    hipLaunchKernelGGL(k_btiles, dim3((b.t.max_tiles + 255) / 256), dim3(256), 0, b.stream, p);
+    hipLaunchKernelGGL(k_tzero_u32, dim3(256), dim3(256), 0, b.stream, b.t.cnt, b.t.max_tiles);
+    hipLaunchKernelGGL(k_tzero_u32, dim3(1), dim3(64), 0, b.stream, reinterpret_cast<uint32_t *>(b.t.ctrl),
+                       (uint32_t)(sizeof(TCtrl) / sizeof(uint32_t)));
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_march(const BatchLaunch &b, int round) {
+    if (b.fp64) {
+        if (b.species == 1) return b.thermal ? bround<double, 1, true>(b, round) : bround<double, 1, false>(b, round);
+        return b.thermal ? bround<double, 3, true>(b, round) : bround<double, 3, false>(b, round);
+    }
+    if (b.species == 1) return b.thermal ? bround<float, 1, true>(b, round) : bround<float, 1, false>(b, round);
+    return b.thermal ? bround<float, 3, true>(b, round) : bround<float, 3, false>(b, round);
+}
+
+hipError_t batch_march_occupancy(int fp64, int species, int thermal, int mb, int *o) {
+    if (fp64) {
+        if (species == 1) return thermal ? bocc<double, 1, true>(mb, o) : bocc<double, 1, false>(mb, o);
+        return thermal ? bocc<double, 3, true>(mb, o) : bocc<double, 3, false>(mb, o);
+    }
+    if (species == 1) return thermal ? bocc<float, 1, true>(mb, o) : bocc<float, 1, false>(mb, o);
+    return thermal ? bocc<float, 3, true>(mb, o) : bocc<float, 3, false>(mb, o);
+}
+
+size_t batch_record_bytes(int fp64, int species, int mb) { return tiled_record_bytes(fp64, species, mb); }
 
 size_t tiled_record_bytes(int fp64, int species, int mb) {
     if (fp64) {

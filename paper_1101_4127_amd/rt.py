@@ -22,10 +22,11 @@ RT_ESCRATCH = -7
 RT_STATIC_WORKSPACE_BYTES = 64 << 20
 RT_ISOTHERMAL, RT_FP64, RT_TIME_MARCH, RT_DIRECT_MARCH, RT_RECOMB, RT_PERIODIC = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
 RT_MAX_PATH_CELLS = 2046
+RT_MAX_FINISH_PASS = 65535
 RT_SRC_CORNER_OCTANT = 0x1
 RT_TRACE_HDR = 8
 RT_FATE_TRUNC, RT_FATE_ESCAPE, RT_FATE_PATH = 1, 2, 3
-RT_MAX_BATCH = 64
+RT_MAX_BATCH = 256
 RT_BATCH_GRAPH = 0x1
 
 FIELDS = ("nh", "x_hi", "x_hii", "x_hei", "x_heii", "x_heiii", "temp", "d_hi", "d_hei", "d_heii", "q",
@@ -46,7 +47,7 @@ class GridDesc(C.Structure):
         ("brick_log2", C.c_int32), ("wave_chunk", C.c_int32), ("refill_min", C.c_int32),
         ("blocks_per_cu", C.c_int32), ("trace_packets", C.c_int32), ("trace_len", C.c_int32),
         ("trace_stride", C.c_int32), ("run_len", C.c_int32), ("park_lanes", C.c_int32),
-        ("inflight", C.c_int64), ("path_cells", C.c_int32),
+        ("inflight", C.c_int64), ("path_cells", C.c_int32), ("finish_pass", C.c_int32),
     ]
 
 
@@ -82,8 +83,8 @@ SIGNATURES = {
     "rt_set_recombination": (_I32, [_VP, _D, _I32, _D, _D, _VP, _VP, _I32]),
     "rt_set_background": (_I32, [_VP, _D, _VP, _I64]),
     "rt_release": (_I32, [_VP]),
-    "rt_batch_workspace_bytes": (_I32, [_I32, C.POINTER(C.c_size_t)]),
-    "rt_batch_init": (_I32, [_I32, _VP, C.c_size_t, _VP, _U32, C.POINTER(_VP)]),
+    "rt_batch_workspace_bytes": (_I32, [_I32, C.POINTER(GridDesc), _I64, _I64, C.POINTER(C.c_size_t)]),
+    "rt_batch_init": (_I32, [_I32, C.POINTER(GridDesc), _I64, _I64, _VP, C.c_size_t, _VP, _U32, C.POINTER(_VP)]),
     "rt_step_many": (_I32, [_VP, C.POINTER(_VP), _I32, C.POINTER(_D), C.POINTER(_I64), C.POINTER(_U64),
                             C.POINTER(StepStats)]),
     "rt_batch_release": (_I32, [_VP]),
@@ -263,15 +264,18 @@ def rt_release(h):
     _check("rt_release", lib().rt_release(h))
 
 
-def rt_batch_workspace_bytes(max_solves: int) -> int:
+def rt_batch_workspace_bytes(max_solves: int, shape: GridDesc, max_round_packets: int, max_tiles: int) -> int:
     out = C.c_size_t(0)
-    _check("rt_batch_workspace_bytes", lib().rt_batch_workspace_bytes(int(max_solves), C.byref(out)))
+    _check("rt_batch_workspace_bytes", lib().rt_batch_workspace_bytes(
+        int(max_solves), C.byref(shape), int(max_round_packets), int(max_tiles), C.byref(out)))
     return int(out.value)
 
 
-def rt_batch_init(max_solves: int, workspace, stream, flags: int = RT_BATCH_GRAPH):
+def rt_batch_init(max_solves: int, shape: GridDesc, max_round_packets: int, max_tiles: int, workspace, stream,
+                  flags: int = RT_BATCH_GRAPH):
     b = C.c_void_p()
-    _check("rt_batch_init", lib().rt_batch_init(int(max_solves), _ptr(workspace),
+    _check("rt_batch_init", lib().rt_batch_init(int(max_solves), C.byref(shape), int(max_round_packets),
+                                                int(max_tiles), _ptr(workspace),
                                                 workspace.numel() * workspace.element_size(),
                                                 _stream_ptr(stream), int(flags), C.byref(b)))
     return b
@@ -302,7 +306,7 @@ def desc_from_workload(work, *, fp64: Optional[bool] = None, brick_log2: int = -
                        refill_min: int = 0, blocks_per_cu: int = 0, trace_packets: int = 0,
                        trace_len: int = 0, trace_stride: int = 1, time_march: bool = False,
                        direct: bool = False, run_len: int = 0, inflight: int = 0,
-                       park_lanes: int = 0) -> GridDesc:
+                       park_lanes: int = 0, finish_pass: int = 0) -> GridDesc:
     d = rt_desc_defaults()
     for a in range(3):
         d.n[a] = int(work.n[a])
@@ -333,6 +337,7 @@ def desc_from_workload(work, *, fp64: Optional[bool] = None, brick_log2: int = -
     d.trace_stride = int(trace_stride)
     d.run_len = int(run_len)
     d.park_lanes = int(park_lanes)
+    d.finish_pass = int(finish_pass)
     d.inflight = int(inflight)
     d.path_cells = int(getattr(work, "path_cells", 0) or 0)
     return d
@@ -406,15 +411,27 @@ class Solve:
             pass
 
 
-class Batch:
-    """Fused steps of up to max_solves solves on their own stream (torch device
-    memory for the workspace); graph=True captures each call shape once."""
+def tiles_of(n) -> int:
+    """Tiles of 8^3 cells of a grid with n cells per axis."""
+    return int(np.prod([-(-int(v) // 8) for v in n]))
 
-    def __init__(self, max_solves: int = RT_MAX_BATCH, *, graph: bool = True, stream=None, device: str = "cuda"):
+
+class Batch:
+    """Fused steps of up to max_solves solves shaped like `shape` (a workload:
+    precision from fp64, species, bins, thermal) on their own stream (torch
+    device memory for the workspace); graph=True captures each call shape
+    once.  max_round_packets: packets of one sub-step of all solves together;
+    max_tiles: 8^3 tiles of all solves together."""
+
+    def __init__(self, max_solves: int, shape, *, fp64: bool, max_round_packets: int, max_tiles: int,
+                 graph: bool = True, stream=None, device: str = "cuda", **tiles):
         import torch
         self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
-        self.workspace = torch.empty(rt_batch_workspace_bytes(max_solves), dtype=torch.uint8, device=device)
-        self.b = rt_batch_init(max_solves, self.workspace, self.stream, RT_BATCH_GRAPH if graph else 0)
+        self.shape = desc_from_workload(shape, fp64=fp64, **tiles)
+        nbytes = rt_batch_workspace_bytes(max_solves, self.shape, max_round_packets, max_tiles)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.b = rt_batch_init(max_solves, self.shape, max_round_packets, max_tiles, self.workspace, self.stream,
+                               RT_BATCH_GRAPH if graph else 0)
 
     def step(self, solves, dt_s=None, packets=None, seeds=None, stats: bool = False):
         """One step of every Solve in solves; per-solve values default to the

@@ -42,9 +42,15 @@ class Served:
 
 
 def workspace_bytes(work, fp64: bool, direct: bool = True) -> int:
-    """Device bytes a request holds while admitted (its workspace)."""
-    d = rt.desc_from_workload(work, fp64=fp64, direct=direct)
+    """Device bytes a request holds while admitted (its workspace; fields in
+    bricks of 8^3, as the fused tiled march reads them)."""
+    d = rt.desc_from_workload(work, fp64=fp64, direct=direct, brick_log2=3 if direct else -1)
     return rt.rt_workspace_bytes(d, max(1, len(work.src_ndot)))
+
+
+def round_packets(work) -> int:
+    """Packets of one sub-step of a request (the most any of its sub-steps has)."""
+    return -(-int(work.packets) // int(work.n_sub))
 
 
 def percentile(values, q: float) -> float:
@@ -56,17 +62,34 @@ def admissible(need: int, used: int, n_active: int, max_slots: int, budget: int)
     return n_active < max_slots and used + need <= budget
 
 
+def fits_batch(packets: int, tiles: int, used_packets: int, used_tiles: int, max_packets: int,
+               max_tiles: int) -> bool:
+    """... and its packets per sub-step and tiles fit what the fused march holds."""
+    return used_packets + packets <= max_packets and used_tiles + tiles <= max_tiles
+
+
 class GpuExecutor:
     """Solves on the current GPU, stepped together by rt_step_many on the
-    batch's stream (their fields and workspaces stay on the device)."""
+    batch's stream (their fields and workspaces stay on the device).  The
+    batch takes its march instance from the first request it opens."""
 
-    def __init__(self, max_slots: int, *, fp64: bool, graph: bool, device: str = "cuda"):
+    def __init__(self, max_slots: int, *, fp64: bool, graph: bool, max_round_packets: int, max_tiles: int,
+                 device: str = "cuda", **tiles):
         self.fp64 = fp64
         self.device = device
-        self.batch = rt.Batch(max_slots, graph=graph, device=device)
+        self.max_slots = max_slots
+        self.graph = graph
+        self.max_round_packets = max_round_packets
+        self.max_tiles = max_tiles
+        self.tiles = tiles
+        self.batch = None
 
     def open(self, work):
-        return rt.Solve(work, fp64=self.fp64, direct=True, stream=self.batch.stream, device=self.device)
+        if self.batch is None:
+            self.batch = rt.Batch(self.max_slots, work, fp64=self.fp64, max_round_packets=self.max_round_packets,
+                                  max_tiles=self.max_tiles, graph=self.graph, device=self.device, **self.tiles)
+        return rt.Solve(work, fp64=self.fp64, direct=True, brick_log2=3, stream=self.batch.stream,
+                        device=self.device)
 
     def step(self, solves):
         return self.batch.step(solves, stats=True)       # synchronises
@@ -78,7 +101,8 @@ class GpuExecutor:
         solve.release()
 
     def release(self):
-        self.batch.release()
+        if self.batch is not None:
+            self.batch.release()
 
 
 class Server:
@@ -88,19 +112,23 @@ class Server:
 
     def __init__(self, *, max_slots: int = rt.RT_MAX_BATCH, hbm_budget: Optional[int] = None,
                  fp64: bool = False, graph: bool = True, keep_fields: bool = True, device: str = "cuda",
-                 executor=None):
+                 executor=None, max_round_packets: int = rt.RT_MAX_BATCH * 100_000,
+                 max_tiles: int = rt.RT_MAX_BATCH * 512, **tiles):
         if not 1 <= max_slots <= rt.RT_MAX_BATCH:
             raise ValueError(f"max_slots must be in 1..{rt.RT_MAX_BATCH}")
         self.max_slots = max_slots
         self.fp64 = fp64
         self.keep_fields = keep_fields
+        self.max_round_packets = int(max_round_packets)
+        self.max_tiles = int(max_tiles)
         if hbm_budget is None:
             import torch
             free, _ = torch.cuda.mem_get_info()
             hbm_budget = free // 2
         self.hbm_budget = int(hbm_budget)
-        self.ex = executor if executor is not None else GpuExecutor(max_slots, fp64=fp64, graph=graph,
-                                                                    device=device)
+        self.ex = executor if executor is not None else GpuExecutor(
+            max_slots, fp64=fp64, graph=graph, max_round_packets=self.max_round_packets, max_tiles=self.max_tiles,
+            device=device, **tiles)
         self.calls = 0
         self.call_solves = []          # solves per fused call
         self.peak_bytes = 0            # most workspace bytes admitted at once
@@ -111,22 +139,31 @@ class Server:
         start of the run when realtime, else all are present at once."""
         pending = collections.deque(sorted(requests, key=lambda r: (r.arrival_s, r.rid)))
         need = {r.rid: workspace_bytes(r.work, self.fp64) for r in pending}
+        pk = {r.rid: round_packets(r.work) for r in pending}
+        tl = {r.rid: rt.tiles_of(r.work.n) for r in pending}
         for r in pending:
             if need[r.rid] > self.hbm_budget:
                 raise ValueError(f"request {r.rid} needs {need[r.rid]} bytes, above the budget")
+            if pk[r.rid] > self.max_round_packets or tl[r.rid] > self.max_tiles:
+                raise ValueError(f"request {r.rid} does not fit the fused march ({pk[r.rid]} packets per "
+                                 f"sub-step, {tl[r.rid]} tiles)")
         active = []                    # [request, solve, admit time, steps done, ledgers]
-        used = 0
+        used = used_pk = used_tl = 0
         out: List[Served] = []
         t0 = clock()
         while pending or active:
             now = clock() - t0
             while pending and (not realtime or pending[0].arrival_s <= now):
                 r = pending[0]
-                if not admissible(need[r.rid], used, len(active), self.max_slots, self.hbm_budget):
+                if not (admissible(need[r.rid], used, len(active), self.max_slots, self.hbm_budget)
+                        and fits_batch(pk[r.rid], tl[r.rid], used_pk, used_tl, self.max_round_packets,
+                                       self.max_tiles)):
                     break
                 pending.popleft()
                 s = self.ex.open(r.work)
                 used += need[r.rid]
+                used_pk += pk[r.rid]
+                used_tl += tl[r.rid]
                 self.peak_bytes = max(self.peak_bytes, used)
                 active.append([r, s, clock() - t0, 0, []])
             if not active:
@@ -149,6 +186,8 @@ class Server:
                 fields = self.ex.fetch(s) if self.keep_fields else None
                 self.ex.close(s)
                 used -= need[r.rid]
+                used_pk -= pk[r.rid]
+                used_tl -= tl[r.rid]
                 led = a[4]
                 res = max(abs(x["emitted"] - (x["absorbed"] + x["escaped"] + x["truncated"])) / x["emitted"]
                           if x["emitted"] > 0 else 0.0 for x in led)

@@ -91,7 +91,7 @@ def test_workspace_bytes_scales_and_validates(L):
                        ("cell_cm", -1.0), ("brick_log2", 4), ("wave_chunk", 100), ("refill_min", 65),
                        ("flags", 0x40), ("flags", rt.RT_RECOMB | rt.RT_DIRECT_MARCH),
                        ("flags", rt.RT_PERIODIC | rt.RT_DIRECT_MARCH), ("path_cells", -1), ("path_cells", 2047), ("trace_stride", -1), ("brick_log2", 2), ("run_len", 10),
-                       ("run_len", 2049), ("park_lanes", -1), ("park_lanes", 65), ("inflight", -1), ("inflight", 1 << 31)):
+                       ("run_len", 65537), ("park_lanes", -1), ("park_lanes", 65), ("inflight", -1), ("inflight", 1 << 31)):
         e = rt.rt_desc_defaults()
         setattr(e, field, bad)
         with pytest.raises(rt.RTError) as ex:
@@ -184,25 +184,48 @@ def test_init_rejects_bad_arguments_before_touching_the_device(L):
 
 def test_batch_arguments_are_checked_before_the_device(L):
     out = C.c_size_t(0)
-    for bad in (0, 65):
-        assert L.rt_batch_workspace_bytes(bad, C.byref(out)) == rt.RT_EINVAL
-    assert L.rt_batch_workspace_bytes(1, None) == rt.RT_EINVAL
-    assert L.rt_batch_workspace_bytes(64, C.byref(out)) == rt.RT_OK
+    shape = rt.rt_desc_defaults()
+    for bad in (0, rt.RT_MAX_BATCH + 1):
+        assert L.rt_batch_workspace_bytes(bad, C.byref(shape), 1000, 8, C.byref(out)) == rt.RT_EINVAL
+    assert L.rt_batch_workspace_bytes(1, C.byref(shape), 1000, 8, None) == rt.RT_EINVAL
+    assert L.rt_batch_workspace_bytes(1, None, 1000, 8, C.byref(out)) == rt.RT_EINVAL
+    assert L.rt_batch_workspace_bytes(1, C.byref(shape), 0, 8, C.byref(out)) == rt.RT_EINVAL
+    assert L.rt_batch_workspace_bytes(1, C.byref(shape), 1000, 0, C.byref(out)) == rt.RT_EINVAL
+    assert L.rt_batch_workspace_bytes(64, C.byref(shape), 1000, 8, C.byref(out)) == rt.RT_OK
     big = out.value
-    assert L.rt_batch_workspace_bytes(1, C.byref(out)) == rt.RT_OK
+    assert L.rt_batch_workspace_bytes(1, C.byref(shape), 1000, 8, C.byref(out)) == rt.RT_OK
     assert 0 < out.value < big
+    # records for the packets of one round, lists for the tiles
+    assert L.rt_batch_workspace_bytes(1, C.byref(shape), 1 << 20, 8, C.byref(out)) == rt.RT_OK
+    more = out.value
+    assert L.rt_batch_workspace_bytes(1, C.byref(shape), 1 << 21, 8, C.byref(out)) == rt.RT_OK
+    per = (out.value - more) / (1 << 20)
+    assert 64 + 12 <= per <= 64 + 12 + 16 * 2       # one-bin float32 record + lists (+ runs)
+    bad_shape = rt.rt_desc_defaults()
+    bad_shape.n_bins = 3
+    assert L.rt_batch_workspace_bytes(1, C.byref(bad_shape), 1000, 8, C.byref(out)) == rt.RT_EINVAL
+    for fin in (-2, rt.RT_MAX_FINISH_PASS + 1):
+        bad_shape = rt.rt_desc_defaults()
+        bad_shape.finish_pass = fin
+        assert L.rt_batch_workspace_bytes(1, C.byref(bad_shape), 1000, 8, C.byref(out)) == rt.RT_EINVAL
+        assert L.rt_workspace_bytes(C.byref(bad_shape), 1, C.byref(out)) == rt.RT_EINVAL
+    for fin in (-1, 0, 1, rt.RT_MAX_FINISH_PASS):
+        ok_shape = rt.rt_desc_defaults()
+        ok_shape.finish_pass = fin
+        assert L.rt_workspace_bytes(C.byref(ok_shape), 1, C.byref(out)) == rt.RT_OK
     b = C.c_void_p()
-    assert L.rt_batch_init(0, 0x1000, 1 << 30, 0x10, 0, C.byref(b)) == rt.RT_EINVAL
-    assert L.rt_batch_init(65, 0x1000, 1 << 30, 0x10, 0, C.byref(b)) == rt.RT_EINVAL
-    assert L.rt_batch_init(4, 0x1000, 1 << 30, None, rt.RT_BATCH_GRAPH, C.byref(b)) == rt.RT_EINVAL
-    assert L.rt_batch_init(4, 0x1000, 1 << 30, 0x10, 0x2, C.byref(b)) == rt.RT_EINVAL
-    assert L.rt_batch_init(4, 0x1001, 1 << 30, 0x10, 0, C.byref(b)) == rt.RT_EINVAL
-    assert L.rt_batch_init(4, None, 1 << 30, 0x10, 0, C.byref(b)) == rt.RT_EINVAL
-    assert L.rt_batch_init(4, 0x1000, 16, 0x10, 0, C.byref(b)) == rt.RT_ENOMEM
-    assert L.rt_batch_init(4, 0x1000, 1 << 30, 0x10, 0, None) == rt.RT_EINVAL
+    s = C.byref(shape)
+    assert L.rt_batch_init(0, s, 1000, 8, 0x1000, 1 << 30, 0x10, 0, C.byref(b)) == rt.RT_EINVAL
+    assert L.rt_batch_init(rt.RT_MAX_BATCH + 1, s, 1000, 8, 0x1000, 1 << 30, 0x10, 0, C.byref(b)) == rt.RT_EINVAL
+    assert L.rt_batch_init(4, s, 1000, 8, 0x1000, 1 << 30, None, rt.RT_BATCH_GRAPH, C.byref(b)) == rt.RT_EINVAL
+    assert L.rt_batch_init(4, s, 1000, 8, 0x1000, 1 << 30, 0x10, 0x2, C.byref(b)) == rt.RT_EINVAL
+    assert L.rt_batch_init(4, s, 1000, 8, 0x1001, 1 << 30, 0x10, 0, C.byref(b)) == rt.RT_EINVAL
+    assert L.rt_batch_init(4, s, 1000, 8, None, 1 << 30, 0x10, 0, C.byref(b)) == rt.RT_EINVAL
+    assert L.rt_batch_init(4, s, 1000, 8, 0x1000, 16, 0x10, 0, C.byref(b)) == rt.RT_ENOMEM
+    assert L.rt_batch_init(4, None, 1000, 8, 0x1000, 1 << 30, 0x10, 0, C.byref(b)) == rt.RT_EINVAL
+    assert L.rt_batch_init(4, s, 1000, 8, 0x1000, 1 << 30, 0x10, 0, None) == rt.RT_EINVAL
     assert L.rt_step_many(None, None, 1, None, None, None, None) == rt.RT_EINVAL
     assert L.rt_batch_release(None) == rt.RT_EINVAL
-
 
 
 def test_ceilings_library_exports_its_header():

@@ -96,7 +96,8 @@ def test_rejections():
     wh = W.stromgren_c1(n=8, packets=1000, n_sub=1)
     wh = wh.with_(background=W.Background(1e48, np.ones(1), 100))
     sh = rt.Solve(wh)
-    b = rt.Batch(2, graph=False)
+    b = rt.Batch(2, wh, fp64=bool(wh.flags & W.FP64_MARCH), max_round_packets=wh.packets,
+                 max_tiles=2 * rt.tiles_of(wh.n), graph=False)
     with pytest.raises(rt.RTError) as ex:
         b.step([sh])
     assert ex.value.status == rt.RT_EINVAL

@@ -39,11 +39,29 @@ def stream(count=8, seed=41, steps=2, n_sub=4, sides=(16, 24, 32), log_packets=(
                             log_packets=log_packets, max_sources=6)
 
 
+# Fused solves keep their fields in bricks of 8^3 cells, as the fused march
+# reads them: every tiled solve does, and so does a per-packet-march solve
+# asked for that brick size.
+TILED = dict()
+BRICK = dict(direct=True, brick_log2=3)
+
+
+def batch_for(works, fp64, graph=True, max_solves=None, **tiles):
+    """A batch sized for these solves: their tiles and one sub-step of
+    packets of them all."""
+    from paper_1101_4127_amd import rt
+    works = list(works)
+    pk = sum(-(-int(w.packets) // int(w.n_sub)) for w in works)
+    nt = sum(rt.tiles_of(w.n) for w in works)
+    return rt.Batch(max_solves or len(works), works[0], fp64=fp64, max_round_packets=max(pk, 1),
+                    max_tiles=nt, graph=graph, **tiles)
+
+
 def alone(reqs, fp64):
     from paper_1101_4127_amd import rt
     out = []
     for r in reqs:
-        s = rt.Solve(r.work, fp64=fp64, direct=True)
+        s = rt.Solve(r.work, fp64=fp64, **TILED)
         led = [s.step() for _ in range(r.work.steps)]
         out.append((s.fetch(), led))
         s.release()
@@ -52,8 +70,8 @@ def alone(reqs, fp64):
 
 def batched(reqs, fp64, graph):
     from paper_1101_4127_amd import rt
-    b = rt.Batch(len(reqs), graph=graph)
-    solves = [rt.Solve(r.work, fp64=fp64, direct=True, stream=b.stream) for r in reqs]
+    b = batch_for([r.work for r in reqs], fp64, graph)
+    solves = [rt.Solve(r.work, fp64=fp64, stream=b.stream, **TILED) for r in reqs]
     leds = [[] for _ in reqs]
     for _ in range(reqs[0].work.steps):
         for i, st in enumerate(b.step(solves, stats=True)):
@@ -104,9 +122,9 @@ def test_graph_replays_match_eager_launches():
     after every call; then the graph again with another set of solves."""
     from paper_1101_4127_amd import rt
     reqs = stream(count=6, seed=43, steps=3)
-    be, bg = rt.Batch(6, graph=False), rt.Batch(6, graph=True)
-    se = [rt.Solve(r.work, fp64=True, direct=True, stream=be.stream) for r in reqs]
-    sg = [rt.Solve(r.work, fp64=True, direct=True, stream=bg.stream) for r in reqs]
+    be, bg = batch_for([r.work for r in reqs], True, False), batch_for([r.work for r in reqs], True, True)
+    se = [rt.Solve(r.work, fp64=True, stream=be.stream, **TILED) for r in reqs]
+    sg = [rt.Solve(r.work, fp64=True, stream=bg.stream, **TILED) for r in reqs]
     for _ in range(3):
         le = be.step(se, stats=True)
         lg = bg.step(sg, stats=True)
@@ -130,12 +148,13 @@ def test_graph_replays_match_eager_launches():
 
 
 def test_fused_step_against_oracle():
-    """Float64 fused steps of three small solves against the oracle run on
-    each alone (multi-step float64 bar: 1e-6 on fractions and deposits)."""
+    """Float64 fused steps of three small solves (per-packet-march solves in
+    bricks of 8^3) against the oracle run on each alone (multi-step float64
+    bar: 1e-6 on fractions and deposits)."""
     from paper_1101_4127_amd import rt
     reqs = stream(count=3, seed=44, steps=2, n_sub=3, sides=(16,), log_packets=(3.3, 3.6))
-    b = rt.Batch(3, graph=True)
-    solves = [rt.Solve(r.work, fp64=True, direct=True, stream=b.stream) for r in reqs]
+    b = batch_for([r.work for r in reqs], True)
+    solves = [rt.Solve(r.work, fp64=True, stream=b.stream, **BRICK) for r in reqs]
     oracles = [O.OracleSolve(r.work) for r in reqs]
     for _ in range(2):
         led = b.step(solves, stats=True)
@@ -155,18 +174,24 @@ def test_fused_step_against_oracle():
 def test_fused_step_rejects_what_it_cannot_fuse():
     from paper_1101_4127_amd import rt
     reqs = stream(count=2, seed=45)
-    b = rt.Batch(2, graph=False)
-    s64 = rt.Solve(reqs[0].work, fp64=True, direct=True, stream=b.stream)
-    s32 = rt.Solve(reqs[1].work, fp64=False, direct=True, stream=b.stream)
-    hhe = rt.Solve(W.small_mixed(n=8, n_src=2, packets=2000), fp64=True, direct=True, stream=b.stream)
+    b = batch_for([r.work for r in reqs] * 2, True, False, max_solves=2)
+    s64 = rt.Solve(reqs[0].work, fp64=True, stream=b.stream, **BRICK)
+    s32 = rt.Solve(reqs[1].work, fp64=False, stream=b.stream, **BRICK)
+    hhe = rt.Solve(W.small_mixed(n=8, n_src=2, packets=2000), fp64=True, stream=b.stream, **BRICK)
     per = rt.Solve(reqs[0].work.with_(periodic=True), fp64=True, stream=b.stream)
-    for bad in ([s64, s32], [s64, s64], [hhe], [s64, s64, s64], [per], [s64, per]):
+    b1 = rt.Solve(reqs[1].work, fp64=True, direct=True, brick_log2=1, stream=b.stream)
+    traced = rt.Solve(reqs[1].work, fp64=True, stream=b.stream, trace_packets=10, trace_len=8, **BRICK)
+    for bad in ([s64, s32], [s64, s64], [hhe], [s64, s64, s64], [per], [s64, per], [b1], [traced]):
         with pytest.raises(rt.RTError) as e:
             b.step(bad)
         assert e.value.status == rt.RT_EINVAL
+    # more packets in one round than the batch holds
+    with pytest.raises(rt.RTError) as e:
+        b.step([s64], packets=[100 * (reqs[0].work.packets + reqs[1].work.packets)])
+    assert e.value.status == rt.RT_ENOMEM
     # nothing was enqueued: the solves still step alone
     assert s64.step()["packets"] == reqs[0].work.packets
-    for s in (s64, s32, hhe, per):
+    for s in (s64, s32, hhe, per, b1, traced):
         s.release()
     b.release()
 
@@ -181,7 +206,7 @@ def test_served_results_equal_results_alone():
     srv.release()
     assert [g.rid for g in got] == [r.rid for r in reqs]
     assert max(srv.call_solves) <= 5 and srv.calls >= 3 * 12 / 5
-    ref, _ = serve.run_alone(reqs, fp64=False)
+    ref, _ = serve.run_alone(reqs, fp64=False, direct=False)
     for g, a, r in zip(got, ref, reqs):
         assert g.steps == r.work.steps and g.packets == a.packets
         assert g.latency_s > 0 and g.admit_s >= 0
@@ -221,9 +246,9 @@ def test_fused_step_single_solve_and_solve_without_sources():
     empty = reqs[1].work.with_(src_ijk=np.zeros((0, 3), np.int32), src_ndot=np.zeros(0), src_sed=np.zeros((0, 1)))
     works = [reqs[0].work, empty]
     for batch in ([0], [0, 1]):
-        b = rt.Batch(2, graph=True)
-        fused = [rt.Solve(works[i], fp64=True, direct=True, stream=b.stream) for i in batch]
-        alone = [rt.Solve(works[i], fp64=True, direct=True) for i in batch]
+        b = batch_for(works, True, True)
+        fused = [rt.Solve(works[i], fp64=True, stream=b.stream, **BRICK) for i in batch]
+        alone = [rt.Solve(works[i], fp64=True, **BRICK) for i in batch]
         for _ in range(2):
             led = b.step(fused, stats=True)
             ref = [s.step() for s in alone]
@@ -236,3 +261,63 @@ def test_fused_step_single_solve_and_solve_without_sources():
             a.release()
             f.release()
         b.release()
+
+
+
+@pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
+def test_fused_hhe_eight_bins_against_alone_and_oracle(fp64):
+    """H+He solves of 8 black-body bins (thermal) fuse too: each fused solve
+    against the same solve alone (float64: 1e-9; float32: its bars) and, in
+    float64, one sub-step against the oracle (1e-9)."""
+    from paper_1101_4127_amd import rt
+    works = [W.small_mixed(n=n, n_src=k, packets=p, fp64=fp64, seed=sd)
+             for n, k, p, sd in ((12, 2, 3000, 31), (20, 4, 6000, 33), (9, 1, 2000, 35))]
+    works = [w.with_(n_sub=1) for w in works]
+    print(f"fused H+He 8 bins, fp64={fp64}", flush=True)
+    b = batch_for(works, fp64)
+    fused = [rt.Solve(w, fp64=fp64, stream=b.stream, **TILED) for w in works]
+    alone = [rt.Solve(w, fp64=fp64, **TILED) for w in works]
+    led = b.step(fused, stats=True)
+    ref = [s.step() for s in alone]
+    for x, y in zip(ref, led):
+        assert x["packets"] == y["packets"] and x["crossings"] == y["crossings"]
+        for k in ("absorbed", "escaped", "truncated"):
+            assert abs(x[k] - y[k]) <= 1e-9 * x["emitted"], k
+    ft, dt = (1e-9, 1e-9) if fp64 else (1e-4, 1e-5)
+    for w, a, f in zip(works, alone, fused):
+        fa, fm = a.fetch(), f.fetch()
+        for k in range(1, 7):
+            assert np.max(PT.frac_err(fm[k], fa[k], 1e-6)) <= ft, k
+        for k in range(7, 11):
+            assert np.max(PT.deposit_err(fm[k], fa[k])) <= dt, k
+        if fp64:
+            o = O.OracleSolve(w)
+            o.step()
+            PT.compare_state(o, fm, w, frac_tol=1e-9, temp_tol=1e-9, dep_tol=1e-9, frac_floor=1e-7)
+        a.release()
+        f.release()
+    b.release()
+
+
+@pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
+def test_fused_finishing_pass(fp64):
+    """Fused steps whose rounds end with a finishing pass after 2 tile passes
+    (serving-shaped solves of sides 16-48, up to 6 tile passes) against the
+    same solves alone without one: same counters, deposits and fractions
+    within the float64 (1e-9) or float32 bars."""
+    from paper_1101_4127_amd import rt
+    reqs = stream(count=5, seed=48, steps=2, n_sub=3, sides=(16, 32, 48))
+    print(f"fused finishing pass, fp64={fp64}", flush=True)
+    a = alone(reqs, fp64)
+    b = batch_for([r.work for r in reqs], fp64, True, finish_pass=2)
+    solves = [rt.Solve(r.work, fp64=fp64, stream=b.stream, **TILED) for r in reqs]
+    leds = [[] for _ in reqs]
+    for _ in range(2):
+        for i, st in enumerate(b.step(solves, stats=True)):
+            leds[i].append(st)
+    m = [(s.fetch(), led) for s, led in zip(solves, leds)]
+    for s in solves:
+        s.release()
+    b.release()
+    for r, x, y in zip(reqs, a, m):
+        assert_same(x, y, fp64, r.work)

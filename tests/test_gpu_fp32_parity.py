@@ -88,8 +88,10 @@ def test_fp32_fused_batch_against_oracle(steps, n_sub, dep_tol):
     from paper_1101_4127_amd import rt
     reqs = serving_requests(4, 51, steps, n_sub)
     print(f"fp32 fused batch, {steps} steps of {n_sub} sub-steps", flush=True)
-    b = rt.Batch(len(reqs), graph=True)
-    solves = [rt.Solve(r.work, fp64=False, direct=True, stream=b.stream) for r in reqs]
+    pk = sum(-(-r.work.packets // r.work.n_sub) for r in reqs)
+    b = rt.Batch(len(reqs), reqs[0].work, fp64=False, max_round_packets=pk,
+                 max_tiles=sum(rt.tiles_of(r.work.n) for r in reqs), graph=True)
+    solves = [rt.Solve(r.work, fp64=False, direct=True, brick_log2=3, stream=b.stream) for r in reqs]
     oracles = [O.OracleSolve(r.work) for r in reqs]
     for _ in range(steps):
         led = b.step(solves, stats=True)

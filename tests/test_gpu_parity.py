@@ -232,7 +232,8 @@ def test_ledger_counts_under_every_schedule(gpu, fp64, n, packets):
     w = ragged_case(n=n, n_src=3, packets=packets, fp64=fp64)
     r = O.OracleSolve(w).step()
     for tiles in (dict(), dict(run_len=64), dict(refill_min=64), dict(inflight=packets // 7 + 1),
-                  dict(run_len=64, refill_min=1, blocks_per_cu=1),
+                  dict(run_len=64, refill_min=1, blocks_per_cu=1), dict(finish_pass=1),
+                  dict(finish_pass=2, run_len=64, refill_min=1),
                   dict(direct=True), dict(direct=True, wave_chunk=64), dict(direct=True, refill_min=64),
                   dict(direct=True, wave_chunk=1024), dict(direct=True, wave_chunk=1024, refill_min=1),
                   dict(direct=True, blocks_per_cu=1)):
@@ -242,6 +243,40 @@ def test_ledger_counts_under_every_schedule(gpu, fp64, n, packets):
         for k in ("crossings", "packets", "n_escaped", "n_truncated"):
             assert st[k] == r[k], (tiles, k, st[k], r[k])
         assert PT.ledger_close(st, r, 1e-12 if fp64 else 1e-5) <= (1e-12 if fp64 else 1e-6), tiles
+
+
+@pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
+def test_finishing_pass_leaves_results_unchanged(gpu, fp64):
+    """A finishing pass after 1, 2 or 5 tile passes (of the 8 this grid needs)
+    marches the same histories: every counter equal to the plain tiled march's
+    and the oracle's, deposits equal up to the order of float64 additions
+    (the float32 form too: its per-packet arithmetic, bins dropped at tile
+    boundaries included, is the same), and in float64 the state against the
+    oracle at 1e-9."""
+    from paper_1101_4127_amd import rt
+    w = ragged_case(fp64=fp64, packets=20000, tau_kill=30.0 if not fp64 else 6.0)
+    o = O.OracleSolve(w)
+    r = o.step()
+    ref = None
+    for fin in (0, 1, 2, 5):
+        print(f"finishing pass after {fin} passes, fp64={fp64}", flush=True)
+        s = rt.Solve(w, fp64=fp64, finish_pass=fin)
+        st = s.step()
+        f = s.fetch()
+        s.release()
+        for k in ("crossings", "packets", "n_escaped", "n_truncated"):
+            assert st[k] == r[k], (fin, k, st[k], r[k])
+        assert PT.ledger_close(st, r, 1e-12 if fp64 else 1e-5) <= (1e-12 if fp64 else 1e-6)
+        if fp64:
+            PT.compare_state(o, f, w, frac_tol=1e-9, temp_tol=1e-9, dep_tol=1e-9)
+        if ref is None:
+            ref = (st, f)
+            continue
+        for k in ("absorbed", "escaped", "truncated"):
+            assert abs(st[k] - ref[0][k]) <= 1e-12 * st["emitted"], k
+        for k in range(7, 11):
+            assert np.max(PT.deposit_err(f[k], ref[1][k])) < 1e-12, k
+        assert np.max(np.abs(f[1:7] - ref[1][1:7]) / np.maximum(np.abs(ref[1][1:7]), 1e-30)) < 1e-6
 
 
 def test_checkpoint_resume(gpu):

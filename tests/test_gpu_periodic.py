@@ -81,7 +81,8 @@ def test_schedules_do_not_change_results():
     w = periodic_case(n=20, packets=3000, path_cells=40)
     from paper_1101_4127_amd import rt
     ref = None
-    for tiles in (dict(), dict(run_len=64, refill_min=4), dict(inflight=700, park_lanes=8)):
+    for tiles in (dict(), dict(run_len=64, refill_min=4), dict(inflight=700, park_lanes=8), dict(finish_pass=1),
+                  dict(finish_pass=4, run_len=64)):
         s = rt.Solve(w, fp64=True, **tiles)
         st = s.step(seed=9)
         f = s.fetch()

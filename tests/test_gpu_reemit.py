@@ -192,7 +192,8 @@ def test_rejections():
     # solve, which they would take without it)
     wh = W.with_recombination(W.stromgren_c1(n=8, packets=1000, n_sub=1), 0.1)
     sh = rt.Solve(wh)
-    b = rt.Batch(2, graph=False)
+    b = rt.Batch(2, wh, fp64=bool(wh.flags & W.FP64_MARCH), max_round_packets=wh.packets,
+                 max_tiles=2 * rt.tiles_of(wh.n), graph=False)
     with pytest.raises(rt.RTError) as ex:
         b.step([sh])
     assert ex.value.status == rt.RT_EINVAL

@@ -385,10 +385,20 @@ int32_t rt_batch_init(int32_t max_solves, const rt_grid_desc *shape, int64_t max
  * (its n_sub sub-steps; the call runs max n_sub fused rounds).  Returns
  * RT_EINVAL (nothing enqueued) if a solve breaks the rules above or a step
  * argument would be rejected by rt_step, RT_ENOMEM if the solves' tiles or one
- * round's packets exceed the batch's.  Stream-ordered; if stats is not NULL
- * (n entries) the call synchronises and fills each solve's ledger. */
+ * round's packets exceed the batch's.  Stream-ordered: the host may go on
+ * (open the next solves, say) while the call runs; a solve's own stream is
+ * ordered after the call when the solve is next used.  If stats is not NULL
+ * (n entries) the call waits for itself and fills each solve's ledger, as
+ * rt_batch_wait does. */
 int32_t rt_step_many(rt_batch_t b, const rt_solve_t *solves, int32_t n, const double *dt_s,
                      const int64_t *n_packets, const uint64_t *seeds, rt_step_stats *stats);
+
+/* Wait for the batch's last rt_step_many call and fill the ledgers of its n
+ * solves (n: the call's solve count; stats[i] for its solves[i]; march_ms and
+ * kernel_ms are 0).  RT_EINVAL if n differs from the call's count; RT_EINTERNAL
+ * if a solve's consistency check failed (that solve is then unusable, as
+ * after rt_read_stats).  The call's solves must not be released before. */
+int32_t rt_batch_wait(rt_batch_t b, int32_t n, rt_step_stats *stats);
 
 /* Synchronise the batch's stream, destroy its graphs and events and free its
  * pinned staging memory (the workspace may then be freed). */

@@ -270,6 +270,10 @@ struct rt_solve {
     double bg_ndot, bg_carried;
     int64_t bg_packets;
     uint32_t bg_active;
+    // end of the last fused call (rt_step_many) the solve was in; its stream
+    // waits for it before its next own work
+    hipEvent_t after;
+    bool after_pending;
 };
 
 namespace {
@@ -379,6 +383,13 @@ rtk::RecombParams recomb_params(rt_solve_t h) {
 // Fill the handle h and load the initial state into the workspace ws (a plan
 // already validated and the arguments checked).  No device memory is
 // allocated; events are created only for RT_TIME_MARCH.
+// Order the solve's stream after the last fused call it was in (if not yet).
+bool order_after_batch(rt_solve *h) {
+    if (!h->after_pending) return true;
+    h->after_pending = false;
+    return hipStreamWaitEvent(h->stream, h->after, 0) == hipSuccess;
+}
+
 int32_t init_solve(rt_solve *h, const rt_grid_desc *d, const Plan &p, char *ws, int64_t max_sources,
                    const void *d_nh, const void *d_x, const void *d_temp, int32_t fields_fp64, void *hip_stream) {
     int dev = 0, cus = 0;
@@ -405,7 +416,7 @@ int32_t init_solve(rt_solve *h, const rt_grid_desc *d, const Plan &p, char *ws, 
     h->step_index = d->step_index0;
     h->blocks = blocks;
     h->chunk = d->wave_chunk > 0 ? d->wave_chunk : 256;
-    h->refill_min = d->refill_min > 0 ? d->refill_min : (p.tiled ? 16 : 8);
+    h->refill_min = d->refill_min > 0 ? d->refill_min : (p.tiled ? 32 : 8);
     h->dead = false;
     h->timed = 0;
     h->ktimed = 0;
@@ -417,12 +428,20 @@ int32_t init_solve(rt_solve *h, const rt_grid_desc *d, const Plan &p, char *ws, 
     h->bg_active = 0u;
     h->ev.clear();
     h->kev.clear();
+    h->after = nullptr;
+    h->after_pending = false;
     auto destroy_events = [h] {
         for (hipEvent_t e : h->ev) if (e) (void)hipEventDestroy(e);
         for (hipEvent_t e : h->kev) if (e) (void)hipEventDestroy(e);
         h->ev.clear();
         h->kev.clear();
+        if (h->after) (void)hipEventDestroy(h->after);
+        h->after = nullptr;
     };
+    if (hipEventCreateWithFlags(&h->after, hipEventDisableTiming) != hipSuccess) {
+        h->after = nullptr;
+        return RT_EDEVICE;
+    }
     if (d->flags & RT_TIME_MARCH) {
         h->ev.assign(2 * kMaxTimedSubsteps, nullptr);
         h->kev.assign(p.tiled ? 2 * kMaxTimedKernels : 0, nullptr);
@@ -545,6 +564,7 @@ int32_t rt_add_sources(rt_solve_t h, int32_t n, const int32_t *h_ijk, const doub
                        const double *h_sed, uint32_t src_flags) {
     if (!valid(h)) return RT_EINVAL;
     if (h->dead) return RT_ESTATE;
+    if (!order_after_batch(h)) return fail(h);
     if (n < 0 || (src_flags & ~RT_SRC_CORNER_OCTANT)) return RT_EINVAL;
     if (n == 0) return RT_OK;
     if (!h_ijk || !h_ndot || !h_sed) return RT_EINVAL;
@@ -596,6 +616,7 @@ int32_t rt_add_sources(rt_solve_t h, int32_t n, const int32_t *h_ijk, const doub
 int32_t rt_read_stats(rt_solve_t h, rt_step_stats *stats) {
     if (!valid(h) || !stats) return RT_EINVAL;
     if (h->dead) return RT_ESTATE;
+    if (!order_after_batch(h)) return fail(h);
     rtk::StepLedger l;
     if (hipMemcpyAsync(&l, h->ws + h->plan.off_ledger, sizeof(l), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
         hipStreamSynchronize(h->stream) != hipSuccess)
@@ -642,6 +663,7 @@ int32_t rt_read_stats(rt_solve_t h, rt_step_stats *stats) {
 int32_t rt_step(rt_solve_t h, double dt_s, int64_t n_packets, uint64_t seed, rt_step_stats *stats) {
     if (!valid(h)) return RT_EINVAL;
     if (h->dead) return RT_ESTATE;
+    if (!order_after_batch(h)) return fail(h);
     if (!(isfinite(dt_s) && dt_s > 0.0) || n_packets < 0) return RT_EINVAL;
     const int32_t nsub = h->d.n_sub;
     const int64_t base = n_packets / nsub, extra = n_packets % nsub;
@@ -749,6 +771,7 @@ int32_t rt_step(rt_solve_t h, double dt_s, int64_t n_packets, uint64_t seed, rt_
 int32_t rt_fetch_fields(rt_solve_t h, uint32_t mask, void *dst, int32_t dst_is_device, int32_t as_fp64) {
     if (!valid(h)) return RT_EINVAL;
     if (h->dead) return RT_ESTATE;
+    if (!order_after_batch(h)) return fail(h);
     if (!dst || mask == 0 || (mask & ~RT_F_ALL) || (as_fp64 != 0 && as_fp64 != 1) ||
         (dst_is_device != 0 && dst_is_device != 1))
         return RT_EINVAL;
@@ -777,6 +800,7 @@ int32_t rt_set_recombination(rt_solve_t h, double f_rec, int32_t n_t, double log
                              const double *h_milne, const void *d_counters, int32_t counters_fp64) {
     if (!valid(h)) return RT_EINVAL;
     if (h->dead) return RT_ESTATE;
+    if (!order_after_batch(h)) return fail(h);
     const Plan &p = h->plan;
     if (!p.recomb) return RT_ESTATE;
     if (!(isfinite(f_rec) && f_rec >= 0.0) || n_t < 2 || n_t > RT_MAX_MILNE_T || !isfinite(log10_t0) ||
@@ -814,6 +838,7 @@ int32_t rt_set_recombination(rt_solve_t h, double f_rec, int32_t n_t, double log
 int32_t rt_set_background(rt_solve_t h, double ndot, const double *h_sed, int64_t packets_per_step) {
     if (!valid(h)) return RT_EINVAL;
     if (h->dead) return RT_ESTATE;
+    if (!order_after_batch(h)) return fail(h);
     const Plan &p = h->plan;
     if (!p.tiled) return RT_ESTATE;
     if (!finite_nonneg(ndot) || packets_per_step < 0) return RT_EINVAL;
@@ -853,6 +878,7 @@ int32_t rt_set_background(rt_solve_t h, double ndot, const double *h_sed, int64_
 int32_t rt_fetch_trace(rt_solve_t h, int32_t *h_dst, int64_t count) {
     if (!valid(h)) return RT_EINVAL;
     if (h->dead) return RT_ESTATE;
+    if (!order_after_batch(h)) return fail(h);
     if (count < 0 || count > h->d.trace_packets || (count > 0 && !h_dst)) return RT_EINVAL;
     const size_t bytes = (size_t)count * (RT_TRACE_HDR + (size_t)h->d.trace_len) * sizeof(int32_t);
     if (bytes == 0) return RT_OK;
@@ -866,6 +892,7 @@ int32_t rt_trace_rays(rt_solve_t h, int32_t m, const int32_t *d_origin, const in
                       int32_t *d_cells, int32_t *d_count, int32_t *d_face) {
     if (!valid(h)) return RT_EINVAL;
     if (h->dead) return RT_ESTATE;
+    if (!order_after_batch(h)) return fail(h);
     if (m < 0 || max_len < 0) return RT_EINVAL;
     if (m == 0) return RT_OK;
     if (!d_origin || !d_dir || !d_count || !d_face || (max_len > 0 && !d_cells)) return RT_EINVAL;
@@ -883,11 +910,13 @@ int32_t rt_get_step_index(rt_solve_t h, uint64_t *out) {
 
 int32_t rt_release(rt_solve_t h) {
     if (!valid(h)) return RT_EINVAL;
-    const bool ok = h->dead || hipStreamSynchronize(h->stream) == hipSuccess;
+    const bool ok = h->dead || (order_after_batch(h) && hipStreamSynchronize(h->stream) == hipSuccess);
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : h->kev) (void)hipEventDestroy(e);
     h->ev.clear();
     h->kev.clear();
+    if (h->after) (void)hipEventDestroy(h->after);
+    h->after = nullptr;
     if (h->is_static) {
         std::lock_guard<std::mutex> lock(g_static_mu);
         h->magic = 0;                     // the device's static storage is free again
@@ -923,7 +952,7 @@ int32_t batch_shape(const rt_grid_desc *d, BatchShape *s) {
     s->species = p.species;
     s->mb = p.mb;
     s->thermal = p.thermal;
-    s->refill_min = d->refill_min > 0 ? d->refill_min : 16;
+    s->refill_min = d->refill_min > 0 ? d->refill_min : 32;
     s->cmax = d->run_len > 0 ? d->run_len : kDefaultRun;
     s->bpcu = d->blocks_per_cu;
     s->finish = d->finish_pass > 0 ? (uint32_t)d->finish_pass : 0u;
@@ -933,7 +962,7 @@ int32_t batch_shape(const rt_grid_desc *d, BatchShape *s) {
 
 struct BatchLayout {
     size_t off_head, off_table, off_slots, off_queue, off_rec, off_idx0, off_idx1, off_side, off_cnt, off_off,
-        off_tsolve, off_cbase, off_bsum, off_ch0, off_ch1, off_ctrl, off_first, total;
+        off_tsolve, off_cbase, off_bsum, off_ch0, off_ch1, off_ctrl, off_first, off_ledgers, total;
     uint32_t capacity, max_tiles, max_chunks, scan_blocks;
 };
 
@@ -953,7 +982,7 @@ int32_t batch_layout(int32_t max_solves, const BatchShape &sh, int64_t max_round
     l->off_head = o;
     l->off_table = o + sizeof(rtk::BatchHead);
     o = align_up(l->off_table + (size_t)max_solves * sizeof(rtk::BatchSolve));
-    l->off_slots = o; o = align_up(o + (size_t)rtk::kMaxBatch * kMaxBatchBlocks * sizeof(rtk::LedgerSlot));
+    l->off_slots = o; o = align_up(o + (size_t)max_solves * kMaxBatchBlocks * sizeof(rtk::LedgerSlot));
     l->off_queue = o; o = align_up(o + sizeof(unsigned long long));
     l->off_rec = o; o = align_up(o + cap * sh.rec_bytes);
     l->off_idx0 = o; o = align_up(o + cap * sizeof(uint32_t));
@@ -968,6 +997,7 @@ int32_t batch_layout(int32_t max_solves, const BatchShape &sh, int64_t max_round
     l->off_ch1 = o; o = align_up(o + mc * sizeof(rtk::TChunk));
     l->off_ctrl = o; o = align_up(o + sizeof(rtk::TCtrl));
     l->off_first = o; o = align_up(o + (rtk::kMaxBatch + 1) * sizeof(uint32_t));
+    l->off_ledgers = o; o = align_up(o + (size_t)max_solves * sizeof(rtk::StepLedger));
     l->total = o;
     return RT_OK;
 }
@@ -993,9 +1023,11 @@ struct rt_batch {
     void *staging;                 // pinned: head then table
     hipEvent_t staged;             // the last table copy has been read
     bool staged_pending;
-    hipEvent_t done;               // end of the last fused call
+    hipEvent_t done;               // end of the last fused call (its ledgers copied out)
     std::vector<hipEvent_t> ev_in; // one per solve slot: its stream's work before the call
     std::vector<BatchGraph> graphs;
+    rtk::StepLedger *ledgers;      // pinned: the solves' ledgers after the last call
+    std::vector<rt_solve_t> last;  // the solves of the last call, in its order
 };
 
 namespace {
@@ -1088,6 +1120,7 @@ void batch_destroy(rt_batch_t b) {
     if (b->staged) (void)hipEventDestroy(b->staged);
     if (b->done) (void)hipEventDestroy(b->done);
     if (b->staging) (void)hipHostFree(b->staging);
+    if (b->ledgers) (void)hipHostFree(b->ledgers);
     b->magic = 0;
     delete b;
 }
@@ -1136,6 +1169,7 @@ int32_t rt_batch_init(int32_t max_solves, const rt_grid_desc *shape, int64_t max
     b->staged = nullptr;
     b->done = nullptr;
     b->staged_pending = false;
+    b->ledgers = nullptr;
     int occ = 0;
     bool ok = hipGetDevice(&b->device) == hipSuccess &&
               hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->device) == hipSuccess;
@@ -1146,6 +1180,8 @@ int32_t rt_batch_init(int32_t max_solves, const rt_grid_desc *shape, int64_t max
     if (b->blocks > kMaxBatchBlocks) b->blocks = kMaxBatchBlocks;
     if (b->blocks < 1) b->blocks = 1;
     ok = ok && hipHostMalloc(&b->staging, sizeof(rtk::BatchHead) + (size_t)max_solves * sizeof(rtk::BatchSolve),
+                             hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipHostMalloc(reinterpret_cast<void **>(&b->ledgers), (size_t)max_solves * sizeof(rtk::StepLedger),
                              hipHostMallocDefault) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&b->done, hipEventDisableTiming) == hipSuccess;
@@ -1270,21 +1306,57 @@ int32_t rt_step_many(rt_batch_t b, const rt_solve_t *solves, int32_t n, const do
     } else if (batch_enqueue(l, rounds) != hipSuccess) {
         return RT_EDEVICE;
     }
-    if (hipEventRecord(b->done, b->stream) != hipSuccess) return RT_EDEVICE;
+    // every solve's ledger, in call order, copied out at once
+    rtk::StepLedger *gathered = reinterpret_cast<rtk::StepLedger *>(b->ws + b->lay.off_ledgers);
+    if (rtk::launch_batch_gather(l, gathered) != hipSuccess ||
+        hipMemcpyAsync(b->ledgers, gathered, (size_t)n * sizeof(rtk::StepLedger), hipMemcpyDeviceToHost,
+                       b->stream) != hipSuccess ||
+        hipEventRecord(b->done, b->stream) != hipSuccess)
+        return RT_EDEVICE;
+    b->last.assign(solves, solves + n);
     for (int i = 0; i < n; ++i) {
         rt_solve_t h = solves[i];
         h->step_index += (uint64_t)h->d.n_sub;
         h->timed = 0;
         h->ktimed = 0;
-        if (h->stream != b->stream && hipStreamWaitEvent(h->stream, b->done, 0) != hipSuccess) return fail(h);
-    }
-    if (stats) {
-        for (int i = 0; i < n; ++i) {
-            const int32_t r = rt_read_stats(solves[i], &stats[i]);
-            if (r != RT_OK) return r;
+        // the solve's own stream is ordered after the call only when it is next used
+        if (h->stream != b->stream) {
+            if (hipEventRecord(h->after, b->stream) != hipSuccess) return fail(h);
+            h->after_pending = true;
         }
     }
-    return RT_OK;
+    return stats ? rt_batch_wait(b, n, stats) : RT_OK;
+}
+
+int32_t rt_batch_wait(rt_batch_t b, int32_t n, rt_step_stats *stats) {
+    if (!batch_valid(b) || !stats || n < 0 || (size_t)n != b->last.size()) return RT_EINVAL;
+    if (hipEventSynchronize(b->done) != hipSuccess) return RT_EDEVICE;
+    int32_t status = RT_OK;
+    for (int i = 0; i < n; ++i) {
+        const rtk::StepLedger &l = b->ledgers[i];
+        rt_step_stats &st = stats[i];
+        memset(&st, 0, sizeof(st));
+        st.emitted = l.s[0] + l.s[1];
+        st.absorbed = l.s[2] + l.s[3];
+        st.escaped = l.s[4] + l.s[5];
+        st.truncated = l.s[6] + l.s[7];
+        st.crossings = (int64_t)l.c[0];
+        st.packets = (int64_t)l.c[1];
+        st.n_escaped = (int64_t)l.c[2];
+        st.n_truncated = (int64_t)l.c[3];
+        st.substeps = (int64_t)l.substeps;
+        st.nonfinite = l.nonfinite;
+        st.errors = l.errors;
+        st.diffuse_emitted = l.d_emit;
+        st.diffuse_packets = (int64_t)l.d_packets;
+        if (l.errors) {
+            // (as rt_read_stats: a failed consistency check ends the solve)
+            rt_solve_t h = b->last[i];
+            if (valid(h)) h->dead = true;
+            status = RT_EINTERNAL;
+        }
+    }
+    return status;
 }
 
 int32_t rt_batch_release(rt_batch_t b) {

@@ -86,48 +86,61 @@ struct TFac {
     double lt;                              // ln T (not formed when EXACT)
 };
 
-template <bool EXACT>
+// HE false (pure hydrogen): the helium factors are not formed (left 0).
+template <bool EXACT, bool HE = true>
 __device__ __forceinline__ TFac tfac(double T) {
     TFac f;
     f.lt = EXACT ? 0.0 : log(T);
     f.damp = 1.0 / (1.0 + sqrt(T * 1.0e-5));
     f.rt = sqrt(T);
     f.e_hi = exp(-157809.1 / T);
-    f.e_hei = exp(-285335.4 / T);
-    f.e_heii = exp(-631515.0 / T);
-    f.p15 = EXACT ? pow(T, -1.5) : exp(-1.5 * f.lt);
-    f.e470 = exp(-470000.0 / T);
-    f.e94 = 1.0 + 0.3 * exp(-94000.0 / T);
+    f.e_hei = f.e_heii = f.p15 = f.e470 = f.e94 = 0.0;
+    if constexpr (HE) {
+        f.e_hei = exp(-285335.4 / T);
+        f.e_heii = exp(-631515.0 / T);
+        f.p15 = EXACT ? pow(T, -1.5) : exp(-1.5 * f.lt);
+        f.e470 = exp(-470000.0 / T);
+        f.e94 = 1.0 + 0.3 * exp(-94000.0 / T);
+    }
     return f;
 }
 
-// Case A with pow (recombination counting, EXACT) or case B from ln T.
-template <bool EXACT>
+// Case A with pow (recombination counting, EXACT) or case B from ln T.  HE
+// false (pure hydrogen): the helium rates are not formed (left 0).
+template <bool EXACT, bool HE = true>
 __device__ Rates rates_at(double T, const TFac &f) {
     constexpr bool case_a = EXACT;
     Rates r;
     const double damp = f.damp;
     const double rt = f.rt;
-    const double diel = 1.9e-3 * f.p15 * f.e470 * f.e94;
+    r.rec_heii = r.rec_heiii = r.col_hei = r.col_heii = 0.0;
+    const double diel = HE ? 1.9e-3 * f.p15 * f.e470 * f.e94 : 0.0;
     if (case_a) {
         r.rec_hii = hydrogenic_casea(T, 157807.0);
-        r.rec_heiii = 2.0 * hydrogenic_casea(T, 631515.0);
-        r.rec_heii = heii_rad_casea(T) + diel;
+        if constexpr (HE) {
+            r.rec_heiii = 2.0 * hydrogenic_casea(T, 631515.0);
+            r.rec_heii = heii_rad_casea(T) + diel;
+        }
     } else {
         // lambda^1.5 / (1 + (lambda / 2.740)^0.407)^2.242 with ln lambda = ln 2 T_ion - ln T
         const double lh = 12.662275226919286 - f.lt, lhe = 14.049024154019651 - f.lt;   // ln 2 x 157807, 631515
         r.rec_hii = 2.753e-14 * exp(1.5 * lh - 2.242 * log1p(exp(0.407 * (lh - 1.007957920399979))));  // ln 2.740
-        r.rec_heiii = 2.0 * (2.753e-14 * exp(1.5 * lhe - 2.242 * log1p(exp(0.407 * (lhe - 1.007957920399979)))));
-        r.rec_heii = 1.26e-14 * exp(0.750 * (13.254566388120152 - f.lt)) + diel;                         // ln 570670
+        if constexpr (HE) {
+            r.rec_heiii = 2.0 * (2.753e-14 * exp(1.5 * lhe - 2.242 * log1p(exp(0.407 * (lhe - 1.007957920399979)))));
+            r.rec_heii = 1.26e-14 * exp(0.750 * (13.254566388120152 - f.lt)) + diel;                     // ln 570670
+        }
     }
     r.col_hi = 5.85e-11 * rt * f.e_hi * damp;
-    r.col_hei = 2.38e-11 * rt * f.e_hei * damp;
-    r.col_heii = 5.68e-12 * rt * f.e_heii * damp;
+    if constexpr (HE) {
+        r.col_hei = 2.38e-11 * rt * f.e_hei * damp;
+        r.col_heii = 5.68e-12 * rt * f.e_heii * damp;
+    }
     return r;
 }
 
-// Cooling [erg cm^-3 s^-1] without the Compton term.
-template <bool EXACT>
+// Cooling [erg cm^-3 s^-1] without the Compton term.  HE false: no helium
+// (its densities are 0, and the terms proportional to them are left out).
+template <bool EXACT, bool HE = true>
 __device__ double cooling_rate(double T, const TFac &f, double ne, double n_hi, double n_hii, double n_hei,
                                double n_heii, double n_heiii) {
     const double damp = f.damp;
@@ -140,6 +153,10 @@ __device__ double cooling_rate(double T, const TFac &f, double ne, double n_hi, 
     const double gaunt = 1.1 + 0.34 * exp(-(5.5 - lg) * (5.5 - lg) / 3.0);
     double per_ne_hi = 7.50e-19 * exp(-118348.0 / T) * damp      // excitation
                      + 1.27e-21 * rt * e_hi * damp;              // ionisation
+    if constexpr (!HE) {
+        // the sum below without its helium terms (their densities are 0)
+        return ne * (per_ne_hi * n_hi + 8.70e-27 * rt * t3 * t6 * n_hii + 1.42e-27 * gaunt * rt * n_hii);
+    }
     double per_ne_heii = 5.54e-17 * (ex ? pow(T, -0.397) : exp(-0.397 * f.lt)) * exp(-473638.0 / T) * damp
                        + 4.95e-22 * rt * e_heii * damp
                        + 1.55e-26 * (ex ? pow(T, 0.3647) : exp(0.3647 * f.lt))                // recombination
@@ -158,6 +175,10 @@ __device__ double cooling_rate(double T, const TFac &f, double ne, double n_hi, 
 // come from the two non-zero eigenvalues of the generator M.
 struct Frac { double hi, hii, hei, heii, heiii; };
 
+// EXACT (recombination counting): the divisions as the formulas write them
+// (the counters' integrals cancel strongly and follow these values to the
+// last bit); else one reciprocal per denominator.
+template <bool EXACT>
 __device__ void evolve(Frac &x, const Frac &x0, const Rates &r, const double gam[3], double ne,
                        double h, bool he) {
     {
@@ -165,7 +186,15 @@ __device__ void evolve(Frac &x, const Frac &x0, const Rates &r, const double gam
         const double lam = ion + rec;
         if (lam > 0.0) {
             const double e = exp(-lam * h);
-            const double eq_hi = rec / lam, eq_hii = ion / lam;
+            double eq_hi, eq_hii;
+            if constexpr (EXACT) {
+                eq_hi = rec / lam;
+                eq_hii = ion / lam;
+            } else {
+                const double il = 1.0 / lam;
+                eq_hi = rec * il;
+                eq_hii = ion * il;
+            }
             x.hi = eq_hi + (x0.hi - eq_hi) * e;
             x.hii = eq_hii + (x0.hii - eq_hii) * e;
         } else {
@@ -195,7 +224,14 @@ __device__ void evolve(Frac &x, const Frac &x0, const Rates &r, const double gam
     }
     const double c0 = ea - c1 * la;
     double q1 = 0.0, q2 = 0.0, q3 = 0.0;
-    if (det > 0.0) { q1 = r2 * r3 / det; q2 = i1 * r3 / det; q3 = i1 * i2 / det; }
+    if (det > 0.0) {
+        if constexpr (EXACT) {
+            q1 = r2 * r3 / det; q2 = i1 * r3 / det; q3 = i1 * i2 / det;
+        } else {
+            const double id = 1.0 / det;
+            q1 = r2 * r3 * id; q2 = i1 * r3 * id; q3 = i1 * i2 * id;
+        }
+    }
     const double m1 = -i1 * x0.hei + r2 * x0.heii;
     const double m2 = i1 * x0.hei - (r2 + i2) * x0.heii + r3 * x0.heiii;
     const double m3 = i2 * x0.heii - r3 * x0.heiii;
@@ -258,18 +294,18 @@ __device__ __forceinline__ void update_slot(const GridGeom &G, R *__restrict__ s
         double n_rec[3] = {0.0, 0.0, 0.0};
         if (count)
             for (int q = 0; q < S; ++q) n_rec[q] = rc[(size_t)q * np + s];
-        TFac tf = tfac<CNT>(T);
-        Rates r = rates_at<CNT>(T, tf);
+        TFac tf = tfac<CNT, he>(T);
+        Rates r = rates_at<CNT, he>(T, tf);
         for (int m = 0; m < n_chem; ++m) {
             if (TH && m > 0) {
-                tf = tfac<CNT>(T);
-                r = rates_at<CNT>(T, tf);
+                tf = tfac<CNT, he>(T);
+                r = rates_at<CNT, he>(T, tf);
             }
             const double ne0 = nh * x.hii + nhe * (x.heii + 2.0 * x.heiii);
             Frac xp, xn;
-            evolve(xp, x, r, gam, ne0, h, he);
+            evolve<CNT>(xp, x, r, gam, ne0, h, he);
             const double ne_bar = 0.5 * (ne0 + (nh * xp.hii + nhe * (xp.heii + 2.0 * xp.heiii)));
-            evolve(xn, x, r, gam, ne_bar, h, he);
+            evolve<CNT>(xn, x, r, gam, ne_bar, h, he);
             if (count) {
                 const double rh = r.rec_hii * ne_bar;
                 n_rec[0] += rh * hii_time(x.hii, xn.hii, gam[0] + r.col_hi * ne_bar, rh, h);
@@ -285,17 +321,31 @@ __device__ __forceinline__ void update_slot(const GridGeom &G, R *__restrict__ s
             // clamp and renormalise each element's fractions
             xn.hi = fmax(xn.hi, 0.0); xn.hii = fmax(xn.hii, 0.0);
             const double sh = xn.hi + xn.hii;
-            if (sh > 0.0) { xn.hi = xn.hi / sh; xn.hii = xn.hii / sh; }
+            if (sh > 0.0) {
+                if constexpr (CNT) {
+                    xn.hi = xn.hi / sh; xn.hii = xn.hii / sh;
+                } else {
+                    const double is = 1.0 / sh;
+                    xn.hi = xn.hi * is; xn.hii = xn.hii * is;
+                }
+            }
             if (he) {
                 xn.hei = fmax(xn.hei, 0.0); xn.heii = fmax(xn.heii, 0.0); xn.heiii = fmax(xn.heiii, 0.0);
                 const double she = (xn.hei + xn.heii) + xn.heiii;
-                if (she > 0.0) { xn.hei = xn.hei / she; xn.heii = xn.heii / she; xn.heiii = xn.heiii / she; }
+                if (she > 0.0) {
+                    if constexpr (CNT) {
+                        xn.hei = xn.hei / she; xn.heii = xn.heii / she; xn.heiii = xn.heiii / she;
+                    } else {
+                        const double is = 1.0 / she;
+                        xn.hei = xn.hei * is; xn.heii = xn.heii * is; xn.heiii = xn.heiii * is;
+                    }
+                }
             }
             if (TH) {
                 const double ntot0 = nh * (1.0 + x.hii) + nhe * (1.0 + x.heii + 2.0 * x.heiii);
                 const double ntot1 = nh * (1.0 + xn.hii) + nhe * (1.0 + xn.heii + 2.0 * xn.heiii);
                 const double ne1 = nh * xn.hii + nhe * (xn.heii + 2.0 * xn.heiii);
-                const double lam = cooling_rate<CNT>(T, tf, ne1, nh * xn.hi, nh * xn.hii, nhe * xn.hei,
+                const double lam = cooling_rate<CNT, he>(T, tf, ne1, nh * xn.hi, nh * xn.hii, nhe * xn.hei,
                                                 nhe * xn.heii, nhe * xn.heiii);
                 const double cne = ccomp * ne1;
                 double tn = (1.5 * kb * ntot0 * T + h * (heat + cne * tcmb))
@@ -622,6 +672,17 @@ hipError_t launch_batch_update(const BatchLaunch &b, int round) {
     }
     return hipGetLastError();
 }
+// Each solve's step ledger into out[solve] (table order), for one copy to the host.
+__global__ void k_bgather(const BatchHead *hd, const BatchSolve *tb, StepLedger *out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < hd->n) out[b] = *tb[b].ledger;
+}
+
+hipError_t launch_batch_gather(const BatchLaunch &b, StepLedger *out) {
+    hipLaunchKernelGGL(k_bgather, dim3(kMaxBatch / 64), dim3(64), 0, b.stream, b.head, b.table, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_prep(const CellLaunch &c) {
     const int nb = cell_blocks(c.geo.ncell_pad);
     if (c.fp64) {

@@ -254,6 +254,7 @@ hipError_t launch_batch_prep(const BatchLaunch &b, int round);
 hipError_t launch_batch_march(const BatchLaunch &b, int round);
 hipError_t launch_batch_ledger(const BatchLaunch &b, int round);
 hipError_t launch_batch_update(const BatchLaunch &b, int round);
+hipError_t launch_batch_gather(const BatchLaunch &b, StepLedger *out);   // every solve's ledger, table order
 hipError_t batch_march_occupancy(int fp64, int species, int thermal, int mb, int *blocks_per_cu);
 size_t batch_record_bytes(int fp64, int species, int mb);
 

@@ -527,21 +527,35 @@ __global__ void __launch_bounds__(kTBlock) k_bemit(const TParams p) {
 }
 
 // First fused packet id of every solve in this round (round_packets summed in
-// table order); a round beyond the records is flagged.
-__global__ void k_bfirst(const TParams p) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// table order; one block of kMaxBatch threads, one solve each); a round beyond
+// the records is flagged.
+__global__ void __launch_bounds__(kMaxBatch) k_bfirst(const TParams p) {
+    __shared__ unsigned long long s_w[kMaxBatch / 64];
     const int n = p.hd->n;
-    uint64_t a = 0;
-    for (int b = 0; b < n; ++b) {
-        const_cast<uint32_t *>(p.first)[b] = (uint32_t)a;
-        a += round_packets(p.tb[b], p.round);
+    const int b = threadIdx.x;
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const unsigned long long mine = b < n ? round_packets(p.tb[b], p.round) : 0ull;
+    unsigned long long v = mine;                  // inclusive scan over the wavefront
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const unsigned long long u = (unsigned long long)__shfl_up((long long)v, d);
+        if (lane >= (uint32_t)d) v += u;
     }
-    if (a > p.capacity) {
-        p.ctrl->err |= 256u;
-        a = 0;
-        for (int b = 0; b < n; ++b) const_cast<uint32_t *>(p.first)[b] = 0u;
+    if (lane == 63u) s_w[wv] = v;
+    __syncthreads();
+    unsigned long long before = 0ull, total = 0ull;
+    for (uint32_t u = 0; u < (uint32_t)(kMaxBatch / 64); ++u) {
+        if (u < wv) before += s_w[u];
+        total += s_w[u];
     }
-    const_cast<uint32_t *>(p.first)[n] = (uint32_t)a;
+    const unsigned long long excl = before + v - mine;
+    const bool over = total > p.capacity;
+    uint32_t *first = const_cast<uint32_t *>(p.first);
+    if (b < n) first[b] = over ? 0u : (uint32_t)excl;
+    if (b == 0) {
+        first[n] = over ? 0u : (uint32_t)total;
+        if (over) p.ctrl->err |= 256u;
+    }
 }
 
 // Solve of every fused tile (tiles of solve s: [tile0, tile0 + n_tiles)).
@@ -1732,7 +1746,7 @@ hipError_t run_bround(const BatchLaunch &b, int round) {
     const TParams p = make_bparams(b, round);
     const hipStream_t st = b.stream;
     const dim3 grid(b.blocks), blk(kTBlock);
-    hipLaunchKernelGGL(k_bfirst, dim3(1), dim3(64), 0, st, p);
+    hipLaunchKernelGGL(k_bfirst, dim3(1), dim3(kMaxBatch), 0, st, p);
     hipLaunchKernelGGL(k_bslots_zero, dim3(256), dim3(256), 0, st, p);
     hipLaunchKernelGGL((k_bemit<R, S, MB>), grid, blk, 0, st, p);
     scan_lists<true>(p, b.t.scan_blocks, st, 0);

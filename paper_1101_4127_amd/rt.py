@@ -7,6 +7,7 @@ the library raises if it has not been built.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 from typing import Optional
@@ -87,6 +88,7 @@ SIGNATURES = {
     "rt_batch_init": (_I32, [_I32, C.POINTER(GridDesc), _I64, _I64, _VP, C.c_size_t, _VP, _U32, C.POINTER(_VP)]),
     "rt_step_many": (_I32, [_VP, C.POINTER(_VP), _I32, C.POINTER(_D), C.POINTER(_I64), C.POINTER(_U64),
                             C.POINTER(StepStats)]),
+    "rt_batch_wait": (_I32, [_VP, _I32, C.POINTER(StepStats)]),
     "rt_batch_release": (_I32, [_VP]),
     "rt_strerror": (C.c_char_p, [_I32]),
 }
@@ -294,6 +296,13 @@ def rt_step_many(b, handles, dt_s, n_packets, seeds, stats: bool = False):
     return [x.as_dict() for x in st] if stats else None
 
 
+def rt_batch_wait(b, n: int):
+    """Ledger dicts of the n solves of the batch's last fused call (waits for it)."""
+    st = (StepStats * n)()
+    _check("rt_batch_wait", lib().rt_batch_wait(b, int(n), st))
+    return [x.as_dict() for x in st]
+
+
 def rt_batch_release(b):
     _check("rt_batch_release", lib().rt_batch_release(b))
 
@@ -361,9 +370,11 @@ class Solve:
         nbytes = rt_workspace_bytes(self.desc, len(work.src_ndot))
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
         dt = torch.float64 if self.fp64 else torch.float32
-        nh = torch.as_tensor(np.asarray(work.n_h), dtype=dt, device=device).contiguous()
-        x = torch.as_tensor(np.asarray(work.x).reshape(5, -1), dtype=dt, device=device).contiguous()
-        t = torch.as_tensor(np.asarray(work.temp), dtype=dt, device=device).contiguous()
+        # the inputs go up on the solve's stream, which the import then follows
+        with torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext():
+            nh = torch.as_tensor(np.asarray(work.n_h), dtype=dt, device=device).contiguous()
+            x = torch.as_tensor(np.asarray(work.x).reshape(5, -1), dtype=dt, device=device).contiguous()
+            t = torch.as_tensor(np.asarray(work.temp), dtype=dt, device=device).contiguous()
         self.h = rt_init_grid(self.desc, self.workspace, len(work.src_ndot), nh, x, t, stream)
         if len(work.src_ndot):
             rt_add_sources(self.h, work.src_ijk, work.src_ndot, work.src_sed, work.src_flags)
@@ -432,6 +443,7 @@ class Batch:
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.b = rt_batch_init(max_solves, self.shape, max_round_packets, max_tiles, self.workspace, self.stream,
                                RT_BATCH_GRAPH if graph else 0)
+        self.last_n = 0
 
     def step(self, solves, dt_s=None, packets=None, seeds=None, stats: bool = False):
         """One step of every Solve in solves; per-solve values default to the
@@ -439,7 +451,15 @@ class Batch:
         dt_s = [s.work.dt_s for s in solves] if dt_s is None else dt_s
         packets = [s.work.packets for s in solves] if packets is None else packets
         seeds = [s.work.seed for s in solves] if seeds is None else seeds
+        self.last_n = len(solves)
         return rt_step_many(self.b, [s.h for s in solves], dt_s, packets, seeds, stats)
+
+    def launch(self, solves, dt_s=None, packets=None, seeds=None):
+        """step() without waiting; wait() then returns the ledgers."""
+        self.step(solves, dt_s, packets, seeds, stats=False)
+
+    def wait(self):
+        return rt_batch_wait(self.b, self.last_n)
 
     def synchronize(self):
         self.stream.synchronize()

@@ -6,7 +6,11 @@ admitted solve keeps its fields and workspace on the device until it has run
 all its steps.  Each fused call (rt_step_many) advances every admitted solve
 by one step; requests that arrive meanwhile join at the next call, and a
 solve that has finished leaves its slot and memory to the next request.
-Latency is completion minus arrival.
+While a call runs on the GPU, the host opens (uploads) the requests that are
+next in line, for as long as the call runs, up to a batch's worth and within
+the memory budget, so that they join a later call without waiting for their
+upload.  Latency is
+completion minus arrival.
 
 Host-side scheduling only: every step of every solve runs in the library's
 kernels.  The baseline is the same requests run one at a time through rt_step.
@@ -71,7 +75,9 @@ def fits_batch(packets: int, tiles: int, used_packets: int, used_tiles: int, max
 class GpuExecutor:
     """Solves on the current GPU, stepped together by rt_step_many on the
     batch's stream (their fields and workspaces stay on the device).  The
-    batch takes its march instance from the first request it opens."""
+    batch takes its march instance from the first request it opens.  Solves
+    are opened on a stream of their own, so that an upload runs beside a
+    fused call instead of after it."""
 
     def __init__(self, max_slots: int, *, fp64: bool, graph: bool, max_round_packets: int, max_tiles: int,
                  device: str = "cuda", **tiles):
@@ -83,16 +89,32 @@ class GpuExecutor:
         self.max_tiles = max_tiles
         self.tiles = tiles
         self.batch = None
+        self.open_stream = None
 
     def open(self, work):
         if self.batch is None:
+            import torch
             self.batch = rt.Batch(self.max_slots, work, fp64=self.fp64, max_round_packets=self.max_round_packets,
                                   max_tiles=self.max_tiles, graph=self.graph, device=self.device, **self.tiles)
-        return rt.Solve(work, fp64=self.fp64, direct=True, brick_log2=3, stream=self.batch.stream,
+            self.open_stream = torch.cuda.Stream(device=self.device)
+        return rt.Solve(work, fp64=self.fp64, direct=True, brick_log2=3, stream=self.open_stream,
                         device=self.device)
 
     def step(self, solves):
         return self.batch.step(solves, stats=True)       # synchronises
+
+    def launch(self, solves):
+        import torch
+        self.batch.launch(solves)                        # returns at once
+        self.launched = torch.cuda.Event()
+        self.launched.record(self.batch.stream)
+
+    def busy(self) -> bool:
+        """The last launched call is still running."""
+        return not self.launched.query()
+
+    def wait(self):
+        return self.batch.wait()
 
     def fetch(self, solve):
         return solve.fetch()
@@ -148,20 +170,27 @@ class Server:
                 raise ValueError(f"request {r.rid} does not fit the fused march ({pk[r.rid]} packets per "
                                  f"sub-step, {tl[r.rid]} tiles)")
         active = []                    # [request, solve, admit time, steps done, ledgers]
-        used = used_pk = used_tl = 0
+        opened = {}                    # rid -> solve opened ahead of admission (memory held, no slot)
+        used = used_pk = used_tl = 0   # used: bytes of admitted and opened-ahead solves
         out: List[Served] = []
+        overlap = hasattr(self.ex, "launch")
         t0 = clock()
         while pending or active:
             now = clock() - t0
             while pending and (not realtime or pending[0].arrival_s <= now):
                 r = pending[0]
-                if not (admissible(need[r.rid], used, len(active), self.max_slots, self.hbm_budget)
+                ahead = r.rid in opened
+                if not (admissible(0 if ahead else need[r.rid], used, len(active), self.max_slots,
+                                   self.hbm_budget)
                         and fits_batch(pk[r.rid], tl[r.rid], used_pk, used_tl, self.max_round_packets,
                                        self.max_tiles)):
                     break
                 pending.popleft()
-                s = self.ex.open(r.work)
-                used += need[r.rid]
+                if ahead:
+                    s = opened.pop(r.rid)
+                else:
+                    s = self.ex.open(r.work)
+                    used += need[r.rid]
                 used_pk += pk[r.rid]
                 used_tl += tl[r.rid]
                 self.peak_bytes = max(self.peak_bytes, used)
@@ -171,7 +200,23 @@ class Server:
                 if wait > 0:
                     time.sleep(min(wait, 0.05))
                 continue
-            ledgers = self.ex.step([a[1] for a in active])
+            if overlap:
+                self.ex.launch([a[1] for a in active])
+                # the next requests in line go up while the call runs
+                now = clock() - t0
+                for r in pending:
+                    if not self.ex.busy() or len(opened) >= self.max_slots or (realtime and r.arrival_s > now):
+                        break
+                    if r.rid in opened:
+                        continue
+                    if used + need[r.rid] > self.hbm_budget:
+                        break
+                    opened[r.rid] = self.ex.open(r.work)
+                    used += need[r.rid]
+                    self.peak_bytes = max(self.peak_bytes, used)
+                ledgers = self.ex.wait()
+            else:
+                ledgers = self.ex.step([a[1] for a in active])
             self.calls += 1
             self.call_solves.append(len(active))
             done_t = clock() - t0

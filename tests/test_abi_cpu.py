@@ -225,6 +225,7 @@ def test_batch_arguments_are_checked_before_the_device(L):
     assert L.rt_batch_init(4, None, 1000, 8, 0x1000, 1 << 30, 0x10, 0, C.byref(b)) == rt.RT_EINVAL
     assert L.rt_batch_init(4, s, 1000, 8, 0x1000, 1 << 30, 0x10, 0, None) == rt.RT_EINVAL
     assert L.rt_step_many(None, None, 1, None, None, None, None) == rt.RT_EINVAL
+    assert L.rt_batch_wait(None, 0, None) == rt.RT_EINVAL
     assert L.rt_batch_release(None) == rt.RT_EINVAL
 
 

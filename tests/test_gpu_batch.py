@@ -321,3 +321,40 @@ def test_fused_finishing_pass(fp64):
     b.release()
     for r, x, y in zip(reqs, a, m):
         assert_same(x, y, fp64, r.work)
+
+
+def test_launch_then_wait_and_ordering_of_the_solves_streams():
+    """A fused call that returns at once: the solves' fields fetched before
+    the wait (their own streams, opened on another stream than the batch's,
+    are ordered after the call when next used) and the ledgers from
+    rt_batch_wait equal those of the same call made synchronously; a wait
+    for another solve count is refused."""
+    import torch
+    from paper_1101_4127_amd import rt
+    reqs = stream(count=4, seed=49, steps=2, n_sub=3)
+    side = torch.cuda.Stream()
+    ref_b = batch_for([r.work for r in reqs], True, True)
+    ref = [rt.Solve(r.work, fp64=True, stream=ref_b.stream, **TILED) for r in reqs]
+    b = batch_for([r.work for r in reqs], True, True)
+    sv = [rt.Solve(r.work, fp64=True, stream=side, **TILED) for r in reqs]
+    for _ in range(2):
+        lr = ref_b.step(ref, stats=True)
+        b.launch(sv)
+        fields = [s.fetch() for s in sv]           # before the wait
+        with pytest.raises(rt.RTError) as e:
+            rt.rt_batch_wait(b.b, len(sv) - 1)
+        assert e.value.status == rt.RT_EINVAL
+        lw = b.wait()
+        for x, y in zip(lr, lw):
+            assert x["packets"] == y["packets"] and x["crossings"] == y["crossings"]
+            assert x["substeps"] == y["substeps"]
+            for k in ("emitted", "absorbed", "escaped", "truncated"):
+                assert abs(x[k] - y[k]) <= 1e-12 * x["emitted"], k
+        for s, f in zip(ref, fields):
+            fr = s.fetch()
+            assert np.max(PT.frac_err(f[1], fr[1], 1e-6)) <= 1e-9
+            assert np.max(PT.deposit_err(f[7], fr[7])) <= 1e-9
+    for s in ref + sv:
+        s.release()
+    ref_b.release()
+    b.release()

@@ -72,6 +72,32 @@ class FakeExecutor:
         pass
 
 
+class FakeAsyncExecutor(FakeExecutor):
+    """As FakeExecutor, with the call split into launch and wait (the server
+    then opens the next requests while a call runs)."""
+
+    def __init__(self, clock):
+        super().__init__(clock)
+        self.pending = None
+        self.opened_during_call = 0
+
+    def open(self, work):
+        if self.pending is not None:
+            self.opened_during_call += 1
+        return super().open(work)
+
+    def launch(self, solves):
+        assert self.pending is None
+        self.pending = solves
+
+    def busy(self):
+        return True
+
+    def wait(self):
+        solves, self.pending = self.pending, None
+        return self.step(solves)
+
+
 class FakeClock:
     def __init__(self):
         self.t = 0.0
@@ -81,16 +107,19 @@ class FakeClock:
         return self.t
 
 
+@pytest.mark.parametrize("overlap", [False, True], ids=["sync", "open-during-call"])
 @pytest.mark.parametrize("slots,budget_solves", [(4, 100), (8, 3), (64, 1000)])
-def test_continuous_batching_loop(slots, budget_solves, monkeypatch):
+def test_continuous_batching_loop(slots, budget_solves, overlap, monkeypatch):
     reqs = W.serving_stream(count=30, seed=6, sides=(16, 24), log_packets=(4.0, 4.5), rate_per_s=500.0)
     need = {r.rid: serve.workspace_bytes(r.work, fp64=False) for r in reqs}
     budget = int(budget_solves * max(need.values()))
     clock = FakeClock()
     monkeypatch.setattr(serve.time, "sleep", lambda s: setattr(clock, "t", clock.t + s))
-    ex = FakeExecutor(clock)
+    ex = FakeAsyncExecutor(clock) if overlap else FakeExecutor(clock)
     srv = serve.Server(max_slots=slots, hbm_budget=budget, executor=ex, keep_fields=False)
     out = srv.run(reqs, clock=clock)
+    if overlap and slots == 4:
+        assert ex.opened_during_call > 0                    # requests in line went up during calls
     assert [o.rid for o in out] == [r.rid for r in reqs]
     assert not ex.open_now                                  # every solve closed
     steps = {}
@@ -126,3 +155,24 @@ def test_percentiles():
     v = list(range(1, 101))
     assert serve.percentile(v, 50) == pytest.approx(50.5, abs=0)
     assert serve.percentile(v, 99) == pytest.approx(99.01, abs=0)
+
+
+def test_opened_ahead_requests_are_admitted_in_order(monkeypatch):
+    """All present, two slots, room for every workspace: the requests opened
+    during a call are the next ones in arrival order, and each is admitted
+    (and closed) exactly once."""
+    reqs = W.serving_stream(count=9, seed=8, sides=(16,), log_packets=(4.0, 4.2), rate_per_s=500.0)
+    clock = FakeClock()
+    monkeypatch.setattr(serve.time, "sleep", lambda s: setattr(clock, "t", clock.t + s))
+    ex = FakeAsyncExecutor(clock)
+    srv = serve.Server(max_slots=2, hbm_budget=1 << 40, executor=ex, keep_fields=False)
+    out = srv.run(reqs, realtime=False, clock=clock)
+    assert [o.rid for o in out] == [r.rid for r in reqs]
+    assert not ex.open_now and ex.opened_during_call >= 2
+    seen = []
+    for call in ex.calls:
+        for sid in call:
+            if sid not in seen:
+                seen.append(sid)
+    assert seen == [r.work.solve_id for r in reqs]
+    assert srv.peak_bytes <= 4 * max(serve.workspace_bytes(r.work, fp64=False) for r in reqs)

@@ -32,12 +32,17 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cell crossings/s + HBM GB/s at 256^3; batched-solve p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+# VALU issue peak of MI355X for unpacked 32-bit operations: 256 compute units x
+# 4 SIMDs x 16 lanes per cycle x 2.4 GHz (a wavefront instruction of 64 lanes
+# every 4 cycles per SIMD; the build keeps packed float32 off)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # algorithmic HBM bytes per crossing: absorber gather + four float64
 # accumulator updates (H+He with heating)
 BYTES_F32 = 3 * 4 + 4 * 8
 BYTES_F64 = 3 * 8 + 4 * 8
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "march_traffic.json")
-KERNELS = {False: "k_tmarch<float, 3, true, 8, 3, 2, false>", True: "k_march<float, 3, true, 8, 3, 2>"}
+COUNTERS_JSON = os.path.join(ROOT, "profiles", "march_counters.json")
+KERNELS = {False: "k_tmarch<float, 3, true, 8, 3, 2, false, false, false, false>", True: "k_march<float, 3, true, 8, 3, 2>"}
 
 
 def log(*a):
@@ -108,49 +113,156 @@ def copy_calibration(mib: int):
     del a, b
 
 
-def cpu_baseline(work, target_s: float):
-    """The float64 oracle on a bounded sample of the same step: packet ranges
-    spread over all sources plus a random sample of cell updates, scaled to a
-    full step."""
+def host_threads() -> int:
+    """Host threads for the oracle: the cores this process may run on, at most
+    16 (one GPU's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_model() -> str:
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+    except (OSError, subprocess.SubprocessError):
+        return "unknown"
+    for line in out.splitlines():
+        if line.startswith("Model name:"):
+            return line.split(":", 1)[1].strip()
+    return "unknown"
+
+
+def oracle_step(work, threads: int):
+    """One full step of the float64 oracle on `threads` host threads (the
+    oracle's C routines release the interpreter lock): the packets of the
+    step marched in ranges taken from a shared counter, each thread with its
+    own accumulators (summed in thread order), then the cell update over
+    ranges of cells.  Returns the solve (state after the step) and timings."""
+    import threading
     import numpy as np
     from oracle import oracle as O
     o = O.OracleSolve(work)
     o.absorbers()
-    P = work.packets
-    nrange = 64
-    per = 400
-    acc = np.zeros((4, work.ncell))
-    cross = 0
-    used = 0
-    t_march = 0.0
-    k = 0
-    while True:
-        g0 = (k * 7919 % nrange) * (P // nrange) + (k // nrange) * per
-        t0 = time.perf_counter()
-        _, led, _ = o.march(g0, g0 + per, dt=work.dt_s, packets=P, seed=1, step_index=0, acc=acc,
-                            absorbers=False)
-        t_march += time.perf_counter() - t0
-        cross += led["crossings"]
-        used += per
-        k += 1
-        if t_march > 0.8 * target_s or used >= P:
-            break
-    rng = np.random.default_rng(0)
-    nupd = min(work.ncell, 200_000)
-    idx = np.sort(rng.choice(work.ncell, nupd, replace=False))
+    P, nc = work.packets, work.ncell
+    per = max(64, P // (threads * 64))
+    ranges = [(g, min(P, g + per)) for g in range(0, P, per)]
+    nxt = [0]
+    lock = threading.Lock()
+    accs = [np.zeros((4, nc)) for _ in range(threads)]
+    leds = [[] for _ in range(threads)]
+
+    def march(t):
+        while True:
+            with lock:
+                k = nxt[0]
+                nxt[0] += 1
+            if k >= len(ranges):
+                return
+            g0, g1 = ranges[k]
+            _, led, _ = o.march(g0, g1, dt=work.dt_s / work.n_sub, packets=P, seed=work.seed, step_index=0,
+                                acc=accs[t], absorbers=False)
+            leds[t].append(led)
+
     t0 = time.perf_counter()
-    o.update_cells(work.dt_s, acc, idx)
+    ths = [threading.Thread(target=march, args=(t,)) for t in range(threads)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    t_march = time.perf_counter() - t0
+    acc = accs[0]
+    for a in accs[1:]:
+        acc += a
+    del accs
+    led = {}
+    for ls in leds:
+        for d in ls:
+            for k, v in d.items():
+                led[k] = led.get(k, 0) + v
+    cells = np.array_split(np.arange(nc, dtype=np.int64), threads * 8)
+    nxt[0] = 0
+
+    def update(t):
+        while True:
+            with lock:
+                k = nxt[0]
+                nxt[0] += 1
+            if k >= len(cells):
+                return
+            o.update_cells(work.dt_s / work.n_sub, acc, cells[k])
+
+    t0 = time.perf_counter()
+    ths = [threading.Thread(target=update, args=(t,)) for t in range(threads)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
     t_upd = time.perf_counter() - t0
-    full_cross = cross * P / used
-    full_time = t_march * P / used + t_upd * work.ncell / nupd
-    return {
-        "value": full_cross / full_time, "unit": "crossings/s", "cores": 1, "kind": "oracle",
-        "sample": (f"{used} packets in {k} ranges spread over all sources ({cross} crossings, "
-                   f"{t_march:.1f} s) + {nupd} cell updates ({t_upd:.1f} s), scaled to one full step "
-                   f"of {P} packets and {work.ncell} cells; single-threaded float64 C oracle"),
-        "march_crossings_per_s": cross / t_march,
-        "update_cells_per_s": nupd / t_upd,
+    o.acc = acc
+    return o, led, t_march, t_upd
+
+
+def field_errors(o, f, work, emitted):
+    """Per-field errors of a GPU step against the oracle's: fractions
+    relative to max(x, 1e-8), temperature relative, deposits and heat
+    relative to max(|ref|, 1e-12 mean) after the photons the float32 form's
+    bin dropping may move (e^-30 of those emitted; heat: times the largest
+    photon energy above the HI threshold)."""
+    import math
+    import numpy as np
+    from paper_1101_4127_amd import workloads as W
+    out = {}
+    names = ("x_HI", "x_HII", "x_HeI", "x_HeII", "x_HeIII")
+    for i, n in enumerate(names):
+        e = np.abs(f[1 + i] - o.x[i]) / np.maximum(o.x[i], 1e-8)
+        out[n] = e
+    out["T"] = np.abs(f[6] - o.T) / o.T
+    drop = math.exp(-30.0) * emitted
+    de = float(np.max(np.asarray(work.bins.e_ev) - W.E_TH_EV[0])) * W.EV_ERG
+    for i, n in enumerate(("D_HI", "D_HeI", "D_HeII", "Q")):
+        ref, allow = o.acc[i], (drop if i < 3 else drop * de)
+        floor = 1e-12 * float(np.mean(np.abs(ref))) or 1e-300
+        out[n] = np.maximum(np.abs(f[7 + i] - ref) - allow, 0.0) / np.maximum(np.abs(ref), floor)
+    return {k: {"max": float(np.max(v)), "p99": float(np.percentile(v, 99))} for k, v in out.items()}
+
+
+def oracle_leg(work, packets: int):
+    """The float64 oracle on a bounded sample of the benchmark step (the same
+    gas, sources and seed, `packets` packets: a fresh solve's first step) on
+    the host's cores, and the same step of the float32-march form on the GPU,
+    compared field by field.  Returns (cpu_baseline, accuracy)."""
+    import torch
+    from paper_1101_4127_amd import rt
+    w = work.with_(packets=packets)
+    threads = host_threads()
+    o, led, t_march, t_upd = oracle_step(w, threads)
+    s = rt.Solve(w, fp64=False, inflight=w.packets)
+    st = s.step(seed=w.seed)
+    f = s.fetch()
+    s.release()
+    torch.cuda.synchronize()
+    acc = field_errors(o, f, w, st["emitted"])
+    cross = led["crossings"]
+    model = cpu_model()
+    cpu = {
+        "value": cross / (t_march + t_upd), "unit": "crossings/s", "cores": threads, "kind": "oracle",
+        "cpu_model": model,
+        "sample": (f"one full step of the benchmark gas and sources with {packets} packets ({cross} crossings, "
+                   f"{cross / packets:.1f} per packet; the metric's step has {work.packets}): march "
+                   f"{t_march:.1f} s + update of all {w.ncell} cells {t_upd:.1f} s on {threads} threads of "
+                   f"{model}; float64 C oracle"),
+        "march_crossings_per_s": cross / t_march, "update_cells_per_s": w.ncell / t_upd,
     }
+    log(f"oracle: {cpu['value']:.4g} crossings/s on {threads} threads ({model}); march {t_march:.1f} s, "
+        f"update {t_upd:.1f} s")
+    accuracy = {"workload": w.name, "packets": packets, "against": "float64 oracle, same inputs and seed",
+                "form": "float32 march, float64 accumulators and cell update", "fields": acc,
+                "crossings_gpu": st["crossings"], "crossings_oracle": cross}
+    log("accuracy vs oracle: " + ", ".join(f"{k} {v['max']:.2e}" for k, v in acc.items()))
+    return cpu, accuracy
 
 
 def traffic_for(launch_crossings: float):
@@ -163,6 +275,23 @@ def traffic_for(launch_crossings: float):
     if t.get("march_hash") != march_hash():
         return None
     return t.get("bytes_per_launch")
+
+
+def counters_for():
+    """VALU counters of the march kernel per crossing from committed rocprofv3
+    runs, or None when they were taken on a different march kernel."""
+    if not os.path.exists(COUNTERS_JSON):
+        return None
+    with open(COUNTERS_JSON) as f:
+        t = json.load(f)
+    return t if t.get("march_hash") == march_hash() else None
+
+
+# the server's fused calls: up to 256 solves, each sub-step's tile passes cut
+# short after 4 by a finishing pass (the serving solves' packets cross few
+# tiles; the passes after the fourth carry little work each)
+SERVE_SLOTS = 256
+SERVE_FINISH = 4
 
 
 def serving_leg(count: int, accuracy_requests: int = 32):
@@ -178,7 +307,7 @@ def serving_leg(count: int, accuracy_requests: int = 32):
     reqs = W.serving_stream(count=count)
     log(f"serving: {count} requests ({time.perf_counter() - t0:.1f} s to generate), "
         f"arrivals over {reqs[-1].arrival_s:.2f} s")
-    srv = serve.Server(max_slots=64, fp64=False, graph=True, keep_fields=False)
+    srv = serve.Server(max_slots=SERVE_SLOTS, fp64=False, graph=True, keep_fields=False, finish_pass=SERVE_FINISH)
     srv.run(W.serving_stream(count=8, seed=99), realtime=False)           # capture and first launches
     srv.calls, srv.call_solves = 0, []
     t = time.perf_counter()
@@ -196,7 +325,7 @@ def serving_leg(count: int, accuracy_requests: int = 32):
     cross_base = sum(g.crossings for g in base)
     # accuracy of the served form against the plain float64 form
     sub = reqs[:accuracy_requests]
-    srv = serve.Server(max_slots=64, fp64=False, graph=True, keep_fields=True)
+    srv = serve.Server(max_slots=SERVE_SLOTS, fp64=False, graph=True, keep_fields=True, finish_pass=SERVE_FINISH)
     acc32 = srv.run(sub, realtime=False)
     srv.release()
     acc64, _ = serve.run_alone(sub, fp64=True, direct=True, keep_fields=True)
@@ -210,7 +339,8 @@ def serving_leg(count: int, accuracy_requests: int = 32):
     dep = np.concatenate(dep)
     out = {
         "workload": f"poisson_{count}_pure_H_16-64^3", "requests": count, "rate_per_s": 200.0,
-        "form": "float32 march, float64 accumulators; fused steps of up to 64 solves replayed as a hipGraph",
+        "form": f"float32 march, float64 accumulators; fused tiled steps of up to {SERVE_SLOTS} solves (finishing "
+                f"pass after {SERVE_FINISH} tile passes) replayed as a hipGraph",
         "p50_latency_ms": 1e3 * serve.percentile(lat, 50), "p99_latency_ms": 1e3 * serve.percentile(lat, 99),
         "wall_s": wall, "solves_per_s": count / wall, "crossings_per_s": cross / wall,
         "fused_calls": calls, "mean_solves_per_call": mean_batch,
@@ -309,6 +439,37 @@ def periodic_leg(steps: int, packets):
             "conservation_residual": resid}
 
 
+def roofline(per_launch, avg_ms, achieved, args, f32):
+    """The march kernel against its bound.  The kernel issues VALU
+    instructions ~85 % of its time (committed counters), so its roofline is
+    the VALU issue rate: VALU lane-operations per crossing (wavefront
+    instructions x 64, from the counters) x crossings per launch / launch
+    time, against 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.  Beside it the HBM
+    roofline of the algorithmic bytes per crossing (absorber gather + float64
+    accumulator updates) against the nominal 8 TB/s and the measured copy
+    peak, and the HBM bytes the counters saw."""
+    traffic = traffic_for(per_launch)
+    ctr = counters_for()
+    hbm = {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+           "bytes_per_crossing": BYTES_F32, "traffic": traffic}
+    if traffic is not None:
+        hbm["measured_gbs"] = traffic / (avg_ms * 1e-3) / 1e9
+        hbm["measured_frac"] = hbm["measured_gbs"] / HBM_PEAK_GBS
+    out = {"kernel": KERNELS[args.direct], "crossings_per_launch": per_launch, "avg_launch_ms": avg_ms,
+           "whole_march_ms_per_step": f32["march_ms"] / args.steps,
+           "whole_march_gcross_per_s": f32["crossings"] / (f32["march_ms"] * 1e-3) / 1e9}
+    if ctr is not None:
+        ops = 64.0 * ctr["valu_insts_per_crossing"] * per_launch / (avg_ms * 1e-3) / 1e12
+        out.update({"bound": "alu", "achieved": ops, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
+                    "frac": ops / VALU_PEAK_TOPS, "traffic": traffic,
+                    "valu_insts_per_crossing": ctr["valu_insts_per_crossing"],
+                    "lane_utilisation": ctr.get("lane_utilisation"), "hbm": hbm})
+    else:
+        out.update({"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "hbm": hbm})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,7 +478,8 @@ def main():
     ap.add_argument("--workload", default="lognormal_256")
     ap.add_argument("--packets", type=int, default=None)
     ap.add_argument("--fp64-steps", type=int, default=2, help="timed steps of the plain float64 form")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget")
+    ap.add_argument("--oracle-packets", type=int, default=2_000_000,
+                    help="packets of the step the oracle runs (CPU baseline and per-field errors)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--direct", action="store_true", help="per-packet march instead of the tiled one")
     ap.add_argument("--inflight", type=int, default=0)
@@ -388,12 +550,7 @@ def main():
                    "form": "float32 march, float64 accumulators and cell update",
                    "march": "per-packet" if args.direct else "tiled",
                    "crossings_per_step": f32["crossings"] / args.steps},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(per_launch),
-                     "kernel": KERNELS[args.direct], "bytes_per_crossing": BYTES_F32,
-                     "crossings_per_launch": per_launch, "avg_launch_ms": avg_ms,
-                     "whole_march_ms_per_step": f32["march_ms"] / args.steps,
-                     "whole_march_gcross_per_s": f32["crossings"] / (f32["march_ms"] * 1e-3) / 1e9},
+        "roofline": roofline(per_launch, avg_ms, achieved, args, f32),
         "conservation_residual": f32["resid"],
     }
     if ceil is not None:
@@ -420,10 +577,7 @@ def main():
     if args.periodic_steps > 0:
         out["periodic_background"] = periodic_leg(args.periodic_steps, args.packets)
     if not args.no_cpu_baseline:
-        t0 = time.perf_counter()
-        out["cpu_baseline"] = cpu_baseline(work, args.cpu_seconds)
-        log(f"cpu baseline: {out['cpu_baseline']['value']:.4g} crossings/s "
-            f"({time.perf_counter() - t0:.1f} s)")
+        out["cpu_baseline"], out["accuracy_vs_oracle"] = oracle_leg(work, args.oracle_packets)
     print(json.dumps(out), flush=True)
 
 

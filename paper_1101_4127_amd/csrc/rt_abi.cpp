@@ -20,6 +20,7 @@ constexpr uint64_t kMagic = 0x52544d4352543031ull;   // handle tag
 constexpr int kMaxMarchBlocks = 8192;                // ledger slots reserved in the workspace
 constexpr size_t kAlign = 256;
 const double kThresholdEv[3] = {13.598434, 24.587387, 54.417760};
+const double kEvErg = 1.602176634e-12;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
@@ -213,8 +214,8 @@ int32_t make_plan(const rt_grid_desc *d, int64_t max_sources, Plan *p) {
 // number of values).  Rows 0-2: the
 // cross-sections of HI, HeI, HeII (float32 form: in units of 1e-18 cm^2,
 // lengths then in 1e18 cm, so optical depths stay far from the float32 range
-// limits).  Rows 3-5: heat factors in eV: pure hydrogen E_j - E_th,HI; H+He
-// sigma_s,j (E_j - E_th,s).  Row 6: E_j - E_th,HI.
+// limits).  Rows 3-5: heat factors in erg: pure hydrogen E_j - E_th,HI; H+He
+// sigma_s,j (E_j - E_th,s).  Row 6: E_j - E_th,HI in erg.
 int march_table(const rt_grid_desc *d, const Plan &p, double *t) {
     const int n = 7 * p.mb;
     for (int i = 0; i < n; ++i) t[i] = 0.0;
@@ -222,7 +223,9 @@ int march_table(const rt_grid_desc *d, const Plan &p, double *t) {
     for (int s = 0; s < 3; ++s)
         for (int j = 0; j < d->n_bins; ++j) {
             const double sig = d->sigma_cm2[s][j];
-            const double de = sig > 0.0 ? d->e_bin_ev[j] - kThresholdEv[s] : 0.0;
+            // heat per absorbed photon, in erg (so the march's heat needs no
+            // conversion where it is deposited)
+            const double de = sig > 0.0 ? (d->e_bin_ev[j] - kThresholdEv[s]) * kEvErg : 0.0;
             t[(size_t)s * p.mb + j] = sig * scale;
             t[(size_t)(3 + s) * p.mb + j] = p.species == 1 ? de : sig * scale * de;
             if (s == 0) t[(size_t)6 * p.mb + j] = de;

@@ -19,7 +19,7 @@ template <> struct Vec4<float> { using T = float4; };
 template <> struct Vec4<double> { using T = double4; };
 
 // Per-bin table of the march precision, [7][MB]: cross-sections of HI, HeI,
-// HeII, their heat factors, then E_j - E_th,HI.  Read through the constant address
+// HeII, their heat factors (erg), then E_j - E_th,HI (erg).  Read through the constant address
 // space: the indices are uniform, so the values live in scalar registers.
 template <typename R> using CTab = const __attribute__((address_space(4))) R *;
 
@@ -96,10 +96,10 @@ struct MarchTab<R, MB, true> {
 // such lane has bit j of `active`).  Wave-uniform.
 template <int MB>
 __device__ __forceinline__ uint32_t wave_bins(bool lane_on, uint32_t active) {
+    const uint32_t v = lane_on ? active : 0u;     // one select, then one bit test per bin
     uint32_t m = 0;
 #pragma unroll
-    for (int j = 0; j < MB; ++j)
-        if (__ballot(lane_on && ((active >> j) & 1u)) != 0ull) m |= 1u << j;
+    for (int j = 0; j < MB; ++j) m |= (__ballot((v >> j) & 1u) != 0ull) ? (1u << j) : 0u;
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)m);
 }
 
@@ -121,7 +121,7 @@ __device__ __forceinline__ float column_depth(float sH, float sHe1, float sHe2, 
 // in the march precision: the photons absorbed over all bins; per absorber,
 // kappa_s * sum_j sigma_s,j d_j / K_j (the photons the absorber takes); the
 // heat sum_s kappa_s sum_j h_s,j d_j / K_j (pure hydrogen: sum_j h_j d_j), in
-// eV per photon of the packet's weight; and, in the float64 form, the
+// erg per photon of the packet's weight; and, in the float64 form, the
 // smallest accumulated optical depth over the bins (those the source does
 // not populate hold +inf), which ends the packet once it reaches tau_kill
 // (float32 form: see Extinction).

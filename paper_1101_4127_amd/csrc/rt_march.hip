@@ -20,8 +20,6 @@
 
 namespace rtk {
 
-constexpr double kEvErg = 1.602176634e-12;
-
 struct MarchParams {
     GridGeom geo;
     double half_dl;        // half cell size [cm]
@@ -268,7 +266,7 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
                 const double v = w * (double)absorbed;
                 if (v != 0.0) unsafeAtomicAdd(cell, v);
                 if (TH) {
-                    const double q = w * ((double)hs * kEvErg);
+                    const double q = w * (double)hs;
                     if (q != 0.0) unsafeAtomicAdd(cell + 1, q);
                 }
             } else {
@@ -279,7 +277,7 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
                 if (v1 != 0.0) unsafeAtomicAdd(cell + 1, v1);
                 if (v2 != 0.0) unsafeAtomicAdd(cell + 2, v2);
                 if (TH) {
-                    const double q = w * ((double)hs * kEvErg);
+                    const double q = w * (double)hs;
                     if (q != 0.0) unsafeAtomicAdd(cell + 3, q);
                 }
             }

@@ -41,7 +41,6 @@ namespace rtk {
 
 namespace {
 
-constexpr double kEvErg = 1.602176634e-12;
 constexpr int kTBlock = 256;              // threads of the emission, march and scatter blocks
 constexpr int kTWaves = kTBlock / 64;
 constexpr int kScanBlock = 1024;
@@ -1336,23 +1335,23 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                     double *g = rs.acc + (size_t)gcell * ACC;
                     if (S == 1) {
                         unsafeAtomicAdd(g, w * (double)absorbed);
-                        if (TH) unsafeAtomicAdd(g + 1, w * ((double)hs * kEvErg));
+                        if (TH) unsafeAtomicAdd(g + 1, w * (double)hs);
                     } else {
                         unsafeAtomicAdd(g, w * (double)e0);
                         unsafeAtomicAdd(g + 1, w * (double)e1);
                         unsafeAtomicAdd(g + 2, w * (double)e2);
-                        if (TH) unsafeAtomicAdd(g + 3, w * ((double)hs * kEvErg));
+                        if (TH) unsafeAtomicAdd(g + 3, w * (double)hs);
                     }
                 } else {
                     double *cell = s_acc + loc;
                     if (S == 1) {
                         atomicAdd(cell, w * (double)absorbed);
-                        if (TH) atomicAdd(cell + kTileCells, w * ((double)hs * kEvErg));
+                        if (TH) atomicAdd(cell + kTileCells, w * (double)hs);
                     } else {
                         atomicAdd(cell, w * (double)e0);
                         atomicAdd(cell + kTileCells, w * (double)e1);
                         atomicAdd(cell + 2 * kTileCells, w * (double)e2);
-                        if (TH) atomicAdd(cell + 3 * kTileCells, w * ((double)hs * kEvErg));
+                        if (TH) atomicAdd(cell + 3 * kTileCells, w * (double)hs);
                     }
                 }
                 absd += (double)absorbed;

@@ -128,11 +128,10 @@ typedef struct {
     double y_he;                  /* n_He / n_H ; 0 = pure hydrogen */
     int32_t n_bins;               /* frequency bins: 1 or RT_SUPPORTED_BINS (arrays
                                      hold RT_MAX_BINS; other counts -> RT_EINVAL).
-                                     H+He with 8 bins in the tiled march: the
-                                     table must be threshold-aligned (HeI and HeII
-                                     cross-sections 0 in bins 0-2, HeII 0 in bins
-                                     3-4), else RT_EINVAL; the per-packet march
-                                     takes any table */
+                                     H+He with 8 bins: the table must be
+                                     threshold-aligned (HeI and HeII cross-sections
+                                     0 in bins 0-2, HeII 0 in bins 3-4), else
+                                     RT_EINVAL, in either march */
     double e_bin_ev[RT_MAX_BINS]; /* photon energy of each bin (heat per absorption
                                      is E_j minus the species' threshold) */
     double sigma_cm2[3][RT_MAX_BINS]; /* HI, HeI, HeII cross-sections per bin;

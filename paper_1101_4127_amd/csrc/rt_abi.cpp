@@ -102,10 +102,11 @@ int32_t make_plan(const rt_grid_desc *d, int64_t max_sources, Plan *p) {
     *p = Plan{};
     if (max_sources < 0 || max_sources > (int64_t)1 << 30) return RT_EINVAL;
     p->species = d->y_he > 0.0 ? 3 : 1;
-    // the tiled march has an instance for the threshold-aligned H+He table
-    // only (helium cross-sections zero in bins 0-2, HeII zero in bins 3-4);
-    // other H+He tables of several bins run in the per-packet march
-    if (p->species == 3 && d->n_bins > 1 && !(d->flags & RT_DIRECT_MARCH)) {
+    // H+He tables of several bins: the threshold-aligned layout only (helium
+    // cross-sections zero in bins 0-2, HeII zero in bins 3-4), the one both
+    // marches have a tested instance for; the generic instance stays unused
+    // while the fault of an earlier generic-layout instance is unexplained
+    if (p->species == 3 && d->n_bins > 1) {
         for (int j = 0; j < 5; ++j)
             if (d->sigma_cm2[2][j] != 0.0 || (j < 3 && d->sigma_cm2[1][j] != 0.0)) return RT_EINVAL;
     }

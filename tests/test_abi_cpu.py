@@ -118,7 +118,7 @@ def test_workspace_bytes_scales_and_validates(L):
         with pytest.raises(rt.RTError) as ex:
             rt.rt_workspace_bytes(e, 1)
         assert ex.value.status == rt.RT_EINVAL, nb
-    # H+He with 8 bins: the tiled march takes the threshold-aligned table only
+    # H+He with 8 bins: the threshold-aligned table only, in either march
     e = rt.rt_desc_defaults()
     e.n_bins = 8
     e.y_he = 0.08
@@ -128,12 +128,12 @@ def test_workspace_bytes_scales_and_validates(L):
         e.sigma_cm2[1][j] = 1e-19 if j >= 3 else 0.0
         e.sigma_cm2[2][j] = 1e-19 if j >= 5 else 0.0
     assert rt.rt_workspace_bytes(e, 1) > 0
-    e.sigma_cm2[2][4] = 1e-19                     # HeII in bin 4: no tiled instance
-    with pytest.raises(rt.RTError) as ex:
-        rt.rt_workspace_bytes(e, 1)
-    assert ex.value.status == rt.RT_EINVAL
-    e.flags = rt.RT_DIRECT_MARCH                  # the per-packet march takes it
-    assert rt.rt_workspace_bytes(e, 1) > 0
+    e.sigma_cm2[2][4] = 1e-19                     # HeII in bin 4: not the aligned layout
+    for flags in (0, rt.RT_DIRECT_MARCH):
+        e.flags = flags
+        with pytest.raises(rt.RTError) as ex:
+            rt.rt_workspace_bytes(e, 1)
+        assert ex.value.status == rt.RT_EINVAL
     # a cross-section above zero below its threshold is rejected
     e = rt.rt_desc_defaults()
     e.e_bin_ev[0] = 20.0

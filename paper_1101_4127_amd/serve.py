@@ -175,70 +175,78 @@ class Server:
         out: List[Served] = []
         overlap = hasattr(self.ex, "launch")
         t0 = clock()
-        while pending or active:
-            now = clock() - t0
-            while pending and (not realtime or pending[0].arrival_s <= now):
-                r = pending[0]
-                ahead = r.rid in opened
-                if not (admissible(0 if ahead else need[r.rid], used, len(active), self.max_slots,
-                                   self.hbm_budget)
-                        and fits_batch(pk[r.rid], tl[r.rid], used_pk, used_tl, self.max_round_packets,
-                                       self.max_tiles)):
-                    break
-                pending.popleft()
-                if ahead:
-                    s = opened.pop(r.rid)
-                else:
-                    s = self.ex.open(r.work)
-                    used += need[r.rid]
-                used_pk += pk[r.rid]
-                used_tl += tl[r.rid]
-                self.peak_bytes = max(self.peak_bytes, used)
-                active.append([r, s, clock() - t0, 0, []])
-            if not active:
-                wait = pending[0].arrival_s - (clock() - t0)
-                if wait > 0:
-                    time.sleep(min(wait, 0.05))
-                continue
-            if overlap:
-                self.ex.launch([a[1] for a in active])
-                # the next requests in line go up while the call runs
+        try:
+            while pending or active:
                 now = clock() - t0
-                for r in pending:
-                    if not self.ex.busy() or len(opened) >= self.max_slots or (realtime and r.arrival_s > now):
+                while pending and (not realtime or pending[0].arrival_s <= now):
+                    r = pending[0]
+                    ahead = r.rid in opened
+                    if not (admissible(0 if ahead else need[r.rid], used, len(active), self.max_slots,
+                                       self.hbm_budget)
+                            and fits_batch(pk[r.rid], tl[r.rid], used_pk, used_tl, self.max_round_packets,
+                                           self.max_tiles)):
                         break
-                    if r.rid in opened:
-                        continue
-                    if used + need[r.rid] > self.hbm_budget:
-                        break
-                    opened[r.rid] = self.ex.open(r.work)
-                    used += need[r.rid]
+                    pending.popleft()
+                    if ahead:
+                        s = opened.pop(r.rid)
+                    else:
+                        s = self.ex.open(r.work)
+                        used += need[r.rid]
+                    used_pk += pk[r.rid]
+                    used_tl += tl[r.rid]
                     self.peak_bytes = max(self.peak_bytes, used)
-                ledgers = self.ex.wait()
-            else:
-                ledgers = self.ex.step([a[1] for a in active])
-            self.calls += 1
-            self.call_solves.append(len(active))
-            done_t = clock() - t0
-            still = []
-            for a, st in zip(active, ledgers):
-                a[3] += 1
-                a[4].append(st)
-                if a[3] < a[0].work.steps:
-                    still.append(a)
+                    active.append([r, s, clock() - t0, 0, []])
+                if not active:
+                    wait = pending[0].arrival_s - (clock() - t0)
+                    if wait > 0:
+                        time.sleep(min(wait, 0.05))
                     continue
-                r, s = a[0], a[1]
-                fields = self.ex.fetch(s) if self.keep_fields else None
+                if overlap:
+                    self.ex.launch([a[1] for a in active])
+                    # the next requests in line go up while the call runs
+                    now = clock() - t0
+                    for r in pending:
+                        if not self.ex.busy() or len(opened) >= self.max_slots or (realtime and r.arrival_s > now):
+                            break
+                        if r.rid in opened:
+                            continue
+                        if used + need[r.rid] > self.hbm_budget:
+                            break
+                        opened[r.rid] = self.ex.open(r.work)
+                        used += need[r.rid]
+                        self.peak_bytes = max(self.peak_bytes, used)
+                    ledgers = self.ex.wait()
+                else:
+                    ledgers = self.ex.step([a[1] for a in active])
+                self.calls += 1
+                self.call_solves.append(len(active))
+                done_t = clock() - t0
+                still = []
+                for a, st in zip(active, ledgers):
+                    a[3] += 1
+                    a[4].append(st)
+                    if a[3] < a[0].work.steps:
+                        still.append(a)
+                        continue
+                    r, s = a[0], a[1]
+                    fields = self.ex.fetch(s) if self.keep_fields else None
+                    self.ex.close(s)
+                    used -= need[r.rid]
+                    used_pk -= pk[r.rid]
+                    used_tl -= tl[r.rid]
+                    led = a[4]
+                    res = max(abs(x["emitted"] - (x["absorbed"] + x["escaped"] + x["truncated"])) / x["emitted"]
+                              if x["emitted"] > 0 else 0.0 for x in led)
+                    out.append(Served(r.rid, r.arrival_s, a[2], done_t, a[3], sum(x["crossings"] for x in led),
+                                      sum(x["packets"] for x in led), sum(x["emitted"] for x in led), res, fields))
+                active = still
+        except BaseException:
+            # a failed run leaves no solve open behind it
+            for a in active:
+                self.ex.close(a[1])
+            for s in opened.values():
                 self.ex.close(s)
-                used -= need[r.rid]
-                used_pk -= pk[r.rid]
-                used_tl -= tl[r.rid]
-                led = a[4]
-                res = max(abs(x["emitted"] - (x["absorbed"] + x["escaped"] + x["truncated"])) / x["emitted"]
-                          if x["emitted"] > 0 else 0.0 for x in led)
-                out.append(Served(r.rid, r.arrival_s, a[2], done_t, a[3], sum(x["crossings"] for x in led),
-                                  sum(x["packets"] for x in led), sum(x["emitted"] for x in led), res, fields))
-            active = still
+            raise
         return sorted(out, key=lambda x: x.rid)
 
     def release(self):

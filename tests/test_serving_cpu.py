@@ -176,3 +176,23 @@ def test_opened_ahead_requests_are_admitted_in_order(monkeypatch):
                 seen.append(sid)
     assert seen == [r.work.solve_id for r in reqs]
     assert srv.peak_bytes <= 4 * max(serve.workspace_bytes(r.work, fp64=False) for r in reqs)
+
+
+def test_a_failed_run_closes_its_solves(monkeypatch):
+    """A request whose opening fails ends the run with its error, and every
+    solve the run opened (admitted or opened ahead) is closed again."""
+    reqs = W.serving_stream(count=6, seed=9, sides=(16,), log_packets=(4.0, 4.2), rate_per_s=500.0)
+    clock = FakeClock()
+    monkeypatch.setattr(serve.time, "sleep", lambda s: setattr(clock, "t", clock.t + s))
+
+    class Failing(FakeAsyncExecutor):
+        def open(self, work):
+            if work.solve_id == reqs[3].work.solve_id:
+                raise RuntimeError("no memory")
+            return super().open(work)
+
+    ex = Failing(clock)
+    srv = serve.Server(max_slots=2, hbm_budget=1 << 40, executor=ex, keep_fields=False)
+    with pytest.raises(RuntimeError):
+        srv.run(reqs, realtime=False, clock=clock)
+    assert not ex.open_now

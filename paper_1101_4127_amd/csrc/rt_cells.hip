@@ -256,6 +256,14 @@ struct UpdateConst {
     }
 };
 
+// Rates of the last temperature a thread evaluated them at (isothermal
+// updates: they depend on T alone, so a thread's next cell at the same T
+// takes them as they are, bit for bit).
+struct RateCache {
+    double T = -1.0;
+    Rates r;
+};
+
 // The update of slot s (padding slots outside the grid are left alone); bad is
 // set when a result is not finite.  rc non-null: case-A rates, and the
 // recombinations per atom of each ion over the sub-step are added to its
@@ -266,7 +274,7 @@ template <typename R, int S, bool TH, bool CNT>
 __device__ __forceinline__ void update_slot(const GridGeom &G, R *__restrict__ st, const double *__restrict__ acc,
                                             int acc_stride, double y_he, double dt, int n_chem,
                                             const UpdateConst &u, uint32_t s, unsigned int &bad,
-                                            double *__restrict__ rc = nullptr) {
+                                            RateCache &cache, double *__restrict__ rc = nullptr) {
     constexpr bool he = (S == 3);
     const uint32_t np = G.ncell_pad;
     const double V = u.V, kb = u.kb, tcmb = u.tcmb, ccomp = u.ccomp, h = u.h;
@@ -294,8 +302,18 @@ __device__ __forceinline__ void update_slot(const GridGeom &G, R *__restrict__ s
         double n_rec[3] = {0.0, 0.0, 0.0};
         if (count)
             for (int q = 0; q < S; ++q) n_rec[q] = rc[(size_t)q * np + s];
-        TFac tf = tfac<CNT, he>(T);
-        Rates r = rates_at<CNT, he>(T, tf);
+        TFac tf;
+        Rates r;
+        if constexpr (TH) {
+            tf = tfac<CNT, he>(T);
+            r = rates_at<CNT, he>(T, tf);
+        } else {
+            if (!(T == cache.T)) {
+                cache.r = rates_at<CNT, he>(T, tfac<CNT, he>(T));
+                cache.T = T;
+            }
+            r = cache.r;
+        }
         for (int m = 0; m < n_chem; ++m) {
             if (TH && m > 0) {
                 tf = tfac<CNT, he>(T);
@@ -376,12 +394,13 @@ __global__ void __launch_bounds__(kCellBlock, (TH ? 3 : 4)) k_update(GridGeom G,
     const uint32_t stride = gridDim.x * blockDim.x;
     const UpdateConst u(cell_cm, dt, redshift, n_chem);
     unsigned int bad = 0;
+    RateCache cache;
     if (rc != nullptr) {
         for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < np; s += stride)
-            update_slot<R, S, TH, true>(G, st, acc, acc_stride, y_he, dt, n_chem, u, s, bad, rc);
+            update_slot<R, S, TH, true>(G, st, acc, acc_stride, y_he, dt, n_chem, u, s, bad, cache, rc);
     } else {
         for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < np; s += stride)
-            update_slot<R, S, TH, false>(G, st, acc, acc_stride, y_he, dt, n_chem, u, s, bad);
+            update_slot<R, S, TH, false>(G, st, acc, acc_stride, y_he, dt, n_chem, u, s, bad, cache);
     }
     if (bad) atomicOr(&ledger->nonfinite, 1u);
 }
@@ -612,6 +631,7 @@ __global__ void __launch_bounds__(64) k_bledger(const BatchHead *hd, const Batch
 template <typename R, int S, bool TH>
 __global__ void __launch_bounds__(kCellBlock) k_bupdate(const BatchHead *hd, const BatchSolve *tb, int round) {
     __shared__ uint64_t s_first[kMaxBatch];
+    RateCache cache;
     const int n = hd->n;
     for (int i = threadIdx.x; i < n; i += blockDim.x) s_first[i] = tb[i].cell0;
     __syncthreads();
@@ -624,7 +644,7 @@ __global__ void __launch_bounds__(kCellBlock) k_bupdate(const BatchHead *hd, con
         const UpdateConst u(sv.cell_cm, sv.dt, sv.redshift, sv.n_chem);
         unsigned int bad = 0;
         update_slot<R, S, TH, false>(sv.geo, reinterpret_cast<R *>(sv.state), sv.acc, sv.acc_stride, sv.y_he, sv.dt,
-                              sv.n_chem, u, (uint32_t)(g - s_first[b]), bad);
+                              sv.n_chem, u, (uint32_t)(g - s_first[b]), bad, cache);
         if (bad) atomicOr(&sv.ledger->nonfinite, 1u);
     }
 }

@@ -1074,7 +1074,6 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
         uint32_t gcell = 0;                      // finishing pass: the grid slot of its cell
         DepthTest<R, S, MB> dtest;
         int32_t tix = -1;
-        KV kap{};
         R F[MB], D[ND];
 #pragma unroll
         for (int j = 0; j < MB; ++j) F[j] = R(0);
@@ -1251,9 +1250,6 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                                     lty = ty;
                                     ltz = tz;
                                     gcell = (tile << (3 * kTileLog2)) | local_to_morton(loc);
-                                    kap = kg[gcell];
-                                } else {
-                                    kap = s_kap[loc];
                                 }
                                 alive = true;
                             }
@@ -1272,6 +1268,10 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
             // path through the loop body keeps the packet state in its registers)
             uint32_t it_cross = 0;
             if (alive && !pend) {
+                // this cell's absorbers (the load runs while the traversal arithmetic does)
+                KV kap;
+                if constexpr (FIN) kap = kg[gcell];
+                else kap = s_kap[loc];
                 bool m0, m1, m2;
                 const int ax = exit_face(d0, d1, d2, a0, a1, a2, m0, m1, m2);
                 const uint32_t num = ax == 0 ? d0 : (ax == 1 ? d1 : d2);
@@ -1311,17 +1311,13 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                     dz = (k2 >> kTileLog2) - (FIN ? ltz : tz);
                 }
                 const bool leave = !out && (dx | dy | dz) != 0;
-                // next cell's absorbers, read before this cell's arithmetic (the
-                // masked index stays inside the tile; unused when the packet leaves)
+                // next cell's index in the tile (masked, so it stays inside the
+                // tile; unused when the packet leaves)
                 const uint32_t nloc = local_cell(k0, k1, k2);
-                KV knext;
                 uint32_t ngc = gcell;
                 if constexpr (FIN) {
-                    // (a packet that left the grid reads its last cell again)
+                    // (a packet that left the grid keeps its last cell)
                     if (!out) ngc = (tile_of_cell(geo, k0, k1, k2) << (3 * kTileLog2)) | local_to_morton(nloc);
-                    knext = kg[ngc];
-                } else {
-                    knext = s_kap[nloc];
                 }
 
                 R absorbed, e0, e1, e2, hs, tmin;
@@ -1366,7 +1362,6 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                 // the state moves on to the next cell; a packet that left the tile,
                 // the grid, or whose witness depth reached the cut is settled later
                 loc = nloc;
-                kap = knext;
                 if constexpr (FIN) gcell = ngc;
                 lax = (uint32_t)ax;
                 if (F64) sprev = snew; else { pnum = num; pden = den; }

@@ -139,7 +139,7 @@ int32_t make_plan(const rt_grid_desc *d, int64_t max_sources, Plan *p) {
     p->off_ndot = o; o = align_up(o + ms * sizeof(double));
     p->off_sedsum = o; o = align_up(o + ms * sizeof(double));
     p->off_sed = o; o = align_up(o + ms * p->mb * p->real);
-    p->off_tab = o; o = align_up(o + 7 * (size_t)p->mb * p->real);
+    p->off_tab = o; o = align_up(o + rtk::kTabRows * (size_t)p->mb * p->real);
     p->off_slots = o; o = align_up(o + kMaxMarchBlocks * sizeof(rtk::LedgerSlot));
     p->off_ledger = o; o = align_up(o + sizeof(rtk::StepLedger));
     p->off_queue = o; o = align_up(o + sizeof(unsigned long long));
@@ -211,14 +211,14 @@ int32_t make_plan(const rt_grid_desc *d, int64_t max_sources, Plan *p) {
     return RT_OK;
 }
 
-// Per-bin march table, [7][mb] in the march precision, into t (returns the
-// number of values).  Rows 0-2: the
-// cross-sections of HI, HeI, HeII (float32 form: in units of 1e-18 cm^2,
-// lengths then in 1e18 cm, so optical depths stay far from the float32 range
-// limits).  Rows 3-5: heat factors in erg: pure hydrogen E_j - E_th,HI; H+He
-// sigma_s,j (E_j - E_th,s).  Row 6: E_j - E_th,HI in erg.
+// Per-bin march table, [kTabRows][mb] in the march precision, into t (returns
+// the number of values).  Rows 0-2: the cross-sections of HI, HeI, HeII
+// (float32 form: in units of 1e-18 cm^2, lengths then in 1e18 cm, so optical
+// depths stay far from the float32 range limits).  Rows 3-5: heat factors in
+// erg: pure hydrogen E_j - E_th,HI; H+He sigma_s,j (E_j - E_th,s).  Row 6:
+// E_j - E_th,HI in erg.
 int march_table(const rt_grid_desc *d, const Plan &p, double *t) {
-    const int n = 7 * p.mb;
+    const int n = rtk::kTabRows * p.mb;
     for (int i = 0; i < n; ++i) t[i] = 0.0;
     const double scale = p.fp64 ? 1.0 : 1.0e18;
     for (int s = 0; s < 3; ++s)
@@ -459,9 +459,9 @@ int32_t init_solve(rt_solve *h, const rt_grid_desc *d, const Plan &p, char *ws, 
     }
 
     rtk::CellLaunch c = cell_launch(h, 0.0);
-    // the per-bin march table in the march precision (at most 7 x 8 values)
-    double tab[7 * kMaxSupportedBins];
-    float tab_f[7 * kMaxSupportedBins];
+    // the per-bin march table in the march precision
+    double tab[rtk::kTabRows * kMaxSupportedBins];
+    float tab_f[rtk::kTabRows * kMaxSupportedBins];
     const int ntab = march_table(d, p, tab);
     for (int i = 0; i < ntab; ++i) tab_f[i] = (float)tab[i];
     const void *tab_src = p.fp64 ? (const void *)tab : (const void *)tab_f;

@@ -19,20 +19,10 @@ template <> struct Vec4<float> { using T = float4; };
 template <> struct Vec4<double> { using T = double4; };
 
 // Per-bin table of the march precision, [7][MB]: cross-sections of HI, HeI,
-// HeII, their heat factors (erg), then E_j - E_th,HI (erg).  Read through the constant address
-// space: the indices are uniform, so the values live in scalar registers.
+// HeII, their heat factors (erg), then E_j - E_th,HI (erg).  Read through the
+// constant address space: the indices are uniform, so the values live in
+// scalar registers.
 template <typename R> using CTab = const __attribute__((address_space(4))) R *;
-
-// The per-bin table of one monochromatic solve held in registers, indexed like
-// the [7][1] table in memory (rows 0-2 cross-sections, 3-5 heat factors, 6 the
-// hydrogen heat factor); a march whose lanes carry packets of different solves
-// passes this instead of a pointer.  Indices are compile-time constants once
-// the bin loops are unrolled, so the lookup folds away.
-template <typename R>
-struct LaneTab1 {
-    R sig, heat;
-    __device__ __forceinline__ R operator[](int i) const { return i == 0 ? sig : (i == 3 || i == 6 ? heat : R(0)); }
-};
 
 constexpr uint32_t kNeg = 0x80000000u;      // sign flag packed above |c| (|c| <= 2^20)
 constexpr uint32_t kMag = 0x00ffffffu;
@@ -78,11 +68,11 @@ struct RegTab {
 // would not fit the scalar registers).
 template <typename R, int MB, bool F64 = std::is_same<R, double>::value>
 struct MarchTab {
-    using type = RegTab<R, 7 * MB>;
+    using type = RegTab<R, kTabRows * MB>;
     __device__ __forceinline__ static type make(CTab<R> t) {
         type r;
 #pragma unroll
-        for (int i = 0; i < 7 * MB; ++i) r.v[i] = t[i];
+        for (int i = 0; i < kTabRows * MB; ++i) r.v[i] = t[i];
         return r;
     }
 };
@@ -129,77 +119,141 @@ __device__ __forceinline__ float column_depth(float sH, float sHe1, float sHe2, 
 // Bins outside `wbins` (wave-uniform; a superset of the bins the wavefront's
 // crossing lanes still carry, e.g. from wave_bins) are skipped: every crossing
 // lane holds exactly 0 photons in them, so skipping changes nothing.
-template <typename R, int S, bool TH, int MB, int NA = 0, int NB = 0, typename KV, typename TT>
-__device__ __forceinline__ void cross_cell(R l, const KV &kap, TT tab, R (&F)[MB],
-                                           R (&D)[DepthState<R, S, MB>::N], R &absorbed, R &e0, R &e1,
-                                           R &e2, R &heat, R &tmin, uint32_t wbins = ~0u) {
-    constexpr bool SKIP = !std::is_same<R, double>::value && MB > 1;
-    constexpr bool F64 = std::is_same<R, double>::value;
-    R kH, kHe1 = R(0), kHe2 = R(0);
+//
+// The float32 form forms each bin's optical depth from the cell's columns,
+// tau_j = sum_s (l kappa_s) sigma_s,j, and works with q_j = (1 - e^-tau_j) /
+// tau_j: the absorbed photons are d_j = F_j q_j tau_j, and d_j / K_j =
+// l F_j q_j, so the split among absorbers needs no division by K_j: per
+// absorber (l kappa_s) sum_j sigma_s,j F_j q_j, and the heat likewise.  q_j
+// comes from its Taylor series below tau = kSeriesTau (truncation after the
+// tau^4 term, relative error below tau^5/720 = 4.2e-8) and from 1 - e^-tau_j
+// (the hardware 2^x) times the hardware reciprocal above (relative error a
+// few times 1e-7 just above the switch, where 1 - e^-tau_j cancels most, and
+// smaller beyond).  The transmitted part is F_j - d_j below the switch and
+// F_j e^-tau_j above it, so an opaque cell's remainder keeps its digits.
+constexpr float kSeriesTau = 0.125f;
+
+__device__ __forceinline__ float absorbed_over_depth(float t) {
+    // 1 - t/2 + t^2/6 - t^3/24 + t^4/120
+    float q = __builtin_fmaf(t, 0.008333333767950535f, -0.0416666679084301f);
+    q = __builtin_fmaf(t, q, 0.1666666716337204f);
+    q = __builtin_fmaf(t, q, -0.5f);
+    return __builtin_fmaf(t, q, 1.0f);
+}
+
+template <int S, bool TH, int MB, int NA, int NB, typename KV, typename TT>
+__device__ __forceinline__ void cross_cell_f32(float l, const KV &kap, TT tab, float (&F)[MB],
+                                               float (&D)[S == 1 ? 1 : 3], float &absorbed, float &e0,
+                                               float &e1, float &e2, float &heat, uint32_t wbins) {
+    float kH, kHe1 = 0.0f, kHe2 = 0.0f;
     if constexpr (S == 1) kH = kap;
     else { kH = kap.x; kHe1 = kap.y; kHe2 = kap.z; }
-    if constexpr (!F64) {
-        // column densities through the end of this cell
-        D[0] = __builtin_fmaf(l, kH, D[0]);
-        if (S == 3) {
-            D[1] = __builtin_fmaf(l, kHe1, D[1]);
-            D[2] = __builtin_fmaf(l, kHe2, D[2]);
-        }
+    // column densities through the end of this cell
+    D[0] = __builtin_fmaf(l, kH, D[0]);
+    if (S == 3) {
+        D[1] = __builtin_fmaf(l, kHe1, D[1]);
+        D[2] = __builtin_fmaf(l, kHe2, D[2]);
     }
-    R ab = R(0), g0 = R(0), g1 = R(0), g2 = R(0), h0 = R(0), h1 = R(0), h2 = R(0);
-    R dH = R(0), qH = R(0);     // bins absorbed by hydrogen alone (j < NA): photons, heat
-    R tm = R(INFINITY);
+    // the cell's columns l kappa_s
+    const float cH = l * kH, cHe1 = S == 3 ? l * kHe1 : 0.0f, cHe2 = S == 3 ? l * kHe2 : 0.0f;
+    float ab = 0.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, h0 = 0.0f, h1 = 0.0f, h2 = 0.0f;
+    float dH = 0.0f, qH = 0.0f;     // bins absorbed by hydrogen alone (j < NA): photons, heat
 #pragma unroll
     for (int j = 0; j < MB; ++j) {
-        if constexpr (SKIP) {
+        if constexpr (MB > 1) {
             if (!((wbins >> j) & 1u)) continue;
         }
-        struct { R x, y, z; } sg = {tab[j], tab[MB + j], tab[2 * MB + j]};
         // helium terms of a bin below a helium threshold are zero: with a bin
         // layout known at compile time (the first NA bins hydrogen only, the
         // next NB without HeII; checked on the table by the host) they are
         // skipped, which adds nothing and changes no bit
         const bool he1 = S == 3 && j >= NA, he2 = S == 3 && j >= NA + NB;   // constant once unrolled
-        R K;
-        if (S == 1) K = kH * sg.x;
-        else if (F64) {
-            K = kH * sg.x;
-            if (he1) K = K + kHe1 * sg.y;
-            if (he2) K = K + kHe2 * sg.z;
+        float t = cH * tab[j];
+        if (he1) t = __builtin_fmaf(cHe1, tab[MB + j], t);
+        if (he2) t = __builtin_fmaf(cHe2, tab[2 * MB + j], t);
+        const float tr = __builtin_amdgcn_exp2f(-1.4426950408889634f * t);
+        const float qs = absorbed_over_depth(t);
+        const bool lo = t < kSeriesTau;
+        float d;
+        if (S == 3 && j >= NA) {
+            // several absorbers share the bin: F_j q_j = d_j / tau_j weighs them
+            const float q = lo ? qs : (1.0f - tr) * __builtin_amdgcn_rcpf(t);
+            const float gk = F[j] * q;
+            d = gk * t;
+            g0 = __builtin_fmaf(tab[j], gk, g0);
+            if (he1) g1 = __builtin_fmaf(tab[MB + j], gk, g1);
+            if (he2) g2 = __builtin_fmaf(tab[2 * MB + j], gk, g2);
+            if (TH) {
+                h0 = __builtin_fmaf(tab[3 * MB + j], gk, h0);
+                if (he1) h1 = __builtin_fmaf(tab[4 * MB + j], gk, h1);
+                if (he2) h2 = __builtin_fmaf(tab[5 * MB + j], gk, h2);
+            }
         } else {
-            K = kH * sg.x;
-            if (he1) K = __builtin_fmaf(kHe1, sg.y, K);
-            if (he2) K = __builtin_fmaf(kHe2, sg.z, K);
+            // hydrogen alone absorbs: its share is 1, its heat E_j - E_th,HI
+            d = F[j] * (lo ? qs * t : 1.0f - tr);
+            if (S == 3) {
+                dH += d;
+                if (TH) qH = __builtin_fmaf(d, tab[6 * MB + j], qH);
+            } else if (TH) {
+                h0 = __builtin_fmaf(d, tab[3 * MB + j], h0);
+            }
         }
-        const R tau = l * K;
-        R d;
-        if constexpr (F64) {
+        F[j] = lo ? F[j] - d : F[j] * tr;
+        ab += d;
+    }
+    absorbed = ab;
+    if (S == 1) {
+        e0 = ab;
+        e1 = e2 = 0.0f;
+        heat = h0;
+    } else {
+        e0 = __builtin_fmaf(cH, g0, dH);
+        e1 = cHe1 * g1;
+        e2 = cHe2 * g2;
+        heat = TH ? __builtin_fmaf(cHe2, h2, __builtin_fmaf(cHe1, h1, __builtin_fmaf(cH, h0, qH))) : 0.0f;
+    }
+}
+
+template <typename R, int S, bool TH, int MB, int NA = 0, int NB = 0, typename KV, typename TT>
+__device__ __forceinline__ void cross_cell(R l, const KV &kap, TT tab, R (&F)[MB],
+                                           R (&D)[DepthState<R, S, MB>::N], R &absorbed, R &e0, R &e1,
+                                           R &e2, R &heat, R &tmin, uint32_t wbins = ~0u) {
+    if constexpr (!std::is_same<R, double>::value) {
+        cross_cell_f32<S, TH, MB, NA, NB>(l, kap, tab, F, D, absorbed, e0, e1, e2, heat, wbins);
+        tmin = R(INFINITY);
+    } else {
+        // float64 form: the oracle's order of operations, no contraction
+        R kH, kHe1 = R(0), kHe2 = R(0);
+        if constexpr (S == 1) kH = kap;
+        else { kH = kap.x; kHe1 = kap.y; kHe2 = kap.z; }
+        R ab = R(0), g0 = R(0), g1 = R(0), g2 = R(0), h0 = R(0), h1 = R(0), h2 = R(0);
+        R dH = R(0), qH = R(0);     // bins absorbed by hydrogen alone (j < NA): photons, heat
+        R tm = R(INFINITY);
+#pragma unroll
+        for (int j = 0; j < MB; ++j) {
+            struct { R x, y, z; } sg = {tab[j], tab[MB + j], tab[2 * MB + j]};
+            const bool he1 = S == 3 && j >= NA, he2 = S == 3 && j >= NA + NB;   // constant once unrolled
+            R K = kH * sg.x;
+            if (S == 3) {
+                if (he1) K = K + kHe1 * sg.y;
+                if (he2) K = K + kHe2 * sg.z;
+            }
+            const R tau = l * K;
             // absorbed share 1 - e^-tau and transmitted share e^-tau, each
             // with a few ulp of relative error at every tau (an opaque cell's
             // remainder keeps its digits)
             double em, tr;
             attenuation(tau, em, tr);
-            d = F[j] * em;
+            const R d = F[j] * em;
             F[j] = F[j] * tr;
             D[j] = D[j] + tau;
             tm = D[j] < tm ? D[j] : tm;
-        } else {
-            float em, tr;
-            attenuation(tau, em, tr);
-            d = F[j] * em;
-            F[j] = F[j] * tr;
-        }
-        ab += d;
-        if (S == 3 && j < NA) {
-            // hydrogen alone absorbs here: its share is 1, its heat E_j - E_th,HI
-            dH += d;
-            if (TH) {
-                if constexpr (F64) qH += d * tab[6 * MB + j];
-                else qH = __builtin_fmaf(d, tab[6 * MB + j], qH);
-            }
-        } else if constexpr (F64) {
-            // float64 form: the oracle's order, no contraction
-            if (S == 1) {
+            ab += d;
+            if (S == 3 && j < NA) {
+                // hydrogen alone absorbs here: its share is 1, its heat E_j - E_th,HI
+                dH += d;
+                if (TH) qH += d * tab[6 * MB + j];
+            } else if (S == 1) {
                 if (TH) h0 += d * tab[3 * MB + j];
             } else {
                 const R gk = K > R(0) ? d / K : R(0);
@@ -212,38 +266,18 @@ __device__ __forceinline__ void cross_cell(R l, const KV &kap, TT tab, R (&F)[MB
                     if (he2) h2 += tab[5 * MB + j] * gk;
                 }
             }
-        } else {
-            if (S == 1) {
-                if (TH) h0 = __builtin_fmaf(d, tab[3 * MB + j], h0);
-            } else {
-                // d_j / K_j; K_j = 0 only where d_j = 0
-                const float gk = d * __builtin_amdgcn_rcpf(fmaxf(K, 1e-30f));
-                g0 = __builtin_fmaf(sg.x, gk, g0);
-                if (he1) g1 = __builtin_fmaf(sg.y, gk, g1);
-                if (he2) g2 = __builtin_fmaf(sg.z, gk, g2);
-                if (TH) {
-                    h0 = __builtin_fmaf(tab[3 * MB + j], gk, h0);
-                    if (he1) h1 = __builtin_fmaf(tab[4 * MB + j], gk, h1);
-                    if (he2) h2 = __builtin_fmaf(tab[5 * MB + j], gk, h2);
-                }
-            }
         }
-    }
-    absorbed = ab;
-    tmin = tm;
-    if (S == 1) {
-        e0 = ab;
-        e1 = e2 = R(0);
-        heat = h0;
-    } else {
-        e0 = kH * g0 + dH;
-        e1 = kHe1 * g1;
-        e2 = kHe2 * g2;
-        if (TH) {
-            if (F64) heat = ((kH * h0 + kHe1 * h1) + kHe2 * h2) + qH;
-            else heat = __builtin_fmaf(kHe2, h2, __builtin_fmaf(kHe1, h1, __builtin_fmaf(kH, h0, qH)));
+        absorbed = ab;
+        tmin = tm;
+        if (S == 1) {
+            e0 = ab;
+            e1 = e2 = R(0);
+            heat = h0;
         } else {
-            heat = R(0);
+            e0 = kH * g0 + dH;
+            e1 = kHe1 * g1;
+            e2 = kHe2 * g2;
+            heat = TH ? ((kH * h0 + kHe1 * h1) + kHe2 * h2) + qH : R(0);
         }
     }
 }

@@ -184,29 +184,7 @@ __device__ __forceinline__ bool slot_cell(const GridGeom &G, uint32_t slot, int 
 }
 
 // ---------------------------------------------------------------------------
-// Attenuation factors of one cell in float32: em = 1 - exp(-tau) and
-// tr = exp(-tau), each with a small relative error at every tau >= 0.
-// 1 - expf(-tau) alone would lose all digits of em for tau ~ 1e-8, and
-// 1 - em would lose those of tr for tau >> 1 (the transmitted fraction of an
-// opaque cell), so each comes from the form that is accurate where it is used:
-// below tau = 0.25 em is the Taylor series of 1 - e^-t to t^6 (truncation
-// t^6/5040 < 5e-8 relative, under float32 rounding) and tr = 1 - em; above,
-// tr = 2^(-tau log2 e) from the hardware exponential and em = 1 - tr.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void attenuation(float t, float &em, float &tr) {
-    float p = __builtin_fmaf(t, -1.0f / 720.0f, 1.0f / 120.0f);
-    p = __builtin_fmaf(t, p, -1.0f / 24.0f);
-    p = __builtin_fmaf(t, p, 1.0f / 6.0f);
-    p = __builtin_fmaf(t, p, -0.5f);
-    p = __builtin_fmaf(t, p, 1.0f);
-    const float small = t * p;
-    const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * t);
-    const bool lo = t < 0.25f;
-    em = lo ? small : 1.0f - e;
-    tr = lo ? 1.0f - small : e;
-}
-
-// Float64 form of the same pair, em = 1 - e^-t and tr = e^-t, both from one
+// Attenuation factors of one cell in float64, em = 1 - e^-t and tr = e^-t, both from one
 // range reduction (Cody & Waite: -t = k ln2 + r, |r| <= ln2 / 2, ln2 split in
 // two parts so k ln2 is exact) and one Taylor polynomial p = e^r - 1 to r^13
 // (truncation below 2e-17 relative): tr = 2^k (1 + p) and

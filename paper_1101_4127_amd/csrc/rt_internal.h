@@ -8,6 +8,7 @@ namespace rtk {
 
 constexpr int kMaxBins = 16;
 constexpr int kMarchBlock = 256;          // threads per march block (4 wavefronts)
+constexpr int kTabRows = 7;               // rows of the per-bin march table ([rows][bins])
 #define RT_TRACE_HDR_DEV 8                // int32 header words of a trace record
 
 struct GridGeom {

@@ -21,6 +21,7 @@ constexpr int kMaxMarchBlocks = 8192;                // ledger slots reserved in
 constexpr size_t kAlign = 256;
 const double kThresholdEv[3] = {13.598434, 24.587387, 54.417760};
 const double kEvErg = 1.602176634e-12;
+const double kLog2e = 1.4426950408889634;            // log2(e)
 
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
@@ -216,7 +217,9 @@ int32_t make_plan(const rt_grid_desc *d, int64_t max_sources, Plan *p) {
 // (float32 form: in units of 1e-18 cm^2, lengths then in 1e18 cm, so optical
 // depths stay far from the float32 range limits).  Rows 3-5: heat factors in
 // erg: pure hydrogen E_j - E_th,HI; H+He sigma_s,j (E_j - E_th,s).  Row 6:
-// E_j - E_th,HI in erg.
+// E_j - E_th,HI in erg.  The float32 form's table holds rows 0-2, and for H+He
+// rows 3-5, times log2(e), formed in float64 (its optical depths come in units
+// of ln 2).
 int march_table(const rt_grid_desc *d, const Plan &p, double *t) {
     const int n = rtk::kTabRows * p.mb;
     for (int i = 0; i < n; ++i) t[i] = 0.0;
@@ -231,6 +234,10 @@ int march_table(const rt_grid_desc *d, const Plan &p, double *t) {
             t[(size_t)(3 + s) * p.mb + j] = p.species == 1 ? de : sig * scale * de;
             if (s == 0) t[(size_t)6 * p.mb + j] = de;
         }
+    if (!p.fp64) {
+        const int rows = p.species == 3 ? 6 : 3;
+        for (int i = 0; i < rows * p.mb; ++i) t[i] *= kLog2e;
+    }
     return n;
 }
 

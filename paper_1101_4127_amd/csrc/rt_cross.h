@@ -19,9 +19,11 @@ template <> struct Vec4<float> { using T = float4; };
 template <> struct Vec4<double> { using T = double4; };
 
 // Per-bin table of the march precision, [7][MB]: cross-sections of HI, HeI,
-// HeII, their heat factors (erg), then E_j - E_th,HI (erg).  Read through the
-// constant address space: the indices are uniform, so the values live in
-// scalar registers.
+// HeII, their heat factors (erg), then E_j - E_th,HI (erg).  The float32
+// form's table holds the cross-sections (and the H+He heat factors, which
+// carry one) times log2(e), so its optical depths come in units of ln 2 (see
+// cross_cell).  Read through the constant address space: the indices are
+// uniform, so the values live in scalar registers.
 template <typename R> using CTab = const __attribute__((address_space(4))) R *;
 
 constexpr uint32_t kNeg = 0x80000000u;      // sign flag packed above |c| (|c| <= 2^20)
@@ -96,6 +98,10 @@ __device__ __forceinline__ uint32_t wave_bins(bool lane_on, uint32_t active) {
 // Depth below which the float32 form keeps computing a bin whatever tau_kill.
 constexpr float kDropDepth = 30.0f;
 
+// An optical depth in the float32 form's units (ln 2): tau log2(e), rounded
+// once to float32.
+__device__ __forceinline__ float depth_threshold(double tau) { return (float)(tau * 1.4426950408889634); }
+
 // Optical depth T = sigma_HI N_HI + sigma_HeI N_HeI + sigma_HeII N_HeII of one
 // bin from a packet's column densities (float32 form), in one fixed order of
 // operations used by every test that compares it with tau_kill.
@@ -120,25 +126,28 @@ __device__ __forceinline__ float column_depth(float sH, float sHe1, float sHe2, 
 // crossing lanes still carry, e.g. from wave_bins) are skipped: every crossing
 // lane holds exactly 0 photons in them, so skipping changes nothing.
 //
-// The float32 form forms each bin's optical depth from the cell's columns,
-// tau_j = sum_s (l kappa_s) sigma_s,j, and works with q_j = (1 - e^-tau_j) /
-// tau_j: the absorbed photons are d_j = F_j q_j tau_j, and d_j / K_j =
-// l F_j q_j, so the split among absorbers needs no division by K_j: per
-// absorber (l kappa_s) sum_j sigma_s,j F_j q_j, and the heat likewise.  q_j
-// comes from its Taylor series below tau = kSeriesTau (truncation after the
-// tau^4 term, relative error below tau^5/720 = 4.2e-8) and from 1 - e^-tau_j
-// (the hardware 2^x) times the hardware reciprocal above (relative error a
-// few times 1e-7 just above the switch, where 1 - e^-tau_j cancels most, and
-// smaller beyond).  The transmitted part is F_j - d_j below the switch and
-// F_j e^-tau_j above it, so an opaque cell's remainder keeps its digits.
-constexpr float kSeriesTau = 0.125f;
+// The float32 form forms each bin's optical depth in units of ln 2 from the
+// cell's columns and the table's scaled cross-sections,
+// t_j = tau_j log2(e) = sum_s (l kappa_s)(sigma_s,j log2(e)), so e^-tau_j is
+// the hardware 2^-t_j.  With q_j = (1 - 2^-t_j) / t_j the absorbed photons
+// are d_j = F_j q_j t_j, and d_j / K_j = l log2(e) F_j q_j, so the split among
+// absorbers needs no division by K_j: per absorber
+// (l kappa_s) sum_j (sigma_s,j log2(e)) F_j q_j, and the heat likewise from
+// the scaled heat factors.  q_j comes from its Taylor series below
+// t = kSeriesT (tau = 1/8; truncation after the tau^4 term, relative error
+// below tau^5/720 = 4.2e-8) and from 1 - 2^-t_j times the hardware
+// reciprocal above (relative error a few times 1e-7 just above the switch,
+// where 1 - 2^-t_j cancels most, and smaller beyond).  The transmitted part
+// is F_j - d_j below the switch and F_j 2^-t_j above it, so an opaque cell's
+// remainder keeps its digits.
+constexpr float kSeriesT = 0.1803368777036667f;   // tau = 1/8 in units of ln 2
 
 __device__ __forceinline__ float absorbed_over_depth(float t) {
-    // 1 - t/2 + t^2/6 - t^3/24 + t^4/120
-    float q = __builtin_fmaf(t, 0.008333333767950535f, -0.0416666679084301f);
-    q = __builtin_fmaf(t, q, 0.1666666716337204f);
-    q = __builtin_fmaf(t, q, -0.5f);
-    return __builtin_fmaf(t, q, 1.0f);
+    // ln2 (1 - u/2 + u^2/6 - u^3/24 + u^4/120) with u = t ln2
+    float q = __builtin_fmaf(t, 0.0013333557872101665f, -0.009618128649890423f);
+    q = __builtin_fmaf(t, q, 0.05550410971045494f);
+    q = __builtin_fmaf(t, q, -0.24022650718688965f);
+    return __builtin_fmaf(t, q, 0.6931471824645996f);
 }
 
 template <int S, bool TH, int MB, int NA, int NB, typename KV, typename TT>
@@ -171,12 +180,12 @@ __device__ __forceinline__ void cross_cell_f32(float l, const KV &kap, TT tab, f
         float t = cH * tab[j];
         if (he1) t = __builtin_fmaf(cHe1, tab[MB + j], t);
         if (he2) t = __builtin_fmaf(cHe2, tab[2 * MB + j], t);
-        const float tr = __builtin_amdgcn_exp2f(-1.4426950408889634f * t);
+        const float tr = __builtin_amdgcn_exp2f(-t);
         const float qs = absorbed_over_depth(t);
-        const bool lo = t < kSeriesTau;
+        const bool lo = t < kSeriesT;
         float d;
         if (S == 3 && j >= NA) {
-            // several absorbers share the bin: F_j q_j = d_j / tau_j weighs them
+            // several absorbers share the bin: F_j q_j = d_j / t_j weighs them
             const float q = lo ? qs : (1.0f - tr) * __builtin_amdgcn_rcpf(t);
             const float gk = F[j] * q;
             d = gk * t;
@@ -286,7 +295,8 @@ __device__ __forceinline__ void cross_cell(R l, const KV &kap, TT tab, R (&F)[MB
 // cells into the next: a bin whose optical depth T_j has reached tau_drop
 // leaves the packet (its bit cleared in `active`, its remaining photons
 // returned for the truncated ledger).  The caller passes
-// tau_drop = max(tau_kill, kDropDepth): a bin so dropped keeps at most e^-30
+// tau_drop = depth_threshold(max(tau_kill, kDropDepth)) (depths in units of
+// ln 2, as the table's cross-sections): a bin so dropped keeps at most e^-30
 // (9.4e-14) of its share.  Decided from the packet's own history at tile
 // boundaries, so every march organisation drops the same bins at the same
 // cells; T_j is formed as in the extinction test (zero helium cross-sections
@@ -317,7 +327,8 @@ __device__ __forceinline__ float drop_exhausted(TT tab, uint32_t &active, float 
 }
 
 // Extinction test of the float32 form: a packet ends once every bin the
-// source populates has T_j = sum_s sigma_s,j N_s >= tau_kill.  The packet
+// source populates has T_j = sum_s sigma_s,j N_s >= tau_kill (both in units
+// of ln 2: the table's scaled cross-sections, depth_threshold(tau_kill)).  The packet
 // keeps a witness bin whose T_j was below tau_kill at the last full check;
 // as long as the witness stays below, some bin is (so the packet lives) and
 // one T_j is formed per crossing instead of all of them.  When the witness
@@ -383,7 +394,7 @@ struct DepthTest {
     __device__ __forceinline__ bool extinguished(TT tab, uint32_t active, double tau_kill, R tmin,
                                                  const R (&D)[DepthState<R, S, MB>::N]) {
         if constexpr (F64) return tmin >= tau_kill;
-        else return ext.extinguished(tab, active, (float)tau_kill, D);
+        else return ext.extinguished(tab, active, depth_threshold(tau_kill), D);
     }
 };
 

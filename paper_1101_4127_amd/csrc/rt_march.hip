@@ -295,7 +295,7 @@ __global__ void __launch_bounds__(kMarchBlock, (MarchOcc<R, MB>::value)) k_march
                 // tile of 8^3 cells leave it (as in the tiled march)
                 const bool next_tile = ((here_k0 ^ k0) | (here_k1 ^ k1) | (here_k2 ^ k2)) >> 3 != 0;
                 if (fate == 0 && next_tile)
-                    dropf += drop_exhausted<S, MB, NA, NB>(tab, active, fmaxf((float)p.tau_kill, kDropDepth), D, F);
+                    dropf += drop_exhausted<S, MB, NA, NB>(tab, active, depth_threshold(fmax(p.tau_kill, (double)kDropDepth)), D, F);
             }
             if (fate == 0) {
                 slot = nslot;

@@ -1039,6 +1039,9 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
         const int ty = (int)((tile / (uint32_t)geo.nb[0]) % (uint32_t)geo.nb[1]);
         const int tz = (int)(tile / ((uint32_t)geo.nb[0] * (uint32_t)geo.nb[1]));
         const double tau_kill = rs.tau_kill;
+        // float32 form: the extinction and drop depths in units of ln 2
+        const float kill_t = depth_threshold(tau_kill);
+        const float drop_t = depth_threshold(fmax(tau_kill, (double)kDropDepth));
         const CTab<R> ctab = (CTab<R>)rs.tab;
         if (!F64 && threadIdx.x < 3 * MB) s_sigf[threadIdx.x] = (float)ctab[threadIdx.x];
         const typename MarchTab<R, MB>::type tab = MarchTab<R, MB>::make(ctab);
@@ -1094,7 +1097,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
             uint32_t st_nesc = 0, st_ntrunc = 0;
             if (trigger && npend != 0u && pend) {
                 bool ex = kill;
-                if constexpr (!F64) ex = kill && dtest.ext.full(tab, active, (float)tau_kill, D);
+                if constexpr (!F64) ex = kill && dtest.ext.full(tab, active, kill_t, D);
                 // (periodic: the cell has been wrapped at the crossing; "out" is
                 // the end of the packet's path)
                 const bool o0 = !PER && (uint32_t)k0 >= (uint32_t)geo.n[0];
@@ -1112,7 +1115,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                 if constexpr (!F64 && MB > 1) {
                     // float32 form: bins exhausted at the tile boundary leave the packet
                     if (fate == 3u)
-                        dropf += drop_exhausted<S, MB, NA, NB>(tab, active, fmaxf((float)tau_kill, kDropDepth), D, F,
+                        dropf += drop_exhausted<S, MB, NA, NB>(tab, active, drop_t, D, F,
                                                                wbins);
                 }
                 if (fate != 0u) {                  // fate 0: a new witness bin, the packet marches on
@@ -1368,7 +1371,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                 if constexpr (TR) hlast = here;
                 if constexpr (F64) kill = tmin >= tau_kill;
                 else kill = Extinction<S, MB>::depth(dtest.ext.wH, dtest.ext.wHe1, dtest.ext.wHe2, D)
-                            >= (float)tau_kill;
+                            >= kill_t;
                 if constexpr (FIN) {
                     // into the next tile without a hand-over: the bins exhausted at
                     // the boundary leave the packet there all the same (the order
@@ -1379,7 +1382,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                         lty = k1 >> kTileLog2;
                         ltz = k2 >> kTileLog2;
                         if constexpr (!F64 && MB > 1)
-                            dropf += drop_exhausted<S, MB, NA, NB>(tab, active, fmaxf((float)tau_kill, kDropDepth), D,
+                            dropf += drop_exhausted<S, MB, NA, NB>(tab, active, drop_t, D,
                                                                    F, wbins);
                     }
                     pend = kill || out;

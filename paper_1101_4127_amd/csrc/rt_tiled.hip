@@ -525,10 +525,20 @@ __global__ void __launch_bounds__(kTBlock) k_bemit(const TParams p) {
     }
 }
 
-// First fused packet id of every solve in this round (round_packets summed in
-// table order; one block of kMaxBatch threads, one solve each); a round beyond
-// the records is flagged.
-__global__ void __launch_bounds__(kMaxBatch) k_bfirst(const TParams p) {
+// Start of a round of a fused step.  Block 0: the first fused packet id of
+// every solve in this round (round_packets summed in table order, one thread
+// per solve); a round beyond the records is flagged.  Every block: the ledger
+// slots of the call's solves ([solve][march block]) cleared.
+__global__ void __launch_bounds__(kMaxBatch) k_bstart(const TParams p) {
+    {
+        const uint32_t ns = (uint32_t)p.hd->n * p.nblocks;
+        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += gridDim.x * blockDim.x) {
+            LedgerSlot &sl = p.slots[i];
+            for (int k = 0; k < 8; ++k) sl.s[k] = 0.0;
+            for (int k = 0; k < 4; ++k) sl.c[k] = 0ull;
+        }
+    }
+    if (blockIdx.x != 0) return;
     __shared__ unsigned long long s_w[kMaxBatch / 64];
     const int n = p.hd->n;
     const int b = threadIdx.x;
@@ -880,28 +890,31 @@ __global__ void __launch_bounds__(kScanBlock) k_tscan_a(const TParams p) {
     }
 }
 
-__global__ void __launch_bounds__(kScanBlock) k_tscan_b(const TParams p, uint32_t nblk, int nxt) {
-    const uint32_t i = threadIdx.x;
-    uint32_t a = i < nblk ? p.bsum[2 * i] : 0u, b = i < nblk ? p.bsum[2 * i + 1] : 0u;
-    uint32_t ta, tb;
-    block_scan2(a, b, ta, tb);
-    if (i < nblk) {
-        p.bsum[2 * i] = a;
-        p.bsum[2 * i + 1] = b;
-    }
-    if (i == 0) {
-        const bool bad = ta > p.capacity || tb > p.max_chunks;
-        if (bad) p.ctrl->err |= 2u;
-        p.ctrl->total[nxt] = bad ? 0u : ta;
-        p.ctrl->n_chunks[nxt] = bad ? 0u : tb;
-        p.ctrl->claim = 0u;
-    }
-}
-
 // A run's `shared` word: bit 0 the tile has more than one run this pass, bits
 // 1 and up the solve of the tile (fused steps; 0 in a single solve).
+//
+// Every block first forms the pass's totals and its own offsets from the
+// block sums of k_tscan_a (nblk of them); block 0 publishes the totals.
 template <bool B>
-__global__ void __launch_bounds__(kScanBlock) k_tscan_c(const TParams p, int nxt) {
+__global__ void __launch_bounds__(kScanBlock) k_tscan_c(const TParams p, uint32_t nblk, int nxt) {
+    uint32_t pa = 0, pb = 0, sa = 0, sb = 0;
+    for (uint32_t i = threadIdx.x; i < nblk; i += kScanBlock) {
+        const uint32_t x = p.bsum[2 * i], y = p.bsum[2 * i + 1];
+        sa += x;
+        sb += y;
+        if (i < blockIdx.x) { pa += x; pb += y; }
+    }
+    uint32_t base_a, base_b, total_a, total_b;
+    block_scan2(pa, pb, base_a, base_b);
+    block_scan2(sa, sb, total_a, total_b);
+    const bool bad = total_a > p.capacity || total_b > p.max_chunks;
+    const uint32_t nch = bad ? 0u : total_b;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (bad) p.ctrl->err |= 2u;
+        p.ctrl->total[nxt] = bad ? 0u : total_a;
+        p.ctrl->n_chunks[nxt] = nch;
+        p.ctrl->claim = 0u;
+    }
     const uint32_t t0 = blockIdx.x * kScanTiles + threadIdx.x * kScanPer;
     uint32_t n[kScanPer];
     uint32_t a = 0, b = 0;
@@ -914,9 +927,8 @@ __global__ void __launch_bounds__(kScanBlock) k_tscan_c(const TParams p, int nxt
     }
     uint32_t ta, tb;
     block_scan2(a, b, ta, tb);
-    a += p.bsum[2 * blockIdx.x];
-    b += p.bsum[2 * blockIdx.x + 1];
-    const uint32_t nch = p.ctrl->n_chunks[nxt];
+    a += base_a;
+    b += base_b;
     TChunk *out = nxt ? p.ch1 : p.ch0;
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
@@ -1468,16 +1480,6 @@ __global__ void k_tslots_zero(LedgerSlot *s, int n) {
     }
 }
 
-// The ledger slots of the solves of this fused call ([solve][block]).
-__global__ void k_bslots_zero(const TParams p) {
-    const uint32_t n = (uint32_t)p.hd->n * p.nblocks;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        LedgerSlot &s = p.slots[i];
-        for (int k = 0; k < 8; ++k) s.s[k] = 0.0;
-        for (int k = 0; k < 4; ++k) s.c[k] = 0ull;
-    }
-}
-
 __global__ void k_tzero_u32(uint32_t *p, uint32_t n) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
 }
@@ -1554,8 +1556,7 @@ TParams make_params(const TiledLaunch &t) {
 template <bool B = false>
 void scan_lists(const TParams &p, uint32_t scan_blocks, hipStream_t st, int nxt) {
     hipLaunchKernelGGL(k_tscan_a, dim3(scan_blocks), dim3(kScanBlock), 0, st, p);
-    hipLaunchKernelGGL(k_tscan_b, dim3(1), dim3(kScanBlock), 0, st, p, scan_blocks, nxt);
-    hipLaunchKernelGGL(k_tscan_c<B>, dim3(scan_blocks), dim3(kScanBlock), 0, st, p, nxt);
+    hipLaunchKernelGGL(k_tscan_c<B>, dim3(scan_blocks), dim3(kScanBlock), 0, st, p, scan_blocks, nxt);
 }
 
 void scan(const TParams &p, const TiledLaunch &t, int nxt) { scan_lists<false>(p, t.scan_blocks, t.m.stream, nxt); }
@@ -1743,8 +1744,7 @@ hipError_t run_bround(const BatchLaunch &b, int round) {
     const TParams p = make_bparams(b, round);
     const hipStream_t st = b.stream;
     const dim3 grid(b.blocks), blk(kTBlock);
-    hipLaunchKernelGGL(k_bfirst, dim3(1), dim3(kMaxBatch), 0, st, p);
-    hipLaunchKernelGGL(k_bslots_zero, dim3(256), dim3(256), 0, st, p);
+    hipLaunchKernelGGL(k_bstart, dim3(256), dim3(kMaxBatch), 0, st, p);
     hipLaunchKernelGGL((k_bemit<R, S, MB>), grid, blk, 0, st, p);
     scan_lists<true>(p, b.t.scan_blocks, st, 0);
     hipLaunchKernelGGL(k_tscatter_emit<true>, dim3(8 * b.blocks), blk, 0, st, p);

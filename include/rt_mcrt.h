@@ -159,7 +159,8 @@ typedef struct {
     int32_t trace_stride;         /* spacing of traced packet ids; 0 = 1 */
     int32_t run_len;              /* tiled march: packets of one tile one block
                                      marches before it writes the tile's deposits
-                                     out; 0 = default (2048), else 64..65536 */
+                                     out; 0 = default (4096; 2048 in
+                                     rt_step_many), else 64..65536 */
     int32_t park_lanes;           /* tiled march: once a run of a tile is used up,
                                      a wavefront with at most this many packets
                                      still marching writes them back; they resume

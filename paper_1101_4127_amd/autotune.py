@@ -26,7 +26,7 @@ import statistics
 from typing import Callable, Dict, List, Optional, Tuple
 
 SPACE_TILED: Dict[str, List[int]] = {
-    "run_len": [512, 1024, 2048],
+    "run_len": [1024, 2048, 4096, 8192],
     "refill_min": [8, 16, 24, 32],
     "blocks_per_cu": [0, 2, 3],
 }

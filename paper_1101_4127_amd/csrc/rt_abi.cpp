@@ -30,7 +30,8 @@ constexpr int kMaxSupportedBins = 8;   // widest compiled march instance
 int bin_capacity(int n_bins) { return n_bins <= 1 ? 1 : 8; }
 
 constexpr int64_t kDefaultInflight = (int64_t)1 << 24;   // packets in flight in the tiled march
-constexpr int kDefaultRun = 2048;                         // packets per tile run
+constexpr int kDefaultRun = 4096;                         // packets per tile run (single solve)
+constexpr int kDefaultBatchRun = 2048;                    // packets per tile run (fused steps)
 constexpr int kMaxRunLen = 1 << 16;                       // longest run a description may ask for
 
 struct Plan {
@@ -964,7 +965,7 @@ int32_t batch_shape(const rt_grid_desc *d, BatchShape *s) {
     s->mb = p.mb;
     s->thermal = p.thermal;
     s->refill_min = d->refill_min > 0 ? d->refill_min : 32;
-    s->cmax = d->run_len > 0 ? d->run_len : kDefaultRun;
+    s->cmax = d->run_len > 0 ? d->run_len : kDefaultBatchRun;
     s->bpcu = d->blocks_per_cu;
     s->finish = d->finish_pass > 0 ? (uint32_t)d->finish_pass : 0u;
     s->rec_bytes = rtk::batch_record_bytes(p.fp64, p.species, p.mb);

@@ -43,16 +43,18 @@ struct DepthState {
 
 // Exit face of the current cell by exact integer comparison of the ray
 // parameters d_a / |c_a| (all products < 2^32); ties cross several faces at
-// once.  Returns the lowest crossed axis.
+// once.  Returns the lowest crossed axis.  The 24-bit multiplies read only the
+// magnitude bits of a_a (the sign flag sits above them).  An axis the ray does
+// not move along (|c_a| = 0, d_a = 1) never wins: its two comparisons need
+// d_a |c_b| <= 0 and d_a |c_c| <= 0, i.e. both other components zero as well.
 __device__ __forceinline__ int exit_face(uint32_t d0, uint32_t d1, uint32_t d2, uint32_t a0, uint32_t a1,
                                          uint32_t a2, bool &m0, bool &m1, bool &m2) {
-    const uint32_t m0a = a0 & kMag, m1a = a1 & kMag, m2a = a2 & kMag;
-    const uint32_t p01 = __umul24(d0, m1a), p10 = __umul24(d1, m0a);
-    const uint32_t p02 = __umul24(d0, m2a), p20 = __umul24(d2, m0a);
-    const uint32_t p12 = __umul24(d1, m2a), p21 = __umul24(d2, m1a);
-    m0 = m0a != 0u && p01 <= p10 && p02 <= p20;
-    m1 = m1a != 0u && p10 <= p01 && p12 <= p21;
-    m2 = m2a != 0u && p20 <= p02 && p21 <= p12;
+    const uint32_t p01 = __umul24(d0, a1), p10 = __umul24(d1, a0);
+    const uint32_t p02 = __umul24(d0, a2), p20 = __umul24(d2, a0);
+    const uint32_t p12 = __umul24(d1, a2), p21 = __umul24(d2, a1);
+    m0 = p01 <= p10 && p02 <= p20;
+    m1 = p10 <= p01 && p12 <= p21;
+    m2 = p20 <= p02 && p21 <= p12;
     return m0 ? 0 : (m1 ? 1 : 2);
 }
 

@@ -1303,9 +1303,16 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                 }
                 int here = 0;                          // natural index, for traces only
                 if constexpr (TR) here = k0 + geo.n[0] * (k1 + geo.n[1] * k2);
-                if (m0) { k0 += (a0 & kNeg) ? -1 : 1; d0 += 2u; }
-                if (m1) { k1 += (a1 & kNeg) ? -1 : 1; d1 += 2u; }
-                if (m2) { k2 += (a2 & kNeg) ? -1 : 1; d2 += 2u; }
+                // the cell steps along the crossed axes (ties cross several)
+                const int s0 = m0 ? ((a0 & kNeg) ? -1 : 1) : 0;
+                const int s1 = m1 ? ((a1 & kNeg) ? -1 : 1) : 0;
+                const int s2 = m2 ? ((a2 & kNeg) ? -1 : 1) : 0;
+                k0 += s0;
+                k1 += s1;
+                k2 += s2;
+                if (m0) d0 += 2u;
+                if (m1) d1 += 2u;
+                if (m2) d2 += 2u;
                 bool out;
                 int dx, dy, dz;
                 if constexpr (PER) {
@@ -1326,9 +1333,13 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
                     dz = (k2 >> kTileLog2) - (FIN ? ltz : tz);
                 }
                 const bool leave = !out && (dx | dy | dz) != 0;
-                // next cell's index in the tile (masked, so it stays inside the
-                // tile; unused when the packet leaves)
-                const uint32_t nloc = local_cell(k0, k1, k2);
+                // next cell's index in the tile: one step from this cell's (unused
+                // when the packet leaves the tile in a tile pass).  Masked from the
+                // cell instead in the finishing pass (the tile the packet enters)
+                // and with periodic boundaries (a wrap can stay in the tile when an
+                // axis has one tile)
+                const uint32_t nloc = (FIN || PER) ? local_cell(k0, k1, k2)
+                                                   : (uint32_t)((int)loc + s0 + (s1 << kTileLog2) + (s2 << (2 * kTileLog2)));
                 uint32_t ngc = gcell;
                 if constexpr (FIN) {
                     // (a packet that left the grid keeps its last cell)

@@ -9,7 +9,9 @@ solve that has finished leaves its slot and memory to the next request.
 While a call runs on the GPU, the host opens (uploads) the requests that are
 next in line, for as long as the call runs, up to a batch's worth and within
 the memory budget, so that they join a later call without waiting for their
-upload.  Latency is
+upload.  Between calls at most `sync_open` requests are opened before the
+next call starts (none while solves are active and more than that are
+waiting: the backlog goes up while the calls run).  Latency is
 completion minus arrival.
 
 Host-side scheduling only: every step of every solve runs in the library's
@@ -135,10 +137,13 @@ class Server:
     def __init__(self, *, max_slots: int = rt.RT_MAX_BATCH, hbm_budget: Optional[int] = None,
                  fp64: bool = False, graph: bool = True, keep_fields: bool = True, device: str = "cuda",
                  executor=None, max_round_packets: int = rt.RT_MAX_BATCH * 100_000,
-                 max_tiles: int = rt.RT_MAX_BATCH * 512, **tiles):
+                 max_tiles: int = rt.RT_MAX_BATCH * 512, sync_open: int = 32, **tiles):
         if not 1 <= max_slots <= rt.RT_MAX_BATCH:
             raise ValueError(f"max_slots must be in 1..{rt.RT_MAX_BATCH}")
+        if sync_open < 1:
+            raise ValueError("sync_open must be at least 1")
         self.max_slots = max_slots
+        self.sync_open = int(sync_open)
         self.fp64 = fp64
         self.keep_fields = keep_fields
         self.max_round_packets = int(max_round_packets)
@@ -178,9 +183,23 @@ class Server:
         try:
             while pending or active:
                 now = clock() - t0
+                n_sync = 0                 # requests opened now, with the GPU idle
+                cap = self.sync_open
+                if overlap and active:
+                    # a backlog longer than sync_open goes up while calls run:
+                    # opening it now would hold the next call back
+                    waiting = 0
+                    for r in pending:
+                        if realtime and r.arrival_s > now:
+                            break
+                        waiting += r.rid not in opened
+                    if waiting > self.sync_open:
+                        cap = 0
                 while pending and (not realtime or pending[0].arrival_s <= now):
                     r = pending[0]
                     ahead = r.rid in opened
+                    if overlap and not ahead and n_sync >= cap:
+                        break              # the rest go up while the next call runs
                     if not (admissible(0 if ahead else need[r.rid], used, len(active), self.max_slots,
                                        self.hbm_budget)
                             and fits_batch(pk[r.rid], tl[r.rid], used_pk, used_tl, self.max_round_packets,
@@ -191,6 +210,7 @@ class Server:
                         s = opened.pop(r.rid)
                     else:
                         s = self.ex.open(r.work)
+                        n_sync += 1
                         used += need[r.rid]
                     used_pk += pk[r.rid]
                     used_tl += tl[r.rid]

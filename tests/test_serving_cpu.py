@@ -196,3 +196,34 @@ def test_a_failed_run_closes_its_solves(monkeypatch):
     with pytest.raises(RuntimeError):
         srv.run(reqs, realtime=False, clock=clock)
     assert not ex.open_now
+
+
+def test_backlog_is_opened_while_calls_run(monkeypatch):
+    """All present, a backlog longer than sync_open: only sync_open requests
+    are opened before the first call; every later one goes up while a call
+    runs, and all are served in arrival order."""
+    reqs = W.serving_stream(count=40, seed=10, sides=(16,), log_packets=(4.0, 4.2), rate_per_s=500.0)
+    clock = FakeClock()
+    monkeypatch.setattr(serve.time, "sleep", lambda s: setattr(clock, "t", clock.t + s))
+
+    class Counting(FakeAsyncExecutor):
+        opened_between_calls = 0
+
+        def open(self, work):
+            if self.pending is None:
+                self.opened_between_calls += 1
+            return super().open(work)
+
+    ex = Counting(clock)
+    srv = serve.Server(max_slots=16, hbm_budget=1 << 40, executor=ex, keep_fields=False, sync_open=4)
+    out = srv.run(reqs, realtime=False, clock=clock)
+    assert [o.rid for o in out] == [r.rid for r in reqs]
+    assert not ex.open_now
+    assert len(ex.calls[0]) == 4
+    assert ex.opened_between_calls == 4 and ex.opened_during_call == len(reqs) - 4
+    assert max(len(c) for c in ex.calls) == 16
+
+
+def test_server_rejects_a_zero_sync_open():
+    with pytest.raises(ValueError):
+        serve.Server(max_slots=4, hbm_budget=1 << 30, executor=FakeExecutor(FakeClock()), sync_open=0)

@@ -10,7 +10,7 @@ While a call runs on the GPU, the host opens (uploads) the requests that are
 next in line, for as long as the call runs, up to a batch's worth and within
 the memory budget, so that they join a later call without waiting for their
 upload.  Between calls at most `sync_open` requests are opened before the
-next call starts (none while solves are active and more than that are
+next call starts (none once the batch is half full and more than that are
 waiting: the backlog goes up while the calls run).  Latency is
 completion minus arrival.
 
@@ -185,9 +185,10 @@ class Server:
                 now = clock() - t0
                 n_sync = 0                 # requests opened now, with the GPU idle
                 cap = self.sync_open
-                if overlap and active:
-                    # a backlog longer than sync_open goes up while calls run:
-                    # opening it now would hold the next call back
+                if overlap and 2 * len(active) >= self.max_slots:
+                    # with the batch at least half full, a backlog longer than
+                    # sync_open goes up while calls run: opening it now would
+                    # hold the next call back
                     waiting = 0
                     for r in pending:
                         if realtime and r.arrival_s > now:

@@ -1036,7 +1036,7 @@ struct rt_batch {
     hipEvent_t staged;             // the last table copy has been read
     bool staged_pending;
     hipEvent_t done;               // end of the last fused call (its ledgers copied out)
-    std::vector<hipEvent_t> ev_in; // one per solve slot: its stream's work before the call
+    std::vector<hipEvent_t> ev_in; // one per distinct solve stream of a call: its work before the call
     std::vector<BatchGraph> graphs;
     rtk::StepLedger *ledgers;      // pinned: the solves' ledgers after the last call
     std::vector<rt_solve_t> last;  // the solves of the last call, in its order
@@ -1298,11 +1298,18 @@ int32_t rt_step_many(rt_batch_t b, const rt_solve_t *solves, int32_t n, const do
     hd->tiles = tile0;
 
     // order: each solve's earlier work, the table copy, the fused launches
+    // (one event per distinct stream: solves opened on one stream share it)
+    int n_in = 0;
     for (int i = 0; i < n; ++i) {
         const hipStream_t s = solves[i]->stream;
         if (s == b->stream) continue;
-        if (hipEventRecord(b->ev_in[i], s) != hipSuccess || hipStreamWaitEvent(b->stream, b->ev_in[i], 0) != hipSuccess)
+        bool seen = false;
+        for (int k = 0; k < i && !seen; ++k) seen = solves[k]->stream == s;
+        if (seen) continue;
+        if (hipEventRecord(b->ev_in[n_in], s) != hipSuccess ||
+            hipStreamWaitEvent(b->stream, b->ev_in[n_in], 0) != hipSuccess)
             return RT_EDEVICE;
+        ++n_in;
     }
     if (hipMemcpyAsync(b->ws + b->lay.off_head, b->staging,
                        sizeof(rtk::BatchHead) + (size_t)n * sizeof(rtk::BatchSolve), hipMemcpyHostToDevice,

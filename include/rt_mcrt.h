@@ -387,7 +387,8 @@ int32_t rt_batch_init(int32_t max_solves, const rt_grid_desc *shape, int64_t max
  * argument would be rejected by rt_step, RT_ENOMEM if the solves' tiles or one
  * round's packets exceed the batch's.  Stream-ordered: the host may go on
  * (open the next solves, say) while the call runs; a solve's own stream is
- * ordered after the call when the solve is next used.  If stats is not NULL
+ * ordered after the call when the solve is next used (by its own calls or by
+ * a call of another batch).  If stats is not NULL
  * (n entries) the call waits for itself and fills each solve's ledger, as
  * rt_batch_wait does. */
 int32_t rt_step_many(rt_batch_t b, const rt_solve_t *solves, int32_t n, const double *dt_s,

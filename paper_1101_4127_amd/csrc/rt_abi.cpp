@@ -282,9 +282,11 @@ struct rt_solve {
     double bg_ndot, bg_carried;
     int64_t bg_packets;
     uint32_t bg_active;
-    // end of the last fused call (rt_step_many) the solve was in; its stream
-    // waits for it before its next own work
+    // end of the last fused call (rt_step_many) the solve was in, recorded on
+    // that batch's stream (after_stream); the solve's stream waits for it
+    // before its next own work or a call of another batch
     hipEvent_t after;
+    hipStream_t after_stream;
     bool after_pending;
 };
 
@@ -441,6 +443,7 @@ int32_t init_solve(rt_solve *h, const rt_grid_desc *d, const Plan &p, char *ws, 
     h->ev.clear();
     h->kev.clear();
     h->after = nullptr;
+    h->after_stream = nullptr;
     h->after_pending = false;
     auto destroy_events = [h] {
         for (hipEvent_t e : h->ev) if (e) (void)hipEventDestroy(e);
@@ -1297,6 +1300,12 @@ int32_t rt_step_many(rt_batch_t b, const rt_solve_t *solves, int32_t n, const do
     hd->cells = cells;
     hd->tiles = tile0;
 
+    // a solve last stepped by another batch: its stream first waits for that
+    // call (this batch's own earlier calls are ordered by its stream)
+    for (int i = 0; i < n; ++i) {
+        rt_solve_t h = solves[i];
+        if (h->after_pending && h->after_stream != b->stream && !order_after_batch(h)) return fail(h);
+    }
     // order: each solve's earlier work, the table copy, the fused launches
     // (one event per distinct stream: solves opened on one stream share it)
     int n_in = 0;
@@ -1341,6 +1350,7 @@ int32_t rt_step_many(rt_batch_t b, const rt_solve_t *solves, int32_t n, const do
         // the solve's own stream is ordered after the call only when it is next used
         if (h->stream != b->stream) {
             if (hipEventRecord(h->after, b->stream) != hipSuccess) return fail(h);
+            h->after_stream = b->stream;
             h->after_pending = true;
         }
     }

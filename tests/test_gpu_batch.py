@@ -358,3 +358,37 @@ def test_launch_then_wait_and_ordering_of_the_solves_streams():
         s.release()
     ref_b.release()
     b.release()
+
+
+@pytest.mark.gpu
+def test_two_batches_stepping_the_same_solves_in_turn():
+    """Solves stepped by one batch and, before that call has ended, by
+    another: the second batch's call waits for the first's, so both ledgers
+    and the final state equal those of one batch stepping them every time."""
+    import torch
+    from paper_1101_4127_amd import rt
+    reqs = stream(count=3, seed=53, steps=4, n_sub=2)
+    side = torch.cuda.Stream()
+    ref_b = batch_for([r.work for r in reqs], True, True)
+    ref = [rt.Solve(r.work, fp64=True, stream=side, **TILED) for r in reqs]
+    b1 = batch_for([r.work for r in reqs], True, True)
+    b2 = batch_for([r.work for r in reqs], True, False)
+    sv = [rt.Solve(r.work, fp64=True, stream=side, **TILED) for r in reqs]
+    for _ in range(2):
+        lr = [ref_b.step(ref, stats=True), ref_b.step(ref, stats=True)]
+        b1.launch(sv)
+        b2.launch(sv)                                # while the first call may still run
+        lw = [b1.wait(), b2.wait()]
+        for a, c in zip(lr, lw):
+            for x, y in zip(a, c):
+                assert x["packets"] == y["packets"] and x["crossings"] == y["crossings"]
+                for key in ("emitted", "absorbed", "escaped", "truncated"):
+                    assert abs(x[key] - y[key]) <= 1e-12 * x["emitted"], key
+    for s, r in zip(sv, ref):
+        f, fr = s.fetch(), r.fetch()
+        assert np.max(PT.frac_err(f[1], fr[1], 1e-6)) <= 1e-9
+        assert np.max(PT.deposit_err(f[7], fr[7])) <= 1e-9
+    for s in ref + sv:
+        s.release()
+    for x in (ref_b, b1, b2):
+        x.release()

@@ -216,28 +216,32 @@ int32_t make_plan(const rt_grid_desc *d, int64_t max_sources, Plan *p) {
 // Per-bin march table, [kTabRows][mb] in the march precision, into t (returns
 // the number of values).  Rows 0-2: the cross-sections of HI, HeI, HeII
 // (float32 form: in units of 1e-18 cm^2, lengths then in 1e18 cm, so optical
-// depths stay far from the float32 range limits).  Rows 3-5: heat factors in
-// erg: pure hydrogen E_j - E_th,HI; H+He sigma_s,j (E_j - E_th,s).  Row 6:
-// E_j - E_th,HI in erg.  The float32 form's table holds rows 0-2, and for H+He
-// rows 3-5, times log2(e), formed in float64 (its optical depths come in units
-// of ln 2).
+// depths stay far from the float32 range limits; times log2(e), formed in
+// float64, since its optical depths come in units of ln 2).  Heat, in erg:
+// pure hydrogen, row 3 E_j - E_th,HI.  H+He, float64 form: rows 3-5
+// sigma_s,j (E_j - E_th,s), row 6 E_j - E_th,HI.  H+He, float32 form: row 3
+// the photon energy E_j, row 4 the thresholds E_th,s (first three entries):
+// it forms the heat as the energy of the absorbed photons less the
+// thresholds of the photons each species absorbed, one product per bin.
 int march_table(const rt_grid_desc *d, const Plan &p, double *t) {
     const int n = rtk::kTabRows * p.mb;
     for (int i = 0; i < n; ++i) t[i] = 0.0;
     const double scale = p.fp64 ? 1.0 : 1.0e18;
+    const bool energies = !p.fp64 && p.species == 3;
     for (int s = 0; s < 3; ++s)
         for (int j = 0; j < d->n_bins; ++j) {
             const double sig = d->sigma_cm2[s][j];
             // heat per absorbed photon, in erg (so the march's heat needs no
             // conversion where it is deposited)
             const double de = sig > 0.0 ? (d->e_bin_ev[j] - kThresholdEv[s]) * kEvErg : 0.0;
-            t[(size_t)s * p.mb + j] = sig * scale;
+            t[(size_t)s * p.mb + j] = sig * scale * (p.fp64 ? 1.0 : kLog2e);
+            if (energies) continue;
             t[(size_t)(3 + s) * p.mb + j] = p.species == 1 ? de : sig * scale * de;
             if (s == 0) t[(size_t)6 * p.mb + j] = de;
         }
-    if (!p.fp64) {
-        const int rows = p.species == 3 ? 6 : 3;
-        for (int i = 0; i < rows * p.mb; ++i) t[i] *= kLog2e;
+    if (energies) {
+        for (int j = 0; j < d->n_bins; ++j) t[(size_t)3 * p.mb + j] = d->e_bin_ev[j] * kEvErg;
+        for (int s = 0; s < 3; ++s) t[(size_t)4 * p.mb + s] = kThresholdEv[s] * kEvErg;
     }
     return n;
 }

@@ -167,8 +167,8 @@ __device__ __forceinline__ void cross_cell_f32(float l, const KV &kap, TT tab, f
     }
     // the cell's columns l kappa_s
     const float cH = l * kH, cHe1 = S == 3 ? l * kHe1 : 0.0f, cHe2 = S == 3 ? l * kHe2 : 0.0f;
-    float ab = 0.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, h0 = 0.0f, h1 = 0.0f, h2 = 0.0f;
-    float dH = 0.0f, qH = 0.0f;     // bins absorbed by hydrogen alone (j < NA): photons, heat
+    float ab = 0.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, h0 = 0.0f;
+    float dH = 0.0f;                // photons of the bins hydrogen alone absorbs (j < NA)
 #pragma unroll
     for (int j = 0; j < MB; ++j) {
         if constexpr (MB > 1) {
@@ -194,20 +194,15 @@ __device__ __forceinline__ void cross_cell_f32(float l, const KV &kap, TT tab, f
             g0 = __builtin_fmaf(tab[j], gk, g0);
             if (he1) g1 = __builtin_fmaf(tab[MB + j], gk, g1);
             if (he2) g2 = __builtin_fmaf(tab[2 * MB + j], gk, g2);
-            if (TH) {
-                h0 = __builtin_fmaf(tab[3 * MB + j], gk, h0);
-                if (he1) h1 = __builtin_fmaf(tab[4 * MB + j], gk, h1);
-                if (he2) h2 = __builtin_fmaf(tab[5 * MB + j], gk, h2);
-            }
+            // photon energy absorbed (the ionisation energies come off below)
+            if (TH) h0 = __builtin_fmaf(d, tab[3 * MB + j], h0);
         } else {
-            // hydrogen alone absorbs: its share is 1, its heat E_j - E_th,HI
+            // hydrogen alone absorbs: its share is 1
             d = F[j] * (lo ? qs * t : 1.0f - tr);
-            if (S == 3) {
-                dH += d;
-                if (TH) qH = __builtin_fmaf(d, tab[6 * MB + j], qH);
-            } else if (TH) {
-                h0 = __builtin_fmaf(d, tab[3 * MB + j], h0);
-            }
+            if (S == 3) dH += d;
+            // heat E_j - E_th,HI per photon (one absorber); photon energy E_j
+            // (several absorbers, S == 3)
+            if (TH) h0 = __builtin_fmaf(d, tab[3 * MB + j], h0);
         }
         F[j] = lo ? F[j] - d : F[j] * tr;
         ab += d;
@@ -221,7 +216,11 @@ __device__ __forceinline__ void cross_cell_f32(float l, const KV &kap, TT tab, f
         e0 = __builtin_fmaf(cH, g0, dH);
         e1 = cHe1 * g1;
         e2 = cHe2 * g2;
-        heat = TH ? __builtin_fmaf(cHe2, h2, __builtin_fmaf(cHe1, h1, __builtin_fmaf(cH, h0, qH))) : 0.0f;
+        // heat = sum_j E_j d_j - sum_s E_th,s (photons species s absorbed):
+        // each absorbed photon leaves E_j minus its absorber's threshold
+        heat = TH ? __builtin_fmaf(-tab[4 * MB + 2], e2,
+                                   __builtin_fmaf(-tab[4 * MB + 1], e1, __builtin_fmaf(-tab[4 * MB], e0, h0)))
+                  : 0.0f;
     }
 }
 

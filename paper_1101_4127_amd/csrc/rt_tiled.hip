@@ -168,6 +168,7 @@ struct TRec {
 // Record ids of a run staged in LDS (the first kMaxRun of the run; a longer
 // run reads the rest of its list from memory).
 constexpr int kMaxRun = 2048;
+static_assert(kMaxRun % kTBlock == 0 && kTileCells % kTBlock == 0, "whole loads per thread");
 
 __device__ __forceinline__ uint32_t pack_cell(int k0, int k1, int k2, uint32_t axis) {
     return (uint32_t)k0 | ((uint32_t)k1 << 10) | ((uint32_t)k2 << 20) | (axis << 30);
@@ -1060,12 +1061,36 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
 
         // stage the tile's absorbers, clear its accumulators
         const KV *kg = reinterpret_cast<const KV *>(rs.kappa);
+        // (each thread issues all its loads before it waits for the first; its
+        // index is made opaque here so that the per-thread offsets are formed
+        // per run, not kept in registers across the march)
+        uint32_t tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
         if constexpr (!FIN) {
             const KV *kt = kg + ((size_t)tile << (3 * kTileLog2));
-            for (int i = threadIdx.x; i < kTileCells; i += kTBlock) s_kap[i] = kt[local_to_morton(i)];
+            constexpr int KPT = kTileCells / kTBlock;
+            KV kv[KPT];
+#pragma unroll
+            for (int k = 0; k < KPT; ++k) kv[k] = kt[local_to_morton(tid + k * kTBlock)];
+#pragma unroll
+            for (int k = 0; k < KPT; ++k) s_kap[tid + k * kTBlock] = kv[k];
             for (int i = threadIdx.x; i < kTileCells * (int)ACC; i += kTBlock) s_acc[i] = 0.0;
         }
-        for (uint32_t i = threadIdx.x; i < ch.len && i < (uint32_t)kMaxRun; i += kTBlock) s_list[i] = list[ch.start + i];
+        {
+            constexpr int LPT = kMaxRun / kTBlock;
+            const uint32_t ns = min(ch.len, (uint32_t)kMaxRun);
+            uint32_t iv[LPT];
+#pragma unroll
+            for (int k = 0; k < LPT; ++k) {
+                const uint32_t i = tid + k * kTBlock;
+                iv[k] = i < ns ? list[ch.start + i] : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < LPT; ++k) {
+                const uint32_t i = tid + k * kTBlock;
+                if (i < ns) s_list[i] = iv[k];
+            }
+        }
         if (threadIdx.x < kCodes) s_cnt[threadIdx.x] = 0u;
         if (threadIdx.x == 0) s_next = 0u;
         __syncthreads();
@@ -1443,14 +1468,37 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
         __syncthreads();
 
         // ---- the tile's deposits into the grid's accumulators ----
+        // (a run that shares its tile with other runs adds by atomics; the
+        // others read a group of their cells' values before the first wait, a
+        // cell with nothing to add reading the tile's first value unused, so
+        // that every load is issued and one wait covers the group)
         if constexpr (!FIN) {
             double *ga = rs.acc + ((size_t)tile << (3 * kTileLog2)) * ACC;
-            for (int i = threadIdx.x; i < kTileCells * (int)ACC; i += kTBlock) {
-                const double v = s_acc[((uint32_t)i % ACC) * kTileCells + (uint32_t)i / ACC];
-                if (v != 0.0) {
-                    double *g = ga + local_to_morton((uint32_t)i / ACC) * ACC + (uint32_t)i % ACC;
-                    if (ch.shared & 1u) unsafeAtomicAdd(g, v);
-                    else *g += v;
+            uint32_t ftid = threadIdx.x;
+            asm volatile("" : "+v"(ftid));
+            constexpr int FPT = kTileCells * (int)ACC / kTBlock;
+            constexpr int G = FPT < 4 ? FPT : 4;
+            static_assert(FPT % G == 0, "flush groups");
+#pragma unroll
+            for (int k0 = 0; k0 < FPT; k0 += G) {
+                double v[G], o[G];
+                uint32_t off[G];
+#pragma unroll
+                for (int k = 0; k < G; ++k) {
+                    const uint32_t i = ftid + (uint32_t)((k0 + k) * kTBlock);
+                    v[k] = s_acc[(i % ACC) * kTileCells + i / ACC];
+                    off[k] = local_to_morton(i / ACC) * ACC + i % ACC;
+                }
+                if (ch.shared & 1u) {
+#pragma unroll
+                    for (int k = 0; k < G; ++k)
+                        if (v[k] != 0.0) unsafeAtomicAdd(ga + off[k], v[k]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < G; ++k) o[k] = ga[v[k] != 0.0 ? off[k] : 0u];
+#pragma unroll
+                    for (int k = 0; k < G; ++k)
+                        if (v[k] != 0.0) ga[off[k]] = o[k] + v[k];
                 }
             }
         }

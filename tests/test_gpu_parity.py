@@ -203,7 +203,7 @@ def test_tiles_do_not_change_results(gpu):
                   dict(refill_min=64),
                   dict(),
                   dict(run_len=64, inflight=3000, refill_min=1),
-                  dict(run_len=2048, blocks_per_cu=1),
+                  dict(run_len=2048, blocks_per_cu=1), dict(run_len=8192),
                   dict(park_lanes=64, run_len=64), dict(park_lanes=24)):
         s = rt.Solve(w, trace_packets=5000, trace_len=96, **tiles)
         st = s.step()

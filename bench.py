@@ -265,6 +265,14 @@ def oracle_leg(work, packets: int):
     return cpu, accuracy
 
 
+def counted_config(args) -> bool:
+    """The committed counter runs are of the default benchmark: the 256^3
+    workload, its packet count, the tiled march and default launch
+    parameters.  Other workloads and launch shapes get no counter figures."""
+    return (args.workload == "lognormal_256" and args.packets is None and not args.direct
+            and args.inflight == 0 and args.run_len == 0 and args.refill == 0 and args.bpcu == 0)
+
+
 def traffic_for(launch_crossings: float):
     """HBM bytes per march launch from committed rocprofv3 counter runs, or
     None when the counters were taken on a different march kernel."""
@@ -448,8 +456,9 @@ def roofline(per_launch, avg_ms, achieved, args, f32):
     roofline of the algorithmic bytes per crossing (absorber gather + float64
     accumulator updates) against the nominal 8 TB/s and the measured copy
     peak, and the HBM bytes the counters saw."""
-    traffic = traffic_for(per_launch)
-    ctr = counters_for()
+    counted = counted_config(args)
+    traffic = traffic_for(per_launch) if counted else None
+    ctr = counters_for() if counted else None
     hbm = {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
            "bytes_per_crossing": BYTES_F32, "traffic": traffic}
     if traffic is not None:

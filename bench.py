@@ -49,11 +49,38 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def code_text(src: str) -> str:
+    """C++ source without its comments and blank space (string and character
+    literals kept whole), so that the march hash names the code alone."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if src.startswith("//", i):
+            i = src.find("\n", i)
+            i = n if i < 0 else i
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def march_hash() -> str:
+    """Identifies the march kernel's code (its sources without comments): the
+    committed counters apply while the code hashes to their march_hash."""
     h = hashlib.sha256()
     for name in ("rt_tiled.hip", "rt_march.hip", "rt_cross.h", "rt_device.h", "rt_internal.h"):
-        with open(os.path.join(ROOT, "paper_1101_4127_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_1101_4127_amd", "csrc", name), encoding="utf-8") as f:
+            h.update(code_text(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -134,8 +134,11 @@ __device__ __forceinline__ float column_depth(float sH, float sHe1, float sHe2, 
 // the hardware 2^-t_j.  With q_j = (1 - 2^-t_j) / t_j the absorbed photons
 // are d_j = F_j q_j t_j, and d_j / K_j = l log2(e) F_j q_j, so the split among
 // absorbers needs no division by K_j: per absorber
-// (l kappa_s) sum_j (sigma_s,j log2(e)) F_j q_j, and the heat likewise from
-// the scaled heat factors.  q_j comes from its Taylor series below
+// (l kappa_s) sum_j (sigma_s,j log2(e)) F_j q_j.  The H+He heat is the same
+// sum written as the energy of the absorbed photons less each absorber's
+// threshold times the photons it took, sum_j E_j d_j - sum_s E_th,s n_s (the
+// photons of bin j absorbed by all species add up to d_j), one product per
+// bin.  q_j comes from its Taylor series below
 // t = kSeriesT (tau = 1/8; truncation after the tau^4 term, relative error
 // below tau^5/720 = 4.2e-8) and from 1 - 2^-t_j times the hardware
 // reciprocal above (relative error a few times 1e-7 just above the switch,

@@ -88,9 +88,21 @@ struct MarchTab<R, MB, true> {
 
 // Bins any lane of the wavefront with lane_on set still carries (bit j: some
 // such lane has bit j of `active`).  Wave-uniform.
+// With every lane of the wavefront executing, the masks are OR-ed across it
+// by DPP moves (within quads, half rows and rows, then row broadcasts into
+// the last row) and read from lane 63; otherwise one ballot per bin.
 template <int MB>
 __device__ __forceinline__ uint32_t wave_bins(bool lane_on, uint32_t active) {
-    const uint32_t v = lane_on ? active : 0u;     // one select, then one bit test per bin
+    uint32_t v = lane_on ? active : 0u;
+    if (__builtin_amdgcn_read_exec() == ~0ull) {
+        v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);    // quad_perm 1,0,3,2
+        v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);    // quad_perm 2,3,0,1
+        v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);   // row_half_mirror
+        v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false);   // row_mirror
+        v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);   // row_bcast:15
+        v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);   // row_bcast:31
+        return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+    }
     uint32_t m = 0;
 #pragma unroll
     for (int j = 0; j < MB; ++j) m |= (__ballot((v >> j) & 1u) != 0ull) ? (1u << j) : 0u;

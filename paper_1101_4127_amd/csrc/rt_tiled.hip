@@ -1477,7 +1477,7 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
             uint32_t ftid = threadIdx.x;
             asm volatile("" : "+v"(ftid));
             constexpr int FPT = kTileCells * (int)ACC / kTBlock;
-            constexpr int G = FPT < 4 ? FPT : 4;
+            constexpr int G = FPT < 8 ? FPT : 8;
             static_assert(FPT % G == 0, "flush groups");
 #pragma unroll
             for (int k0 = 0; k0 < FPT; k0 += G) {

@@ -1056,7 +1056,6 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
         const float kill_t = depth_threshold(tau_kill);
         const float drop_t = depth_threshold(fmax(tau_kill, (double)kDropDepth));
         const CTab<R> ctab = (CTab<R>)rs.tab;
-        if (!F64 && threadIdx.x < 3 * MB) s_sigf[threadIdx.x] = (float)ctab[threadIdx.x];
         const typename MarchTab<R, MB>::type tab = MarchTab<R, MB>::make(ctab);
 
         // stage the tile's absorbers, clear its accumulators
@@ -1066,30 +1065,36 @@ __global__ void __launch_bounds__(kTBlock, (TOcc<R, MB>::value)) k_tmarch(const 
         // per run, not kept in registers across the march)
         uint32_t tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
-        if constexpr (!FIN) {
-            const KV *kt = kg + ((size_t)tile << (3 * kTileLog2));
-            constexpr int KPT = kTileCells / kTBlock;
-            KV kv[KPT];
-#pragma unroll
-            for (int k = 0; k < KPT; ++k) kv[k] = kt[local_to_morton(tid + k * kTBlock)];
-#pragma unroll
-            for (int k = 0; k < KPT; ++k) s_kap[tid + k * kTBlock] = kv[k];
-            for (int i = threadIdx.x; i < kTileCells * (int)ACC; i += kTBlock) s_acc[i] = 0.0;
-        }
         {
+            constexpr int KPT = FIN ? 1 : kTileCells / kTBlock;
             constexpr int LPT = kMaxRun / kTBlock;
             const uint32_t ns = min(ch.len, (uint32_t)kMaxRun);
+            KV kv[KPT];
             uint32_t iv[LPT];
+            // float32 form: the run's cross-sections, indexed per lane
+            const bool sig_lane = !F64 && tid < 3u * MB;
+            const float sg = sig_lane ? (float)ctab[tid] : 0.0f;
+            if constexpr (!FIN) {
+                const KV *kt = kg + ((size_t)tile << (3 * kTileLog2));
+#pragma unroll
+                for (int k = 0; k < KPT; ++k) kv[k] = kt[local_to_morton(tid + k * kTBlock)];
+            }
 #pragma unroll
             for (int k = 0; k < LPT; ++k) {
                 const uint32_t i = tid + k * kTBlock;
                 iv[k] = i < ns ? list[ch.start + i] : 0u;
+            }
+            if constexpr (!FIN) {
+#pragma unroll
+                for (int k = 0; k < KPT; ++k) s_kap[tid + k * kTBlock] = kv[k];
+                for (int i = threadIdx.x; i < kTileCells * (int)ACC; i += kTBlock) s_acc[i] = 0.0;
             }
 #pragma unroll
             for (int k = 0; k < LPT; ++k) {
                 const uint32_t i = tid + k * kTBlock;
                 if (i < ns) s_list[i] = iv[k];
             }
+            if (sig_lane) s_sigf[tid] = sg;
         }
         if (threadIdx.x < kCodes) s_cnt[threadIdx.x] = 0u;
         if (threadIdx.x == 0) s_next = 0u;
